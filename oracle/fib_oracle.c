@@ -1,0 +1,437 @@
+/*
+ * fib_oracle.c -- plain FP64 CPU oracle for the Strang-split monodomain solve
+ * on many independent 1D muscle fibers (Maier, "Scalable Biophysical
+ * Simulations of the Neuromuscular System", 2021).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
+ * reference that the GPU library is judged against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may build, load
+ * or call it.  It shares no code, header or table with the GPU library.
+ *
+ * Everything is double precision, scalar loops, no fast-math.  Each function
+ * names the passage of the thesis it follows:
+ *   - subcellular model: section "Subcellular Model", eqs. subcellular_model_
+ *     helper3-5 and subcellular; the Hodgkin-Huxley rate functions in the
+ *     -75 mV resting-potential convention fixed by the generated-code excerpt
+ *     in section "Computation of CellML Models" (Hodgkin & Huxley 1952);
+ *   - monodomain equation on a fiber: eq. monodomain, no-flux ends
+ *     eq. monodomain_bc1;
+ *   - operator splitting: eq. monodomain_strang (0D, 1D, 0D order, figure
+ *     splitting_schemes), eq. monodomain_godunov;
+ *   - time stepping: eq. heun (0D), eq. crank_nicolson with theta = 1/2 (1D);
+ *   - 1D linear finite elements: tables stencils_laplace and
+ *     stencils_mass_laplace, mass lumping (section "Using Mass Lumping for
+ *     Implicit Timestepping", eq. lumping_crank_nicolson);
+ *   - block-diagonal per-fiber system: eq. discretized_fibers_1;
+ *   - Thomas algorithm: section "Improved Parallel Solver Scheme using the
+ *     Thomas Algorithm";
+ *   - stimulation of the nodes around a neuromuscular junction: section
+ *     "Specification of Stimulation Times Using Callback Functions".
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_OK 0
+#define OR_EINVAL (-1)
+#define OR_ENOMEM (-2)
+
+/* ------------------------------------------------------------------------ */
+/* Parameters                                                                */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+  int32_t model;   /* 0: Hodgkin-Huxley (4 states), 1: ST57 (57 states) */
+  int32_t scheme;  /* 0: Strang  R(dt/2) D(dt) R(dt/2);  1: Godunov R(dt) D(dt) */
+  double Cm;       /* membrane capacitance, uF/cm^2 */
+  double Am;       /* surface-to-volume ratio, 1/cm */
+  double sigma;    /* effective conductivity along the fiber, mS/cm */
+  double h;        /* node spacing, cm */
+  double dt_0D;    /* largest reaction substep, ms */
+  double dt_1D;    /* largest diffusion substep, ms */
+  double dt_split; /* splitting step, ms */
+  double v_th;     /* activation threshold for the activation-time observable, mV */
+} or_params;
+
+typedef struct {
+  int32_t fiber;      /* fiber index */
+  int32_t node;       /* centre node j (0-based, within the fiber) */
+  int32_t half_width; /* nodes j-hw .. j+hw are stimulated (clipped to the fiber) */
+  int32_t pad_;
+  int64_t step_on;    /* first split step with current on */
+  int64_t n_steps;    /* number of consecutive split steps with current on */
+  int64_t period;     /* 0: one pulse; >0: the pulse repeats every `period` steps */
+  double amp;         /* current density, uA/cm^2 */
+} or_stim;
+
+/* ------------------------------------------------------------------------ */
+/* Hodgkin-Huxley membrane (section "Subcellular Model")                     */
+/* ------------------------------------------------------------------------ */
+
+#define HH_ER (-75.0)
+#define HH_GNA 120.0
+#define HH_GK 36.0
+#define HH_GL 0.3
+#define HH_ENA (HH_ER + 115.0)
+#define HH_EK (HH_ER - 12.0)
+#define HH_EL (HH_ER + 10.613)
+
+/* x / (exp(x) - 1), the shape of alpha_m and alpha_n; removable singularity
+ * at x = 0 where the value is 1.  Near 0 the Taylor series 1 - x/2 + x^2/12
+ * is used (its truncation error x^4/720 is below 1e-18 for |x| < 1e-4). */
+static double x_over_expm1(double x) {
+  if (fabs(x) < 1e-4) return 1.0 - 0.5 * x + x * x / 12.0;
+  return x / expm1(x);
+}
+
+/* Rate constants (1/ms) of the three gates at membrane voltage V (mV).
+ * With v = V - E_R the classic forms are
+ *   alpha_m = 0.1 (25-v)/(exp((25-v)/10)-1),  beta_m = 4 exp(-v/18),
+ *   alpha_h = 0.07 exp(-v/20),                beta_h = 1/(exp((30-v)/10)+1),
+ *   alpha_n = 0.01 (10-v)/(exp((10-v)/10)-1), beta_n = 0.125 exp(-v/80). */
+void or_hh_gate_rates(double V, double ab[6]) {
+  double v = V - HH_ER;
+  ab[0] = x_over_expm1((25.0 - v) / 10.0);
+  ab[1] = 4.0 * exp(-v / 18.0);
+  ab[2] = 0.07 * exp(-v / 20.0);
+  ab[3] = 1.0 / (exp((30.0 - v) / 10.0) + 1.0);
+  ab[4] = 0.1 * x_over_expm1((10.0 - v) / 10.0);
+  ab[5] = 0.125 * exp(-v / 80.0);
+}
+
+/* Ionic current density I_ion (uA/cm^2), eq. subcellular_model_helper5 with
+ * g_Na = gbar_Na m^3 h and g_K = gbar_K n^4. */
+double or_hh_iion(const double y[4]) {
+  double V = y[0], m = y[1], h = y[2], n = y[3];
+  double gna = HH_GNA * m * m * m * h;
+  double gk = HH_GK * n * n * n * n;
+  return gna * (V - HH_ENA) + gk * (V - HH_EK) + HH_GL * (V - HH_EL);
+}
+
+/* Right-hand side G(y) of the subcellular model, eq. subcellular:
+ *   Cm dV/dt = -I_ion + I_stim           (eq. subcellular_model_helper3)
+ *   dy/dt    = alpha (1 - y) - beta y    for y in {m, h, n}. */
+void or_hh_rhs(double Cm, const double y[4], double I_stim, double dydt[4]) {
+  double ab[6];
+  or_hh_gate_rates(y[0], ab);
+  dydt[0] = (-or_hh_iion(y) + I_stim) / Cm;
+  dydt[1] = ab[0] * (1.0 - y[1]) - ab[1] * y[1];
+  dydt[2] = ab[2] * (1.0 - y[2]) - ab[3] * y[2];
+  dydt[3] = ab[4] * (1.0 - y[3]) - ab[5] * y[3];
+}
+
+/* Steady-state ionic current with every gate at its equilibrium
+ * y_inf = alpha / (alpha + beta) (the frozen-voltage limit of the gate ODE). */
+static double hh_iss(double V) {
+  double ab[6], y[4];
+  or_hh_gate_rates(V, ab);
+  y[0] = V;
+  y[1] = ab[0] / (ab[0] + ab[1]);
+  y[2] = ab[2] / (ab[2] + ab[3]);
+  y[3] = ab[4] / (ab[4] + ab[5]);
+  return or_hh_iion(y);
+}
+
+/* Resting state of the membrane: the voltage where the steady-state current
+ * vanishes, found by bisection on [-80, -70] mV (I_ss changes sign there)
+ * followed by secant polishing; gates at their equilibria. */
+int or_hh_rest(double y[4]) {
+  double lo = -80.0, hi = -70.0, flo = hh_iss(lo), fhi = hh_iss(hi);
+  if (!(flo < 0.0 && fhi > 0.0)) return OR_EINVAL;
+  for (int it = 0; it < 200; ++it) {
+    double mid = 0.5 * (lo + hi), fm = hh_iss(mid);
+    if (fm == 0.0) { lo = hi = mid; break; }
+    if (fm < 0.0) lo = mid; else hi = mid;
+    if (hi - lo < 1e-15) break;
+  }
+  double V = 0.5 * (lo + hi);
+  double ab[6];
+  or_hh_gate_rates(V, ab);
+  y[0] = V;
+  y[1] = ab[0] / (ab[0] + ab[1]);
+  y[2] = ab[2] / (ab[2] + ab[3]);
+  y[3] = ab[4] / (ab[4] + ab[5]);
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Model dispatch                                                            */
+/* ------------------------------------------------------------------------ */
+
+int or_n_states(int model) {
+  if (model == 0) return 4;
+  return -1;
+}
+
+static void model_rhs(int model, double Cm, const double* y, double I, double* dydt) {
+  (void)model;
+  or_hh_rhs(Cm, y, I, dydt);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Heun's method, eq. heun                                                   */
+/* ------------------------------------------------------------------------ */
+
+#define OR_MAX_STATES 64
+
+/* One Heun step of width tau on one node:
+ *   y+ = y + tau/2 (G(y) + G(y + tau G(y))). */
+static void heun_step(int model, int S, double Cm, double* y, double I, double tau) {
+  double k1[OR_MAX_STATES], k2[OR_MAX_STATES], yt[OR_MAX_STATES];
+  model_rhs(model, Cm, y, I, k1);
+  for (int k = 0; k < S; ++k) yt[k] = y[k] + tau * k1[k];
+  model_rhs(model, Cm, yt, I, k2);
+  for (int k = 0; k < S; ++k) y[k] = y[k] + 0.5 * tau * (k1[k] + k2[k]);
+}
+
+/* Number of equal reaction substeps that cover `span` with width <= dt_0D. */
+int64_t or_n_substeps(double span, double dt) {
+  int64_t n = (int64_t)ceil(span / dt - 1e-9);
+  return n < 1 ? 1 : n;
+}
+
+/* Reaction part over `span` for nodes [i0, i1) of the SoA state
+ * y[k * n_total + i]: n_sub equal Heun substeps per node, stimulus current
+ * I[i] held constant over the span. */
+static void reaction_range(const or_params* p, int S, double* y, int64_t n_total,
+                           int64_t i0, int64_t i1, const double* I, double span) {
+  int64_t nsub = or_n_substeps(span, p->dt_0D);
+  double tau = span / (double)nsub;
+  double yn[OR_MAX_STATES];
+  for (int64_t i = i0; i < i1; ++i) {
+    for (int k = 0; k < S; ++k) yn[k] = y[(int64_t)k * n_total + i];
+    for (int64_t s = 0; s < nsub; ++s) heun_step(p->model, S, p->Cm, yn, I ? I[i] : 0.0, tau);
+    for (int k = 0; k < S; ++k) y[(int64_t)k * n_total + i] = yn[k];
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Thomas algorithm                                                          */
+/* ------------------------------------------------------------------------ */
+
+/* Solves the tridiagonal system
+ *   a[i] x[i-1] + d[i] x[i] + c[i] x[i+1] = b[i],  i = 0..n-1
+ * (a[0] and c[n-1] are ignored) by a forward elimination sweep and a back
+ * substitution sweep, without pivoting.  `work` holds n doubles. */
+void or_thomas(int64_t n, const double* a, const double* d, const double* c,
+               const double* b, double* x, double* work) {
+  if (n <= 0) return;
+  double* cp = work;
+  double den = d[0];
+  cp[0] = (n > 1 ? c[0] : 0.0) / den;
+  x[0] = b[0] / den;
+  for (int64_t i = 1; i < n; ++i) {
+    den = d[i] - a[i] * cp[i - 1];
+    cp[i] = (i < n - 1 ? c[i] : 0.0) / den;
+    x[i] = (b[i] - a[i] * x[i - 1]) / den;
+  }
+  for (int64_t i = n - 2; i >= 0; --i) x[i] -= cp[i] * x[i + 1];
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1D diffusion along one fiber: lumped linear FE + Crank-Nicolson           */
+/* ------------------------------------------------------------------------ */
+
+/* Row i of M_L^{-1} K for a fiber of n nodes with spacing h and no-flux ends.
+ * Element stiffness (1/h)[-1 1; 1 -1] and element mass (h/6)[2 1; 1 2]
+ * (tables stencils_laplace, stencils_mass_laplace) assemble to
+ * K = (1/h) tridiag(1, -2, 1) with corner entries -1, and the lumped mass
+ * (row sums) is h * diag(1/2, 1, ..., 1, 1/2).  Hence row i of M_L^{-1} K is
+ * (wl, -(wl+wr), wr) / h^2 with wl, wr in {0, 1, 2}. */
+static void lumped_row(int64_t i, int64_t n, double* wl, double* wr) {
+  if (n == 1) { *wl = 0.0; *wr = 0.0; return; }
+  if (i == 0) { *wl = 0.0; *wr = 2.0; return; }
+  if (i == n - 1) { *wl = 2.0; *wr = 0.0; return; }
+  *wl = 1.0; *wr = 1.0;
+}
+
+/* One Crank-Nicolson step of width dt on one fiber,
+ *   (I - dt/2 c M_L^{-1} K) V+ = (I + dt/2 c M_L^{-1} K) V,
+ * with c = sigma / (Am Cm) (eq. monodomain, eq. lumping_crank_nicolson).
+ * The left-hand matrix is assembled row by row and solved by Thomas. */
+static void cn_step(const or_params* p, int64_t n, double* V, double dt,
+                    double* a, double* d, double* c, double* b, double* x, double* work) {
+  double coef = p->sigma / (p->Am * p->Cm);
+  double half = 0.5 * dt * coef / (p->h * p->h);
+  for (int64_t i = 0; i < n; ++i) {
+    double wl, wr;
+    lumped_row(i, n, &wl, &wr);
+    double left = (i > 0) ? V[i - 1] : 0.0;
+    double right = (i < n - 1) ? V[i + 1] : 0.0;
+    /* right-hand side (I + dt/2 L) V */
+    b[i] = V[i] + half * (wl * left - (wl + wr) * V[i] + wr * right);
+    /* left-hand matrix (I - dt/2 L) */
+    a[i] = -half * wl;
+    d[i] = 1.0 + half * (wl + wr);
+    c[i] = -half * wr;
+  }
+  or_thomas(n, a, d, c, b, x, work);
+  for (int64_t i = 0; i < n; ++i) V[i] = x[i];
+}
+
+/* Diffusion part over `span` on one fiber: equal CN substeps of width
+ * <= dt_1D. */
+static void diffusion_fiber(const or_params* p, int64_t n, double* V, double span,
+                            double* scratch) {
+  int64_t m = or_n_substeps(span, p->dt_1D);
+  double dt = span / (double)m;
+  double *a = scratch, *d = a + n, *c = d + n, *b = c + n, *x = b + n, *w = x + n;
+  for (int64_t s = 0; s < m; ++s) cn_step(p, n, V, dt, a, d, c, b, x, w);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Stimulus                                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* True if stimulus entry `s` is on during split step `step`: a pulse of
+ * n_steps split steps starting at step_on, repeated every `period` steps when
+ * period > 0.  The current is held for the whole split step (both reaction
+ * halves). */
+static int stim_on(const or_stim* s, int64_t step) {
+  if (step < s->step_on || s->n_steps <= 0) return 0;
+  int64_t k = step - s->step_on;
+  if (s->period > 0) k = k % s->period;
+  return k < s->n_steps;
+}
+
+/* Stimulus current of every node of fiber f (local node index) at `step`. */
+static void fiber_current(int32_t f, int64_t n, const or_stim* stim, int32_t n_stim,
+                          int64_t step, double* I) {
+  for (int64_t i = 0; i < n; ++i) I[i] = 0.0;
+  for (int32_t e = 0; e < n_stim; ++e) {
+    const or_stim* s = &stim[e];
+    if (s->fiber != f || !stim_on(s, step)) continue;
+    for (int64_t j = (int64_t)s->node - s->half_width; j <= (int64_t)s->node + s->half_width; ++j)
+      if (j >= 0 && j < n) I[j] += s->amp;
+  }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-phase entry points (for phase-by-phase comparisons)                */
+/* ------------------------------------------------------------------------ */
+
+/* Reaction over `span` on every node of the SoA state y[S][n_total] with the
+ * per-node current I (nullable: no current). */
+int or_reaction(const or_params* p, int64_t n_total, double* y, const double* I, double span) {
+  int S = or_n_states(p->model);
+  if (S <= 0 || n_total < 0 || !(span > 0.0)) return OR_EINVAL;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n_total; ++i) reaction_range(p, S, y, n_total, i, i + 1, I, span);
+  return OR_OK;
+}
+
+/* Diffusion over `span` on the concatenated membrane voltages of n_fibers
+ * fibers (fiber f occupies n_nodes[f] consecutive entries of V). */
+int or_diffusion(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double* V,
+                 double span) {
+  if (n_fibers < 0 || !(span > 0.0)) return OR_EINVAL;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_fibers + 1));
+  if (!off) return OR_ENOMEM;
+  off[0] = 0;
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    if (n_nodes[f] < 1) { free(off); return OR_EINVAL; }
+    off[f + 1] = off[f] + n_nodes[f];
+  }
+  int err = OR_OK;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    int64_t n = n_nodes[f];
+    double* scratch = (double*)malloc(sizeof(double) * 6 * (size_t)n);
+    if (!scratch) { err = OR_ENOMEM; continue; }
+    diffusion_fiber(p, n, V + off[f], span, scratch);
+    free(scratch);
+  }
+  free(off);
+  return err;
+}
+
+/* Per-node stimulus current at split step `step` for the concatenated
+ * fibers (I has sum(n_nodes) entries). */
+int or_stimulus_current(int32_t n_fibers, const int32_t* n_nodes, const or_stim* stim,
+                        int32_t n_stim, int64_t step, double* I) {
+  int64_t off = 0;
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    fiber_current(f, n_nodes[f], stim, n_stim, step, I + off);
+    off += n_nodes[f];
+  }
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The splitting loop                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Runs split steps step0 .. step0+n_steps-1 on all fibers.
+ *
+ * y       SoA state y[k * n_total + i], in/out (k = 0 is V_m in mV).
+ * stim    stimulus table (n_stim entries).
+ * samples nullable; if sample_every > 0, after every split step n with
+ *         (n + 1) % sample_every == 0 the membrane voltage is written to
+ *         samples[s * n_total + i], s = (n + 1) / sample_every - 1 - first,
+ *         where first = step0 / sample_every counts samples of earlier calls.
+ * t_act   nullable, in/out: per node the time (ms) of the first upward
+ *         crossing of v_th, linearly interpolated between the ends of the
+ *         split step; +inf until it happens.
+ *
+ * Fibers are independent (eq. discretized_fibers_1 is block diagonal), so
+ * each fiber is advanced through all steps on its own. */
+int or_run(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double* y,
+           const or_stim* stim, int32_t n_stim, int64_t step0, int64_t n_steps,
+           int64_t sample_every, double* samples, double* t_act) {
+  int S = or_n_states(p->model);
+  if (S <= 0 || n_fibers < 0 || n_steps < 0 || step0 < 0 || !(p->dt_split > 0.0)) return OR_EINVAL;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_fibers + 1));
+  if (!off) return OR_ENOMEM;
+  off[0] = 0;
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    if (n_nodes[f] < 1) { free(off); return OR_EINVAL; }
+    off[f + 1] = off[f] + n_nodes[f];
+  }
+  const int64_t n_total = off[n_fibers];
+  const double dt = p->dt_split;
+  int err = OR_OK;
+
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    const int64_t n = n_nodes[f], o = off[f];
+    double* buf = (double*)malloc(sizeof(double) * ((size_t)S * n + 9 * (size_t)n));
+    if (!buf) { err = OR_ENOMEM; continue; }
+    double* yf = buf;               /* SoA state of this fiber, S x n */
+    double* I = yf + (size_t)S * n; /* stimulus current */
+    double* vprev = I + n;          /* V at the start of the split step */
+    double* scratch = vprev + n;    /* 6 n for the CN solve */
+    for (int k = 0; k < S; ++k)
+      memcpy(yf + (size_t)k * n, y + (int64_t)k * n_total + o, sizeof(double) * n);
+
+    for (int64_t step = step0; step < step0 + n_steps; ++step) {
+      memcpy(vprev, yf, sizeof(double) * n);
+      fiber_current(f, n, stim, n_stim, step, I);
+      if (p->scheme == 0) {
+        reaction_range(p, S, yf, n, 0, n, I, 0.5 * dt);
+        diffusion_fiber(p, n, yf, dt, scratch);
+        reaction_range(p, S, yf, n, 0, n, I, 0.5 * dt);
+      } else {
+        reaction_range(p, S, yf, n, 0, n, I, dt);
+        diffusion_fiber(p, n, yf, dt, scratch);
+      }
+      if (t_act) {
+        double t0 = (double)step * dt;
+        for (int64_t i = 0; i < n; ++i) {
+          double v0 = vprev[i], v1 = yf[i];
+          if (isinf(t_act[o + i]) && v0 < p->v_th && v1 >= p->v_th)
+            t_act[o + i] = t0 + dt * (p->v_th - v0) / (v1 - v0);
+        }
+      }
+      if (samples && sample_every > 0 && (step + 1) % sample_every == 0) {
+        int64_t s = (step + 1) / sample_every - 1 - step0 / sample_every;
+        memcpy(samples + s * n_total + o, yf, sizeof(double) * n);
+      }
+    }
+    for (int k = 0; k < S; ++k)
+      memcpy(y + (int64_t)k * n_total + o, yf + (size_t)k * n, sizeof(double) * n);
+    free(buf);
+  }
+  free(off);
+  return err;
+}
