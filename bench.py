@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput of the Strang-split fiber monodomain solver on one MI355X.
+
+Workload (the batched plain Hodgkin-Huxley case): 1369 fibers with lengths
+drawn uniformly from 1000..1500 nodes (h = 0.01 cm), each stimulated for
+0.1 ms on three nodes in the central 10 % of the fiber at a seeded time in
+[0, 5] ms, V_m noise N(0, 0.1 mV); dt_0D = dt_1D = dt_split = 1e-3 ms,
+20 ms simulated (20000 split steps), FP32 on the GPU.
+
+One bench step is the whole hot path over that batch: the initial state
+(resting state plus noise, on the device), then fib_run over all 20000
+split steps -- stimulus, R(dt/2) D(dt) R(dt/2), activation times and V_m
+samples every 0.1 ms -- with inputs resident in HBM.
+
+Prints one JSON line.  `value` = node-steps per second (one node advanced
+through one split step), whole job.  `roofline` reports the fused kernel's
+achieved VALU issue rate from its algorithmic op count against the chip's
+FP32 VALU issue peak; `cpu_baseline` times the FP64 oracle on a bounded
+subset of the same fibers on the host cores and doubles as a parity check
+of those fibers.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "subcellular node-steps/sec at ≤0.5 mV Vm error: plain FP32 vs surrogate"
+
+# Algorithmic cost of one node-step of the plain Hodgkin-Huxley path, in
+# FP32 VALU issue slots (one slot = one lane-cycle of a 16-lane SIMD; add,
+# mul, FMA, compare = 1 slot; exp2 and reciprocal = 4 slots, quarter rate):
+#   right-hand side G: 34 simple ops + 6 exp + 3 reciprocals = 70 slots
+#   Heun step: 2 G + 12 update ops = 152 slots
+#   reaction: 2 half steps x 1 Heun substep = 304 slots
+#   Crank-Nicolson (right-hand side 4, elimination 3, back substitution 2) = 9
+#   activation-time test = 2
+SLOTS_PER_NODE_STEP = 315
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=int(os.environ.get("WORLD_SIZE", "1")))
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--t-end", type=float, default=20.0, help="simulated ms per bench step")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-fibers", type=int, default=0,
+                    help="fibers in the oracle sample (default: 2 per host thread)")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, gpu_samples, gpu_tact, fibers):
+    """Times the FP64 oracle on the first `fibers` fibers of the workload and
+    compares them with the GPU run."""
+    from oracle import oracle as O
+    sub = w.subset(list(range(fibers)))
+    cfg = O.Config(dt_0D=sub.dt_0D, dt_1D=sub.dt_1D, dt_split=sub.dt_split, v_th=sub.v_th)
+    y0 = np.tile(O.rest_state()[:, None], (1, sub.n_total))
+    y0[0] += sub.vm_noise.astype(np.float32)
+    t0 = time.perf_counter()
+    yo, so, to = O.run(cfg, sub.n_nodes, y0, sub.stims, sub.n_steps,
+                       sample_every=sub.sample_every)
+    dt = time.perf_counter() - t0
+    n = sub.n_total
+    vm_err = float(np.max(np.abs(gpu_samples[:, :n] - so)))
+    tg = gpu_tact[:n].astype(np.float64)
+    both = np.isfinite(tg) & np.isfinite(to)
+    tact_err = float(np.max(np.abs(tg[both] - to[both]))) if both.any() else 0.0
+    mismatch = int(np.sum(np.isfinite(tg) != np.isfinite(to)))
+    return sub.node_steps() / dt, dict(fibers=fibers, nodes=n, seconds=dt, vm_max_err_mV=vm_err,
+                                       tact_max_err_ms=tact_err, tact_mismatch=mismatch,
+                                       activated=int(both.sum()))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the fibers are "
+              "independent, so a multi-GPU run would shard whole fibers with no "
+              "communication -- not measured here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+
+    torch.cuda.set_device(0)
+    w = I.batched_hh(t_end=args.t_end)
+    stream = torch.cuda.current_stream()
+    s = F.Solver(w.n_nodes, stream=stream.cuda_stream, dt_0D=w.dt_0D, dt_1D=w.dt_1D,
+                 dt_split=w.dt_split)
+    s.set_stimulus(w.stims)
+    vm = torch.as_tensor(w.vm_noise.astype(np.float32), device="cuda")
+    rows = w.n_steps // w.sample_every
+    samples = torch.empty((rows, w.n_total), device="cuda")
+    plan = s.plan()
+    print(f"# workload {w.name}: {w.n_total} nodes, {w.n_steps} split steps; plan {plan}",
+          file=sys.stderr, flush=True)
+
+    def step(ev=None):
+        F.fib_init_state(s.ctx, vm.data_ptr(), 0)
+        if ev is not None:
+            ev[0].record(stream)
+        s.run(0, w.n_steps, w.sample_every, samples)
+        if ev is not None:
+            ev[1].record(stream)
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        print(f"# warmup step {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    s.sync()
+
+    events = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(events[i])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    s.sync()
+    kernel_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    print(f"# timed {args.steps} steps in {elapsed:.3f} s; fused kernel {kernel_ms:.2f} ms/launch",
+          file=sys.stderr, flush=True)
+
+    node_steps = w.node_steps()
+    value = node_steps * args.steps / elapsed
+    achieved = node_steps * SLOTS_PER_NODE_STEP / (kernel_ms * 1e-3)
+    roofline = {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": VALU_PEAK_SLOTS / 1e12,
+        "unit": "Tslot/s (FP32 VALU issue slots)",
+        "frac": achieved / VALU_PEAK_SLOTS,
+        "traffic": None,
+        "kernel": "k_run_hh",
+        "kernel_ms_per_launch": kernel_ms,
+        "slots_per_node_step": SLOTS_PER_NODE_STEP,
+    }
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        fibers = args.cpu_fibers or 2 * threads
+        gs = samples.cpu().numpy().astype(np.float64)
+        gt = s.tact()
+        rate, parity = cpu_baseline(w, gs, gt, min(fibers, len(w.n_nodes)))
+        cpu = {"value": rate, "unit": "node-steps/s", "cores": threads, "kind": "oracle",
+               "sample": f"first {parity['fibers']} fibers ({parity['nodes']} nodes) of the "
+                         f"same workload, all {w.n_steps} split steps, FP64, OpenMP over fibers"}
+        print(f"# oracle: {rate:.3e} node-steps/s on {threads} threads; parity {parity}",
+              file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "node-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "hh_batched_1369_fibers_1000-1500_nodes_20ms",
+                   "fibers": int(len(w.n_nodes)), "nodes": int(w.n_total),
+                   "split_steps": int(w.n_steps), "dt_split_ms": w.dt_split,
+                   "schedule": "fused", "plan": plan, "path": "plain"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_vs_oracle": parity,
+    }
+    s.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

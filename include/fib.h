@@ -1,0 +1,208 @@
+/*
+ * fib.h -- C ABI of libfib.so, an MI355X (gfx950) solver for the
+ * Strang-split monodomain equation on many independent 1D muscle fibers
+ * (B. Maier, "Scalable Biophysical Simulations of the Neuromuscular System",
+ * 2021).
+ *
+ * The problem (thesis section "Discretization of the Monodomain Model" and
+ * eq. discretized_fibers_1):
+ *   on every fiber, dV/dt = sigma/(Am Cm) d2V/dx2 - I_ion(V, y)/Cm with
+ *   no-flux ends (eqs. monodomain, monodomain_bc1), and dy/dt = G(V, y) at
+ *   every node (eq. subcellular).  One split step of width dt is
+ *   R(dt/2) D(dt) R(dt/2) (eq. monodomain_strang, 0D-1D-0D order):
+ *     R: Heun's method (eq. heun) on all states of every node, in
+ *        ceil((dt/2)/dt_0D) equal substeps, with the node's stimulus current
+ *        held constant over the split step;
+ *     D: Crank-Nicolson (eq. crank_nicolson, theta = 1/2) with linear finite
+ *        elements and a lumped mass matrix (section "Using Mass Lumping for
+ *        Implicit Timestepping", eq. lumping_crank_nicolson) in
+ *        ceil(dt/dt_1D) equal substeps, i.e. one tridiagonal system per fiber
+ *        per substep (section "Improved Parallel Solver Scheme using the
+ *        Thomas Algorithm").
+ *   Stimulus: a current density on the nodes around a neuromuscular junction
+ *   (section "Specification of Stimulation Times Using Callback Functions").
+ *
+ * Units: cm, ms, mV, uA/cm^2, uF/cm^2, mS/cm.
+ *
+ * Conventions for every function below:
+ *   - Return 0 (FIB_OK) on success or a negative fib_status.  After an error,
+ *     fib_last_error() returns a message for the calling thread.  No C++
+ *     exception crosses this boundary.
+ *   - "host" pointers are ordinary CPU memory; "device" pointers are HIP
+ *     device memory on the context's device.  Host arrays are copied; the
+ *     library never keeps a caller pointer beyond the call.
+ *   - All device work is enqueued on the stream given to fib_create (NULL =
+ *     the null stream) and is asynchronous unless stated otherwise.
+ *   - The state is structure of arrays: value k of global node i is at
+ *     index k * n_total + i, nodes of fiber f at offsets
+ *     sum(n_nodes[0..f-1]) .. + n_nodes[f] - 1 (the order given to
+ *     fib_create).  State 0 is V_m (mV) in every host array.  On the device
+ *     the state is FP32 and row 0 holds V_m - v_ref, v_ref being the
+ *     model's resting potential rounded to FP32 (see fib_state_device).
+ *   - A context is not thread safe; calls on one context from several
+ *     threads must be serialized by the caller.
+ */
+#ifndef FIB_H
+#define FIB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FIB_OK = 0,
+  FIB_EINVAL = -1,       /* invalid argument (nothing was changed) */
+  FIB_ENOMEM = -2,       /* device or host allocation failed */
+  FIB_EHIP = -3,         /* a HIP runtime call failed */
+  FIB_ENONFINITE = -4,   /* a non-finite state value was detected */
+  FIB_ESTATE = -5,       /* call not valid in the context's current state */
+  FIB_EUNSUPPORTED = -6  /* valid request that this build cannot serve */
+} fib_status;
+
+enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1 };
+
+/* Execution schedule of fib_run.
+ *   FUSED: one persistent kernel keeps every node's states in registers and
+ *          every fiber's V_m exchange in LDS for all split steps of the call.
+ *   SPLIT: one reaction kernel and one diffusion kernel per split step with
+ *          states in device memory.
+ *   AUTO:  FUSED where the model fits it (Hodgkin-Huxley), else SPLIT. */
+enum { FIB_SCHED_AUTO = 0, FIB_SCHED_FUSED = 1, FIB_SCHED_SPLIT = 2 };
+
+typedef struct {
+  int32_t model;      /* FIB_MODEL_* */
+  int32_t schedule;   /* FIB_SCHED_* */
+  double Cm;          /* membrane capacitance, uF/cm^2 (> 0) */
+  double Am;          /* surface-to-volume ratio, 1/cm (> 0) */
+  double sigma;       /* effective conductivity, mS/cm (>= 0) */
+  double h;           /* node spacing, cm (> 0) */
+  double dt_0D;       /* largest reaction substep, ms (> 0) */
+  double dt_1D;       /* largest diffusion substep, ms (> 0) */
+  double dt_split;    /* split step, ms (> 0) */
+  double v_th;        /* activation threshold of the activation-time observable, mV */
+  int32_t pcr_full;   /* 0: stop the reduced-system PCR once every remaining coupling is
+                         below 2^-40 of the diagonal; 1: run all log2(threads) levels */
+  int32_t threads_per_group; /* 0: automatic; else 64..1024, a power of two */
+  int32_t nodes_per_thread;  /* 0: automatic; else 2..8 */
+  int32_t groups;            /* 0: automatic (one per compute unit); else the number of
+                                fiber bins, i.e. workgroups of the fused kernel */
+} fib_params;
+
+/* One stimulus entry: current density `amp` on nodes node-half_width ..
+ * node+half_width of fiber `fiber` (clipped to the fiber), during split
+ * steps n with n >= step_on and (n - step_on) mod period < n_steps
+ * (period = 0: only step_on <= n < step_on + n_steps).  A node may be
+ * covered by at most one entry.  Step indices must be below 2^31. */
+typedef struct {
+  int32_t fiber;
+  int32_t node;
+  int32_t half_width;
+  int32_t pad_;
+  int64_t step_on;
+  int64_t n_steps;
+  int64_t period;
+  double amp;
+} fib_stim;
+
+typedef struct fib_ctx fib_t;
+
+/* Number of states per node of a model (4 for Hodgkin-Huxley), or
+ * FIB_EINVAL. */
+int fib_n_states(int32_t model);
+
+/* Resting state of the model: the voltage at which the ionic current with
+ * all gates at equilibrium vanishes, and the gates' equilibria there
+ * (thesis section "Subcellular Model").  Host computation in FP64;
+ * y_out (host) receives fib_n_states(p->model) values. */
+int fib_rest_state(const fib_params* p, double* y_out);
+
+/* Checks a parameter set without touching the GPU: FIB_OK or FIB_EINVAL. */
+int fib_check_params(const fib_params* p);
+
+/* Creates a context for n_fibers fibers with n_nodes[f] >= 1 nodes each
+ * (host array).  Allocates the FP32 state, the activation-time array and
+ * the schedule tables on the current HIP device and plans how fibers are
+ * grouped into workgroups.  `stream` is a hipStream_t (may be NULL); it is
+ * borrowed and must outlive the context.  The state starts uninitialized:
+ * call fib_init_state or fib_set_state before stepping. */
+int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, void* stream,
+               fib_t** out);
+
+/* Releases every resource of the context (waits for its stream first).
+ * NULL is a no-op. */
+void fib_destroy(fib_t* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* fib_last_error(void);
+
+/* Total number of nodes of the context. */
+int64_t fib_n_total(const fib_t* ctx);
+
+/* Initial state (on the device): every node starts at the model's resting
+ * state y*, each state multiplied by (1 + rel_noise[k * n_total + i]) and
+ * V_m then shifted by vm_noise[i] (mV).  Both arrays are FP32 device
+ * pointers and may be NULL (no noise).  Also resets the observables. */
+int fib_init_state(fib_t* ctx, const float* vm_noise, const float* rel_noise);
+
+/* Copies a full FP64 host state (n_values = n_states * n_total, layout as
+ * above) to the device, rounding to FP32.  Blocking. */
+int fib_set_state(fib_t* ctx, const double* y, int64_t n_values);
+
+/* Copies the device state to FP64 host memory (n_values as above).
+ * Blocking; returns FIB_ENONFINITE if any value is NaN or infinite. */
+int fib_get_state(fib_t* ctx, double* y, int64_t n_values);
+
+/* Device pointer to the FP32 state (n_states * n_total floats) that the
+ * context owns, valid until fib_destroy, for zero-copy access.  Row 0 of
+ * the device state holds V_m - v_ref; *v_ref (nullable) receives v_ref. */
+int fib_state_device(fib_t* ctx, float** state, double* v_ref);
+
+/* Replaces the stimulus table (host array of n entries, copied). */
+int fib_set_stimulus(fib_t* ctx, const fib_stim* stim, int32_t n);
+
+/* Reaction part only: ceil(span/dt_0D) equal Heun substeps on every node,
+ * with the stimulus current of split step `step`.  One kernel launch. */
+int fib_step_reaction(fib_t* ctx, int64_t step, double span);
+
+/* Diffusion part only: ceil(span/dt_1D) equal Crank-Nicolson substeps on
+ * every fiber.  One kernel launch. */
+int fib_step_diffusion(fib_t* ctx, double span);
+
+/* Split steps step0 .. step0 + n_steps - 1 (step n covers the time
+ * [n dt_split, (n+1) dt_split]).  Observables:
+ *   - activation time per node (kept by the context, see fib_get_tact):
+ *     the first upward crossing of v_th between the ends of two
+ *     consecutive split steps, interpolated linearly;
+ *   - if samples != NULL and sample_every > 0: after every step n with
+ *     (n + 1) % sample_every == 0, V_m of all nodes is written to the FP32
+ *     device array samples at row (n + 1) / sample_every - 1 -
+ *     step0 / sample_every (row length n_total); sample_rows is the number
+ *     of rows the array holds (FIB_EINVAL if too small).
+ * Asynchronous. */
+int fib_run(fib_t* ctx, int64_t step0, int64_t n_steps, int64_t sample_every, float* samples,
+            int64_t sample_rows);
+
+/* Activation times (ms, +inf where V_m has not crossed v_th) into a host
+ * FP32 array of n_total values.  Blocking. */
+int fib_get_tact(fib_t* ctx, float* t_act, int64_t n);
+
+/* Sets every activation time back to +inf. */
+int fib_reset_observables(fib_t* ctx);
+
+/* Waits for the context's stream; returns FIB_EHIP on a deferred device
+ * error and FIB_ENONFINITE if a kernel flagged a non-finite V_m. */
+int fib_sync(fib_t* ctx);
+
+/* Describes the plan chosen by fib_create: workgroups (fiber bins),
+ * threads per workgroup, nodes per thread, and PCR levels of the fused
+ * diffusion solve.  Any pointer may be NULL. */
+int fib_plan_info(const fib_t* ctx, int32_t* groups, int32_t* threads, int32_t* nodes_per_thread,
+                  int32_t* pcr_levels);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIB_H */

@@ -1,0 +1,682 @@
+// Host runtime of libfib.so: the C ABI declared in include/fib.h.
+//
+// Responsibilities: argument checking, device buffers, the fiber-to-bin
+// plan of the fused / diffusion kernels, the stimulus tables, kernel
+// launches on the caller's stream, and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <queue>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/fib.h"
+#include "fib_internal.h"
+
+using fib::KArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (expr);                                                            \
+    if (e_ != hipSuccess) return fail(FIB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int n_states_of(int model) { return model == FIB_MODEL_HH ? 4 : -1; }
+
+// ---------------------------------------------------------------------------
+// Hodgkin-Huxley resting state on the host (FP64)
+// ---------------------------------------------------------------------------
+
+// Equilibrium gate values at voltage V and the ionic current they carry.
+double hh_steady_current(double V, double gates[3]) {
+  const double v = V + 75.0;
+  auto lin = [](double x) { return std::fabs(x) < 1e-6 ? 1.0 - 0.5 * x : x / std::expm1(x); };
+  const double am = lin((25.0 - v) / 10.0);
+  const double bm = 4.0 * std::exp(-v / 18.0);
+  const double ah = 0.07 * std::exp(-v / 20.0);
+  const double bh = 1.0 / (std::exp((30.0 - v) / 10.0) + 1.0);
+  const double an = 0.1 * lin((10.0 - v) / 10.0);
+  const double bn = 0.125 * std::exp(-v / 80.0);
+  const double m = am / (am + bm), h = ah / (ah + bh), n = an / (an + bn);
+  gates[0] = m;
+  gates[1] = h;
+  gates[2] = n;
+  return 120.0 * m * m * m * h * (V - 40.0) + 36.0 * n * n * n * n * (V + 87.0) +
+         0.3 * (V + 64.387);
+}
+
+// Newton's method on the steady-state current with a central-difference
+// derivative, started at the nominal resting potential of -75 mV.
+int hh_rest(double* y) {
+  double g[3];
+  double V = -75.0;
+  for (int it = 0; it < 50; ++it) {
+    const double f = hh_steady_current(V, g);
+    const double e = 1e-6;
+    const double df = (hh_steady_current(V + e, g) - hh_steady_current(V - e, g)) / (2 * e);
+    if (!(df > 0.0)) return fail(FIB_EINVAL, "resting-state search: non-positive slope");
+    const double dV = f / df;
+    V -= dV;
+    if (std::fabs(dV) < 1e-13) break;
+  }
+  hh_steady_current(V, g);
+  y[0] = V;
+  y[1] = g[0];
+  y[2] = g[1];
+  y[3] = g[2];
+  return FIB_OK;
+}
+
+int64_t ceil_steps(double span, double dt) {
+  const double n = std::ceil(span / dt - 1e-9);
+  return n < 1.0 ? 1 : (int64_t)n;
+}
+
+bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Context
+// ---------------------------------------------------------------------------
+
+struct fib_ctx {
+  fib_params p{};
+  int S = 0;
+  int32_t n_fibers = 0;
+  std::vector<int32_t> n_nodes;
+  std::vector<int64_t> offsets;
+  int64_t n_total = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cu_count = 0;
+  size_t max_lds = 0;
+  double rest[fib::MAX_STATES] = {};
+
+  // plan
+  int groups = 0, threads = 0, K = 0, cap = 0, levels = 0;
+  std::vector<int32_t> slot_gidx;      // groups * cap
+  std::vector<uint32_t> slot_base;     // coupling and real-node bits
+  std::vector<std::vector<int32_t>> bin_fibers;
+
+  // device buffers
+  float* d_state = nullptr;
+  float* d_tact = nullptr;
+  float* d_vprev = nullptr;
+  int* d_flag = nullptr;
+  int32_t* d_slot_gidx = nullptr;
+  uint32_t* d_slot_info = nullptr;
+  int32_t* d_node_stim = nullptr;
+  fib::StimDev* d_stim = nullptr;
+  int32_t n_stim = 0;
+  bool state_ready = false;
+};
+
+namespace {
+
+// Packs fibers into `groups` bins by longest-processing-time-first: fibers
+// in order of decreasing length, each into the currently lightest bin.
+void pack_bins(fib_ctx* c, int groups) {
+  std::vector<int32_t> order(c->n_fibers);
+  for (int32_t f = 0; f < c->n_fibers; ++f) order[f] = f;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int32_t a, int32_t b) { return c->n_nodes[a] > c->n_nodes[b]; });
+  using Item = std::pair<int64_t, int>;  // (load, bin)
+  std::priority_queue<Item, std::vector<Item>, std::greater<Item>> heap;
+  for (int b = 0; b < groups; ++b) heap.push({0, b});
+  c->bin_fibers.assign(groups, {});
+  for (int32_t f : order) {
+    Item it = heap.top();
+    heap.pop();
+    c->bin_fibers[it.second].push_back(f);
+    heap.push({it.first + c->n_nodes[f], it.second});
+  }
+}
+
+// Reduced-system coefficients (Ra, Rd, Rc) of every thread of one bin in
+// FP64, the same quantities the kernels derive in FP32; used to pick the
+// number of PCR levels after which every remaining coupling is below
+// 2^-40 of its diagonal.
+int pcr_levels_needed(const fib_ctx* c, int bin, double r, bool full) {
+  const int T = c->threads, K = c->K;
+  const int full_levels = (int)std::ceil(std::log2((double)T) - 1e-12);
+  if (full) return full_levels;
+  std::vector<double> Ra(T), Rd(T), Rc(T), v0(T), w0(T), vL(T), wL(T), ae(T), ce(T), de(T);
+  for (int t = 0; t < T; ++t) {
+    std::vector<double> a(K), cc(K), d(K);
+    for (int q = 0; q < K; ++q) {
+      const uint32_t info = c->slot_base[(size_t)bin * c->cap + (size_t)t * K + q];
+      const bool L = info & fib::SLOT_L, R = info & fib::SLOT_R;
+      const double wl = L ? (R ? 0.5 * r : r) : 0.0, wr = R ? (L ? 0.5 * r : r) : 0.0;
+      a[q] = -wl;
+      cc[q] = -wr;
+      d[q] = 1.0 + wl + wr;
+    }
+    // interior responses to z_{t-1} (v) and z_t (w) by dense elimination
+    const int m = K - 1;
+    std::vector<double> inv(m), cp(m), vp(m), v(m), w(m);
+    for (int q = 0; q < m; ++q) {
+      const double den = q == 0 ? d[0] : d[q] - a[q] * cp[q - 1];
+      inv[q] = 1.0 / den;
+      cp[q] = cc[q] * inv[q];
+      vp[q] = q == 0 ? -a[0] * inv[0] : -a[q] * vp[q - 1] * inv[q];
+    }
+    v[m - 1] = vp[m - 1];
+    w[m - 1] = -cp[m - 1];
+    for (int q = m - 2; q >= 0; --q) {
+      v[q] = vp[q] - cp[q] * v[q + 1];
+      w[q] = -cp[q] * w[q + 1];
+    }
+    v0[t] = v[0];
+    w0[t] = w[0];
+    vL[t] = v[m - 1];
+    wL[t] = w[m - 1];
+    ae[t] = a[K - 1];
+    ce[t] = cc[K - 1];
+    de[t] = d[K - 1];
+  }
+  for (int t = 0; t < T; ++t) {
+    const double vn = t + 1 < T ? v0[t + 1] : 0.0, wn = t + 1 < T ? w0[t + 1] : 0.0;
+    Ra[t] = ae[t] * vL[t];
+    Rd[t] = de[t] + ae[t] * wL[t] + ce[t] * vn;
+    Rc[t] = ce[t] * wn;
+  }
+  const double tol = std::ldexp(1.0, -40);
+  auto coupling = [&]() {
+    double mu = 0.0;
+    for (int t = 0; t < T; ++t) mu = std::max(mu, (std::fabs(Ra[t]) + std::fabs(Rc[t])) / std::fabs(Rd[t]));
+    return mu;
+  };
+  int l = 0;
+  while (l < full_levels && coupling() > tol) {
+    const int s = 1 << l;
+    std::vector<double> na(T), nd(T), nc(T);
+    for (int t = 0; t < T; ++t) {
+      const bool hl = t - s >= 0, hr = t + s < T;
+      const double ra_l = hl ? Ra[t - s] : 0.0, rd_l = hl ? Rd[t - s] : 1.0, rc_l = hl ? Rc[t - s] : 0.0;
+      const double ra_r = hr ? Ra[t + s] : 0.0, rd_r = hr ? Rd[t + s] : 1.0, rc_r = hr ? Rc[t + s] : 0.0;
+      const double al = -Ra[t] / rd_l, ga = -Rc[t] / rd_r;
+      nd[t] = Rd[t] + al * rc_l + ga * ra_r;
+      na[t] = al * ra_l;
+      nc[t] = ga * rc_r;
+    }
+    Ra.swap(na);
+    Rd.swap(nd);
+    Rc.swap(nc);
+    ++l;
+  }
+  return l;
+}
+
+double cn_r(const fib_ctx* c, double dt_cn) {
+  return c->p.sigma / (c->p.Am * c->p.Cm) * dt_cn / (c->p.h * c->p.h);
+}
+
+// Chooses bins, threads per bin and nodes per thread, and fills the slot
+// tables.
+int make_plan(fib_ctx* c) {
+  const int64_t max_len =
+      c->n_fibers ? *std::max_element(c->n_nodes.begin(), c->n_nodes.end()) : 0;
+  if (max_len > 8 * 1024)
+    return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the 8192 nodes one workgroup holds",
+                (long long)max_len);
+  int groups = c->p.groups > 0 ? c->p.groups : c->cu_count;
+  groups = (int)std::min<int64_t>(groups, std::max<int32_t>(c->n_fibers, 1));
+  for (;;) {
+    pack_bins(c, groups);
+    int64_t load = 0;
+    for (auto& b : c->bin_fibers) {
+      int64_t s = 0;
+      for (int32_t f : b) s += c->n_nodes[f];
+      load = std::max(load, s);
+    }
+    load = std::max<int64_t>(load, 1);
+    int K = c->p.nodes_per_thread;
+    int T = c->p.threads_per_group;
+    if (K == 0 && T == 0) {
+      K = (int)std::min<int64_t>(8, std::max<int64_t>(2, (load + 1023) / 1024));
+      T = 64;
+      while ((int64_t)T * K < load) T *= 2;
+    } else if (K == 0) {
+      K = (int)std::max<int64_t>(2, (load + T - 1) / T);
+    } else if (T == 0) {
+      T = 64;
+      while ((int64_t)T * K < load && T < 1024) T *= 2;
+    }
+    if (K <= 8 && T <= 1024 && (int64_t)T * K >= load) {
+      c->K = K;
+      c->threads = T;
+      c->groups = groups;
+      break;
+    }
+    if (c->p.groups > 0 || groups >= c->n_fibers)
+      return fail(FIB_EUNSUPPORTED, "cannot fit %lld nodes into %d bins with the requested shape",
+                  (long long)load, groups);
+    groups = std::min(groups * 2, c->n_fibers);
+  }
+  c->cap = c->threads * c->K;
+  const size_t nslots = (size_t)c->groups * c->cap;
+  c->slot_gidx.assign(nslots, -1);
+  c->slot_base.assign(nslots, 0u);
+  for (int b = 0; b < c->groups; ++b) {
+    size_t pos = (size_t)b * c->cap;
+    for (int32_t f : c->bin_fibers[b]) {
+      const int32_t n = c->n_nodes[f];
+      for (int32_t j = 0; j < n; ++j) {
+        uint32_t info = fib::SLOT_REAL;
+        if (j > 0) info |= fib::SLOT_L;
+        if (j + 1 < n) info |= fib::SLOT_R;
+        c->slot_gidx[pos] = (int32_t)(c->offsets[f] + j);
+        c->slot_base[pos] = info;
+        ++pos;
+      }
+    }
+  }
+  // PCR levels for the split step's diffusion substep
+  const int64_t n_cn = ceil_steps(c->p.dt_split, c->p.dt_1D);
+  const double r = cn_r(c, c->p.dt_split / (double)n_cn);
+  int lv = 0;
+  for (int b = 0; b < c->groups; ++b)
+    lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
+  c->levels = lv;
+  return FIB_OK;
+}
+
+KArgs base_args(const fib_ctx* c) {
+  KArgs a{};
+  a.state = c->d_state;
+  a.n_total = c->n_total;
+  a.slot_gidx = c->d_slot_gidx;
+  a.slot_info = c->d_slot_info;
+  a.node_stim = c->d_node_stim;
+  a.stim = c->d_stim;
+  a.t_act = c->d_tact;
+  a.v_prev = c->d_vprev;
+  a.flag = c->d_flag;
+  a.cap = c->cap;
+  a.inv_cm = (float)(1.0 / c->p.Cm);
+  a.v_th = (float)c->p.v_th;
+  a.dt = (float)c->p.dt_split;
+  for (int k = 0; k < c->S; ++k) a.rest[k] = (float)c->rest[k];
+  a.vref = (float)c->rest[0];
+  return a;
+}
+
+int check_ctx(const fib_ctx* c) {
+  if (!c) return fail(FIB_EINVAL, "null context");
+  return FIB_OK;
+}
+
+int check_levels_fit(const fib_ctx* c, int levels) {
+  const size_t need = fib::lds_bytes_for(c->threads, levels);
+  if (need > c->max_lds)
+    return fail(FIB_EUNSUPPORTED, "the diffusion solve needs %zu bytes of LDS, the device offers %zu",
+                need, c->max_lds);
+  return FIB_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+
+extern "C" {
+
+const char* fib_last_error(void) { return g_err.c_str(); }
+
+int fib_n_states(int32_t model) {
+  const int s = n_states_of(model);
+  return s > 0 ? s : fail(FIB_EINVAL, "unknown model %d", model);
+}
+
+int fib_check_params(const fib_params* p) {
+  if (!p) return fail(FIB_EINVAL, "null parameters");
+  if (n_states_of(p->model) <= 0) return fail(FIB_EINVAL, "unknown model %d", p->model);
+  if (p->schedule < FIB_SCHED_AUTO || p->schedule > FIB_SCHED_SPLIT)
+    return fail(FIB_EINVAL, "unknown schedule %d", p->schedule);
+  auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+  if (!pos(p->Cm) || !pos(p->Am) || !pos(p->h)) return fail(FIB_EINVAL, "Cm, Am and h must be > 0");
+  if (!(std::isfinite(p->sigma) && p->sigma >= 0.0)) return fail(FIB_EINVAL, "sigma must be >= 0");
+  if (!pos(p->dt_0D) || !pos(p->dt_1D) || !pos(p->dt_split))
+    return fail(FIB_EINVAL, "time steps must be > 0");
+  if (!std::isfinite(p->v_th)) return fail(FIB_EINVAL, "v_th must be finite");
+  if (p->threads_per_group != 0 &&
+      (!is_pow2(p->threads_per_group) || p->threads_per_group < 64 || p->threads_per_group > 1024))
+    return fail(FIB_EINVAL, "threads_per_group must be 0 or a power of two in [64, 1024]");
+  if (p->nodes_per_thread != 0 && (p->nodes_per_thread < 2 || p->nodes_per_thread > 8))
+    return fail(FIB_EINVAL, "nodes_per_thread must be 0 or in [2, 8]");
+  if (p->groups < 0) return fail(FIB_EINVAL, "groups must be >= 0");
+  if (ceil_steps(p->dt_split * 0.5, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
+    return fail(FIB_EINVAL, "more than 2^20 substeps per split step");
+  return FIB_OK;
+}
+
+int fib_rest_state(const fib_params* p, double* y_out) {
+  if (!p || !y_out) return fail(FIB_EINVAL, "null argument");
+  if (p->model == FIB_MODEL_HH) return hh_rest(y_out);
+  return fail(FIB_EINVAL, "unknown model %d", p->model);
+}
+
+int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, void* stream,
+               fib_t** out) {
+  if (!out) return fail(FIB_EINVAL, "null output pointer");
+  *out = nullptr;
+  int rc = fib_check_params(p);
+  if (rc) return rc;
+  if (n_fibers < 0 || (n_fibers > 0 && !n_nodes)) return fail(FIB_EINVAL, "bad fiber list");
+  int64_t total = 0;
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    if (n_nodes[f] < 1) return fail(FIB_EINVAL, "fiber %d has %d nodes", f, n_nodes[f]);
+    total += n_nodes[f];
+  }
+  if (total >= (int64_t)1 << 31) return fail(FIB_EUNSUPPORTED, "more than 2^31 - 1 nodes");
+
+  fib_ctx* c = new (std::nothrow) fib_ctx();
+  if (!c) return fail(FIB_ENOMEM, "host allocation failed");
+  c->p = *p;
+  c->S = n_states_of(p->model);
+  c->n_fibers = n_fibers;
+  c->n_nodes.assign(n_nodes, n_nodes + n_fibers);
+  c->offsets.assign(n_fibers + 1, 0);
+  for (int32_t f = 0; f < n_fibers; ++f) c->offsets[f + 1] = c->offsets[f] + n_nodes[f];
+  c->n_total = total;
+  c->stream = (hipStream_t)stream;
+
+  auto bail = [&](int code) {
+    fib_destroy(c);
+    return code;
+  };
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&c->device) != hipSuccess || hipGetDeviceProperties(&prop, c->device) != hipSuccess)
+    return bail(fail(FIB_EHIP, "no HIP device"));
+  c->cu_count = prop.multiProcessorCount;
+  c->max_lds = prop.sharedMemPerBlock;
+  if ((rc = fib_rest_state(p, c->rest))) return bail(rc);
+  if ((rc = make_plan(c))) return bail(rc);
+  if ((rc = check_levels_fit(c, c->levels))) return bail(rc);
+
+  const size_t nt = (size_t)std::max<int64_t>(total, 1);
+  const size_t nslots = std::max<size_t>(c->slot_gidx.size(), 1);
+  if (hipMalloc(&c->d_state, sizeof(float) * nt * c->S) != hipSuccess ||
+      hipMalloc(&c->d_tact, sizeof(float) * nt) != hipSuccess ||
+      hipMalloc(&c->d_vprev, sizeof(float) * nt) != hipSuccess ||
+      hipMalloc(&c->d_node_stim, sizeof(int32_t) * nt) != hipSuccess ||
+      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
+      hipMalloc(&c->d_slot_gidx, sizeof(int32_t) * nslots) != hipSuccess ||
+      hipMalloc(&c->d_slot_info, sizeof(uint32_t) * nslots) != hipSuccess)
+    return bail(fail(FIB_ENOMEM, "device allocation failed"));
+  if (hipMemcpy(c->d_slot_gidx, c->slot_gidx.data(), sizeof(int32_t) * c->slot_gidx.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->d_slot_info, c->slot_base.data(), sizeof(uint32_t) * c->slot_base.size(),
+                hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(c->d_node_stim, 0, sizeof(int32_t) * nt) != hipSuccess ||
+      hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess)
+    return bail(fail(FIB_EHIP, "device upload failed"));
+  if (fib::launch_fill(c->d_tact, total, INFINITY, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess)
+    return bail(fail(FIB_EHIP, "device initialization failed"));
+  *out = c;
+  return FIB_OK;
+}
+
+void fib_destroy(fib_t* c) {
+  if (!c) return;
+  if (c->d_state) (void)hipStreamSynchronize(c->stream);
+  (void)hipFree(c->d_state);
+  (void)hipFree(c->d_tact);
+  (void)hipFree(c->d_vprev);
+  (void)hipFree(c->d_flag);
+  (void)hipFree(c->d_slot_gidx);
+  (void)hipFree(c->d_slot_info);
+  (void)hipFree(c->d_node_stim);
+  (void)hipFree(c->d_stim);
+  delete c;
+}
+
+int64_t fib_n_total(const fib_t* c) { return c ? c->n_total : 0; }
+
+int fib_plan_info(const fib_t* c, int32_t* groups, int32_t* threads, int32_t* nodes_per_thread,
+                  int32_t* pcr_levels) {
+  if (int rc = check_ctx(c)) return rc;
+  if (groups) *groups = c->groups;
+  if (threads) *threads = c->threads;
+  if (nodes_per_thread) *nodes_per_thread = c->K;
+  if (pcr_levels) *pcr_levels = c->levels;
+  return FIB_OK;
+}
+
+int fib_state_device(fib_t* c, float** state, double* v_ref) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!state) return fail(FIB_EINVAL, "null output pointer");
+  *state = c->d_state;
+  if (v_ref) *v_ref = (double)(float)c->rest[0];
+  return FIB_OK;
+}
+
+int fib_init_state(fib_t* c, const float* vm_noise, const float* rel_noise) {
+  if (int rc = check_ctx(c)) return rc;
+  KArgs a = base_args(c);
+  HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  HIP_TRY(fib::launch_init(c->p.model, vm_noise, rel_noise, a, c->stream));
+  c->state_ready = true;
+  return FIB_OK;
+}
+
+int fib_set_state(fib_t* c, const double* y, int64_t n_values) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n_values != (int64_t)c->S * c->n_total) return fail(FIB_EINVAL, "expected %lld values",
+                                                          (long long)c->S * c->n_total);
+  if (n_values == 0) { c->state_ready = true; return FIB_OK; }
+  if (!y) return fail(FIB_EINVAL, "null state");
+  std::vector<float> f(n_values);
+  const double vref = (double)(float)c->rest[0];
+  for (int64_t i = 0; i < n_values; ++i) f[i] = (float)(i < c->n_total ? y[i] - vref : y[i]);
+  HIP_TRY(hipMemcpyAsync(c->d_state, f.data(), sizeof(float) * n_values, hipMemcpyHostToDevice,
+                         c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
+                         hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->state_ready = true;
+  return FIB_OK;
+}
+
+int fib_get_state(fib_t* c, double* y, int64_t n_values) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n_values != (int64_t)c->S * c->n_total) return fail(FIB_EINVAL, "expected %lld values",
+                                                          (long long)c->S * c->n_total);
+  if (n_values == 0) return FIB_OK;
+  if (!y) return fail(FIB_EINVAL, "null output");
+  std::vector<float> f(n_values);
+  HIP_TRY(hipMemcpyAsync(f.data(), c->d_state, sizeof(float) * n_values, hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  bool bad = false;
+  const double vref = (double)(float)c->rest[0];
+  for (int64_t i = 0; i < n_values; ++i) {
+    y[i] = i < c->n_total ? (double)f[i] + vref : (double)f[i];
+    bad |= !std::isfinite(f[i]);
+  }
+  if (bad) return fail(FIB_ENONFINITE, "the state holds non-finite values");
+  return FIB_OK;
+}
+
+int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n < 0 || (n > 0 && !s)) return fail(FIB_EINVAL, "bad stimulus table");
+  std::vector<int32_t> node_stim(c->n_total, 0);
+  std::vector<fib::StimDev> tab(n);
+  const int64_t lim = ((int64_t)1 << 31) - 1;
+  for (int32_t e = 0; e < n; ++e) {
+    const fib_stim& x = s[e];
+    if (x.fiber < 0 || x.fiber >= c->n_fibers) return fail(FIB_EINVAL, "entry %d: bad fiber", e);
+    if (x.half_width < 0) return fail(FIB_EINVAL, "entry %d: negative half width", e);
+    if (x.step_on < 0 || x.step_on > lim || x.n_steps < 0 || x.n_steps > lim || x.period < 0 ||
+        x.period > lim)
+      return fail(FIB_EINVAL, "entry %d: step indices must lie in [0, 2^31)", e);
+    if (!std::isfinite(x.amp)) return fail(FIB_EINVAL, "entry %d: non-finite amplitude", e);
+    tab[e] = fib::StimDev{(int32_t)x.step_on, (int32_t)x.n_steps, (int32_t)x.period, (float)x.amp};
+    const int64_t n_f = c->n_nodes[x.fiber];
+    for (int64_t j = (int64_t)x.node - x.half_width; j <= (int64_t)x.node + x.half_width; ++j) {
+      if (j < 0 || j >= n_f) continue;
+      int32_t& slot = node_stim[c->offsets[x.fiber] + j];
+      if (slot != 0) return fail(FIB_EINVAL, "entry %d: node %lld of fiber %d already stimulated",
+                                 e, (long long)j, x.fiber);
+      slot = e + 1;
+    }
+  }
+  if ((int64_t)n + 1 >= ((int64_t)1 << (32 - fib::SLOT_STIM_SHIFT)))
+    return fail(FIB_EINVAL, "too many stimulus entries");
+  std::vector<uint32_t> info(c->slot_base);
+  for (size_t k = 0; k < info.size(); ++k)
+    if (c->slot_gidx[k] >= 0) info[k] |= (uint32_t)node_stim[c->slot_gidx[k]] << fib::SLOT_STIM_SHIFT;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  (void)hipFree(c->d_stim);
+  c->d_stim = nullptr;
+  c->n_stim = 0;
+  if (n > 0) {
+    if (hipMalloc(&c->d_stim, sizeof(fib::StimDev) * n) != hipSuccess)
+      return fail(FIB_ENOMEM, "device allocation failed");
+    HIP_TRY(hipMemcpy(c->d_stim, tab.data(), sizeof(fib::StimDev) * n, hipMemcpyHostToDevice));
+  }
+  c->n_stim = n;
+  if (c->n_total > 0)
+    HIP_TRY(hipMemcpy(c->d_node_stim, node_stim.data(), sizeof(int32_t) * c->n_total,
+                      hipMemcpyHostToDevice));
+  if (!info.empty())
+    HIP_TRY(hipMemcpy(c->d_slot_info, info.data(), sizeof(uint32_t) * info.size(),
+                      hipMemcpyHostToDevice));
+  return FIB_OK;
+}
+
+int fib_step_reaction(fib_t* c, int64_t step, double span) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!(std::isfinite(span) && span > 0.0)) return fail(FIB_EINVAL, "span must be > 0");
+  if (step < 0 || step >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  KArgs a = base_args(c);
+  const int64_t ns = ceil_steps(span, c->p.dt_0D);
+  if (ns > (1 << 20)) return fail(FIB_EINVAL, "more than 2^20 substeps");
+  a.n_sub = (int32_t)ns;
+  a.tau = (float)(span / (double)ns);
+  HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)step, a, c->stream));
+  return FIB_OK;
+}
+
+int fib_step_diffusion(fib_t* c, double span) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!(std::isfinite(span) && span > 0.0)) return fail(FIB_EINVAL, "span must be > 0");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (c->n_total == 0) return FIB_OK;
+  KArgs a = base_args(c);
+  const int64_t m = ceil_steps(span, c->p.dt_1D);
+  if (m > (1 << 20)) return fail(FIB_EINVAL, "more than 2^20 substeps");
+  a.n_cn = (int32_t)m;
+  const double r = cn_r(c, span / (double)m);
+  a.r = (float)r;
+  int lv = 0;
+  for (int b = 0; b < c->groups; ++b)
+    lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
+  if (int rc = check_levels_fit(c, lv)) return rc;
+  a.pcr_levels = lv;
+  HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, fib::lds_bytes_for(c->threads, lv),
+                                a, c->stream));
+  return FIB_OK;
+}
+
+int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, float* samples,
+            int64_t sample_rows) {
+  if (int rc = check_ctx(c)) return rc;
+  const int64_t lim = ((int64_t)1 << 31) - 1;
+  if (step0 < 0 || n_steps < 0 || step0 + n_steps > lim)
+    return fail(FIB_EINVAL, "steps must lie in [0, 2^31)");
+  if (sample_every < 0) return fail(FIB_EINVAL, "sample_every must be >= 0");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (n_steps == 0 || c->n_total == 0) return FIB_OK;
+  KArgs a = base_args(c);
+  if (samples && sample_every > 0) {
+    const int64_t rows = (step0 + n_steps) / sample_every - step0 / sample_every;
+    if (sample_rows < rows) return fail(FIB_EINVAL, "samples holds %lld rows, %lld needed",
+                                        (long long)sample_rows, (long long)rows);
+    a.samples = samples;
+    a.sample_every = sample_every;
+    a.sample_row0 = step0 / sample_every;
+    a.sample_rows = sample_rows;
+  }
+  const int64_t ns = ceil_steps(0.5 * c->p.dt_split, c->p.dt_0D);
+  const int64_t nc = ceil_steps(c->p.dt_split, c->p.dt_1D);
+  a.n_sub = (int32_t)ns;
+  a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
+  a.n_cn = (int32_t)nc;
+  a.r = (float)cn_r(c, c->p.dt_split / (double)nc);
+  a.pcr_levels = c->levels;
+  a.step0 = (int32_t)step0;
+  a.n_steps = (int32_t)n_steps;
+  const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
+                     (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH);
+  if (fused) {
+    HIP_TRY(fib::launch_run_fused(c->p.model, c->K, c->groups, c->threads,
+                                  fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
+    return FIB_OK;
+  }
+  // SPLIT: one launch per phase
+  HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
+                         hipMemcpyDeviceToDevice, c->stream));
+  KArgs half = a;
+  for (int64_t n = step0; n < step0 + n_steps; ++n) {
+    HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)n, half, c->stream));
+    HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads,
+                                  fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
+    HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)n, half, c->stream));
+    HIP_TRY(fib::launch_observe((int32_t)n, a, c->stream));
+  }
+  return FIB_OK;
+}
+
+int fib_get_tact(fib_t* c, float* t_act, int64_t n) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n != c->n_total) return fail(FIB_EINVAL, "expected %lld values", (long long)c->n_total);
+  if (n == 0) return FIB_OK;
+  if (!t_act) return fail(FIB_EINVAL, "null output");
+  HIP_TRY(hipMemcpyAsync(t_act, c->d_tact, sizeof(float) * n, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return FIB_OK;
+}
+
+int fib_reset_observables(fib_t* c) {
+  if (int rc = check_ctx(c)) return rc;
+  HIP_TRY(fib::launch_fill(c->d_tact, c->n_total, INFINITY, c->stream));
+  return FIB_OK;
+}
+
+int fib_sync(fib_t* c) {
+  if (int rc = check_ctx(c)) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  int flag = 0;
+  HIP_TRY(hipMemcpy(&flag, c->d_flag, sizeof(int), hipMemcpyDeviceToHost));
+  if (flag) return fail(FIB_ENONFINITE, "a kernel saw a non-finite membrane voltage");
+  return FIB_OK;
+}
+
+}  // extern "C"

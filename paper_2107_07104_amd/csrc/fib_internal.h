@@ -1,0 +1,79 @@
+// Internal declarations shared by the host runtime (fib_api.hip) and the
+// kernels (fib_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fib {
+
+// Stimulus entry as the kernels see it: step indices as int32.
+struct StimDev {
+  int32_t on;      // first split step with current
+  int32_t dur;     // consecutive split steps with current
+  int32_t period;  // 0: single pulse
+  float amp;       // uA/cm^2
+};
+
+// Per-slot descriptor of the fused / diffusion kernels.
+//   bit 0: the node has a left neighbour in the same fiber
+//   bit 1: the node has a right neighbour in the same fiber
+//   bit 2: the slot holds a real node (not padding)
+//   bits 3..31: stimulus entry + 1 (0: none)
+constexpr uint32_t SLOT_L = 1u;
+constexpr uint32_t SLOT_R = 2u;
+constexpr uint32_t SLOT_REAL = 4u;
+constexpr int SLOT_STIM_SHIFT = 3;
+
+constexpr int MAX_STATES = 64;
+
+// Everything a kernel launch needs, passed by value.
+struct KArgs {
+  float* state;             // SoA [S][n_total]
+  int64_t n_total;
+  const int32_t* slot_gidx; // [groups * cap], -1 for padding
+  const uint32_t* slot_info;// [groups * cap]
+  const int32_t* node_stim; // [n_total], stimulus entry + 1 (0: none)
+  const StimDev* stim;      // stimulus table
+  float* t_act;             // [n_total]
+  float* v_prev;            // [n_total], V_m at the end of the previous split step (SPLIT)
+  float* samples;           // [rows][n_total] or null
+  int64_t sample_every;     // 0: no samples
+  int64_t sample_row0;      // rows written by earlier calls: step0 / sample_every
+  int64_t sample_rows;      // capacity of `samples`
+  int* flag;                // bit 0: non-finite V_m seen
+  int32_t cap;              // slots per group = threads * nodes_per_thread
+  int32_t step0;
+  int32_t n_steps;
+  int32_t n_sub;            // reaction substeps per half split step
+  int32_t n_cn;             // Crank-Nicolson substeps per split step
+  int32_t pcr_levels;       // reduced-system PCR levels
+  float dt;                 // split step (ms)
+  float tau;                // reaction substep (ms)
+  float r;                  // c * dt_cn / h^2 with c = sigma / (Am Cm)
+  float inv_cm;             // 1 / Cm
+  float v_th;               // activation threshold (mV)
+  float vref;               // offset of the in-register voltage (mV), the resting potential
+  float rest[MAX_STATES];   // resting state, used for padding slots
+};
+
+// Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds_bytes,
+                            const KArgs& a, hipStream_t s);
+hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, const KArgs& a,
+                            hipStream_t s);
+hipError_t launch_reaction(int model, int32_t step, const KArgs& a, hipStream_t s);
+hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s);
+hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
+                       hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
+
+// LDS bytes the fused / diffusion kernels need for `threads` threads and
+// `levels` PCR levels.
+inline size_t lds_bytes_for(int threads, int levels) {
+  return sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
+}
+
+}  // namespace fib

@@ -1,0 +1,506 @@
+// HIP kernels of the fiber monodomain solver (gfx950).
+//
+// Data layout in HBM: structure of arrays, state k of global node i at
+// state[k * n_total + i], fibers concatenated in the caller's order.  Row 0
+// holds the membrane voltage as its offset u = V_m - vref from the resting
+// potential vref: increments that are small next to 75 mV but not next to
+// |u| keep their bits while the membrane is near rest, where a propagating
+// front's foot lives, and the state round-trips through checkpoints exactly.
+//
+// Work decomposition of the fused and diffusion kernels: fibers are packed
+// into "bins" (one workgroup each) of at most threads * K nodes; thread t of
+// a bin owns the K consecutive slots t*K .. t*K+K-1 of the bin's
+// concatenated fibers.  Fiber boundaries inside a bin are rows without
+// coupling, so a bin's Crank-Nicolson matrix is one block-diagonal
+// tridiagonal system (eq. discretized_fibers_1) that the partitioned solve
+// below handles as a whole.
+//
+// Partitioned tridiagonal solve (exact up to rounding, see cn_setup /
+// cn_solve): in each thread's segment the last slot is an interface unknown
+// z_t and the K-1 interior unknowns are eliminated locally, leaving one
+// tridiagonal equation per thread in (z_{t-1}, z_t, z_{t+1}); that reduced
+// system is solved by parallel cyclic reduction (PCR) through LDS, and the
+// interior values follow by back substitution.  The matrix does not change
+// between steps, so all elimination factors and PCR multipliers are
+// computed once per launch; a step only moves right-hand sides.
+#include "fib_internal.h"
+#include "hh_model.h"
+
+namespace fib {
+
+// ---------------------------------------------------------------------------
+// Stimulus
+// ---------------------------------------------------------------------------
+
+// Current of stimulus entry `sid1 - 1` (0: none) during split step n.
+__device__ __forceinline__ float stim_current(uint32_t sid1, const StimDev* __restrict__ tab,
+                                              int32_t n) {
+  if (sid1 == 0) return 0.0f;
+  const StimDev e = tab[sid1 - 1];
+  int32_t k = n - e.on;
+  if (k < 0) return 0.0f;
+  if (e.period > 0) k = k % e.period;
+  return k < e.dur ? e.amp : 0.0f;
+}
+
+// ---------------------------------------------------------------------------
+// Lumped Crank-Nicolson rows
+// ---------------------------------------------------------------------------
+
+// Row of (dt/2) c M_L^{-1} K for a slot: weights of the left and right
+// neighbours.  Linear elements with lumped mass h (1/2, 1, ..., 1, 1/2)
+// give (r/2, -r, r/2) inside a fiber and (0, -r, r) / (r, -r, 0) at its
+// no-flux ends, r = c dt / h^2.
+__device__ __forceinline__ void row_weights(uint32_t info, float r, float& wl, float& wr) {
+  const bool L = (info & SLOT_L) != 0u;
+  const bool R = (info & SLOT_R) != 0u;
+  wl = L ? (R ? 0.5f * r : r) : 0.0f;
+  wr = R ? (L ? 0.5f * r : r) : 0.0f;
+}
+
+// LDS layout (floats, T = threads):
+//   [0, T)        V of each thread's first slot
+//   [T, 2T)       V of each thread's last slot
+//   [2T, 3T)      first interior value of y (local solve)
+//   [3T, 5T)      PCR right-hand sides, ping-pong
+//   [5T, 6T)      interface values z
+//   [6T, 6T+2LT)  PCR multipliers alpha_l, gamma_l
+template <int K>
+struct CNConst {
+  float inv[K - 1];   // 1 / pivot of the interior elimination
+  float ainv[K - 1];  // a_q / pivot_q
+  float cp[K - 1];    // c_q / pivot_q
+  float v[K - 1];     // interior response to z_{t-1}
+  float w[K - 1];     // interior response to z_t
+  float ae, ce;       // couplings of the interface row
+  float inv_rd;       // 1 / diagonal of the reduced row after the PCR levels
+};
+
+// Elimination factors, interior responses and PCR multipliers for the
+// current bin.  Must be called by all threads of the workgroup.
+template <int K>
+__device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, float* lds, int T,
+                         int t, int levels) {
+  float a[K], c[K], d[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    float wl, wr;
+    row_weights(info[q], r, wl, wr);
+    a[q] = -wl;
+    c[q] = -wr;
+    d[q] = 1.0f + wl + wr;
+  }
+  // forward elimination over the interior slots 0..K-2 (no pivoting: the
+  // matrix is strictly diagonally dominant)
+  float vp[K - 1];
+#pragma unroll
+  for (int q = 0; q < K - 1; ++q) {
+    const float den = (q == 0) ? d[0] : fmaf(-a[q], cc.cp[q - 1 < 0 ? 0 : q - 1], d[q]);
+    cc.inv[q] = 1.0f / den;
+    cc.ainv[q] = a[q] * cc.inv[q];
+    cc.cp[q] = c[q] * cc.inv[q];
+    vp[q] = (q == 0) ? -a[0] * cc.inv[0] : -cc.ainv[q] * vp[q - 1 < 0 ? 0 : q - 1];
+  }
+  // back substitution for the responses to z_{t-1} (v) and z_t (w)
+  cc.v[K - 2] = vp[K - 2];
+  cc.w[K - 2] = cc.cp[K - 2] * -1.0f;
+#pragma unroll
+  for (int q = K - 3; q >= 0; --q) {
+    cc.v[q] = fmaf(-cc.cp[q], cc.v[q + 1], vp[q]);
+    cc.w[q] = -cc.cp[q] * cc.w[q + 1];
+  }
+  cc.ae = a[K - 1];
+  cc.ce = c[K - 1];
+
+  // reduced row of thread t: Ra z_{t-1} + Rd z_t + Rc z_{t+1} = Rb
+  float* s_v0 = lds;       // v[0] of each thread
+  float* s_w0 = lds + T;   // w[0] of each thread
+  s_v0[t] = cc.v[0];
+  s_w0[t] = cc.w[0];
+  __syncthreads();
+  const float vn = (t + 1 < T) ? s_v0[t + 1] : 0.0f;
+  const float wn = (t + 1 < T) ? s_w0[t + 1] : 0.0f;
+  __syncthreads();
+  float Ra = cc.ae * cc.v[K - 2];
+  float Rd = d[K - 1] + cc.ae * cc.w[K - 2] + cc.ce * vn;
+  float Rc = cc.ce * wn;
+
+  // PCR on the coefficients, once; level l pairs rows t - 2^l and t + 2^l
+  float* s_ra = lds;
+  float* s_rd = lds + T;
+  float* s_rc = lds + 2 * T;
+  float* s_al = lds + 6 * T;
+  float* s_ga = s_al + levels * T;
+  for (int l = 0; l < levels; ++l) {
+    const int s = 1 << l;
+    s_ra[t] = Ra;
+    s_rd[t] = Rd;
+    s_rc[t] = Rc;
+    __syncthreads();
+    const bool hl = t - s >= 0, hr = t + s < T;
+    const float ra_l = hl ? s_ra[t - s] : 0.0f, rd_l = hl ? s_rd[t - s] : 1.0f,
+                rc_l = hl ? s_rc[t - s] : 0.0f;
+    const float ra_r = hr ? s_ra[t + s] : 0.0f, rd_r = hr ? s_rd[t + s] : 1.0f,
+                rc_r = hr ? s_rc[t + s] : 0.0f;
+    __syncthreads();
+    const float al = -Ra / rd_l;
+    const float ga = -Rc / rd_r;
+    s_al[l * T + t] = al;
+    s_ga[l * T + t] = ga;
+    Rd = Rd + al * rc_l + ga * ra_r;
+    Ra = al * ra_l;
+    Rc = ga * rc_r;
+  }
+  cc.inv_rd = 1.0f / Rd;
+  __syncthreads();
+}
+
+// One Crank-Nicolson substep on the thread's K slots of V (in registers),
+//   (I - dt/2 L) V+ = (I + dt/2 L) V,  L = c M_L^{-1} K,
+// for the whole bin.  V may hold V_m or V_m minus any constant (the step
+// commutes with adding a constant).  All threads of the workgroup must call
+// it.
+template <int K>
+__device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K], float r,
+                                         const CNConst<K>& cc, float* lds, int T, int t,
+                                         int levels) {
+  float* s_vf = lds;
+  float* s_vl = lds + T;
+  float* s_y0 = lds + 2 * T;
+  float* s_rb = lds + 3 * T;
+  float* s_z = lds + 5 * T;
+  const float* s_al = lds + 6 * T;
+  const float* s_ga = s_al + levels * T;
+
+  // Increment form: with A = I - dt/2 L the step V+ = A^{-1} (I + dt/2 L) V
+  // equals V + d where A d = dt L V.  The right-hand side is built from
+  // neighbour differences, so a constant field gives d = 0 exactly and the
+  // rounding error of the solve scales with the increment, not with |V|.
+  s_vf[t] = V[0];
+  s_vl[t] = V[K - 1];
+  __syncthreads();
+  const float vleft = (t > 0) ? s_vl[t - 1] : 0.0f;
+  const float vright = (t + 1 < T) ? s_vf[t + 1] : 0.0f;
+  float b[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const float l = (q == 0) ? vleft : V[q == 0 ? 0 : q - 1];
+    const float rr = (q == K - 1) ? vright : V[q == K - 1 ? K - 1 : q + 1];
+    float wl, wr;
+    row_weights(info[q], r, wl, wr);
+    // dt L V = 2 (wl (V_l - V) + wr (V_r - V)); a zero weight removes the
+    // (possibly unrelated) neighbour value exactly
+    b[q] = 2.0f * fmaf(wl, l - V[q], wr * (rr - V[q]));
+  }
+  // interior solve with the right-hand side only
+  float y[K - 1];
+  y[0] = b[0] * cc.inv[0];
+#pragma unroll
+  for (int q = 1; q < K - 1; ++q) y[q] = fmaf(-cc.ainv[q], y[q - 1], b[q] * cc.inv[q]);
+#pragma unroll
+  for (int q = K - 3; q >= 0; --q) y[q] = fmaf(-cc.cp[q], y[q + 1], y[q]);
+
+  // reduced right-hand side needs the next thread's first interior value
+  s_y0[t] = y[0];
+  __syncthreads();
+  const float yn = (t + 1 < T) ? s_y0[t + 1] : 0.0f;
+  float rb = fmaf(-cc.ae, y[K - 2], fmaf(-cc.ce, yn, b[K - 1]));
+
+  for (int l = 0; l < levels; ++l) {
+    const int s = 1 << l;
+    float* buf = s_rb + (l & 1) * T;
+    buf[t] = rb;
+    __syncthreads();
+    const float rl = (t - s >= 0) ? buf[t - s] : 0.0f;
+    const float rr = (t + s < T) ? buf[t + s] : 0.0f;
+    rb = fmaf(s_al[l * T + t], rl, fmaf(s_ga[l * T + t], rr, rb));
+  }
+  const float z = rb * cc.inv_rd;
+
+  s_z[t] = z;
+  __syncthreads();
+  const float zl = (t > 0) ? s_z[t - 1] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < K - 1; ++q) V[q] += fmaf(cc.v[q], zl, fmaf(cc.w[q], z, y[q]));
+  V[K - 1] += z;
+}
+
+// ---------------------------------------------------------------------------
+// Fused persistent kernel, Hodgkin-Huxley
+// ---------------------------------------------------------------------------
+
+// One workgroup per bin runs split steps step0 .. step0+n_steps-1 with every
+// node's four states in registers: R(dt/2) D(dt) R(dt/2), then the
+// observables.  Device memory is read at the start, written at the end and
+// for samples / activation times only.
+template <int K>
+__global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
+  extern __shared__ float lds[];
+  const int T = blockDim.x;
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * A.cap + (int64_t)t * K;
+  const int64_t nt = A.n_total;
+
+  uint32_t info[K];
+  hh::State y[K];
+  uint32_t done = 0;  // bit q: slot q needs no activation-time update
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    info[q] = A.slot_info[base + q];
+    const int32_t g = A.slot_gidx[base + q];
+    if (g >= 0) {
+      y[q].V = A.state[g];
+      y[q].m = A.state[nt + g];
+      y[q].h = A.state[2 * nt + g];
+      y[q].n = A.state[3 * nt + g];
+      if (!isinf(A.t_act[g])) done |= 1u << q;
+    } else {
+      y[q].V = A.rest[0] - A.vref;
+      y[q].m = A.rest[1];
+      y[q].h = A.rest[2];
+      y[q].n = A.rest[3];
+      done |= 1u << q;
+    }
+  }
+  CNConst<K> cc;
+  cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
+
+  const uint32_t all = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
+  const int32_t n_end = A.step0 + A.n_steps;
+  for (int32_t n = A.step0; n < n_end; ++n) {
+    float I[K], v0[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+      I[q] = stim_current(info[q] >> SLOT_STIM_SHIFT, A.stim, n);
+      v0[q] = y[q].V;
+    }
+    for (int s = 0; s < A.n_sub; ++s) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, A.vref);
+    }
+    {
+      float V[K];
+#pragma unroll
+      for (int q = 0; q < K; ++q) V[q] = y[q].V;
+      for (int c = 0; c < A.n_cn; ++c) cn_solve<K>(V, info, A.r, cc, lds, T, t, A.pcr_levels);
+#pragma unroll
+      for (int q = 0; q < K; ++q) y[q].V = V[q];
+    }
+    for (int s = 0; s < A.n_sub; ++s) {
+#pragma unroll
+      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, A.vref);
+    }
+    // activation times: first upward crossing of v_th between step ends
+    // (the offsets u cross v_th - vref)
+    if (done != all) {
+      const float t0 = (float)n * A.dt;
+      const float uth = A.v_th - A.vref;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        if (!((done >> q) & 1u) && v0[q] < uth && y[q].V >= uth) {
+          const int32_t g = A.slot_gidx[base + q];
+          A.t_act[g] = fmaf(A.dt, (uth - v0[q]) / (y[q].V - v0[q]), t0);
+          done |= 1u << q;
+        }
+      }
+    }
+    if (A.sample_every > 0 && ((int64_t)n + 1) % A.sample_every == 0) {
+      const int64_t row = ((int64_t)n + 1) / A.sample_every - 1 - A.sample_row0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const int32_t g = A.slot_gidx[base + q];
+        if (g >= 0) A.samples[row * nt + g] = y[q].V + A.vref;
+      }
+    }
+  }
+
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int32_t g = A.slot_gidx[base + q];
+    if (g >= 0) {
+      A.state[g] = y[q].V;
+      A.state[nt + g] = y[q].m;
+      A.state[2 * nt + g] = y[q].h;
+      A.state[3 * nt + g] = y[q].n;
+      bad |= !isfinite(y[q].V) || !isfinite(y[q].m) || !isfinite(y[q].h) || !isfinite(y[q].n);
+    }
+  }
+  if (bad) atomicOr(A.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Diffusion only (states in device memory)
+// ---------------------------------------------------------------------------
+
+template <int K>
+__global__ __launch_bounds__(1024) void k_diffusion(KArgs A) {
+  extern __shared__ float lds[];
+  const int T = blockDim.x;
+  const int t = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * A.cap + (int64_t)t * K;
+  uint32_t info[K];
+  int32_t gi[K];
+  float V[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    info[q] = A.slot_info[base + q];
+    gi[q] = A.slot_gidx[base + q];
+    V[q] = gi[q] >= 0 ? A.state[gi[q]] : A.rest[0] - A.vref;
+  }
+  CNConst<K> cc;
+  cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
+  for (int c = 0; c < A.n_cn; ++c) cn_solve<K>(V, info, A.r, cc, lds, T, t, A.pcr_levels);
+#pragma unroll
+  for (int q = 0; q < K; ++q)
+    if (gi[q] >= 0) A.state[gi[q]] = V[q];
+}
+
+// ---------------------------------------------------------------------------
+// Reaction only (states in device memory), one node per thread
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_reaction_hh(KArgs A, int32_t step) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_total) return;
+  const int64_t nt = A.n_total;
+  hh::State y{A.state[i], A.state[nt + i], A.state[2 * nt + i], A.state[3 * nt + i]};
+  const float I = stim_current((uint32_t)A.node_stim[i], A.stim, step);
+  for (int s = 0; s < A.n_sub; ++s) hh::heun(y, I, A.tau, A.inv_cm, A.vref);
+  A.state[i] = y.V;
+  A.state[nt + i] = y.m;
+  A.state[2 * nt + i] = y.h;
+  A.state[3 * nt + i] = y.n;
+}
+
+// Observables after split step `step` for the SPLIT schedule: activation
+// times from v_prev and the current V_m, samples, then v_prev := V_m.
+__global__ __launch_bounds__(256) void k_observe(KArgs A, int32_t step) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_total) return;
+  const float v1 = A.state[i];
+  const float v0 = A.v_prev[i];
+  const float uth = A.v_th - A.vref;
+  if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
+    A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
+  if (A.sample_every > 0 && ((int64_t)step + 1) % A.sample_every == 0) {
+    const int64_t row = ((int64_t)step + 1) / A.sample_every - 1 - A.sample_row0;
+    A.samples[row * A.n_total + i] = v1 + A.vref;
+  }
+  A.v_prev[i] = v1;
+  if (!isfinite(v1)) atomicOr(A.flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Initial state and small utilities
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_init(KArgs A, int S, const float* __restrict__ vm_noise,
+                                             const float* __restrict__ rel_noise) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_total) return;
+  const int64_t nt = A.n_total;
+  for (int k = 0; k < S; ++k) {
+    // rest_k (1 + rel) (+ noise for V_m), the voltage as its offset from vref
+    const float base = (k == 0) ? A.rest[0] - A.vref : A.rest[k];
+    float v = rel_noise ? fmaf(A.rest[k], rel_noise[k * nt + i], base) : base;
+    if (k == 0 && vm_noise) v += vm_noise[i];
+    A.state[k * nt + i] = v;
+  }
+  A.t_act[i] = __builtin_inff();
+  A.v_prev[i] = A.state[i];
+}
+
+__global__ __launch_bounds__(256) void k_fill(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_check_finite(const float* p, int64_t n, int* flag) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n && !isfinite(p[i])) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+template <int K>
+static hipError_t run_fused_k(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_run_hh<K>, dim3(groups), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds,
+                            const KArgs& a, hipStream_t s) {
+  if (model != 0) return hipErrorInvalidValue;
+  switch (K) {
+    case 2: return run_fused_k<2>(groups, threads, lds, a, s);
+    case 3: return run_fused_k<3>(groups, threads, lds, a, s);
+    case 4: return run_fused_k<4>(groups, threads, lds, a, s);
+    case 5: return run_fused_k<5>(groups, threads, lds, a, s);
+    case 6: return run_fused_k<6>(groups, threads, lds, a, s);
+    case 7: return run_fused_k<7>(groups, threads, lds, a, s);
+    case 8: return run_fused_k<8>(groups, threads, lds, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int K>
+static hipError_t diffusion_k(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_diffusion<K>, dim3(groups), dim3(threads), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KArgs& a,
+                            hipStream_t s) {
+  switch (K) {
+    case 2: return diffusion_k<2>(groups, threads, lds, a, s);
+    case 3: return diffusion_k<3>(groups, threads, lds, a, s);
+    case 4: return diffusion_k<4>(groups, threads, lds, a, s);
+    case 5: return diffusion_k<5>(groups, threads, lds, a, s);
+    case 6: return diffusion_k<6>(groups, threads, lds, a, s);
+    case 7: return diffusion_k<7>(groups, threads, lds, a, s);
+    case 8: return diffusion_k<8>(groups, threads, lds, a, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_reaction(int model, int32_t step, const KArgs& a, hipStream_t s) {
+  if (model != 0) return hipErrorInvalidValue;
+  if (a.n_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_reaction_hh, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_observe, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, step);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
+                       hipStream_t s) {
+  const int S = (model == 0) ? 4 : 0;
+  if (S == 0) return hipErrorInvalidValue;
+  if (a.n_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, S, vm_noise,
+                     rel_noise);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_check_finite, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, flag);
+  return hipGetLastError();
+}
+
+}  // namespace fib

@@ -1,0 +1,114 @@
+// Hodgkin-Huxley membrane in FP32 for gfx950 (thesis section "Subcellular
+// Model", eqs. subcellular_model_helper3-5 and subcellular; rate functions of
+// Hodgkin & Huxley 1952 in the -75 mV resting-potential convention of the
+// generated-code excerpt in section "Computation of CellML Models").
+//
+// State (V, m, h, n); V in mV, rates in 1/ms.  With v = V + 75:
+//   alpha_m = 0.1 (25-v) / (exp((25-v)/10) - 1)   beta_m = 4 exp(-v/18)
+//   alpha_h = 0.07 exp(-v/20)                      beta_h = 1 / (exp((30-v)/10) + 1)
+//   alpha_n = 0.01 (10-v) / (exp((10-v)/10) - 1)  beta_n = 0.125 exp(-v/80)
+//   I_ion = 120 m^3 h (V - 40) + 36 n^4 (V + 87) + 0.3 (V + 64.387)
+//   dV/dt = (I_stim - I_ion) / Cm,  dy/dt = alpha_y (1 - y) - beta_y y.
+//
+// Every exponential is one v_exp_f32 (2^x) whose argument is a single FMA in
+// V: the 1/ln 2 factor, the 1/10, 1/18, 1/20, 1/80 slopes, the +75 shift and
+// the prefactors 4, 0.07, 0.125 (as +log2 of the prefactor) are folded into
+// the FMA's constants.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fib {
+namespace hh {
+
+constexpr double kL2E = 1.4426950408889634074;  // 1 / ln 2
+
+// exp(s * (V + shift)) * pre  ==  2^(V * K1 + K0)
+struct ExpCoef {
+  float k1, k0;
+};
+constexpr ExpCoef exp_coef(double slope, double shift, double log2_pre) {
+  return ExpCoef{(float)(slope * kL2E), (float)(slope * shift * kL2E + log2_pre)};
+}
+
+// log2 of the prefactors
+constexpr double kLog2_4 = 2.0;
+constexpr double kLog2_007 = -3.8365012677171206;  // log2(0.07)
+constexpr double kLog2_0125 = -3.0;
+
+constexpr ExpCoef kBm = exp_coef(-1.0 / 18.0, 75.0, kLog2_4);     // 4 exp(-v/18)
+constexpr ExpCoef kAh = exp_coef(-1.0 / 20.0, 75.0, kLog2_007);   // 0.07 exp(-v/20)
+constexpr ExpCoef kBh = exp_coef(-1.0 / 10.0, 45.0, 0.0);         // exp((30-v)/10)
+constexpr ExpCoef kBn = exp_coef(-1.0 / 80.0, 75.0, kLog2_0125);  // 0.125 exp(-v/80)
+constexpr ExpCoef kXm = exp_coef(-1.0 / 10.0, 50.0, 0.0);         // exp(x_m), x_m = (25-v)/10
+constexpr ExpCoef kXn = exp_coef(-1.0 / 10.0, 65.0, 0.0);         // exp(x_n), x_n = (10-v)/10
+
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// x / (exp(x) - 1) given e = exp(x).  For |x| < 0.1 the Bernoulli series
+// 1 - x/2 + x^2/12 - x^4/720 (truncation error below x^6/30240 < 4e-11)
+// replaces the quotient, whose cancellation error grows like 6e-8 / |x|.
+__device__ __forceinline__ float x_over_expm1(float x, float e) {
+  float x2 = x * x;
+  float s = fmaf(x, fmaf(x, fmaf(x2, -1.0f / 720.0f, 1.0f / 12.0f), -0.5f), 1.0f);
+  float q = x * rcp(e - 1.0f);
+  return fabsf(x) < 0.1f ? s : q;
+}
+
+// The voltage is carried as its offset u = V - vref from the resting
+// potential vref.
+struct State {
+  float V, m, h, n;  // V holds u = V_m - vref
+};
+
+// Right-hand side G(y) of the membrane model with stimulus current I.
+__device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, float vref) {
+  const float V = y.V + vref;
+  const float xm = fmaf(V, -0.1f, -5.0f);   // (25 - v)/10 = -(V + 50)/10
+  const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
+  const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
+  const float en = ex2(fmaf(V, kXn.k1, kXn.k0));
+  const float am = x_over_expm1(xm, em);
+  const float an = 0.1f * x_over_expm1(xn, en);
+  const float bm = ex2(fmaf(V, kBm.k1, kBm.k0));
+  const float ah = ex2(fmaf(V, kAh.k1, kAh.k0));
+  const float bh = rcp(ex2(fmaf(V, kBh.k1, kBh.k0)) + 1.0f);
+  const float bn = ex2(fmaf(V, kBn.k1, kBn.k0));
+
+  const float m2 = y.m * y.m;
+  const float m3h = m2 * (y.m * y.h);
+  const float n2 = y.n * y.n;
+  const float n4 = n2 * n2;
+  const float ina = m3h * (V - 40.0f);
+  const float ik = n4 * (V + 87.0f);
+  const float il = fmaf(0.3f, V, 0.3f * 64.387f);
+  const float iion = fmaf(120.0f, ina, fmaf(36.0f, ik, il));
+
+  State d;
+  d.V = (I - iion) * inv_cm;
+  d.m = fmaf(-(am + bm), y.m, am);
+  d.h = fmaf(-(ah + bh), y.h, ah);
+  d.n = fmaf(-(an + bn), y.n, an);
+  return d;
+}
+
+// One Heun step of width tau (eq. heun):
+//   y+ = y + tau/2 (G(y) + G(y + tau G(y))).
+__device__ __forceinline__ void heun(State& y, float I, float tau, float inv_cm, float vref) {
+  const State k1 = rhs(y, I, inv_cm, vref);
+  State yt;
+  yt.V = fmaf(tau, k1.V, y.V);
+  yt.m = fmaf(tau, k1.m, y.m);
+  yt.h = fmaf(tau, k1.h, y.h);
+  yt.n = fmaf(tau, k1.n, y.n);
+  const State k2 = rhs(yt, I, inv_cm, vref);
+  const float ht = 0.5f * tau;
+  y.V = fmaf(ht, k1.V + k2.V, y.V);
+  y.m = fmaf(ht, k1.m + k2.m, y.m);
+  y.h = fmaf(ht, k1.h + k2.h, y.h);
+  y.n = fmaf(ht, k1.n + k2.n, y.n);
+}
+
+}  // namespace hh
+}  // namespace fib

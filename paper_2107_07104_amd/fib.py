@@ -1,0 +1,308 @@
+"""ctypes binding of libfib.so (the C ABI in include/fib.h).
+
+Argument marshalling only: every step of the solve runs in the library's
+HIP kernels.  Device arrays are passed as raw pointers, normally taken from
+torch CUDA tensors (``tensor.data_ptr()``); the stream is a raw
+``hipStream_t`` (``torch.cuda.current_stream().cuda_stream``).
+
+The library is loaded on first use; if ``libfib.so`` has not been built the
+loader raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfib.so")
+
+FIB_OK = 0
+FIB_EINVAL = -1
+FIB_ENOMEM = -2
+FIB_EHIP = -3
+FIB_ENONFINITE = -4
+FIB_ESTATE = -5
+FIB_EUNSUPPORTED = -6
+
+FIB_MODEL_HH = 0
+FIB_MODEL_ST57 = 1
+FIB_SCHED_AUTO = 0
+FIB_SCHED_FUSED = 1
+FIB_SCHED_SPLIT = 2
+
+# Every function the header declares, for the export check.
+EXPORTS = (
+    "fib_n_states", "fib_rest_state", "fib_check_params", "fib_create", "fib_destroy",
+    "fib_last_error", "fib_n_total", "fib_init_state", "fib_set_state", "fib_get_state",
+    "fib_state_device", "fib_set_stimulus", "fib_step_reaction", "fib_step_diffusion",
+    "fib_run", "fib_get_tact", "fib_reset_observables", "fib_sync", "fib_plan_info",
+)
+
+
+class fib_params(C.Structure):
+    _fields_ = [("model", C.c_int32), ("schedule", C.c_int32), ("Cm", C.c_double),
+                ("Am", C.c_double), ("sigma", C.c_double), ("h", C.c_double),
+                ("dt_0D", C.c_double), ("dt_1D", C.c_double), ("dt_split", C.c_double),
+                ("v_th", C.c_double), ("pcr_full", C.c_int32),
+                ("threads_per_group", C.c_int32), ("nodes_per_thread", C.c_int32),
+                ("groups", C.c_int32)]
+
+
+class fib_stim(C.Structure):
+    _fields_ = [("fiber", C.c_int32), ("node", C.c_int32), ("half_width", C.c_int32),
+                ("pad_", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
+                ("period", C.c_int64), ("amp", C.c_double)]
+
+
+class FibError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"libfib error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+_vp = C.c_void_p
+_dp = C.POINTER(C.c_double)
+_fp = C.POINTER(C.c_float)
+_i32p = C.POINTER(C.c_int32)
+
+
+def lib():
+    """Loads libfib.so; raises if it is missing (no fallback path exists)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
+                              "or python -m paper_2107_07104_amd.csrc.build")
+        L = C.CDLL(LIB_PATH)
+        sig = {
+            "fib_n_states": ([C.c_int32], C.c_int),
+            "fib_rest_state": ([C.POINTER(fib_params), _dp], C.c_int),
+            "fib_check_params": ([C.POINTER(fib_params)], C.c_int),
+            "fib_create": ([C.POINTER(fib_params), C.c_int32, _i32p, _vp, C.POINTER(_vp)], C.c_int),
+            "fib_destroy": ([_vp], None),
+            "fib_last_error": ([], C.c_char_p),
+            "fib_n_total": ([_vp], C.c_int64),
+            "fib_init_state": ([_vp, _vp, _vp], C.c_int),
+            "fib_set_state": ([_vp, _dp, C.c_int64], C.c_int),
+            "fib_get_state": ([_vp, _dp, C.c_int64], C.c_int),
+            "fib_state_device": ([_vp, C.POINTER(_vp), _dp], C.c_int),
+            "fib_set_stimulus": ([_vp, C.POINTER(fib_stim), C.c_int32], C.c_int),
+            "fib_step_reaction": ([_vp, C.c_int64, C.c_double], C.c_int),
+            "fib_step_diffusion": ([_vp, C.c_double], C.c_int),
+            "fib_run": ([_vp, C.c_int64, C.c_int64, C.c_int64, _vp, C.c_int64], C.c_int),
+            "fib_get_tact": ([_vp, _fp, C.c_int64], C.c_int),
+            "fib_reset_observables": ([_vp], C.c_int),
+            "fib_sync": ([_vp], C.c_int),
+            "fib_plan_info": ([_vp, _i32p, _i32p, _i32p, _i32p], C.c_int),
+        }
+        for name, (args, res) in sig.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FIB_OK:
+        raise FibError(rc, lib().fib_last_error().decode())
+    return rc
+
+
+def make_params(model=FIB_MODEL_HH, schedule=FIB_SCHED_AUTO, Cm=1.0, Am=500.0, sigma=3.828,
+                h=0.01, dt_0D=1e-3, dt_1D=1e-3, dt_split=1e-3, v_th=-20.0, pcr_full=0,
+                threads_per_group=0, nodes_per_thread=0, groups=0) -> fib_params:
+    return fib_params(model, schedule, Cm, Am, sigma, h, dt_0D, dt_1D, dt_split, v_th,
+                      pcr_full, threads_per_group, nodes_per_thread, groups)
+
+
+def _stim_array(stims):
+    arr = (fib_stim * max(len(stims), 1))()
+    for i, s in enumerate(stims):
+        arr[i] = fib_stim(int(s["fiber"]), int(s["node"]), int(s.get("half_width", 1)), 0,
+                          int(s["step_on"]), int(s["n_steps"]), int(s.get("period", 0)),
+                          float(s["amp"]))
+    return arr
+
+
+# ---- functions with the C names ------------------------------------------------
+
+def fib_n_states(model: int) -> int:
+    rc = lib().fib_n_states(model)
+    _check(min(rc, 0))
+    return rc
+
+
+def fib_rest_state(params: fib_params) -> np.ndarray:
+    y = np.zeros(fib_n_states(params.model))
+    _check(lib().fib_rest_state(C.byref(params), y.ctypes.data_as(_dp)))
+    return y
+
+
+def fib_check_params(params: fib_params) -> int:
+    return lib().fib_check_params(C.byref(params))
+
+
+def fib_create(params: fib_params, n_nodes, stream=None) -> int:
+    nn = np.ascontiguousarray(n_nodes, dtype=np.int32)
+    out = _vp()
+    _check(lib().fib_create(C.byref(params), len(nn), nn.ctypes.data_as(_i32p),
+                            _vp(stream) if stream else None, C.byref(out)))
+    return out.value
+
+
+def fib_destroy(ctx) -> None:
+    lib().fib_destroy(_vp(ctx))
+
+
+def fib_last_error() -> str:
+    return lib().fib_last_error().decode()
+
+
+def fib_n_total(ctx) -> int:
+    return lib().fib_n_total(_vp(ctx))
+
+
+def fib_init_state(ctx, vm_noise_ptr=0, rel_noise_ptr=0) -> None:
+    _check(lib().fib_init_state(_vp(ctx), _vp(vm_noise_ptr or None), _vp(rel_noise_ptr or None)))
+
+
+def fib_set_state(ctx, y: np.ndarray) -> None:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    _check(lib().fib_set_state(_vp(ctx), y.ctypes.data_as(_dp), y.size))
+
+
+def fib_get_state(ctx, n_states: int) -> np.ndarray:
+    n = fib_n_total(ctx)
+    y = np.zeros((n_states, n))
+    _check(lib().fib_get_state(_vp(ctx), y.ctypes.data_as(_dp), y.size))
+    return y
+
+
+def fib_state_device(ctx):
+    """(device pointer of the FP32 state, v_ref); row 0 holds V_m - v_ref."""
+    p = _vp()
+    v = C.c_double()
+    _check(lib().fib_state_device(_vp(ctx), C.byref(p), C.byref(v)))
+    return p.value, v.value
+
+
+def fib_set_stimulus(ctx, stims) -> None:
+    arr = _stim_array(stims)
+    _check(lib().fib_set_stimulus(_vp(ctx), arr, len(stims)))
+
+
+def fib_step_reaction(ctx, step: int, span: float) -> None:
+    _check(lib().fib_step_reaction(_vp(ctx), int(step), float(span)))
+
+
+def fib_step_diffusion(ctx, span: float) -> None:
+    _check(lib().fib_step_diffusion(_vp(ctx), float(span)))
+
+
+def fib_run(ctx, step0: int, n_steps: int, sample_every: int = 0, samples_ptr=0,
+            sample_rows: int = 0) -> None:
+    _check(lib().fib_run(_vp(ctx), int(step0), int(n_steps), int(sample_every),
+                         _vp(samples_ptr or None), int(sample_rows)))
+
+
+def fib_get_tact(ctx) -> np.ndarray:
+    n = fib_n_total(ctx)
+    t = np.zeros(n, dtype=np.float32)
+    _check(lib().fib_get_tact(_vp(ctx), t.ctypes.data_as(_fp), n))
+    return t
+
+
+def fib_reset_observables(ctx) -> None:
+    _check(lib().fib_reset_observables(_vp(ctx)))
+
+
+def fib_sync(ctx) -> None:
+    _check(lib().fib_sync(_vp(ctx)))
+
+
+def fib_plan_info(ctx):
+    g, t, k, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().fib_plan_info(_vp(ctx), C.byref(g), C.byref(t), C.byref(k), C.byref(l)))
+    return dict(groups=g.value, threads=t.value, nodes_per_thread=k.value, pcr_levels=l.value)
+
+
+# ---- convenience wrapper (still marshalling only) ---------------------------------
+
+class Solver:
+    """Owns one context; device buffers through torch (current CUDA device)."""
+
+    def __init__(self, n_nodes, stream=None, **params):
+        import torch
+        self.torch = torch
+        self.params = make_params(**params)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.stream = stream
+        self.ctx = fib_create(self.params, n_nodes, stream)
+        self.n_total = fib_n_total(self.ctx)
+        self.S = fib_n_states(self.params.model)
+
+    def close(self):
+        if self.ctx:
+            fib_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def init_state(self, vm_noise=None, rel_noise=None):
+        t = self.torch
+        self._vm = (t.as_tensor(np.asarray(vm_noise, dtype=np.float32), device="cuda")
+                    if vm_noise is not None else None)
+        self._rel = (t.as_tensor(np.asarray(rel_noise, dtype=np.float32), device="cuda")
+                     if rel_noise is not None else None)
+        fib_init_state(self.ctx, self._vm.data_ptr() if self._vm is not None else 0,
+                       self._rel.data_ptr() if self._rel is not None else 0)
+
+    def set_state(self, y):
+        fib_set_state(self.ctx, y)
+
+    def get_state(self):
+        return fib_get_state(self.ctx, self.S)
+
+    def state_tensor(self):
+        """Zero-copy torch view of the FP32 device state [S, n_total] and
+        v_ref; row 0 of the view holds V_m - v_ref."""
+        ptr, vref = fib_state_device(self.ctx)
+        n = self.S * self.n_total
+        t = self.torch
+        # wrap through the CUDA array interface without copying
+        class _Arr:
+            __cuda_array_interface__ = {"shape": (n,), "typestr": "<f4", "data": (ptr, False),
+                                        "version": 2}
+        return t.as_tensor(_Arr(), device="cuda").view(self.S, self.n_total), vref
+
+    def set_stimulus(self, stims):
+        fib_set_stimulus(self.ctx, stims)
+
+    def step_reaction(self, step, span):
+        fib_step_reaction(self.ctx, step, span)
+
+    def step_diffusion(self, span):
+        fib_step_diffusion(self.ctx, span)
+
+    def run(self, step0, n_steps, sample_every=0, samples=None):
+        rows = samples.shape[0] if samples is not None else 0
+        fib_run(self.ctx, step0, n_steps, sample_every,
+                samples.data_ptr() if samples is not None else 0, rows)
+
+    def tact(self):
+        return fib_get_tact(self.ctx)
+
+    def sync(self):
+        fib_sync(self.ctx)
+
+    def plan(self):
+        return fib_plan_info(self.ctx)

@@ -1,0 +1,266 @@
+"""GPU (HIP) path against the FP64 oracle on the same seeded inputs.
+
+Tolerances (FP32 kernels vs FP64 oracle):
+  * one reaction half step from random physiological states: the FP32
+    result carries a few rounding errors of the state's magnitude (ulp of
+    100 mV is 7.6e-6 mV) plus the kernel's exp/reciprocal error (about 1e-6
+    relative) times the increment; 2e-4 mV on V and 2e-6 on the gates bound
+    both with margin;
+  * one diffusion step: |V| <= 100 mV, a handful of FMAs per node in FP32,
+    and a diagonally dominant solve that does not amplify errors: 1e-4 mV;
+  * whole runs: the stated budget of the method, max |V_gpu - V_oracle| <=
+    0.5 mV over all samples (every 0.1 ms) and the final state, activation
+    times within one split step.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2107_07104_amd import fib as F
+from paper_2107_07104_amd import inputs as I
+
+from gpu_helpers import compare_runs, gpu_run, gpu_solver, oracle_cfg, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.lib()
+
+
+def _random_states(rng, n):
+    V = rng.uniform(-90.0, 40.0, n)
+    gates = rng.uniform(0.0, 1.0, (3, n))
+    return np.vstack([V[None], gates])
+
+
+@pytest.mark.parametrize("span,dt0", [(5e-4, 1e-3), (1.5e-3, 5e-4), (2.5e-3, 1e-3)])
+def test_reaction_step_matches_oracle(span, dt0):
+    say(f"[reaction] span={span} dt_0D={dt0}")
+    rng = np.random.default_rng(11)
+    n = [3000, 1, 997]
+    y0 = _random_states(rng, sum(n))
+    stims = [dict(fiber=0, node=100, half_width=3, step_on=0, n_steps=5, period=0, amp=300.0),
+             dict(fiber=2, node=996, half_width=1, step_on=2, n_steps=5, period=0, amp=-50.0)]
+    s = F.Solver(n, dt_0D=dt0)
+    s.set_stimulus(stims)
+    s.set_state(y0)
+    y0f = s.get_state()  # the FP32-rounded start both sides use
+    s.step_reaction(1, span)
+    s.sync()
+    yg = s.get_state()
+    cfg = O.Config(dt_0D=dt0)
+    I_ = O.stimulus_current(n, stims, 1)
+    yo = O.reaction(cfg, y0f, span, I_)
+    assert I_[100] == 300.0 and I_[sum(n) - 1] == 0.0  # step 1: the second pulse is still off
+    assert np.max(np.abs(yg[0] - yo[0])) < 2e-4
+    assert np.max(np.abs(yg[1:] - yo[1:])) < 2e-6
+    s.step_reaction(3, span)  # both pulses on
+    s.sync()
+    yg = s.get_state()
+    yo = O.reaction(cfg, yo, span, O.stimulus_current(n, stims, 3))
+    assert np.max(np.abs(yg[0] - yo[0])) < 4e-4
+    s.close()
+
+
+LENGTHS = [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 63, 64, 65, 100, 1000, 1481, 1500, 2, 1, 333]
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(threads_per_group=256, nodes_per_thread=8),
+                                   dict(threads_per_group=1024, nodes_per_thread=2, groups=3),
+                                   dict(threads_per_group=1024, nodes_per_thread=3, groups=2),
+                                   dict(threads_per_group=1024, nodes_per_thread=5, groups=1),
+                                   dict(pcr_full=1, threads_per_group=512, nodes_per_thread=4)])
+@pytest.mark.parametrize("dt", [1e-3, 5e-3])
+def test_diffusion_step_matches_oracle(shape, dt):
+    say(f"[diffusion] shape={shape} dt={dt}")
+    rng = np.random.default_rng(12)
+    n = LENGTHS
+    V = rng.uniform(-85.0, 35.0, sum(n))
+    y0 = np.vstack([V[None], np.full((3, sum(n)), 0.5)])
+    s = F.Solver(n, dt_1D=dt, dt_split=dt, **shape)
+    say("  plan", s.plan())
+    s.set_state(y0)
+    y0f = s.get_state()
+    s.step_diffusion(dt)
+    s.sync()
+    yg = s.get_state()
+    vo = O.diffusion(O.Config(dt_1D=dt, dt_split=dt), n, y0f[0], dt)
+    assert np.max(np.abs(yg[0] - vo)) < 1e-4
+    np.testing.assert_array_equal(yg[1:], y0f[1:])
+    # three substeps in one call
+    s.step_diffusion(3 * dt)
+    s.sync()
+    vo = O.diffusion(O.Config(dt_1D=dt, dt_split=dt), n, vo, 3 * dt)
+    assert np.max(np.abs(s.get_state()[0] - vo)) < 2e-4
+    s.close()
+
+
+def test_diffusion_conserves_charge_on_gpu():
+    rng = np.random.default_rng(13)
+    n = [1481] * 7 + [1000, 1, 2]
+    V = rng.uniform(-85.0, 35.0, sum(n))
+    s = F.Solver(n)
+    s.set_state(np.vstack([V[None], np.full((3, sum(n)), 0.5)]))
+    v0 = s.get_state()[0]
+    for _ in range(50):
+        s.step_diffusion(1e-3)
+    s.sync()
+    v1 = s.get_state()[0]
+    off = np.concatenate([[0], np.cumsum(n)])
+    for f, m in enumerate(n):
+        w = np.ones(m)
+        if m > 1:
+            w[0] = w[-1] = 0.5
+        a, b = off[f], off[f + 1]
+        q0, q1 = np.dot(w, v0[a:b]), np.dot(w, v1[a:b])
+        # FP32 rounding only: a relative drift of 1e-5 over 50 steps
+        assert abs(q1 - q0) <= 1e-5 * np.sum(np.abs(w * v0[a:b]))
+        assert v1[a:b].min() >= v0[a:b].min() - 1e-4 and v1[a:b].max() <= v0[a:b].max() + 1e-4
+    s.close()
+
+
+def _assert_parity(w, res, end_time):
+    say("  ", res)
+    assert res["vm_err"] <= 0.5
+    assert res["tact_err"] <= 1.0 * w.dt_split
+
+
+@pytest.mark.parametrize("amp", [I.AMP_AS_WRITTEN, I.AMP_SUPRA])
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_single_fiber_run_matches_oracle(amp, schedule):
+    w = I.single_fiber(amp=amp)
+    if schedule == F.FIB_SCHED_SPLIT:
+        w = w.with_steps(3000)  # one launch per phase: keep the step count moderate
+    say(f"[run single fiber] amp={amp} schedule={schedule} steps={w.n_steps}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w, schedule=schedule)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    assert res["tact_mismatch"] == 0
+    if amp == I.AMP_SUPRA and w.n_steps == 10000:
+        assert res["activated"] > 300
+    gpu[3].close()
+
+
+def test_batched_run_matches_oracle_small():
+    w = I.batched_hh(n_fibers=24, t_end=7.0)
+    say(f"[run batched small] fibers={len(w.n_nodes)} steps={w.n_steps}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w)
+    say("  plan", gpu[3].plan())
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    assert res["activated"] > 1000
+    gpu[3].close()
+
+
+def test_ragged_and_degenerate_fibers_run():
+    # fibers of 1..9 nodes mixed with long ones, several per bin
+    n = np.array([1, 2, 3, 1500, 4, 5, 6, 7, 8, 9, 1, 1, 250], dtype=np.int32)
+    base = I.batched_hh(n_fibers=len(n), t_end=2.0, onset_max=0.5)
+    w = I.Workload(name="ragged", model=I.MODEL_HH, n_nodes=n,
+                   vm_noise=base.vm_noise[: n.sum()], rel_noise=None,
+                   stims=[dict(fiber=3, node=700, half_width=1, step_on=10, n_steps=100, period=0,
+                               amp=I.AMP_SUPRA),
+                          dict(fiber=0, node=0, half_width=1, step_on=0, n_steps=100, period=0,
+                               amp=I.AMP_SUPRA),
+                          dict(fiber=12, node=0, half_width=0, step_on=5, n_steps=3, period=50,
+                               amp=800.0)],
+                   n_steps=2000, sample_every=100)
+    for shape in (dict(), dict(threads_per_group=256, nodes_per_thread=8, groups=1)):
+        say(f"[run ragged] shape={shape}")
+        ora = oracle_run(w)
+        gpu = gpu_run(w, **shape)
+        res = compare_runs(w, gpu, ora)
+        _assert_parity(w, res, w.n_steps * w.dt_split)
+        gpu[3].close()
+
+
+def test_chunked_runs_and_reruns_are_bitwise_identical():
+    import torch
+    w = I.batched_hh(n_fibers=10, t_end=3.0, onset_max=1.0)
+    say("[bitwise] chunked vs single run")
+    s1 = gpu_solver(w)
+    a = torch.zeros((30, w.n_total), device="cuda")
+    s1.run(0, 3000, 100, a)
+    s1.sync()
+    y1, t1 = s1.get_state(), s1.tact()
+    s2 = gpu_solver(w)
+    b = torch.zeros((30, w.n_total), device="cuda")
+    s2.run(0, 1234, 100, b[:12])
+    s2.run(1234, 1766, 100, b[12:])
+    s2.sync()
+    np.testing.assert_array_equal(y1, s2.get_state())
+    np.testing.assert_array_equal(t1, s2.tact())
+    assert torch.equal(a, b)
+    # re-initialise and run again: same bits
+    s1.init_state(vm_noise=w.vm_noise.astype(np.float32))
+    s1.run(0, 3000)
+    s1.sync()
+    np.testing.assert_array_equal(y1, s1.get_state())
+    s1.close()
+    s2.close()
+
+
+def test_fused_and_split_schedules_agree():
+    w = I.batched_hh(n_fibers=5, t_end=1.5, onset_max=0.5)
+    say("[fused vs split]")
+    gf = gpu_run(w, schedule=F.FIB_SCHED_FUSED)
+    gs = gpu_run(w, schedule=F.FIB_SCHED_SPLIT)
+    # the fused kernel keeps V_m - V_rest in registers between phases, the
+    # split schedule rounds V_m to FP32 at every phase boundary: both are
+    # within the oracle budget, and within half of it of each other
+    say("   fused vs split max |dV|", np.max(np.abs(gf[0] - gs[0])[0]))
+    assert np.max(np.abs(gf[0] - gs[0])[0]) < 0.25
+    both = np.isfinite(gf[2]) & np.isfinite(gs[2])
+    np.testing.assert_array_equal(np.isfinite(gf[2]), np.isfinite(gs[2]))
+    if both.any():
+        assert np.max(np.abs(gf[2][both] - gs[2][both])) < 0.5 * w.dt_split
+    gf[3].close()
+    gs[3].close()
+
+
+def test_errors_and_edge_cases():
+    say("[edge cases]")
+    s = F.Solver([10, 20])
+    with pytest.raises(F.FibError) as e:
+        s.run(0, 10)  # state not initialized
+    assert e.value.code == F.FIB_ESTATE
+    s.init_state()
+    s.run(0, 0)  # nothing to do
+    with pytest.raises(F.FibError):
+        s.set_stimulus([dict(fiber=0, node=3, half_width=1, step_on=0, n_steps=1, amp=1.0),
+                        dict(fiber=0, node=4, half_width=0, step_on=0, n_steps=1, amp=1.0)])
+    with pytest.raises(F.FibError):
+        s.set_stimulus([dict(fiber=2, node=0, step_on=0, n_steps=1, amp=1.0)])
+    with pytest.raises(F.FibError):
+        s.run(0, 10, 5, torch.zeros((1, 30), device="cuda"))  # needs 2 rows
+    y = s.get_state()
+    y[0, 3] = np.nan
+    s.set_state(y)
+    s.run(0, 5)
+    with pytest.raises(F.FibError) as e:
+        s.sync()
+    assert e.value.code == F.FIB_ENONFINITE
+    s.close()
+    # no fibers at all
+    s0 = F.Solver([])
+    s0.init_state()
+    s0.run(0, 10)
+    s0.sync()
+    assert s0.get_state().shape == (4, 0)
+    s0.close()
+    # rest is a fixed point on the device as well
+    s = F.Solver([7, 1, 300])
+    s.init_state()
+    y0 = s.get_state()
+    s.run(0, 200)
+    s.sync()
+    assert np.max(np.abs(s.get_state() - y0)) < 1e-3
+    s.close()

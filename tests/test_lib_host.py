@@ -1,0 +1,68 @@
+"""Host-side checks of libfib.so that need no GPU: the library loads, it
+exports every function include/fib.h declares, argument checking rejects bad
+parameters, and the library's own resting-state search (Newton's method)
+agrees with the oracle's (bisection), which is an independent
+implementation."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2107_07104_amd import fib as F
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    text = open(os.path.join(ROOT, "include", "fib.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fib_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_loads_and_exports_every_declared_function():
+    L = F.lib()
+    names = _declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(F.EXPORTS) == names
+
+
+def test_n_states():
+    assert F.fib_n_states(F.FIB_MODEL_HH) == 4
+    assert F.lib().fib_n_states(99) == F.FIB_EINVAL
+    assert "unknown model" in F.fib_last_error()
+
+
+@pytest.mark.parametrize("field,value", [
+    ("Cm", 0.0), ("Am", -1.0), ("h", float("nan")), ("sigma", -0.1), ("dt_0D", 0.0),
+    ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
+    ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
+    ("nodes_per_thread", 9), ("groups", -1), ("model", 7), ("schedule", 3)])
+def test_check_params_rejects(field, value):
+    p = F.make_params()
+    setattr(p, field, value)
+    assert F.fib_check_params(p) == F.FIB_EINVAL
+    assert F.fib_last_error() != ""
+
+
+def test_check_params_accepts_defaults():
+    assert F.fib_check_params(F.make_params()) == F.FIB_OK
+    assert F.fib_check_params(F.make_params(threads_per_group=64, nodes_per_thread=8)) == F.FIB_OK
+
+
+def test_rest_state_agrees_with_oracle():
+    y_lib = F.fib_rest_state(F.make_params())
+    y_or = O.rest_state()
+    np.testing.assert_allclose(y_lib, y_or, rtol=0, atol=1e-10)
+
+
+def test_create_rejects_bad_fibers_without_touching_the_gpu():
+    out = F._vp()
+    nn = np.array([5, 0, 3], dtype=np.int32)
+    rc = F.lib().fib_create(F.C.byref(F.make_params()), 3, nn.ctypes.data_as(F._i32p), None,
+                            F.C.byref(out))
+    assert rc == F.FIB_EINVAL and out.value is None
+    assert "fiber 1" in F.fib_last_error()
