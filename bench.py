@@ -36,14 +36,17 @@ if ROOT not in sys.path:
 METRIC = "subcellular node-steps/sec at ≤0.5 mV Vm error: plain FP32 vs surrogate"
 
 # Algorithmic cost of one node-step of the plain Hodgkin-Huxley path, in
-# FP32 VALU issue slots (one slot = one lane-cycle of a 16-lane SIMD; add,
-# mul, FMA, compare = 1 slot; exp2 and reciprocal = 4 slots, quarter rate):
-#   right-hand side G: 34 simple ops + 6 exp + 3 reciprocals = 70 slots
-#   Heun step: 2 G + 12 update ops = 152 slots
-#   reaction: 2 half steps x 1 Heun substep = 304 slots
-#   Crank-Nicolson (right-hand side 4, elimination 3, back substitution 2) = 9
-#   activation-time test = 2
-SLOTS_PER_NODE_STEP = 315
+# FP32 VALU issue slots (one slot = one lane-cycle of a 16-lane SIMD).  add,
+# sub, mul, FMA and compare take one slot; v_exp_f32 and v_rcp_f32 issue at
+# half the FMA rate on gfx950 (measured), so they take two.  Counted from the
+# formulas, not from the compiled code:
+#   right-hand side G: 6 exponent FMAs + 6 exp (12) + alpha_m quotient 5 +
+#     alpha_n quotient 6 + beta_h 3 + gate rates 6 + I_ion 12 + dV/dt 2 = 52
+#   Heun step: 2 G + 12 update ops = 116
+#   reaction: two half steps of one Heun substep each = 232
+#   Crank-Nicolson: right-hand side 5, elimination 3, update 3 = 11
+#   activation-time test: 2
+SLOTS_PER_NODE_STEP = 245
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 

@@ -36,9 +36,10 @@
  *   - The state is structure of arrays: value k of global node i is at
  *     index k * n_total + i, nodes of fiber f at offsets
  *     sum(n_nodes[0..f-1]) .. + n_nodes[f] - 1 (the order given to
- *     fib_create).  State 0 is V_m (mV) in every host array.  On the device
- *     the state is FP32 and row 0 holds V_m - v_ref, v_ref being the
- *     model's resting potential rounded to FP32 (see fib_state_device).
+ *     fib_create).  State 0 is V_m (mV).  Host arrays hold the states
+ *     themselves; on the device the state is FP32 and row k holds
+ *     y_k - ref_k, ref being the model's resting state rounded to FP32
+ *     (see fib_state_device).
  *   - A context is not thread safe; calls on one context from several
  *     threads must be serialized by the caller.
  */
@@ -121,6 +122,16 @@ int fib_rest_state(const fib_params* p, double* y_out);
 /* Checks a parameter set without touching the GPU: FIB_OK or FIB_EINVAL. */
 int fib_check_params(const fib_params* p);
 
+/* The plan fib_create would choose on a device with `compute_units` compute
+ * units, computed on the host without touching the GPU: workgroups (fiber
+ * bins), threads per workgroup, nodes per thread, PCR levels of the fused
+ * diffusion solve, and the node count of the fullest bin.  Any output
+ * pointer may be NULL.  FIB_EUNSUPPORTED if no plan fits (a fiber longer
+ * than 8192 nodes, or a fixed shape that cannot hold the fibers). */
+int fib_plan_preview(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes,
+                     int32_t compute_units, int32_t* groups, int32_t* threads,
+                     int32_t* nodes_per_thread, int32_t* pcr_levels, int64_t* max_load);
+
 /* Creates a context for n_fibers fibers with n_nodes[f] >= 1 nodes each
  * (host array).  Allocates the FP32 state, the activation-time array and
  * the schedule tables on the current HIP device and plans how fibers are
@@ -155,9 +166,10 @@ int fib_set_state(fib_t* ctx, const double* y, int64_t n_values);
 int fib_get_state(fib_t* ctx, double* y, int64_t n_values);
 
 /* Device pointer to the FP32 state (n_states * n_total floats) that the
- * context owns, valid until fib_destroy, for zero-copy access.  Row 0 of
- * the device state holds V_m - v_ref; *v_ref (nullable) receives v_ref. */
-int fib_state_device(fib_t* ctx, float** state, double* v_ref);
+ * context owns, valid until fib_destroy, for zero-copy access.  Row k of
+ * the device state holds y_k - ref_k; ref (host, nullable) receives the
+ * n_states reference values. */
+int fib_state_device(fib_t* ctx, float** state, double* ref);
 
 /* Replaces the stimulus table (host array of n entries, copied). */
 int fib_set_stimulus(fib_t* ctx, const fib_stim* stim, int32_t n);

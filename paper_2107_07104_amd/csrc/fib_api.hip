@@ -134,8 +134,11 @@ struct fib_ctx {
 
 namespace {
 
-// Packs fibers into `groups` bins by longest-processing-time-first: fibers
-// in order of decreasing length, each into the currently lightest bin.
+// Packs fibers into `groups` bins: longest-processing-time-first (fibers in
+// order of decreasing length, each into the currently lightest bin), then
+// pairwise moves and swaps out of the heaviest bin while they lower it.
+// Every workgroup runs the same number of slots, so the heaviest bin sets
+// the slots per thread of the whole launch.
 void pack_bins(fib_ctx* c, int groups) {
   std::vector<int32_t> order(c->n_fibers);
   for (int32_t f = 0; f < c->n_fibers; ++f) order[f] = f;
@@ -150,6 +153,46 @@ void pack_bins(fib_ctx* c, int groups) {
     heap.pop();
     c->bin_fibers[it.second].push_back(f);
     heap.push({it.first + c->n_nodes[f], it.second});
+  }
+  // refinement
+  std::vector<int64_t> load(groups, 0);
+  for (int b = 0; b < groups; ++b)
+    for (int32_t f : c->bin_fibers[b]) load[b] += c->n_nodes[f];
+  for (int iter = 0; iter < 20000; ++iter) {
+    const int hb = (int)(std::max_element(load.begin(), load.end()) - load.begin());
+    const int64_t top = load[hb];
+    int64_t best = top;
+    int bb = -1, bi = -1, bj = -1;  // bin, index in hb, index in bb (-1: move)
+    for (int b = 0; b < groups; ++b) {
+      if (b == hb) continue;
+      for (int i = 0; i < (int)c->bin_fibers[hb].size(); ++i) {
+        const int64_t a = c->n_nodes[c->bin_fibers[hb][i]];
+        // move a to b
+        const int64_t mv = std::max(top - a, load[b] + a);
+        if (mv < best) { best = mv; bb = b; bi = i; bj = -1; }
+        for (int j = 0; j < (int)c->bin_fibers[b].size(); ++j) {
+          const int64_t d = a - c->n_nodes[c->bin_fibers[b][j]];
+          if (d <= 0) continue;
+          const int64_t sw = std::max(top - d, load[b] + d);
+          if (sw < best) { best = sw; bb = b; bi = i; bj = j; }
+        }
+      }
+    }
+    if (bb < 0) break;
+    const int32_t fa = c->bin_fibers[hb][bi];
+    if (bj < 0) {
+      c->bin_fibers[hb].erase(c->bin_fibers[hb].begin() + bi);
+      c->bin_fibers[bb].push_back(fa);
+      load[hb] -= c->n_nodes[fa];
+      load[bb] += c->n_nodes[fa];
+    } else {
+      const int32_t fb = c->bin_fibers[bb][bj];
+      c->bin_fibers[hb][bi] = fb;
+      c->bin_fibers[bb][bj] = fa;
+      const int64_t d = c->n_nodes[fa] - c->n_nodes[fb];
+      load[hb] -= d;
+      load[bb] += d;
+    }
   }
 }
 
@@ -318,7 +361,6 @@ KArgs base_args(const fib_ctx* c) {
   a.v_th = (float)c->p.v_th;
   a.dt = (float)c->p.dt_split;
   for (int k = 0; k < c->S; ++k) a.rest[k] = (float)c->rest[k];
-  a.vref = (float)c->rest[0];
   return a;
 }
 
@@ -369,6 +411,40 @@ int fib_check_params(const fib_params* p) {
   if (p->groups < 0) return fail(FIB_EINVAL, "groups must be >= 0");
   if (ceil_steps(p->dt_split * 0.5, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
     return fail(FIB_EINVAL, "more than 2^20 substeps per split step");
+  return FIB_OK;
+}
+
+int fib_plan_preview(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes,
+                     int32_t compute_units, int32_t* groups, int32_t* threads,
+                     int32_t* nodes_per_thread, int32_t* pcr_levels, int64_t* max_load) {
+  int rc = fib_check_params(p);
+  if (rc) return rc;
+  if (n_fibers < 0 || (n_fibers > 0 && !n_nodes) || compute_units < 1)
+    return fail(FIB_EINVAL, "bad fiber list or compute-unit count");
+  fib_ctx c;
+  c.p = *p;
+  c.S = n_states_of(p->model);
+  c.n_fibers = n_fibers;
+  c.n_nodes.assign(n_nodes, n_nodes + n_fibers);
+  c.offsets.assign(n_fibers + 1, 0);
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    if (n_nodes[f] < 1) return fail(FIB_EINVAL, "fiber %d has %d nodes", f, n_nodes[f]);
+    c.offsets[f + 1] = c.offsets[f] + n_nodes[f];
+  }
+  c.n_total = c.offsets[n_fibers];
+  c.cu_count = compute_units;
+  if ((rc = make_plan(&c))) return rc;
+  int64_t mx = 0;
+  for (auto& b : c.bin_fibers) {
+    int64_t s = 0;
+    for (int32_t f : b) s += c.n_nodes[f];
+    mx = std::max(mx, s);
+  }
+  if (groups) *groups = c.groups;
+  if (threads) *threads = c.threads;
+  if (nodes_per_thread) *nodes_per_thread = c.K;
+  if (pcr_levels) *pcr_levels = c.levels;
+  if (max_load) *max_load = mx;
   return FIB_OK;
 }
 
@@ -466,11 +542,12 @@ int fib_plan_info(const fib_t* c, int32_t* groups, int32_t* threads, int32_t* no
   return FIB_OK;
 }
 
-int fib_state_device(fib_t* c, float** state, double* v_ref) {
+int fib_state_device(fib_t* c, float** state, double* ref) {
   if (int rc = check_ctx(c)) return rc;
   if (!state) return fail(FIB_EINVAL, "null output pointer");
   *state = c->d_state;
-  if (v_ref) *v_ref = (double)(float)c->rest[0];
+  if (ref)
+    for (int k = 0; k < c->S; ++k) ref[k] = (double)(float)c->rest[k];
   return FIB_OK;
 }
 
@@ -490,8 +567,7 @@ int fib_set_state(fib_t* c, const double* y, int64_t n_values) {
   if (n_values == 0) { c->state_ready = true; return FIB_OK; }
   if (!y) return fail(FIB_EINVAL, "null state");
   std::vector<float> f(n_values);
-  const double vref = (double)(float)c->rest[0];
-  for (int64_t i = 0; i < n_values; ++i) f[i] = (float)(i < c->n_total ? y[i] - vref : y[i]);
+  for (int64_t i = 0; i < n_values; ++i) f[i] = (float)(y[i] - (double)(float)c->rest[i / std::max<int64_t>(c->n_total, 1)]);
   HIP_TRY(hipMemcpyAsync(c->d_state, f.data(), sizeof(float) * n_values, hipMemcpyHostToDevice,
                          c->stream));
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
@@ -513,9 +589,8 @@ int fib_get_state(fib_t* c, double* y, int64_t n_values) {
                          c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   bool bad = false;
-  const double vref = (double)(float)c->rest[0];
   for (int64_t i = 0; i < n_values; ++i) {
-    y[i] = i < c->n_total ? (double)f[i] + vref : (double)f[i];
+    y[i] = (double)f[i] + (double)(float)c->rest[i / c->n_total];
     bad |= !std::isfinite(f[i]);
   }
   if (bad) return fail(FIB_ENONFINITE, "the state holds non-finite values");

@@ -54,8 +54,7 @@ struct KArgs {
   float r;                  // c * dt_cn / h^2 with c = sigma / (Am Cm)
   float inv_cm;             // 1 / Cm
   float v_th;               // activation threshold (mV)
-  float vref;               // offset of the in-register voltage (mV), the resting potential
-  float rest[MAX_STATES];   // resting state, used for padding slots
+  float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
 // Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.

@@ -1,11 +1,14 @@
 // HIP kernels of the fiber monodomain solver (gfx950).
 //
 // Data layout in HBM: structure of arrays, state k of global node i at
-// state[k * n_total + i], fibers concatenated in the caller's order.  Row 0
-// holds the membrane voltage as its offset u = V_m - vref from the resting
-// potential vref: increments that are small next to 75 mV but not next to
-// |u| keep their bits while the membrane is near rest, where a propagating
-// front's foot lives, and the state round-trips through checkpoints exactly.
+// state[k * n_total + i], fibers concatenated in the caller's order.  Row k
+// holds state k as its offset y_k - rest_k from the resting state: a node
+// near rest (the foot of a propagating front, the quiet part of a fiber)
+// takes increments far below the FP32 resolution of -75 mV or of a gate at
+// 0.6, and they survive only when added to values near zero.  Without the
+// offsets, FP32 rounding of the gates shifts the arrival of a front by about
+// a split step over 20 ms; with them the FP32 path tracks the FP64 method to
+// a few 1e-7 ms.  The offsets also make checkpoints round-trip exactly.
 //
 // Work decomposition of the fused and diffusion kernels: fibers are packed
 // into "bins" (one workgroup each) of at most threads * K nodes; thread t of
@@ -255,15 +258,13 @@ __global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
       y[q].n = A.state[3 * nt + g];
       if (!isinf(A.t_act[g])) done |= 1u << q;
     } else {
-      y[q].V = A.rest[0] - A.vref;
-      y[q].m = A.rest[1];
-      y[q].h = A.rest[2];
-      y[q].n = A.rest[3];
+      y[q] = hh::State{0.0f, 0.0f, 0.0f, 0.0f};
       done |= 1u << q;
     }
   }
   CNConst<K> cc;
   cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
+  const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
 
   const uint32_t all = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
   const int32_t n_end = A.step0 + A.n_steps;
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
     }
     for (int s = 0; s < A.n_sub; ++s) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, A.vref);
+      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, ref);
     }
     {
       float V[K];
@@ -288,13 +289,13 @@ __global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
     }
     for (int s = 0; s < A.n_sub; ++s) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, A.vref);
+      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, ref);
     }
     // activation times: first upward crossing of v_th between step ends
-    // (the offsets u cross v_th - vref)
+    // (the voltage offsets cross v_th - rest_V)
     if (done != all) {
       const float t0 = (float)n * A.dt;
-      const float uth = A.v_th - A.vref;
+      const float uth = A.v_th - A.rest[0];
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         if (!((done >> q) & 1u) && v0[q] < uth && y[q].V >= uth) {
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
 #pragma unroll
       for (int q = 0; q < K; ++q) {
         const int32_t g = A.slot_gidx[base + q];
-        if (g >= 0) A.samples[row * nt + g] = y[q].V + A.vref;
+        if (g >= 0) A.samples[row * nt + g] = y[q].V + A.rest[0];
       }
     }
   }
@@ -346,7 +347,7 @@ __global__ __launch_bounds__(1024) void k_diffusion(KArgs A) {
   for (int q = 0; q < K; ++q) {
     info[q] = A.slot_info[base + q];
     gi[q] = A.slot_gidx[base + q];
-    V[q] = gi[q] >= 0 ? A.state[gi[q]] : A.rest[0] - A.vref;
+    V[q] = gi[q] >= 0 ? A.state[gi[q]] : 0.0f;
   }
   CNConst<K> cc;
   cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
@@ -366,7 +367,8 @@ __global__ __launch_bounds__(256) void k_reaction_hh(KArgs A, int32_t step) {
   const int64_t nt = A.n_total;
   hh::State y{A.state[i], A.state[nt + i], A.state[2 * nt + i], A.state[3 * nt + i]};
   const float I = stim_current((uint32_t)A.node_stim[i], A.stim, step);
-  for (int s = 0; s < A.n_sub; ++s) hh::heun(y, I, A.tau, A.inv_cm, A.vref);
+  const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
+  for (int s = 0; s < A.n_sub; ++s) hh::heun(y, I, A.tau, A.inv_cm, ref);
   A.state[i] = y.V;
   A.state[nt + i] = y.m;
   A.state[2 * nt + i] = y.h;
@@ -380,12 +382,12 @@ __global__ __launch_bounds__(256) void k_observe(KArgs A, int32_t step) {
   if (i >= A.n_total) return;
   const float v1 = A.state[i];
   const float v0 = A.v_prev[i];
-  const float uth = A.v_th - A.vref;
+  const float uth = A.v_th - A.rest[0];
   if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
     A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
   if (A.sample_every > 0 && ((int64_t)step + 1) % A.sample_every == 0) {
     const int64_t row = ((int64_t)step + 1) / A.sample_every - 1 - A.sample_row0;
-    A.samples[row * A.n_total + i] = v1 + A.vref;
+    A.samples[row * A.n_total + i] = v1 + A.rest[0];
   }
   A.v_prev[i] = v1;
   if (!isfinite(v1)) atomicOr(A.flag, 1);
@@ -401,9 +403,8 @@ __global__ __launch_bounds__(256) void k_init(KArgs A, int S, const float* __res
   if (i >= A.n_total) return;
   const int64_t nt = A.n_total;
   for (int k = 0; k < S; ++k) {
-    // rest_k (1 + rel) (+ noise for V_m), the voltage as its offset from vref
-    const float base = (k == 0) ? A.rest[0] - A.vref : A.rest[k];
-    float v = rel_noise ? fmaf(A.rest[k], rel_noise[k * nt + i], base) : base;
+    // rest_k (1 + rel) (+ noise for V_m), stored as the offset from rest_k
+    float v = rel_noise ? A.rest[k] * rel_noise[k * nt + i] : 0.0f;
     if (k == 0 && vm_noise) v += vm_noise[i];
     A.state[k * nt + i] = v;
   }

@@ -56,15 +56,24 @@ __device__ __forceinline__ float x_over_expm1(float x, float e) {
   return fabsf(x) < 0.1f ? s : q;
 }
 
-// The voltage is carried as its offset u = V - vref from the resting
-// potential vref.
+// Every state is carried as its offset from the resting state (ref): the
+// increments of a node near rest are tiny next to the states themselves
+// (V ~ -75 mV, h ~ 0.6), and FP32 keeps them only when they are added to
+// values near zero.
 struct State {
-  float V, m, h, n;  // V holds u = V_m - vref
+  float V, m, h, n;  // y - ref
+};
+
+struct Ref {
+  float V, m, h, n;  // resting state
 };
 
 // Right-hand side G(y) of the membrane model with stimulus current I.
-__device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, float vref) {
-  const float V = y.V + vref;
+__device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, const Ref& ref) {
+  const float V = y.V + ref.V;
+  const float m = y.m + ref.m;
+  const float h = y.h + ref.h;
+  const float n = y.n + ref.n;
   const float xm = fmaf(V, -0.1f, -5.0f);   // (25 - v)/10 = -(V + 50)/10
   const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
   const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
@@ -76,9 +85,9 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, floa
   const float bh = rcp(ex2(fmaf(V, kBh.k1, kBh.k0)) + 1.0f);
   const float bn = ex2(fmaf(V, kBn.k1, kBn.k0));
 
-  const float m2 = y.m * y.m;
-  const float m3h = m2 * (y.m * y.h);
-  const float n2 = y.n * y.n;
+  const float m2 = m * m;
+  const float m3h = m2 * (m * h);
+  const float n2 = n * n;
   const float n4 = n2 * n2;
   const float ina = m3h * (V - 40.0f);
   const float ik = n4 * (V + 87.0f);
@@ -87,22 +96,22 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, floa
 
   State d;
   d.V = (I - iion) * inv_cm;
-  d.m = fmaf(-(am + bm), y.m, am);
-  d.h = fmaf(-(ah + bh), y.h, ah);
-  d.n = fmaf(-(an + bn), y.n, an);
+  d.m = fmaf(-(am + bm), m, am);
+  d.h = fmaf(-(ah + bh), h, ah);
+  d.n = fmaf(-(an + bn), n, an);
   return d;
 }
 
 // One Heun step of width tau (eq. heun):
 //   y+ = y + tau/2 (G(y) + G(y + tau G(y))).
-__device__ __forceinline__ void heun(State& y, float I, float tau, float inv_cm, float vref) {
-  const State k1 = rhs(y, I, inv_cm, vref);
+__device__ __forceinline__ void heun(State& y, float I, float tau, float inv_cm, const Ref& ref) {
+  const State k1 = rhs(y, I, inv_cm, ref);
   State yt;
   yt.V = fmaf(tau, k1.V, y.V);
   yt.m = fmaf(tau, k1.m, y.m);
   yt.h = fmaf(tau, k1.h, y.h);
   yt.n = fmaf(tau, k1.n, y.n);
-  const State k2 = rhs(yt, I, inv_cm, vref);
+  const State k2 = rhs(yt, I, inv_cm, ref);
   const float ht = 0.5f * tau;
   y.V = fmaf(ht, k1.V + k2.V, y.V);
   y.m = fmaf(ht, k1.m + k2.m, y.m);

@@ -38,6 +38,7 @@ EXPORTS = (
     "fib_last_error", "fib_n_total", "fib_init_state", "fib_set_state", "fib_get_state",
     "fib_state_device", "fib_set_stimulus", "fib_step_reaction", "fib_step_diffusion",
     "fib_run", "fib_get_tact", "fib_reset_observables", "fib_sync", "fib_plan_info",
+    "fib_plan_preview",
 )
 
 
@@ -97,6 +98,8 @@ def lib():
             "fib_reset_observables": ([_vp], C.c_int),
             "fib_sync": ([_vp], C.c_int),
             "fib_plan_info": ([_vp, _i32p, _i32p, _i32p, _i32p], C.c_int),
+            "fib_plan_preview": ([C.POINTER(fib_params), C.c_int32, _i32p, C.c_int32, _i32p, _i32p,
+                                  _i32p, _i32p, C.POINTER(C.c_int64)], C.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -182,12 +185,12 @@ def fib_get_state(ctx, n_states: int) -> np.ndarray:
     return y
 
 
-def fib_state_device(ctx):
-    """(device pointer of the FP32 state, v_ref); row 0 holds V_m - v_ref."""
+def fib_state_device(ctx, n_states: int):
+    """(device pointer of the FP32 state, ref); row k holds y_k - ref[k]."""
     p = _vp()
-    v = C.c_double()
-    _check(lib().fib_state_device(_vp(ctx), C.byref(p), C.byref(v)))
-    return p.value, v.value
+    ref = np.zeros(n_states)
+    _check(lib().fib_state_device(_vp(ctx), C.byref(p), ref.ctypes.data_as(_dp)))
+    return p.value, ref
 
 
 def fib_set_stimulus(ctx, stims) -> None:
@@ -228,6 +231,17 @@ def fib_plan_info(ctx):
     g, t, k, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
     _check(lib().fib_plan_info(_vp(ctx), C.byref(g), C.byref(t), C.byref(k), C.byref(l)))
     return dict(groups=g.value, threads=t.value, nodes_per_thread=k.value, pcr_levels=l.value)
+
+
+def fib_plan_preview(params: fib_params, n_nodes, compute_units: int = 256):
+    nn = np.ascontiguousarray(n_nodes, dtype=np.int32)
+    g, t, k, l = C.c_int32(), C.c_int32(), C.c_int32(), C.c_int32()
+    mx = C.c_int64()
+    _check(lib().fib_plan_preview(C.byref(params), len(nn), nn.ctypes.data_as(_i32p),
+                                  int(compute_units), C.byref(g), C.byref(t), C.byref(k),
+                                  C.byref(l), C.byref(mx)))
+    return dict(groups=g.value, threads=t.value, nodes_per_thread=k.value, pcr_levels=l.value,
+                max_load=mx.value)
 
 
 # ---- convenience wrapper (still marshalling only) ---------------------------------
@@ -273,16 +287,16 @@ class Solver:
         return fib_get_state(self.ctx, self.S)
 
     def state_tensor(self):
-        """Zero-copy torch view of the FP32 device state [S, n_total] and
-        v_ref; row 0 of the view holds V_m - v_ref."""
-        ptr, vref = fib_state_device(self.ctx)
+        """Zero-copy torch view of the FP32 device state [S, n_total] and the
+        reference state; row k of the view holds y_k - ref[k]."""
+        ptr, ref = fib_state_device(self.ctx, self.S)
         n = self.S * self.n_total
         t = self.torch
         # wrap through the CUDA array interface without copying
         class _Arr:
             __cuda_array_interface__ = {"shape": (n,), "typestr": "<f4", "data": (ptr, False),
                                         "version": 2}
-        return t.as_tensor(_Arr(), device="cuda").view(self.S, self.n_total), vref
+        return t.as_tensor(_Arr(), device="cuda").view(self.S, self.n_total), ref
 
     def set_stimulus(self, stims):
         fib_set_stimulus(self.ctx, stims)

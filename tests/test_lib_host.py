@@ -66,3 +66,20 @@ def test_create_rejects_bad_fibers_without_touching_the_gpu():
                             F.C.byref(out))
     assert rc == F.FIB_EINVAL and out.value is None
     assert "fiber 1" in F.fib_last_error()
+
+
+def test_plan_preview_packs_fibers_tightly():
+    from paper_2107_07104_amd import inputs as I
+    w = I.batched_hh()
+    plan = F.fib_plan_preview(F.make_params(), w.n_nodes, 256)
+    avg = w.n_total / 256
+    assert plan["groups"] == 256
+    assert plan["max_load"] <= avg + 10  # near-perfect multiway partition
+    assert plan["threads"] * plan["nodes_per_thread"] >= plan["max_load"]
+    assert plan["nodes_per_thread"] == 7 and plan["threads"] == 1024
+    # one fiber: one bin, all threads of the bin busy
+    one = F.fib_plan_preview(F.make_params(), [1000], 256)
+    assert one["groups"] == 1 and one["threads"] * one["nodes_per_thread"] >= 1000
+    # a fiber too long for a workgroup
+    with pytest.raises(F.FibError):
+        F.fib_plan_preview(F.make_params(), [9000], 256)
