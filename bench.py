@@ -60,7 +60,38 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fibers", type=int, default=0,
                     help="fibers in the oracle sample (default: 2 per host thread)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB before the timed "
+                         "region, as the known-size reference for HBM byte counters")
     return ap.parse_args()
+
+
+KERNEL_SOURCES = ("paper_2107_07104_amd/csrc/fib_kernels.hip",
+                  "paper_2107_07104_amd/csrc/hh_model.h",
+                  "paper_2107_07104_amd/csrc/fib_internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_run_hh.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    counter runs, or None if the kernel sources changed since they were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    return rec.get("hbm_bytes_per_launch")
 
 
 def cpu_baseline(w, gpu_samples, gpu_tact, fibers):
@@ -120,6 +151,16 @@ def main():
         if ev is not None:
             ev[1].record(stream)
 
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        print(f"# calibration copy of {args.copy_calibration_mib} MiB done", file=sys.stderr,
+              flush=True)
+
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -148,7 +189,7 @@ def main():
         "peak": VALU_PEAK_SLOTS / 1e12,
         "unit": "Tslot/s (FP32 VALU issue slots)",
         "frac": achieved / VALU_PEAK_SLOTS,
-        "traffic": None,
+        "traffic": measured_traffic(),
         "kernel": "k_run_hh",
         "kernel_ms_per_launch": kernel_ms,
         "slots_per_node_step": SLOTS_PER_NODE_STEP,
