@@ -159,14 +159,21 @@ int or_hh_rest(double y[4]) {
 /* Model dispatch                                                            */
 /* ------------------------------------------------------------------------ */
 
+/* ST57, the 57-state Shorten-type stand-in (st57_oracle.c) */
+int or_st57_n_states(void);
+void or_st57_rhs(double Cm, const double* y, double I, double* dydt);
+
 int or_n_states(int model) {
   if (model == 0) return 4;
+  if (model == 1) return or_st57_n_states();
   return -1;
 }
 
 static void model_rhs(int model, double Cm, const double* y, double I, double* dydt) {
-  (void)model;
-  or_hh_rhs(Cm, y, I, dydt);
+  if (model == 1)
+    or_st57_rhs(Cm, y, I, dydt);
+  else
+    or_hh_rhs(Cm, y, I, dydt);
 }
 
 /* ------------------------------------------------------------------------ */

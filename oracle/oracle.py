@@ -19,7 +19,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SRC = os.path.join(_HERE, "fib_oracle.c")
+_SRCS = [os.path.join(_HERE, "fib_oracle.c"), os.path.join(_HERE, "st57_oracle.c")]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MODEL_HH = 0
@@ -33,7 +33,7 @@ def build(force: bool = True) -> str:
     if force or not os.path.exists(_LIB_PATH):
         cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-Wall",
-               "-o", _LIB_PATH, _SRC, "-lm"]
+               "-o", _LIB_PATH, *_SRCS, "-lm"]
         subprocess.run(cmd, check=True)
     return _LIB_PATH
 
@@ -68,6 +68,9 @@ def lib():
         L.or_hh_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
         L.or_hh_rest.argtypes = [_dp]
         L.or_n_states.argtypes = [C.c_int]
+        L.or_st57_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
+        L.or_st57_invariants.argtypes = [_dp, _dp]
+        L.or_st57_rest.argtypes = [_dp, C.POINTER(C.c_int)]
         L.or_n_substeps.argtypes = [C.c_double, C.c_double]
         L.or_n_substeps.restype = C.c_int64
         L.or_thomas.argtypes = [C.c_int64, _dp, _dp, _dp, _dp, _dp, _dp]
@@ -135,11 +138,29 @@ def rest_state(model: int = MODEL_HH) -> np.ndarray:
     y = np.zeros(n_states(model))
     if model == MODEL_HH:
         rc = lib().or_hh_rest(_d(y))
+    elif model == MODEL_ST57:
+        it = C.c_int(0)
+        rc = lib().or_st57_rest(_d(y), C.byref(it))
     else:
         raise ValueError("unknown model")
     if rc != 0:
         raise RuntimeError("rest state search failed")
     return y
+
+
+def st57_rhs(y, I_stim: float = 0.0, Cm: float = 1.0) -> np.ndarray:
+    y = _f64(y)
+    out = np.zeros(57)
+    lib().or_st57_rhs(float(Cm), _d(y), float(I_stim), _d(out))
+    return out
+
+
+def st57_invariants(y) -> np.ndarray:
+    """(sum P, sum Q, sum R, sum X, total Ca, total Mg) of one ST57 state."""
+    y = _f64(y)
+    out = np.zeros(6)
+    lib().or_st57_invariants(_d(y), _d(out))
+    return out
 
 
 def n_substeps(span: float, dt: float) -> int:

@@ -1,0 +1,84 @@
+"""Pins of the oracle's ST57 model (the 57-state Shorten-type stand-in).
+
+The real Shorten model is not available, so these pins check the oracle
+against properties its written specification fixes:
+  * the resting state is a fixed point with the seven prescribed conserved
+    sums (four probability chains sum to 1, total Ca 2200 uM, total Mg
+    1500 uM);
+  * Heun steps preserve every linear invariant of the model to rounding
+    (a dropped or mis-signed flux term in any block breaks one of them);
+  * with both membrane voltages frozen (huge capacitance) the voltage-
+    sensor chain relaxes to its closed-form Boltzmann distribution
+    P_{i+1}/P_i = k_f,i/k_b,i = exp(2 (V_t - V_i) / 25);
+  * the model is second order in time under Strang splitting, fires and
+    propagates an action potential of the Hodgkin-Huxley shape, and keeps
+    concentrations and probabilities non-negative.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+
+@pytest.fixture(scope="module")
+def rest():
+    return O.rest_state(O.MODEL_ST57)
+
+
+def test_rest_is_a_fixed_point_with_prescribed_sums(rest):
+    G = O.st57_rhs(rest)
+    scale = np.maximum(np.abs(rest), 1.0)
+    assert np.max(np.abs(G) / scale) < 1e-10
+    inv = O.st57_invariants(rest)
+    np.testing.assert_allclose(inv, [1, 1, 1, 1, 2200, 1500], rtol=1e-13)
+    # membrane near the Hodgkin-Huxley resting potential, gates in [0, 1]
+    assert -80 < rest[0] < -70 and -80 < rest[4] < -70
+    assert np.all(rest[1:4] > 0) and np.all(rest[1:4] < 1)
+    assert np.all(rest[8:] >= 0)
+
+
+def test_invariants_are_preserved_by_heun_steps(rest):
+    rng = np.random.default_rng(1)
+    y = rest[:, None] * (1 + 0.05 * rng.standard_normal((57, 6)))
+    y[0] += np.array([0, 10, 30, 60, 90, 110])  # from rest to strongly depolarized
+    inv0 = np.array([O.st57_invariants(y[:, i]) for i in range(6)])
+    cfg = O.Config(model=O.MODEL_ST57, dt_0D=1e-4)
+    I = np.array([0, 0, 500.0, 0, 0, 1200.0])
+    for _ in range(50):
+        y = O.reaction(cfg, y, 5e-4, I)
+    inv1 = np.array([O.st57_invariants(y[:, i]) for i in range(6)])
+    np.testing.assert_allclose(inv1, inv0, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("Vt", [-90.0, -60.0, -30.0, 0.0, 25.0])
+def test_sensor_chain_reaches_boltzmann_distribution(rest, Vt):
+    y = rest.copy()
+    y[4] = Vt
+    y[8:18] = 0.1
+    cfg = O.Config(model=O.MODEL_ST57, Cm=1e300, dt_0D=2e-3)
+    yy = y[:, None]
+    for _ in range(60):
+        yy = O.reaction(cfg, yy, 1.0)  # 60 ms with frozen V and V_t
+    P = yy[8:18, 0]
+    Vi = -70.0 + 7.5 * np.arange(9)
+    w = np.concatenate([[1.0], np.cumprod(np.exp(2 * (Vt - Vi) / 25.0))])
+    np.testing.assert_allclose(P, w / w.sum(), rtol=1e-6, atol=1e-9)
+
+
+def test_time_order_and_action_potential(rest):
+    n = [120]
+    y0 = np.tile(rest[:, None], (1, 120))
+    stims = [dict(fiber=0, node=60, half_width=1, step_on=0, n_steps=200, period=0, amp=1200.0)]
+    cfg = O.Config(model=O.MODEL_ST57, dt_0D=1e-4, dt_1D=5e-4, dt_split=5e-4)
+    y, s, ta = O.run(cfg, n, y0, stims, 3000, sample_every=100)
+    assert 15.0 < np.nanmax(s) < 45.0           # HH-shaped upstroke
+    assert np.all(np.isfinite(ta[45:76]))       # propagated over +-15 nodes
+    assert np.all(y[8:55] >= -1e-12)            # probabilities, concentrations
+    # second order in time, continuing from the propagating state
+    def solve(dt):
+        c = O.Config(model=O.MODEL_ST57, dt_0D=dt / 2, dt_1D=dt, dt_split=dt)
+        return O.run(c, n, y, [], int(round(0.2 / dt)))[0]
+    ref = solve(0.2 / 3200)
+    errs = np.array([np.max(np.abs(solve(dt)[0] - ref[0])) for dt in (2e-3, 1e-3, 5e-4)])
+    order = np.log2(errs[:-1] / errs[1:])
+    assert np.all(np.abs(order - 2.0) < 0.2), order
