@@ -18,6 +18,7 @@
 
 #include "../../include/fib.h"
 #include "fib_internal.h"
+#include "st57_model.h"
 
 using fib::KArgs;
 
@@ -41,7 +42,11 @@ int fail(int code, const char* fmt, ...) {
     if (e_ != hipSuccess) return fail(FIB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
-int n_states_of(int model) { return model == FIB_MODEL_HH ? 4 : -1; }
+int n_states_of(int model) {
+  if (model == FIB_MODEL_HH) return 4;
+  if (model == FIB_MODEL_ST57) return fib::st57::S;
+  return -1;
+}
 
 // ---------------------------------------------------------------------------
 // Hodgkin-Huxley resting state on the host (FP64)
@@ -85,6 +90,123 @@ int hh_rest(double* y) {
   y[2] = g[1];
   y[3] = g[2];
   return FIB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// ST57 resting state on the host (FP64): Newton's method on G(y) = 0 where
+// one equation of each conserving block is replaced by its conserved sum
+// (four probability chains sum to 1, total Ca 2200 uM, total Mg 1500 uM),
+// finite-difference Jacobian, LU with partial pivoting, step halving.
+// ---------------------------------------------------------------------------
+
+constexpr int kS57 = fib::st57::S;
+
+void st57_residual(const std::vector<double>& y, std::vector<double>& F) {
+  double u[kS57], d[kS57], zero[kS57];
+  for (int k = 0; k < kS57; ++k) {
+    u[k] = y[k];
+    zero[k] = 0.0;
+  }
+  fib::st57::rhs<double>(u, zero, 0.0, 1.0, d);
+  for (int k = 0; k < kS57; ++k) F[k] = d[k];
+  auto sum = [&](int a, int b) {
+    double s = 0.0;
+    for (int i = a; i <= b; ++i) s += y[i];
+    return s;
+  };
+  F[8] = sum(8, 17) - 1.0;
+  F[35] = sum(35, 38) - 1.0;
+  F[39] = sum(39, 46) - 1.0;
+  F[47] = sum(47, 54) - 1.0;
+  F[21] = y[18] + y[21] + y[22] + y[24] + 0.1 * (y[19] + y[27]) + 0.01 * (y[20] + y[28]) - 2200.0;
+  F[23] = y[26] + y[23] + y[25] - 1500.0;
+}
+
+int lu_solve(std::vector<double>& A, std::vector<double>& b, int n) {
+  for (int k = 0; k < n; ++k) {
+    int p = k;
+    for (int i = k + 1; i < n; ++i)
+      if (std::fabs(A[(size_t)i * n + k]) > std::fabs(A[(size_t)p * n + k])) p = i;
+    if (A[(size_t)p * n + k] == 0.0) return -1;
+    if (p != k) {
+      for (int j = 0; j < n; ++j) std::swap(A[(size_t)k * n + j], A[(size_t)p * n + j]);
+      std::swap(b[k], b[p]);
+    }
+    for (int i = k + 1; i < n; ++i) {
+      const double f = A[(size_t)i * n + k] / A[(size_t)k * n + k];
+      A[(size_t)i * n + k] = 0.0;
+      for (int j = k + 1; j < n; ++j) A[(size_t)i * n + j] -= f * A[(size_t)k * n + j];
+      b[i] -= f * b[k];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    double s = b[i];
+    for (int j = i + 1; j < n; ++j) s -= A[(size_t)i * n + j] * b[j];
+    b[i] = s / A[(size_t)i * n + i];
+  }
+  return 0;
+}
+
+int st57_rest(double* out) {
+  std::vector<double> y(kS57, 0.0), F(kS57), Fp(kS57), yp(kS57), J((size_t)kS57 * kS57),
+      dx(kS57);
+  // start: membranes at -75 mV with Hodgkin-Huxley resting gates, every
+  // probability chain uniform, resting free Ca 0.05 uM, SR Ca 1000 uM with
+  // buffers half loaded, ions at their targets
+  const double hh0[4] = {-75.0, 0.05, 0.6, 0.32};
+  for (int k = 0; k < 4; ++k) y[k] = y[4 + k] = hh0[k];
+  for (int i = 8; i <= 17; ++i) y[i] = 0.1;
+  y[18] = 0.05;
+  y[19] = y[20] = 1000.0;
+  y[21] = 5.0;
+  y[22] = 500.0;
+  y[23] = 500.0;
+  y[24] = 2.0;
+  y[25] = 500.0;
+  y[26] = 500.0;
+  y[27] = y[28] = 12000.0;
+  y[29] = 10.0;
+  y[30] = 140.0;
+  y[31] = 5.0;
+  y[32] = 140.0;
+  y[33] = 5.0;
+  y[34] = 128.0;
+  for (int i = 35; i <= 38; ++i) y[i] = 0.25;
+  for (int i = 39; i <= 54; ++i) y[i] = 0.125;
+  y[55] = 1.1;
+  for (int it = 0; it < 300; ++it) {
+    st57_residual(y, F);
+    double nrm = 0.0;
+    for (double f : F) nrm = std::max(nrm, std::fabs(f));
+    if (nrm < 1e-11) {
+      for (int k = 0; k < kS57; ++k) out[k] = y[k];
+      return FIB_OK;
+    }
+    for (int j = 0; j < kS57; ++j) {
+      yp = y;
+      const double e = 1e-7 * std::max(1.0, std::fabs(y[j]));
+      yp[j] += e;
+      st57_residual(yp, Fp);
+      for (int i = 0; i < kS57; ++i) J[(size_t)i * kS57 + j] = (Fp[i] - F[i]) / e;
+    }
+    for (int i = 0; i < kS57; ++i) dx[i] = -F[i];
+    if (lu_solve(J, dx, kS57)) return fail(FIB_EINVAL, "ST57 resting state: singular Jacobian");
+    double lam = 1.0;
+    for (int k = 0; k < 50; ++k, lam *= 0.5) {
+      bool ok = true;
+      for (int i = 0; i < kS57; ++i) {
+        yp[i] = y[i] + lam * dx[i];
+        if (i >= 8 && i <= 54 && yp[i] < 0.0) ok = false;
+      }
+      if (!ok) continue;
+      st57_residual(yp, Fp);
+      double np = 0.0;
+      for (double f : Fp) np = std::max(np, std::fabs(f));
+      if (np < nrm) break;
+    }
+    y = yp;
+  }
+  return fail(FIB_EINVAL, "ST57 resting state: Newton did not converge");
 }
 
 int64_t ceil_steps(double span, double dt) {
@@ -451,6 +573,7 @@ int fib_plan_preview(const fib_params* p, int32_t n_fibers, const int32_t* n_nod
 int fib_rest_state(const fib_params* p, double* y_out) {
   if (!p || !y_out) return fail(FIB_EINVAL, "null argument");
   if (p->model == FIB_MODEL_HH) return hh_rest(y_out);
+  if (p->model == FIB_MODEL_ST57) return st57_rest(y_out);
   return fail(FIB_EINVAL, "unknown model %d", p->model);
 }
 
@@ -655,7 +778,7 @@ int fib_step_reaction(fib_t* c, int64_t step, double span) {
   if (ns > (1 << 20)) return fail(FIB_EINVAL, "more than 2^20 substeps");
   a.n_sub = (int32_t)ns;
   a.tau = (float)(span / (double)ns);
-  HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)step, a, c->stream));
+  HIP_TRY(fib::launch_react(c->p.model, (int32_t)step, 0, 1, a, c->stream));
   return FIB_OK;
 }
 
@@ -711,20 +834,23 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
                      (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH);
   if (fused) {
+    if (c->p.model != FIB_MODEL_HH)
+      return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
     HIP_TRY(fib::launch_run_fused(c->p.model, c->K, c->groups, c->threads,
                                   fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
     return FIB_OK;
   }
-  // SPLIT: one launch per phase
+  // SPLIT: per split step one diffusion launch and one reaction launch that
+  // finishes step n (second half, observables) and starts step n+1 (first half)
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
                          hipMemcpyDeviceToDevice, c->stream));
-  KArgs half = a;
-  for (int64_t n = step0; n < step0 + n_steps; ++n) {
-    HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)n, half, c->stream));
-    HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads,
-                                  fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
-    HIP_TRY(fib::launch_reaction(c->p.model, (int32_t)n, half, c->stream));
-    HIP_TRY(fib::launch_observe((int32_t)n, a, c->stream));
+  const size_t lds = fib::lds_bytes_for(c->threads, c->levels);
+  const int64_t end = step0 + n_steps;
+  HIP_TRY(fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
+  for (int64_t n = step0; n < end; ++n) {
+    HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+    const int flags = 1 | 2 | (n + 1 < end ? 4 : 0);
+    HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
   }
   return FIB_OK;
 }

@@ -62,8 +62,11 @@ hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t ld
                             const KArgs& a, hipStream_t s);
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, const KArgs& a,
                             hipStream_t s);
-hipError_t launch_reaction(int model, int32_t step, const KArgs& a, hipStream_t s);
-hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s);
+// Reaction kernel with states in device memory; flags: 1 = reaction with the
+// stimulus of step_a, 2 = observables after step_a, 4 = reaction with the
+// stimulus of step_b (applied in that order).
+hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,
+                        hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);

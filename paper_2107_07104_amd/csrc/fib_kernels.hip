@@ -28,6 +28,7 @@
 // computed once per launch; a step only moves right-hand sides.
 #include "fib_internal.h"
 #include "hh_model.h"
+#include "st57_model.h"
 
 namespace fib {
 
@@ -358,39 +359,70 @@ __global__ __launch_bounds__(1024) void k_diffusion(KArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Reaction only (states in device memory), one node per thread
+// Reaction with states in device memory, one node per thread
 // ---------------------------------------------------------------------------
 
-__global__ __launch_bounds__(256) void k_reaction_hh(KArgs A, int32_t step) {
+struct ModelHH {
+  static constexpr int S = 4;
+  __device__ static void heun(float (&u)[S], const float* ref, float I, float tau, float inv_cm) {
+    hh::State y{u[0], u[1], u[2], u[3]};
+    const hh::Ref r{ref[0], ref[1], ref[2], ref[3]};
+    hh::heun(y, I, tau, inv_cm, r);
+    u[0] = y.V;
+    u[1] = y.m;
+    u[2] = y.h;
+    u[3] = y.n;
+  }
+};
+
+struct ModelST57 {
+  static constexpr int S = st57::S;
+  __device__ static void heun(float (&u)[S], const float* ref, float I, float tau, float inv_cm) {
+    st57::heun(u, ref, I, tau, inv_cm);
+  }
+};
+
+// flags bit 0: reaction with the stimulus of split step `step_a`;
+// bit 1: then the observables at the end of split step `step_a`
+//        (activation time from v_prev, samples, v_prev := V);
+// bit 2: then reaction with the stimulus of split step `step_b`.
+// The split schedule runs the second half of step n and the first half of
+// step n+1 in one launch, so the states cross HBM once per split step.
+constexpr int REACT_A = 1, REACT_OBSERVE = 2, REACT_B = 4;
+
+template <class M>
+__global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t step_b,
+                                               int flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n_total) return;
   const int64_t nt = A.n_total;
-  hh::State y{A.state[i], A.state[nt + i], A.state[2 * nt + i], A.state[3 * nt + i]};
-  const float I = stim_current((uint32_t)A.node_stim[i], A.stim, step);
-  const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
-  for (int s = 0; s < A.n_sub; ++s) hh::heun(y, I, A.tau, A.inv_cm, ref);
-  A.state[i] = y.V;
-  A.state[nt + i] = y.m;
-  A.state[2 * nt + i] = y.h;
-  A.state[3 * nt + i] = y.n;
-}
-
-// Observables after split step `step` for the SPLIT schedule: activation
-// times from v_prev and the current V_m, samples, then v_prev := V_m.
-__global__ __launch_bounds__(256) void k_observe(KArgs A, int32_t step) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n_total) return;
-  const float v1 = A.state[i];
-  const float v0 = A.v_prev[i];
-  const float uth = A.v_th - A.rest[0];
-  if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
-    A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
-  if (A.sample_every > 0 && ((int64_t)step + 1) % A.sample_every == 0) {
-    const int64_t row = ((int64_t)step + 1) / A.sample_every - 1 - A.sample_row0;
-    A.samples[row * A.n_total + i] = v1 + A.rest[0];
+  float u[M::S];
+#pragma unroll
+  for (int k = 0; k < M::S; ++k) u[k] = A.state[k * nt + i];
+  const uint32_t sid = (uint32_t)A.node_stim[i];
+  if (flags & REACT_A) {
+    const float I = stim_current(sid, A.stim, step_a);
+    for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
   }
-  A.v_prev[i] = v1;
-  if (!isfinite(v1)) atomicOr(A.flag, 1);
+  if (flags & REACT_OBSERVE) {
+    const float v1 = u[0];
+    const float v0 = A.v_prev[i];
+    const float uth = A.v_th - A.rest[0];
+    if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
+      A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step_a * A.dt);
+    if (A.sample_every > 0 && ((int64_t)step_a + 1) % A.sample_every == 0) {
+      const int64_t row = ((int64_t)step_a + 1) / A.sample_every - 1 - A.sample_row0;
+      A.samples[row * nt + i] = v1 + A.rest[0];
+    }
+    A.v_prev[i] = v1;
+    if (!isfinite(v1)) atomicOr(A.flag, 1);
+  }
+  if (flags & REACT_B) {
+    const float I = stim_current(sid, A.stim, step_b);
+    for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+  }
+#pragma unroll
+  for (int k = 0; k < M::S; ++k) A.state[k * nt + i] = u[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -469,22 +501,22 @@ hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KA
   }
 }
 
-hipError_t launch_reaction(int model, int32_t step, const KArgs& a, hipStream_t s) {
-  if (model != 0) return hipErrorInvalidValue;
+hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,
+                        hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_reaction_hh, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, step);
-  return hipGetLastError();
-}
-
-hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s) {
-  if (a.n_total == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_observe, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, step);
+  const dim3 grid(blocks_for(a.n_total, 256)), block(256);
+  if (model == 0)
+    hipLaunchKernelGGL(k_react<ModelHH>, grid, block, 0, s, a, step_a, step_b, flags);
+  else if (model == 1)
+    hipLaunchKernelGGL(k_react<ModelST57>, grid, block, 0, s, a, step_a, step_b, flags);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s) {
-  const int S = (model == 0) ? 4 : 0;
+  const int S = (model == 0) ? ModelHH::S : (model == 1) ? ModelST57::S : 0;
   if (S == 0) return hipErrorInvalidValue;
   if (a.n_total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, S, vm_noise,

@@ -146,6 +146,38 @@ def batched_hh(n_fibers: int = 1369, n_min: int = 1000, n_max: int = 1500,
         sample_every=int(round(0.1 / dt)), dt_0D=dt, dt_1D=dt, dt_split=dt)
 
 
+def st57_bundle(n_fibers: int = 400, n_nodes: int = 1481, t_end: float = 5.0,
+                dt_0D: float = 1e-4, dt_split: float = 5e-4, amp: float = AMP_SUPRA,
+                onset_max: float = 2.0, period_ms: float = 0.0) -> Workload:
+    """ST57 fibers of equal length: every state starts at rest times
+    (1 + 0.01 N(0, 1)) (seed 5); each fiber is stimulated for 0.1 ms on three
+    nodes around a node drawn from the central 10 % (seed 3) at a time drawn
+    from [0, onset_max] ms (seed 4), repeating every period_ms if > 0.
+    dt_0D = 1e-4 ms, dt_1D = dt_split = 5e-4 ms."""
+    S = 57
+    lengths = np.full(n_fibers, n_nodes, dtype=np.int32)
+    n_total = int(lengths.sum())
+    rel = _normal(SEED_REL_NOISE, S * n_total, 0.01).reshape(S, n_total)
+    g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE))
+    u_node = g_node.random(n_fibers)
+    g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME))
+    u_time = g_time.random(n_fibers)
+    pulse = int(round(0.1 / dt_split))
+    period = int(round(period_ms / dt_split)) if period_ms > 0 else 0
+    stims = []
+    lo, hi = int(np.floor(0.45 * n_nodes)), int(np.ceil(0.55 * n_nodes)) - 1
+    for f in range(n_fibers):
+        node = lo + min(int(u_node[f] * (hi - lo + 1)), hi - lo)
+        step_on = int(round(u_time[f] * onset_max / dt_split))
+        stims.append(dict(fiber=f, node=node, half_width=1, step_on=step_on, n_steps=pulse,
+                          period=period, amp=float(amp)))
+    return Workload(
+        name=f"st57_{n_fibers}x{n_nodes}", model=MODEL_ST57, n_nodes=lengths,
+        vm_noise=np.zeros(n_total), rel_noise=rel, stims=stims,
+        n_steps=int(round(t_end / dt_split)), sample_every=int(round(0.1 / dt_split)),
+        dt_0D=dt_0D, dt_1D=dt_split, dt_split=dt_split)
+
+
 def stim_array(stims: List[dict]) -> np.ndarray:
     """Stimulus table as a packed record array matching the C struct layout
     (int32 fiber, node, half_width, pad; int64 step_on, n_steps, period;

@@ -1,0 +1,94 @@
+"""GPU (HIP) path of the ST57 model against the FP64 oracle.
+
+Tolerances:
+  * reaction steps from perturbed states: the device carries every state as
+    an FP32 offset u = y - rest, so each of the 12 Heun substeps adds a few
+    roundings of |u| (2^-24 relative) plus the relative error of the
+    exp2/log2/reciprocal instructions (about 1e-6) times the increment:
+    |dy| <= 2e-6 max(|y0 - rest|, |rest|) + 1e-4 |y1 - y0| + 1e-9 per state;
+  * whole runs: max |V_gpu - V_oracle| <= 0.5 mV over all samples and the
+    final state, activation times within one split step;
+  * conserved sums: Heun conserves them exactly in exact arithmetic; in FP32
+    every update of a probability state rounds at 2^-25 of a value up to 1,
+    and an increment below that is lost with a sign set by the flow, so the
+    sums may drift by up to (Heun steps) x (chain length) x 3e-8: for 6000
+    split steps of 6 Heun substeps on 10-state chains that bound is 0.01;
+    the test allows 2e-3.  Total Ca and Mg carry the same effect relative to
+    their largest pools (1e-4).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2107_07104_amd import fib as F
+from paper_2107_07104_amd import inputs as I
+
+from gpu_helpers import compare_runs, gpu_run, oracle_init, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.lib()
+
+
+def test_st57_reaction_matches_oracle():
+    say("[st57 reaction]")
+    rest = O.rest_state(O.MODEL_ST57)
+    rng = np.random.default_rng(21)
+    n = [257, 3, 740]
+    N = sum(n)
+    y0 = rest[:, None] * (1 + 0.01 * rng.standard_normal((57, N)))
+    y0[0] += rng.uniform(-5, 100, N)  # membranes from rest to depolarized
+    y0[4] += rng.uniform(-5, 60, N)
+    stims = [dict(fiber=0, node=10, half_width=2, step_on=0, n_steps=4, period=0, amp=900.0)]
+    s = F.Solver(n, model=F.FIB_MODEL_ST57, dt_0D=1e-4, dt_1D=5e-4, dt_split=5e-4)
+    s.set_stimulus(stims)
+    s.set_state(y0)
+    y0f = s.get_state()
+    cfg = O.Config(model=O.MODEL_ST57, dt_0D=1e-4)
+    yo = y0f
+    for step in range(4):
+        s.step_reaction(step, 2.5e-4)
+        yo = O.reaction(cfg, yo, 2.5e-4, O.stimulus_current(n, stims, step))
+    s.sync()
+    yg = s.get_state()
+    tol = (2e-6 * np.maximum(np.abs(y0f - rest[:, None]), np.abs(rest)[:, None])
+           + 1e-4 * np.abs(yo - y0f) + 1e-9)
+    bad = np.abs(yg - yo) > tol
+    say("   worst state", int(np.argmax(np.max(np.abs(yg - yo) / tol, axis=1))),
+        "ratio", float(np.max(np.abs(yg - yo) / tol)))
+    assert not bad.any()
+    s.close()
+
+
+def test_st57_run_matches_oracle_and_keeps_invariants():
+    w = I.st57_bundle(n_fibers=4, n_nodes=600, t_end=3.0, onset_max=0.5)
+    say(f"[st57 run] {w.name} steps={w.n_steps}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w)
+    res = compare_runs(w, gpu, ora)
+    say("  ", res)
+    assert res["vm_err"] <= 0.5
+    assert res["tact_err"] <= w.dt_split
+    assert res["tact_mismatch"] == 0 and res["activated"] > 300
+    inv0 = np.array([O.st57_invariants(c) for c in oracle_init(w).T])
+    inv1 = np.array([O.st57_invariants(c) for c in gpu[0].T])
+    say("   max invariant drift", np.max(np.abs(inv1 - inv0), axis=0))
+    np.testing.assert_allclose(inv1[:, :4], inv0[:, :4], rtol=0, atol=2e-3)
+    np.testing.assert_allclose(inv1[:, 4:], inv0[:, 4:], rtol=1e-4)
+    gpu[3].close()
+
+
+def test_st57_fused_schedule_is_refused():
+    s = F.Solver([10], model=F.FIB_MODEL_ST57, schedule=F.FIB_SCHED_FUSED, dt_0D=1e-4,
+                 dt_1D=5e-4, dt_split=5e-4)
+    s.init_state()
+    with pytest.raises(F.FibError) as e:
+        s.run(0, 1)
+    assert e.value.code == F.FIB_EUNSUPPORTED
+    s.close()
