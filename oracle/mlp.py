@@ -1,0 +1,122 @@
+"""FP64 reference of the surrogate network (test infrastructure only).
+
+The surrogate of the subcellular update is a plain multilayer perceptron:
+    z_l = W_l a_{l-1} + b_l,   a_l = SiLU(z_l) for hidden layers,
+    output = z_L (linear),     SiLU(z) = z / (1 + exp(-z)),
+trained on the mean squared error
+    loss = 1 / (2 B n_out) * sum_b sum_k (output_bk - target_bk)^2
+with Adam (Kingma & Ba 2015):
+    m = b1 m + (1 - b1) g,  v = b2 v + (1 - b2) g^2,
+    theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
+
+This module is the oracle for the GPU network kernels: plain NumPy in
+float64, backpropagation written out layer by layer.  Only the test suite
+and the benchmark's baseline leg may import it; it imports nothing from the
+GPU library.
+
+Parameters are a list of (W, b) with W of shape (out, in).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def silu(z):
+    return z / (1.0 + np.exp(-z))
+
+
+def silu_grad(z):
+    s = 1.0 / (1.0 + np.exp(-z))
+    return s * (1.0 + z * (1.0 - s))
+
+
+def init_params(sizes, seed: int):
+    """He-style uniform initialisation, seeded (the GPU side receives these
+    arrays as inputs; it does not draw its own)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    params = []
+    for i in range(len(sizes) - 1):
+        fan_in = sizes[i]
+        bound = np.sqrt(6.0 / fan_in) * 0.5
+        W = rng.uniform(-bound, bound, (sizes[i + 1], sizes[i]))
+        b = np.zeros(sizes[i + 1])
+        params.append((W, b))
+    return params
+
+
+def forward(params, X):
+    """X: (B, in) -> (outputs (B, out), cache of pre-activations)."""
+    a = np.asarray(X, dtype=np.float64)
+    zs, acts = [], [a]
+    for i, (W, b) in enumerate(params):
+        z = a @ W.T + b
+        zs.append(z)
+        a = silu(z) if i < len(params) - 1 else z
+        acts.append(a)
+    return a, (zs, acts)
+
+
+def loss(params, X, T):
+    O, _ = forward(params, X)
+    B, n = O.shape
+    return 0.5 * np.sum((O - T) ** 2) / (B * n)
+
+
+def backward(params, X, T):
+    """Gradients of `loss` with respect to every W and b."""
+    O, (zs, acts) = forward(params, X)
+    B, n = O.shape
+    dz = (O - T) / (B * n)
+    grads = [None] * len(params)
+    for i in range(len(params) - 1, -1, -1):
+        W, _ = params[i]
+        gW = dz.T @ acts[i]
+        gb = dz.sum(axis=0)
+        grads[i] = (gW, gb)
+        if i > 0:
+            da = dz @ W
+            dz = da * silu_grad(zs[i - 1])
+    return grads
+
+
+def adam_step(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update; `state` is a dict holding t, m, v (created if empty)."""
+    if not state:
+        state["t"] = 0
+        state["m"] = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+        state["v"] = [(np.zeros_like(W), np.zeros_like(b)) for W, b in params]
+    state["t"] += 1
+    t = state["t"]
+    out = []
+    for i, ((W, b), (gW, gb)) in enumerate(zip(params, grads)):
+        new = []
+        for j, (p, g) in enumerate(((W, gW), (b, gb))):
+            m = b1 * state["m"][i][j] + (1 - b1) * g
+            v = b2 * state["v"][i][j] + (1 - b2) * g * g
+            state["m"][i] = tuple(m if k == j else state["m"][i][k] for k in range(2))
+            state["v"][i] = tuple(v if k == j else state["v"][i][k] for k in range(2))
+            mh = m / (1 - b1 ** t)
+            vh = v / (1 - b2 ** t)
+            new.append(p - lr * mh / (np.sqrt(vh) + eps))
+        out.append((new[0], new[1]))
+    return out
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([W.ravel(), b.ravel()]) for W, b in params])
+
+
+def unflatten(vec, sizes):
+    params, o = [], 0
+    for i in range(len(sizes) - 1):
+        n_in, n_out = sizes[i], sizes[i + 1]
+        W = vec[o:o + n_in * n_out].reshape(n_out, n_in)
+        o += n_in * n_out
+        b = vec[o:o + n_out]
+        o += n_out
+        params.append((W.copy(), b.copy()))
+    return params
+
+
+def n_params(sizes):
+    return sum(sizes[i] * sizes[i + 1] + sizes[i + 1] for i in range(len(sizes) - 1))

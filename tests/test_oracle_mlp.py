@@ -1,0 +1,85 @@
+"""Pins of the FP64 surrogate-network reference (oracle/mlp.py).
+
+* SiLU and its derivative at closed-form points (SiLU(0) = 0, SiLU'(0) = 1/2,
+  SiLU(z) -> z and SiLU'(z) -> 1 for large z, SiLU(z) -> 0 for z -> -inf);
+* a one-layer (linear) network's gradient equals the normal-equation form
+  (O - T)^T X / (B n) written as a matrix product;
+* a hand-computed two-layer example;
+* backpropagation of the full network against central finite differences;
+* the first Adam step moves every parameter by lr * sign(g) (bias-corrected
+  moments give m/sqrt(v) = g/|g| at t = 1).
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+
+def test_silu_closed_forms():
+    assert M.silu(0.0) == 0.0
+    assert M.silu_grad(0.0) == pytest.approx(0.5)
+    assert M.silu(40.0) == pytest.approx(40.0, rel=1e-15)
+    assert M.silu_grad(40.0) == pytest.approx(1.0, rel=1e-15)
+    assert abs(M.silu(-40.0)) < 1e-15
+    z = np.linspace(-6, 6, 101)
+    h = 1e-6
+    np.testing.assert_allclose(M.silu_grad(z), (M.silu(z + h) - M.silu(z - h)) / (2 * h),
+                               rtol=1e-8, atol=1e-10)
+
+
+def test_linear_network_gradient_is_the_normal_equation_form():
+    rng = np.random.default_rng(0)
+    X = rng.standard_normal((7, 3))
+    T = rng.standard_normal((7, 2))
+    params = [(rng.standard_normal((2, 3)), rng.standard_normal(2))]
+    (gW, gb), = M.backward(params, X, T)
+    O = X @ params[0][0].T + params[0][1]
+    np.testing.assert_allclose(gW, (O - T).T @ X / (7 * 2), rtol=1e-13)
+    np.testing.assert_allclose(gb, (O - T).sum(axis=0) / (7 * 2), rtol=1e-13)
+
+
+def test_hand_computed_two_layer_example():
+    # x = 1, hidden z = 2x + 0 = 2, a = SiLU(2) = 2/(1+e^-2), out = 3a + 1
+    params = [(np.array([[2.0]]), np.array([0.0])), (np.array([[3.0]]), np.array([1.0]))]
+    O, _ = M.forward(params, np.array([[1.0]]))
+    a = 2.0 / (1.0 + np.exp(-2.0))
+    assert O[0, 0] == pytest.approx(3.0 * a + 1.0, rel=1e-15)
+    # target 0: loss = 0.5 (3a+1)^2; dL/db2 = 3a+1; dL/dW2 = (3a+1) a;
+    # dL/dW1 = (3a+1) * 3 * SiLU'(2) * x
+    g = M.backward(params, np.array([[1.0]]), np.array([[0.0]]))
+    e = 3.0 * a + 1.0
+    s = 1.0 / (1.0 + np.exp(-2.0))
+    assert g[1][1][0] == pytest.approx(e)
+    assert g[1][0][0, 0] == pytest.approx(e * a)
+    assert g[0][0][0, 0] == pytest.approx(e * 3.0 * s * (1.0 + 2.0 * (1.0 - s)))
+
+
+@pytest.mark.parametrize("sizes", [[5, 8, 8, 4], [6, 12, 5]])
+def test_backprop_matches_central_differences(sizes):
+    rng = np.random.default_rng(1)
+    params = M.init_params(sizes, seed=3)
+    X = rng.standard_normal((9, sizes[0]))
+    T = rng.standard_normal((9, sizes[-1]))
+    g = M.flatten([(gW, gb) for gW, gb in M.backward(params, X, T)])
+    theta = M.flatten(params)
+    h = 1e-6
+    num = np.zeros_like(theta)
+    for i in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        num[i] = (M.loss(M.unflatten(tp, sizes), X, T) - M.loss(M.unflatten(tm, sizes), X, T)) / (2 * h)
+    np.testing.assert_allclose(g, num, rtol=1e-6, atol=1e-10)
+
+
+def test_first_adam_step_moves_by_lr_times_sign():
+    params = [(np.array([[1.0, -2.0]]), np.array([0.5]))]
+    grads = [(np.array([[0.3, -4.0]]), np.array([0.0]))]
+    new = M.adam_step(params, grads, {}, lr=0.01)
+    np.testing.assert_allclose(new[0][0], [[1.0 - 0.01, -2.0 + 0.01]], rtol=1e-6)
+    assert new[0][1][0] == 0.5
+
+
+def test_param_count_of_the_surrogate_shapes():
+    assert M.n_params([5, 64, 64, 64, 4]) == 8964
+    assert M.n_params([57, 128, 128, 57]) == 31289
