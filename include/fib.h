@@ -213,6 +213,49 @@ int fib_sync(fib_t* ctx);
 int fib_plan_info(const fib_t* ctx, int32_t* groups, int32_t* threads, int32_t* nodes_per_thread,
                   int32_t* pcr_levels);
 
+/* ------------------------------------------------------------------------
+ * Surrogate network: a multilayer perceptron with SiLU hidden layers and a
+ * linear output, z_l = W_l a_{l-1} + b_l, used as a learned replacement of
+ * the subcellular update over one split step (no counterpart in the
+ * thesis, which names learned surrogates only as an outlook).  Matrix
+ * products run on the matrix cores with BF16 operands and FP32
+ * accumulation; parameters, Adam moments and gradients are FP32.
+ *
+ * Parameter layout (flat FP32): for every weight layer l = 1..L the matrix
+ * W_l (sizes[l] rows x sizes[l-1] columns, row-major) followed by b_l.
+ * Data arrays are FP32 device pointers, row-major, one sample per row.
+ * ------------------------------------------------------------------------ */
+typedef struct fib_mlp fib_mlp_t;
+
+/* Creates a network with n_layers weight layers (1..6) and layer widths
+ * sizes[0..n_layers] (1..512; sizes[0] = inputs).  Parameters start at 0:
+ * set them with fib_mlp_set_params.  `stream` as for fib_create. */
+int fib_mlp_create(int32_t n_layers, const int32_t* sizes, void* stream, fib_mlp_t** out);
+void fib_mlp_destroy(fib_mlp_t* net);
+int64_t fib_mlp_n_params(const fib_mlp_t* net);
+
+/* Copies all parameters from / to host memory (blocking). */
+int fib_mlp_set_params(fib_mlp_t* net, const float* params, int64_t n);
+int fib_mlp_get_params(fib_mlp_t* net, float* params, int64_t n);
+
+/* O[b] = network(X[b]) for b < B (X: B x sizes[0], O: B x sizes[L]). */
+int fib_mlp_forward(fib_mlp_t* net, const float* X, int64_t B, float* O);
+
+/* Gradient of loss = sum_b sum_k (O_bk - T_bk)^2 / (2 B sizes[L]) with
+ * respect to the flat parameters into `grad` (device, n_params floats;
+ * NULL: internal buffer) and the loss into loss[0] (device, nullable).
+ * Deterministic: chunk partial sums are reduced in a fixed order. */
+int fib_mlp_gradient(fib_mlp_t* net, const float* X, const float* T, int64_t B, float* grad,
+                     float* loss);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss with
+ * learning rate lr; the loss before the step goes to loss[0] (nullable). */
+int fib_mlp_adam_step(fib_mlp_t* net, const float* X, const float* T, int64_t B, double lr,
+                      float* loss);
+
+/* Clears the Adam moments and step count. */
+int fib_mlp_reset_optimizer(fib_mlp_t* net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,8 +23,18 @@
 using fib::KArgs;
 
 namespace {
-
 thread_local std::string g_err;
+}  // namespace
+
+namespace fib {
+// Records an error message for fib_last_error() and returns `code`.
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace fib
+
+namespace {
 
 int fail(int code, const char* fmt, ...) {
   char buf[512];

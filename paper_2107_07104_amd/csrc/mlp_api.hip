@@ -1,0 +1,179 @@
+// Host runtime of the surrogate network (C ABI in include/fib.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/fib.h"
+#include "mlp_internal.h"
+
+namespace fib {
+int set_error(int code, const char* msg);  // fib_api.hip
+}
+
+struct fib_mlp {
+  fib::MlpShape shape{};
+  hipStream_t stream = nullptr;
+  float* d_params = nullptr;  // FP32 master parameters
+  float* d_m = nullptr;       // Adam first moment
+  float* d_v = nullptr;       // Adam second moment
+  float* d_grad = nullptr;
+  float* d_part = nullptr;    // per-chunk partial gradients
+  float* d_loss_part = nullptr;
+  int64_t part_chunks = 0;
+  int64_t t = 0;              // Adam step count
+};
+
+namespace {
+
+int mfail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return fib::set_error(code, buf);
+}
+
+#define MHIP(expr)                                                                    \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return mfail(FIB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+int ensure_parts(fib_mlp* n, int64_t chunks) {
+  if (chunks <= n->part_chunks) return FIB_OK;
+  (void)hipStreamSynchronize(n->stream);
+  (void)hipFree(n->d_part);
+  (void)hipFree(n->d_loss_part);
+  n->d_part = nullptr;
+  n->d_loss_part = nullptr;
+  n->part_chunks = 0;
+  if (hipMalloc(&n->d_part, sizeof(float) * (size_t)chunks * n->shape.n_params) != hipSuccess ||
+      hipMalloc(&n->d_loss_part, sizeof(float) * (size_t)chunks) != hipSuccess)
+    return mfail(FIB_ENOMEM, "device allocation of %lld gradient chunks failed", (long long)chunks);
+  n->part_chunks = chunks;
+  return FIB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fib_mlp_create(int32_t n_layers, const int32_t* sizes, void* stream, fib_mlp_t** out) {
+  if (!out) return mfail(FIB_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (n_layers < 1 || n_layers > fib::kMaxLayers || !sizes)
+    return mfail(FIB_EINVAL, "the network needs 1..%d weight layers", fib::kMaxLayers);
+  fib::MlpShape s{};
+  s.L = n_layers;
+  int64_t off = 0;
+  for (int l = 0; l <= n_layers; ++l) {
+    if (sizes[l] < 1 || sizes[l] > 512) return mfail(FIB_EINVAL, "layer width %d not in 1..512", sizes[l]);
+    s.size[l] = sizes[l];
+    s.pad[l] = (sizes[l] + fib::kPad - 1) / fib::kPad * fib::kPad;
+  }
+  for (int l = 1; l <= n_layers; ++l) {
+    s.w_off[l] = (int)off;
+    off += (int64_t)s.size[l] * s.size[l - 1];
+    s.b_off[l] = (int)off;
+    off += s.size[l];
+  }
+  s.n_params = (int)off;
+  hipDeviceProp_t prop;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return mfail(FIB_EHIP, "no HIP device");
+  if (fib::mlp_train_lds_bytes(s) > prop.sharedMemPerBlock)
+    return mfail(FIB_EUNSUPPORTED, "network too wide for one workgroup's LDS");
+  fib_mlp* n = new (std::nothrow) fib_mlp();
+  if (!n) return mfail(FIB_ENOMEM, "host allocation failed");
+  n->shape = s;
+  n->stream = (hipStream_t)stream;
+  const size_t bytes = sizeof(float) * (size_t)s.n_params;
+  if (hipMalloc(&n->d_params, bytes) != hipSuccess || hipMalloc(&n->d_m, bytes) != hipSuccess ||
+      hipMalloc(&n->d_v, bytes) != hipSuccess || hipMalloc(&n->d_grad, bytes) != hipSuccess) {
+    fib_mlp_destroy(n);
+    return mfail(FIB_ENOMEM, "device allocation failed");
+  }
+  if (hipMemset(n->d_params, 0, bytes) != hipSuccess || hipMemset(n->d_m, 0, bytes) != hipSuccess ||
+      hipMemset(n->d_v, 0, bytes) != hipSuccess) {
+    fib_mlp_destroy(n);
+    return mfail(FIB_EHIP, "device initialization failed");
+  }
+  *out = n;
+  return FIB_OK;
+}
+
+void fib_mlp_destroy(fib_mlp_t* n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  (void)hipFree(n->d_params);
+  (void)hipFree(n->d_m);
+  (void)hipFree(n->d_v);
+  (void)hipFree(n->d_grad);
+  (void)hipFree(n->d_part);
+  (void)hipFree(n->d_loss_part);
+  delete n;
+}
+
+int64_t fib_mlp_n_params(const fib_mlp_t* n) { return n ? n->shape.n_params : 0; }
+
+int fib_mlp_set_params(fib_mlp_t* n, const float* params, int64_t count) {
+  if (!n || !params) return mfail(FIB_EINVAL, "null argument");
+  if (count != n->shape.n_params) return mfail(FIB_EINVAL, "expected %d parameters", n->shape.n_params);
+  MHIP(hipMemcpyAsync(n->d_params, params, sizeof(float) * count, hipMemcpyHostToDevice, n->stream));
+  MHIP(hipStreamSynchronize(n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_get_params(fib_mlp_t* n, float* params, int64_t count) {
+  if (!n || !params) return mfail(FIB_EINVAL, "null argument");
+  if (count != n->shape.n_params) return mfail(FIB_EINVAL, "expected %d parameters", n->shape.n_params);
+  MHIP(hipMemcpyAsync(params, n->d_params, sizeof(float) * count, hipMemcpyDeviceToHost, n->stream));
+  MHIP(hipStreamSynchronize(n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_forward(fib_mlp_t* n, const float* X, int64_t B, float* O) {
+  if (!n || B < 0 || (B > 0 && (!X || !O))) return mfail(FIB_EINVAL, "bad arguments");
+  MHIP(fib::launch_mlp_forward(n->shape, n->d_params, X, B, O, n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_gradient(fib_mlp_t* n, const float* X, const float* T, int64_t B, float* grad,
+                     float* loss) {
+  if (!n || B < 1 || !X || !T) return mfail(FIB_EINVAL, "bad arguments");
+  const int64_t chunks = (B + fib::kChunk - 1) / fib::kChunk;
+  if (int rc = ensure_parts(n, chunks)) return rc;
+  MHIP(fib::launch_mlp_grad(n->shape, n->d_params, X, T, B, n->d_part, n->d_loss_part,
+                            grad ? grad : n->d_grad, loss, n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_adam_step(fib_mlp_t* n, const float* X, const float* T, int64_t B, double lr,
+                      float* loss) {
+  if (!n || B < 1 || !X || !T || !(lr > 0.0)) return mfail(FIB_EINVAL, "bad arguments");
+  const int64_t chunks = (B + fib::kChunk - 1) / fib::kChunk;
+  if (int rc = ensure_parts(n, chunks)) return rc;
+  MHIP(fib::launch_mlp_grad(n->shape, n->d_params, X, T, B, n->d_part, n->d_loss_part, n->d_grad,
+                            loss, n->stream));
+  n->t += 1;
+  MHIP(fib::launch_mlp_adam(n->d_params, n->d_m, n->d_v, n->d_grad, n->shape.n_params, (float)lr,
+                            0.9f, 0.999f, 1e-8f, n->t, n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_reset_optimizer(fib_mlp_t* n) {
+  if (!n) return mfail(FIB_EINVAL, "null network");
+  const size_t bytes = sizeof(float) * (size_t)n->shape.n_params;
+  MHIP(hipMemsetAsync(n->d_m, 0, bytes, n->stream));
+  MHIP(hipMemsetAsync(n->d_v, 0, bytes, n->stream));
+  n->t = 0;
+  return FIB_OK;
+}
+
+}  // extern "C"

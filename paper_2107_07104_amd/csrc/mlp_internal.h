@@ -1,0 +1,35 @@
+// Internal shape description of the surrogate network, shared by the host
+// runtime and the network kernels.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace fib {
+
+constexpr int kMaxLayers = 6;  // weight layers
+constexpr int kChunk = 32;     // samples per training workgroup
+constexpr int kPad = 32;       // feature dimensions are padded to multiples of this
+
+// Flat parameter layout (FP32): for every layer l = 1..L the weight matrix
+// W_l (size[l] x size[l-1], row-major) followed by the bias b_l.
+struct MlpShape {
+  int L;                        // number of weight layers
+  int size[kMaxLayers + 1];     // features per layer, size[0] = inputs
+  int pad[kMaxLayers + 1];      // size rounded up to kPad
+  int w_off[kMaxLayers + 1];    // offset of W_l in the flat parameters
+  int b_off[kMaxLayers + 1];    // offset of b_l
+  int n_params;
+};
+
+size_t mlp_train_lds_bytes(const MlpShape& s);
+hipError_t launch_mlp_forward(const MlpShape& s, const float* params, const float* X, int64_t B,
+                              float* O, hipStream_t st);
+hipError_t launch_mlp_grad(const MlpShape& s, const float* params, const float* X, const float* T,
+                           int64_t B, float* part, float* loss_part, float* grad, float* loss,
+                           hipStream_t st);
+hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t n, float lr,
+                           float b1, float b2, float eps, int64_t t, hipStream_t st);
+
+}  // namespace fib

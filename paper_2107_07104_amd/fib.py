@@ -38,7 +38,9 @@ EXPORTS = (
     "fib_last_error", "fib_n_total", "fib_init_state", "fib_set_state", "fib_get_state",
     "fib_state_device", "fib_set_stimulus", "fib_step_reaction", "fib_step_diffusion",
     "fib_run", "fib_get_tact", "fib_reset_observables", "fib_sync", "fib_plan_info",
-    "fib_plan_preview",
+    "fib_plan_preview", "fib_mlp_create", "fib_mlp_destroy", "fib_mlp_n_params",
+    "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
+    "fib_mlp_adam_step", "fib_mlp_reset_optimizer",
 )
 
 
@@ -101,6 +103,17 @@ def lib():
             "fib_plan_preview": ([C.POINTER(fib_params), C.c_int32, _i32p, C.c_int32, _i32p, _i32p,
                                   _i32p, _i32p, C.POINTER(C.c_int64)], C.c_int),
         }
+        sig.update({
+            "fib_mlp_create": ([C.c_int32, _i32p, _vp, C.POINTER(_vp)], C.c_int),
+            "fib_mlp_destroy": ([_vp], None),
+            "fib_mlp_n_params": ([_vp], C.c_int64),
+            "fib_mlp_set_params": ([_vp, _fp, C.c_int64], C.c_int),
+            "fib_mlp_get_params": ([_vp, _fp, C.c_int64], C.c_int),
+            "fib_mlp_forward": ([_vp, _vp, C.c_int64, _vp], C.c_int),
+            "fib_mlp_gradient": ([_vp, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
+            "fib_mlp_adam_step": ([_vp, _vp, _vp, C.c_int64, C.c_double, _vp], C.c_int),
+            "fib_mlp_reset_optimizer": ([_vp], C.c_int),
+        })
         for name, (args, res) in sig.items():
             f = getattr(L, name)
             f.argtypes = args
@@ -242,6 +255,104 @@ def fib_plan_preview(params: fib_params, n_nodes, compute_units: int = 256):
                                   C.byref(l), C.byref(mx)))
     return dict(groups=g.value, threads=t.value, nodes_per_thread=k.value, pcr_levels=l.value,
                 max_load=mx.value)
+
+
+def fib_mlp_create(sizes, stream=None) -> int:
+    sz = np.ascontiguousarray(sizes, dtype=np.int32)
+    out = _vp()
+    _check(lib().fib_mlp_create(len(sz) - 1, sz.ctypes.data_as(_i32p),
+                                _vp(stream) if stream else None, C.byref(out)))
+    return out.value
+
+
+def fib_mlp_destroy(net) -> None:
+    lib().fib_mlp_destroy(_vp(net))
+
+
+def fib_mlp_n_params(net) -> int:
+    return int(lib().fib_mlp_n_params(_vp(net)))
+
+
+def fib_mlp_set_params(net, params: np.ndarray) -> None:
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    _check(lib().fib_mlp_set_params(_vp(net), p.ctypes.data_as(_fp), p.size))
+
+
+def fib_mlp_get_params(net) -> np.ndarray:
+    p = np.zeros(fib_mlp_n_params(net), dtype=np.float32)
+    _check(lib().fib_mlp_get_params(_vp(net), p.ctypes.data_as(_fp), p.size))
+    return p
+
+
+def fib_mlp_forward(net, X_ptr: int, B: int, O_ptr: int) -> None:
+    _check(lib().fib_mlp_forward(_vp(net), _vp(X_ptr), int(B), _vp(O_ptr)))
+
+
+def fib_mlp_gradient(net, X_ptr: int, T_ptr: int, B: int, grad_ptr: int = 0,
+                     loss_ptr: int = 0) -> None:
+    _check(lib().fib_mlp_gradient(_vp(net), _vp(X_ptr), _vp(T_ptr), int(B),
+                                  _vp(grad_ptr or None), _vp(loss_ptr or None)))
+
+
+def fib_mlp_adam_step(net, X_ptr: int, T_ptr: int, B: int, lr: float, loss_ptr: int = 0) -> None:
+    _check(lib().fib_mlp_adam_step(_vp(net), _vp(X_ptr), _vp(T_ptr), int(B), float(lr),
+                                   _vp(loss_ptr or None)))
+
+
+def fib_mlp_reset_optimizer(net) -> None:
+    _check(lib().fib_mlp_reset_optimizer(_vp(net)))
+
+
+class Mlp:
+    """Owns one surrogate network; data arrays are torch CUDA tensors."""
+
+    def __init__(self, sizes, stream=None):
+        import torch
+        self.torch = torch
+        self.sizes = list(sizes)
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        self.net = fib_mlp_create(self.sizes, stream)
+
+    def close(self):
+        if self.net:
+            fib_mlp_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_params(self):
+        return fib_mlp_n_params(self.net)
+
+    def set_params(self, flat):
+        fib_mlp_set_params(self.net, flat)
+
+    def get_params(self):
+        return fib_mlp_get_params(self.net)
+
+    def forward(self, X):
+        t = self.torch
+        X = X.contiguous().float()
+        O = t.empty((X.shape[0], self.sizes[-1]), device=X.device)
+        fib_mlp_forward(self.net, X.data_ptr(), X.shape[0], O.data_ptr())
+        return O
+
+    def gradient(self, X, T):
+        t = self.torch
+        g = t.empty(self.n_params, device=X.device)
+        loss = t.empty(1, device=X.device)
+        fib_mlp_gradient(self.net, X.contiguous().data_ptr(), T.contiguous().data_ptr(),
+                         X.shape[0], g.data_ptr(), loss.data_ptr())
+        return g, loss
+
+    def adam_step(self, X, T, lr, loss=None):
+        fib_mlp_adam_step(self.net, X.data_ptr(), T.data_ptr(), X.shape[0], lr,
+                          loss.data_ptr() if loss is not None else 0)
 
 
 # ---- convenience wrapper (still marshalling only) ---------------------------------
