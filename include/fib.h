@@ -256,6 +256,54 @@ int fib_mlp_adam_step(fib_mlp_t* net, const float* X, const float* T, int64_t B,
 /* Clears the Adam moments and step count. */
 int fib_mlp_reset_optimizer(fib_mlp_t* net);
 
+/* ------------------------------------------------------------------------
+ * Surrogate split step.  With a network attached, fib_run (split schedule)
+ * replaces the two reaction halves that meet between consecutive diffusion
+ * steps -- R(dt/2) of step n, then R(dt/2) of step n+1 -- by one
+ * implicit-midpoint step of width dt predicted by the network:
+ *   inputs  x_k = (u_k - in_shift[k]) * in_scale[k], k < n_states, with u
+ *           the state minus the resting state, plus I * flag_scale (the
+ *           stimulus of step n) when the network has n_states + 1 inputs;
+ *   outputs du_k = out_shift[k] + out_scale[k] * o_k (the predictor);
+ *   corrector du1 = dt G(y + du/2, I), du2 = dt G(y + du1/2, I)
+ *   (G: the model's right-hand side; two fixed-point iterations of the
+ *   implicit midpoint rule started from the prediction).
+ * A node takes du2 only if |du1 - du|_k <= tol * res_scale[k] for every
+ * state k (absolute tolerances), its stimulus is the same in both halves,
+ * and (for networks without the flag input) it is not stimulated; all
+ * other nodes take the plain Heun substeps.  Steps that write V_m samples,
+ * and the last step of a call, run the plain path for every node.  For
+ * kept nodes the activation-time test uses the midpoint y + du2/2 as the
+ * state at the end of step n.  The surrogate is an addition of this
+ * library: the thesis names learned surrogate models only as an outlook.
+ * Supported shapes: Hodgkin-Huxley 4 or 5 -> 64 -> 64 -> 64 -> 4, ST57
+ * 57 or 58 -> 128 -> 128 -> 57.  The network's current parameters are
+ * copied (packed to BF16) by this call; later changes to the network need
+ * another call.  Host arrays of n_states values.
+ * ------------------------------------------------------------------------ */
+int fib_set_surrogate(fib_t* ctx, const fib_mlp_t* net, const float* in_shift,
+                      const float* in_scale, const float* out_shift, const float* out_scale,
+                      const float* res_scale, double flag_scale, double tol);
+
+/* The surrogate pair alone: finishes split step `step` and starts step
+ * step + 1 on every node (kept nodes by the corrected prediction, the
+ * others by the plain Heun substeps), with the observables of step `step`.
+ * Asynchronous; FIB_ESTATE without an attached surrogate. */
+int fib_step_surrogate(fib_t* ctx, int64_t step);
+
+/* The network's prediction alone: writes du (device, FP32, [n_states][n_total],
+ * caller-owned) for the current state with the stimulus of step `step`,
+ * denormalized as above; changes no state.  Asynchronous.  For checking a
+ * trained network against its reference and for measuring its error. */
+int fib_surrogate_predict(fib_t* ctx, int64_t step, float* du);
+
+/* Detaches the surrogate: fib_run takes the plain path again. */
+int fib_clear_surrogate(fib_t* ctx);
+
+/* Number of nodes that took the plain path in the last surrogate step
+ * (blocking). */
+int fib_surrogate_last_fallbacks(fib_t* ctx, int64_t* n);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfib.so")
-SOURCES = ["fib_api.hip", "fib_kernels.hip", "mlp_api.hip", "mlp_kernels.hip"]
+SOURCES = ["fib_api.hip", "fib_kernels.hip", "mlp_api.hip", "mlp_kernels.hip",
+           "surrogate_kernels.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

@@ -18,7 +18,9 @@
 
 #include "../../include/fib.h"
 #include "fib_internal.h"
+#include "mlp_internal.h"
 #include "st57_model.h"
+#include "surrogate_internal.h"
 
 using fib::KArgs;
 
@@ -262,6 +264,16 @@ struct fib_ctx {
   fib::StimDev* d_stim = nullptr;
   int32_t n_stim = 0;
   bool state_ready = false;
+
+  // surrogate
+  bool sur_on = false;
+  fib::SurrogateNet sur_net{};
+  fib::SurrogateScales sur_sc{};
+  __bf16* d_sur_frags = nullptr;
+  float* d_sur_bias = nullptr;
+  int* d_sur_list = nullptr;
+  int* d_sur_count = nullptr;
+  int sur_grid = 0;
 };
 
 namespace {
@@ -660,6 +672,10 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_slot_info);
   (void)hipFree(c->d_node_stim);
   (void)hipFree(c->d_stim);
+  (void)hipFree(c->d_sur_frags);
+  (void)hipFree(c->d_sur_bias);
+  (void)hipFree(c->d_sur_list);
+  (void)hipFree(c->d_sur_count);
   delete c;
 }
 
@@ -841,8 +857,10 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   a.pcr_levels = c->levels;
   a.step0 = (int32_t)step0;
   a.n_steps = (int32_t)n_steps;
+  // AUTO: fused for Hodgkin-Huxley unless a surrogate is attached (the
+  // surrogate step belongs to the split schedule)
   const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
-                     (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH);
+                     (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH && !c->sur_on);
   if (fused) {
     if (c->p.model != FIB_MODEL_HH)
       return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
@@ -859,9 +877,142 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   HIP_TRY(fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
   for (int64_t n = step0; n < end; ++n) {
     HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
-    const int flags = 1 | 2 | (n + 1 < end ? 4 : 0);
-    HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
+    const bool last = n + 1 >= end;
+    const bool sample = a.samples && a.sample_every > 0 && (n + 1) % a.sample_every == 0;
+    if (c->sur_on && !last && !sample) {
+      HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
+                                         c->sur_sc, (int32_t)n, c->d_sur_list, c->d_sur_count,
+                                         c->sur_grid, c->stream));
+    } else {
+      const int flags = 1 | 2 | (last ? 0 : 4);
+      HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
+    }
   }
+  return FIB_OK;
+}
+
+int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, const float* in_scale,
+                      const float* out_shift, const float* out_scale, const float* res_scale,
+                      double flag_scale, double tol) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!net || !in_shift || !in_scale || !out_shift || !out_scale || !res_scale)
+    return fail(FIB_EINVAL, "null argument");
+  if (!(tol > 0.0) || !std::isfinite(flag_scale)) return fail(FIB_EINVAL, "bad tolerance or flag scale");
+  const fib::MlpShape& ms = fib::mlp_shape(net);
+  const int S = c->S;
+  // supported shapes: the kernels are compiled for them
+  bool ok = false;
+  if (c->p.model == FIB_MODEL_HH)
+    ok = ms.L == 4 && (ms.size[0] == 4 || ms.size[0] == 5) && ms.size[1] == 64 &&
+         ms.size[2] == 64 && ms.size[3] == 64 && ms.size[4] == 4;
+  else if (c->p.model == FIB_MODEL_ST57)
+    ok = ms.L == 3 && (ms.size[0] == 57 || ms.size[0] == 58) && ms.size[1] == 128 &&
+         ms.size[2] == 128 && ms.size[3] == 57;
+  if (!ok)
+    return fail(FIB_EUNSUPPORTED, "surrogate shape not supported for this model (Hodgkin-Huxley: "
+                "4 or 5 -> 64 -> 64 -> 64 -> 4; ST57: 57 or 58 -> 128 -> 128 -> 57)");
+  fib::SurrogateNet sn{};
+  sn.L = ms.L;
+  int frags = 0, bias = 0;
+  for (int l = 1; l <= ms.L; ++l) {
+    sn.n_in[l] = ms.size[l - 1];
+    sn.n_out[l] = ms.size[l];
+    sn.pad_in[l] = (ms.size[l - 1] + 31) / 32 * 32;
+    sn.pad_out[l] = (ms.size[l] + 15) / 16 * 16;
+    sn.w_off[l] = ms.w_off[l];
+    sn.b_off[l] = ms.b_off[l];
+    sn.frag_off[l] = frags;
+    frags += (sn.pad_out[l] / 16) * (sn.pad_in[l] / 32);
+    sn.bias_off[l] = bias;
+    bias += sn.pad_out[l];
+  }
+  sn.frag_off[ms.L + 1] = frags;
+  sn.bias_off[ms.L + 1] = bias;
+  sn.frag_elems = (int64_t)frags * 512;
+  sn.bias_elems = bias;
+  fib::SurrogateScales sc{};
+  sc.n_in = ms.size[0];
+  sc.flag_scale = (float)flag_scale;
+  sc.tol = (float)tol;
+  for (int k = 0; k < S; ++k) {
+    if (!(in_scale[k] > 0.0f) || !(out_scale[k] > 0.0f) || !(res_scale[k] > 0.0f) ||
+        !std::isfinite(in_shift[k]) || !std::isfinite(out_shift[k]))
+      return fail(FIB_EINVAL, "state %d: scales must be finite and > 0", k);
+    sc.in_shift[k] = in_shift[k];
+    sc.in_scale[k] = in_scale[k];
+    sc.out_shift[k] = out_shift[k];
+    sc.out_scale[k] = out_scale[k];
+    sc.inv_res[k] = 1.0f / res_scale[k];
+  }
+  const size_t lds = fib::surrogate_lds_bytes(c->p.model, sn);
+  if (lds > c->max_lds) return fail(FIB_EUNSUPPORTED, "surrogate needs %zu bytes of LDS", lds);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipStreamSynchronize(fib::mlp_stream(net)));
+  (void)hipFree(c->d_sur_frags);
+  (void)hipFree(c->d_sur_bias);
+  c->d_sur_frags = nullptr;
+  c->d_sur_bias = nullptr;
+  c->sur_on = false;
+  if (hipMalloc(&c->d_sur_frags, (size_t)sn.frag_elems * 2) != hipSuccess ||
+      hipMalloc(&c->d_sur_bias, (size_t)sn.bias_elems * 4) != hipSuccess)
+    return fail(FIB_ENOMEM, "device allocation failed");
+  if (!c->d_sur_list) {
+    if (hipMalloc(&c->d_sur_list, sizeof(int) * (size_t)std::max<int64_t>(c->n_total, 1)) != hipSuccess ||
+        hipMalloc(&c->d_sur_count, sizeof(int)) != hipSuccess)
+      return fail(FIB_ENOMEM, "device allocation failed");
+  }
+  HIP_TRY(fib::launch_pack(sn, fib::mlp_device_params(net), c->d_sur_frags, c->d_sur_bias, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, c->max_lds / lds));
+  c->sur_grid = c->cu_count * per_cu;
+  c->sur_net = sn;
+  c->sur_sc = sc;
+  c->sur_on = true;
+  return FIB_OK;
+}
+
+int fib_step_surrogate(fib_t* c, int64_t step) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!c->sur_on) return fail(FIB_ESTATE, "no surrogate attached");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (step < 0 || step + 1 >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
+  KArgs a = base_args(c);
+  const int64_t ns = ceil_steps(0.5 * c->p.dt_split, c->p.dt_0D);
+  a.n_sub = (int32_t)ns;
+  a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
+  HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
+                                     c->sur_sc, (int32_t)step, c->d_sur_list, c->d_sur_count,
+                                     c->sur_grid, c->stream));
+  return FIB_OK;
+}
+
+int fib_surrogate_predict(fib_t* c, int64_t step, float* du) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!c->sur_on) return fail(FIB_ESTATE, "no surrogate attached");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (!du && c->n_total > 0) return fail(FIB_EINVAL, "du is null");
+  if (step < 0 || step + 1 >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
+  KArgs a = base_args(c);
+  HIP_TRY(fib::launch_surrogate_predict(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
+                                        c->sur_sc, (int32_t)step, du, c->sur_grid, c->stream));
+  return FIB_OK;
+}
+
+int fib_clear_surrogate(fib_t* c) {
+  if (int rc = check_ctx(c)) return rc;
+  c->sur_on = false;
+  return FIB_OK;
+}
+
+int fib_surrogate_last_fallbacks(fib_t* c, int64_t* n) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!n) return fail(FIB_EINVAL, "null output");
+  *n = 0;
+  if (!c->d_sur_count) return FIB_OK;
+  int v = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&v, c->d_sur_count, sizeof(int), hipMemcpyDeviceToHost));
+  *n = v;
   return FIB_OK;
 }
 

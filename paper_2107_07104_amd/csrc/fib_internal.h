@@ -57,6 +57,18 @@ struct KArgs {
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
+// Current of stimulus entry `sid1 - 1` (0: none) during split step n: a
+// pulse of `dur` steps from `on`, repeated every `period` steps if > 0.
+__device__ __forceinline__ float stim_current(uint32_t sid1, const StimDev* __restrict__ tab,
+                                              int32_t n) {
+  if (sid1 == 0) return 0.0f;
+  const StimDev e = tab[sid1 - 1];
+  int32_t k = n - e.on;
+  if (k < 0) return 0.0f;
+  if (e.period > 0) k = k % e.period;
+  return k < e.dur ? e.amp : 0.0f;
+}
+
 // Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds_bytes,
                             const KArgs& a, hipStream_t s);

@@ -33,21 +33,6 @@
 namespace fib {
 
 // ---------------------------------------------------------------------------
-// Stimulus
-// ---------------------------------------------------------------------------
-
-// Current of stimulus entry `sid1 - 1` (0: none) during split step n.
-__device__ __forceinline__ float stim_current(uint32_t sid1, const StimDev* __restrict__ tab,
-                                              int32_t n) {
-  if (sid1 == 0) return 0.0f;
-  const StimDev e = tab[sid1 - 1];
-  int32_t k = n - e.on;
-  if (k < 0) return 0.0f;
-  if (e.period > 0) k = k % e.period;
-  return k < e.dur ? e.amp : 0.0f;
-}
-
-// ---------------------------------------------------------------------------
 // Lumped Crank-Nicolson rows
 // ---------------------------------------------------------------------------
 

@@ -27,6 +27,12 @@ struct fib_mlp {
   int64_t t = 0;              // Adam step count
 };
 
+namespace fib {
+const MlpShape& mlp_shape(const fib_mlp* n) { return n->shape; }
+const float* mlp_device_params(const fib_mlp* n) { return n->d_params; }
+hipStream_t mlp_stream(const fib_mlp* n) { return n->stream; }
+}  // namespace fib
+
 namespace {
 
 int mfail(int code, const char* fmt, ...) {

@@ -33,3 +33,12 @@ hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad,
                            float b1, float b2, float eps, int64_t t, hipStream_t st);
 
 }  // namespace fib
+
+struct fib_mlp;
+namespace fib {
+// Shape and device parameters of a network object (mlp_api.hip).
+const MlpShape& mlp_shape(const fib_mlp* n);
+const float* mlp_device_params(const fib_mlp* n);
+hipStream_t mlp_stream(const fib_mlp* n);
+
+}  // namespace fib

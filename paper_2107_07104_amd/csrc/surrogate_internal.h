@@ -1,0 +1,58 @@
+// Internal description of the surrogate step: the packed network and the
+// per-state scalings.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "fib_internal.h"
+
+namespace fib {
+
+constexpr int kSurMaxLayers = 6;
+constexpr int kSurMaxStates = 64;
+
+// Network packed for the matrix cores.  Layer l = 1..L maps n_in[l] to
+// n_out[l] features; its weights are pad_out[l]/16 x pad_in[l]/32
+// fragments of 64 lanes x 8 BF16 (512 elements), fragment (ob, kb) at
+// index frag_off[l] + ob * (pad_in[l]/32) + kb; its biases (padded to
+// pad_out[l]) start at bias_off[l].  w_off / b_off locate the layer in the
+// flat FP32 parameters.
+struct SurrogateNet {
+  int L;
+  int n_in[kSurMaxLayers + 2], n_out[kSurMaxLayers + 2];
+  int pad_in[kSurMaxLayers + 2], pad_out[kSurMaxLayers + 2];
+  int w_off[kSurMaxLayers + 2], b_off[kSurMaxLayers + 2];
+  int frag_off[kSurMaxLayers + 2];
+  int bias_off[kSurMaxLayers + 2];
+  int64_t frag_elems;
+  int bias_elems;
+};
+
+// Input x_k = (u_k - in_shift_k) in_scale_k for the states, plus the
+// stimulus flag I * flag_scale when the network has S + 1 inputs; output
+// du_k = out_shift_k + out_scale_k o_k; residual scale 1 / s_k.
+struct SurrogateScales {
+  int n_in;
+  float flag_scale;
+  float tol;
+  float in_shift[kSurMaxStates], in_scale[kSurMaxStates];
+  float out_shift[kSurMaxStates], out_scale[kSurMaxStates];
+  float inv_res[kSurMaxStates];
+};
+
+hipError_t launch_pack(const SurrogateNet& net, const float* params, __bf16* frags, float* biases,
+                       hipStream_t s);
+size_t surrogate_lds_bytes(int model, const SurrogateNet& net);
+hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
+                                 const __bf16* frags, const float* biases,
+                                 const SurrogateScales& sc, int32_t step_a, int* list, int* count,
+                                 int grid, hipStream_t s);
+
+hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
+                                    const __bf16* frags, const float* biases,
+                                    const SurrogateScales& sc, int32_t step_a, float* pred,
+                                    int grid, hipStream_t s);
+
+}  // namespace fib

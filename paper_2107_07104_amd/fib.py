@@ -40,7 +40,9 @@ EXPORTS = (
     "fib_run", "fib_get_tact", "fib_reset_observables", "fib_sync", "fib_plan_info",
     "fib_plan_preview", "fib_mlp_create", "fib_mlp_destroy", "fib_mlp_n_params",
     "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
-    "fib_mlp_adam_step", "fib_mlp_reset_optimizer",
+    "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
+    "fib_surrogate_last_fallbacks", "fib_step_surrogate",
+    "fib_surrogate_predict",
 )
 
 
@@ -113,6 +115,12 @@ def lib():
             "fib_mlp_gradient": ([_vp, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
             "fib_mlp_adam_step": ([_vp, _vp, _vp, C.c_int64, C.c_double, _vp], C.c_int),
             "fib_mlp_reset_optimizer": ([_vp], C.c_int),
+            "fib_set_surrogate": ([_vp, _vp, _fp, _fp, _fp, _fp, _fp, C.c_double, C.c_double],
+                                  C.c_int),
+            "fib_clear_surrogate": ([_vp], C.c_int),
+            "fib_step_surrogate": ([_vp, C.c_int64], C.c_int),
+            "fib_surrogate_predict": ([_vp, C.c_int64, _vp], C.c_int),
+            "fib_surrogate_last_fallbacks": ([_vp, C.POINTER(C.c_int64)], C.c_int),
         })
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -303,6 +311,32 @@ def fib_mlp_reset_optimizer(net) -> None:
     _check(lib().fib_mlp_reset_optimizer(_vp(net)))
 
 
+def fib_set_surrogate(ctx, net, in_shift, in_scale, out_shift, out_scale, res_scale,
+                      flag_scale: float, tol: float) -> None:
+    arrs = [np.ascontiguousarray(a, dtype=np.float32)
+            for a in (in_shift, in_scale, out_shift, out_scale, res_scale)]
+    _check(lib().fib_set_surrogate(_vp(ctx), _vp(net), *[a.ctypes.data_as(_fp) for a in arrs],
+                                   float(flag_scale), float(tol)))
+
+
+def fib_step_surrogate(ctx, step: int) -> None:
+    _check(lib().fib_step_surrogate(_vp(ctx), int(step)))
+
+
+def fib_surrogate_predict(ctx, step: int, du_ptr: int) -> None:
+    _check(lib().fib_surrogate_predict(_vp(ctx), int(step), _vp(du_ptr)))
+
+
+def fib_clear_surrogate(ctx) -> None:
+    _check(lib().fib_clear_surrogate(_vp(ctx)))
+
+
+def fib_surrogate_last_fallbacks(ctx) -> int:
+    n = C.c_int64()
+    _check(lib().fib_surrogate_last_fallbacks(_vp(ctx), C.byref(n)))
+    return n.value
+
+
 class Mlp:
     """Owns one surrogate network; data arrays are torch CUDA tensors."""
 
@@ -431,3 +465,25 @@ class Solver:
 
     def plan(self):
         return fib_plan_info(self.ctx)
+
+    def set_surrogate(self, net, scales: dict, tol: float):
+        fib_set_surrogate(self.ctx, net.net, scales["in_shift"], scales["in_scale"],
+                          scales["out_shift"], scales["out_scale"], scales["res_scale"],
+                          scales.get("flag_scale", 0.0), tol)
+
+    def step_surrogate(self, step):
+        fib_step_surrogate(self.ctx, step)
+
+    def surrogate_predict(self, step=0):
+        """Predicted increments [S, n_total] (device tensor) for the current
+        state; no state changes."""
+        import torch
+        du = torch.empty((self.S, self.n_total), dtype=torch.float32, device="cuda")
+        fib_surrogate_predict(self.ctx, step, du.data_ptr())
+        return du
+
+    def clear_surrogate(self):
+        fib_clear_surrogate(self.ctx)
+
+    def last_fallbacks(self):
+        return fib_surrogate_last_fallbacks(self.ctx)

@@ -118,19 +118,22 @@ def single_fiber(amp: float = AMP_AS_WRITTEN, n_nodes: int = 1000, t_end: float 
 
 def batched_hh(n_fibers: int = 1369, n_min: int = 1000, n_max: int = 1500,
                t_end: float = 20.0, amp: float = AMP_SUPRA, dt: float = 1e-3,
-               onset_max: float = 5.0) -> Workload:
+               onset_max: float = 5.0, realization: int = 0) -> Workload:
     """1369 fibers with lengths uniform in {1000..1500}; each fiber is
     stimulated for 0.1 ms on three nodes around a node drawn uniformly from
     the central 10 % of the fiber, at a time drawn uniformly from [0, 5] ms
-    and snapped to a split step; V_m noise N(0, 0.1 mV); 20 ms."""
+    and snapped to a split step; V_m noise N(0, 0.1 mV); 20 ms.
+    `realization` > 0 draws an independent set of stimulus nodes, onsets and
+    noise (seeds shifted by 100 per realization) on the same fibers."""
     g_len = np.random.Generator(np.random.PCG64(SEED_LENGTHS))
     lengths = g_len.integers(n_min, n_max + 1, size=n_fibers).astype(np.int32)
-    g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE))
+    shift = 100 * int(realization)
+    g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE + shift))
     u_node = g_node.random(n_fibers)
-    g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME))
+    g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME + shift))
     u_time = g_time.random(n_fibers)
     n_total = int(lengths.sum())
-    noise = _normal(SEED_VM_NOISE, n_total, 0.1)
+    noise = _normal(SEED_VM_NOISE + shift, n_total, 0.1)
     stims = []
     pulse = int(round(0.1 / dt))
     for f in range(n_fibers):
