@@ -227,10 +227,16 @@ int fib_plan_info(const fib_t* ctx, int32_t* groups, int32_t* threads, int32_t* 
  * ------------------------------------------------------------------------ */
 typedef struct fib_mlp fib_mlp_t;
 
-/* Creates a network with n_layers weight layers (1..6) and layer widths
- * sizes[0..n_layers] (1..512; sizes[0] = inputs).  Parameters start at 0:
- * set them with fib_mlp_set_params.  `stream` as for fib_create. */
-int fib_mlp_create(int32_t n_layers, const int32_t* sizes, void* stream, fib_mlp_t** out);
+/* Hidden-layer activations: SiLU(z) = z / (1 + e^-z); ReLU(z) = max(z, 0). */
+#define FIB_ACT_SILU 0
+#define FIB_ACT_RELU 1
+
+/* Creates a network with n_layers weight layers (1..6), layer widths
+ * sizes[0..n_layers] (1..512; sizes[0] = inputs) and the given hidden
+ * activation (the output layer is linear).  Parameters start at 0: set
+ * them with fib_mlp_set_params.  `stream` as for fib_create. */
+int fib_mlp_create(int32_t n_layers, const int32_t* sizes, int32_t activation, void* stream,
+                   fib_mlp_t** out);
 void fib_mlp_destroy(fib_mlp_t* net);
 int64_t fib_mlp_n_params(const fib_mlp_t* net);
 
@@ -266,14 +272,15 @@ int fib_mlp_reset_optimizer(fib_mlp_t* net);
  *           stimulus of step n) when the network has n_states + 1 inputs;
  *   outputs du_k = out_shift[k] + out_scale[k] * o_k (the predictor);
  *   corrector du1 = dt G(y + du/2, I), du2 = dt G(y + du1/2, I)
- *   (G: the model's right-hand side; two fixed-point iterations of the
- *   implicit midpoint rule started from the prediction).
- * A node takes du2 only if |du1 - du|_k <= tol * res_scale[k] for every
+ *   (G: the model's right-hand side; fixed-point iterations of the
+ *   implicit midpoint rule started from the prediction: two for
+ *   Hodgkin-Huxley, one for ST57, whose right-hand side dominates the cost).
+ * A node takes the last iterate du_c only if |du1 - du|_k <= tol * res_scale[k] for every
  * state k (absolute tolerances), its stimulus is the same in both halves,
  * and (for networks without the flag input) it is not stimulated; all
  * other nodes take the plain Heun substeps.  Steps that write V_m samples,
  * and the last step of a call, run the plain path for every node.  For
- * kept nodes the activation-time test uses the midpoint y + du2/2 as the
+ * kept nodes the activation-time test uses the midpoint y + du_c/2 as the
  * state at the end of step n.  The surrogate is an addition of this
  * library: the thesis names learned surrogate models only as an outlook.
  * Supported shapes: Hodgkin-Huxley 4 or 5 -> 64 -> 64 -> 64 -> 4, ST57

@@ -1,8 +1,10 @@
 """FP64 reference of the surrogate network (test infrastructure only).
 
 The surrogate of the subcellular update is a plain multilayer perceptron:
-    z_l = W_l a_{l-1} + b_l,   a_l = SiLU(z_l) for hidden layers,
-    output = z_L (linear),     SiLU(z) = z / (1 + exp(-z)),
+    z_l = W_l a_{l-1} + b_l,   a_l = f(z_l) for hidden layers,
+    output = z_L (linear),
+with f = SiLU, SiLU(z) = z / (1 + exp(-z)), or f = ReLU, ReLU(z) = max(z, 0)
+(derivative taken as 0 at z = 0),
 trained on the mean squared error
     loss = 1 / (2 B n_out) * sum_b sum_k (output_bk - target_bk)^2
 with Adam (Kingma & Ba 2015):
@@ -30,6 +32,17 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
+def relu(z):
+    return np.maximum(z, 0.0)
+
+
+def relu_grad(z):
+    return (np.asarray(z) > 0.0).astype(np.float64)
+
+
+ACTS = {"silu": (silu, silu_grad), "relu": (relu, relu_grad)}
+
+
 def init_params(sizes, seed: int):
     """He-style uniform initialisation, seeded (the GPU side receives these
     arrays as inputs; it does not draw its own)."""
@@ -44,27 +57,29 @@ def init_params(sizes, seed: int):
     return params
 
 
-def forward(params, X):
+def forward(params, X, act: str = "silu"):
     """X: (B, in) -> (outputs (B, out), cache of pre-activations)."""
+    f = ACTS[act][0]
     a = np.asarray(X, dtype=np.float64)
     zs, acts = [], [a]
     for i, (W, b) in enumerate(params):
         z = a @ W.T + b
         zs.append(z)
-        a = silu(z) if i < len(params) - 1 else z
+        a = f(z) if i < len(params) - 1 else z
         acts.append(a)
     return a, (zs, acts)
 
 
-def loss(params, X, T):
-    O, _ = forward(params, X)
+def loss(params, X, T, act: str = "silu"):
+    O, _ = forward(params, X, act)
     B, n = O.shape
     return 0.5 * np.sum((O - T) ** 2) / (B * n)
 
 
-def backward(params, X, T):
+def backward(params, X, T, act: str = "silu"):
     """Gradients of `loss` with respect to every W and b."""
-    O, (zs, acts) = forward(params, X)
+    fg = ACTS[act][1]
+    O, (zs, acts) = forward(params, X, act)
     B, n = O.shape
     dz = (O - T) / (B * n)
     grads = [None] * len(params)
@@ -75,7 +90,7 @@ def backward(params, X, T):
         grads[i] = (gW, gb)
         if i > 0:
             da = dz @ W
-            dz = da * silu_grad(zs[i - 1])
+            dz = da * fg(zs[i - 1])
     return grads
 
 

@@ -271,6 +271,7 @@ struct fib_ctx {
   fib::SurrogateScales sur_sc{};
   __bf16* d_sur_frags = nullptr;
   float* d_sur_bias = nullptr;
+  float* d_sur_tab = nullptr;
   int* d_sur_list = nullptr;
   int* d_sur_count = nullptr;
   int sur_grid = 0;
@@ -674,6 +675,7 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_stim);
   (void)hipFree(c->d_sur_frags);
   (void)hipFree(c->d_sur_bias);
+  (void)hipFree(c->d_sur_tab);
   (void)hipFree(c->d_sur_list);
   (void)hipFree(c->d_sur_count);
   delete c;
@@ -880,9 +882,9 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     const bool last = n + 1 >= end;
     const bool sample = a.samples && a.sample_every > 0 && (n + 1) % a.sample_every == 0;
     if (c->sur_on && !last && !sample) {
-      HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
-                                         c->sur_sc, (int32_t)n, c->d_sur_list, c->d_sur_count,
-                                         c->sur_grid, c->stream));
+      HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags,
+                                         c->d_sur_bias, c->d_sur_tab, c->sur_sc, (int32_t)n,
+                                         c->d_sur_list, c->d_sur_count, c->sur_grid, c->stream));
     } else {
       const int flags = 1 | 2 | (last ? 0 : 4);
       HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
@@ -913,6 +915,7 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
                 "4 or 5 -> 64 -> 64 -> 64 -> 4; ST57: 57 or 58 -> 128 -> 128 -> 57)");
   fib::SurrogateNet sn{};
   sn.L = ms.L;
+  sn.act = ms.act;
   int frags = 0, bias = 0;
   for (int l = 1; l <= ms.L; ++l) {
     sn.n_in[l] = ms.size[l - 1];
@@ -934,15 +937,20 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   sc.n_in = ms.size[0];
   sc.flag_scale = (float)flag_scale;
   sc.tol = (float)tol;
+  constexpr int T = fib::kSurMaxStates;
+  std::vector<float> tab((size_t)fib::kSurTabs * T, 0.0f);
+  const KArgs a0 = base_args(c);
   for (int k = 0; k < S; ++k) {
     if (!(in_scale[k] > 0.0f) || !(out_scale[k] > 0.0f) || !(res_scale[k] > 0.0f) ||
-        !std::isfinite(in_shift[k]) || !std::isfinite(out_shift[k]))
+        !std::isfinite(in_shift[k]) || !std::isfinite(out_shift[k]) ||
+        !std::isfinite(in_scale[k]) || !std::isfinite(out_scale[k]) || !std::isfinite(res_scale[k]))
       return fail(FIB_EINVAL, "state %d: scales must be finite and > 0", k);
-    sc.in_shift[k] = in_shift[k];
-    sc.in_scale[k] = in_scale[k];
-    sc.out_shift[k] = out_shift[k];
-    sc.out_scale[k] = out_scale[k];
-    sc.inv_res[k] = 1.0f / res_scale[k];
+    tab[fib::kTabInShift * T + k] = in_shift[k];
+    tab[fib::kTabInScale * T + k] = in_scale[k];
+    tab[fib::kTabOutShift * T + k] = out_shift[k];
+    tab[fib::kTabOutScale * T + k] = out_scale[k];
+    tab[fib::kTabInvRes * T + k] = 1.0f / res_scale[k];
+    tab[fib::kTabRest * T + k] = a0.rest[k];
   }
   const size_t lds = fib::surrogate_lds_bytes(c->p.model, sn);
   if (lds > c->max_lds) return fail(FIB_EUNSUPPORTED, "surrogate needs %zu bytes of LDS", lds);
@@ -956,6 +964,9 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   if (hipMalloc(&c->d_sur_frags, (size_t)sn.frag_elems * 2) != hipSuccess ||
       hipMalloc(&c->d_sur_bias, (size_t)sn.bias_elems * 4) != hipSuccess)
     return fail(FIB_ENOMEM, "device allocation failed");
+  if (!c->d_sur_tab && hipMalloc(&c->d_sur_tab, sizeof(float) * tab.size()) != hipSuccess)
+    return fail(FIB_ENOMEM, "device allocation failed");
+  HIP_TRY(hipMemcpy(c->d_sur_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
   if (!c->d_sur_list) {
     if (hipMalloc(&c->d_sur_list, sizeof(int) * (size_t)std::max<int64_t>(c->n_total, 1)) != hipSuccess ||
         hipMalloc(&c->d_sur_count, sizeof(int)) != hipSuccess)
@@ -981,8 +992,8 @@ int fib_step_surrogate(fib_t* c, int64_t step) {
   a.n_sub = (int32_t)ns;
   a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
   HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
-                                     c->sur_sc, (int32_t)step, c->d_sur_list, c->d_sur_count,
-                                     c->sur_grid, c->stream));
+                                     c->d_sur_tab, c->sur_sc, (int32_t)step, c->d_sur_list,
+                                     c->d_sur_count, c->sur_grid, c->stream));
   return FIB_OK;
 }
 
@@ -994,7 +1005,8 @@ int fib_surrogate_predict(fib_t* c, int64_t step, float* du) {
   if (step < 0 || step + 1 >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
   KArgs a = base_args(c);
   HIP_TRY(fib::launch_surrogate_predict(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
-                                        c->sur_sc, (int32_t)step, du, c->sur_grid, c->stream));
+                                        c->d_sur_tab, c->sur_sc, (int32_t)step, du, c->sur_grid,
+                                        c->stream));
   return FIB_OK;
 }
 

@@ -69,13 +69,17 @@ int ensure_parts(fib_mlp* n, int64_t chunks) {
 
 extern "C" {
 
-int fib_mlp_create(int32_t n_layers, const int32_t* sizes, void* stream, fib_mlp_t** out) {
+int fib_mlp_create(int32_t n_layers, const int32_t* sizes, int32_t activation, void* stream,
+                   fib_mlp_t** out) {
   if (!out) return mfail(FIB_EINVAL, "null output pointer");
   *out = nullptr;
   if (n_layers < 1 || n_layers > fib::kMaxLayers || !sizes)
     return mfail(FIB_EINVAL, "the network needs 1..%d weight layers", fib::kMaxLayers);
+  if (activation != FIB_ACT_SILU && activation != FIB_ACT_RELU)
+    return mfail(FIB_EINVAL, "unknown activation %d", activation);
   fib::MlpShape s{};
   s.L = n_layers;
+  s.act = activation;
   int64_t off = 0;
   for (int l = 0; l <= n_layers; ++l) {
     if (sizes[l] < 1 || sizes[l] > 512) return mfail(FIB_EINVAL, "layer width %d not in 1..512", sizes[l]);

@@ -21,6 +21,7 @@ struct MlpShape {
   int w_off[kMaxLayers + 1];    // offset of W_l in the flat parameters
   int b_off[kMaxLayers + 1];    // offset of b_l
   int n_params;
+  int act;                      // hidden activation: FIB_ACT_SILU or FIB_ACT_RELU
 };
 
 size_t mlp_train_lds_bytes(const MlpShape& s);

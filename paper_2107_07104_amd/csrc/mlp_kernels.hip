@@ -1,6 +1,6 @@
 // Surrogate network kernels (gfx950): batched forward pass, backpropagation
-// and Adam for a multilayer perceptron with SiLU hidden layers and a linear
-// output, trained on the mean squared error.  Every matrix product runs on
+// and Adam for a multilayer perceptron with SiLU or ReLU hidden layers and
+// a linear output, trained on the mean squared error.  Every matrix product runs on
 // the matrix cores (v_mfma_f32_16x16x32_bf16: BF16 operands, FP32
 // accumulation); the master weights, moments and gradients are FP32.
 //
@@ -13,6 +13,7 @@
 // plain structure: one wave per workgroup, a chunk of kChunk samples, every
 // activation in LDS in FP32, operands converted to BF16 when they are
 // loaded into the matrix-core registers.
+#include "../../include/fib.h"
 #include "fib_internal.h"
 #include "mlp_internal.h"
 
@@ -62,6 +63,13 @@ __device__ __forceinline__ float silu(float z) { return z * __builtin_amdgcn_rcp
 __device__ __forceinline__ float silu_grad(float z) {
   const float s = __builtin_amdgcn_rcpf(1.0f + __expf(-z));
   return s * fmaf(z, 1.0f - s, 1.0f);
+}
+// Hidden activation and its derivative (ReLU'(0) taken as 0).
+__device__ __forceinline__ float act_fn(int act, float z) {
+  return act == FIB_ACT_RELU ? fmaxf(z, 0.0f) : silu(z);
+}
+__device__ __forceinline__ float act_grad(int act, float z) {
+  return act == FIB_ACT_RELU ? (z > 0.0f ? 1.0f : 0.0f) : silu_grad(z);
 }
 
 // LDS plan of the training kernel (floats): for every layer l = 0..L an
@@ -125,7 +133,7 @@ __device__ void chunk_forward(const MlpShape& s, const float* __restrict__ param
       float v = j < nout ? dst[e] + bias[j] : 0.0f;
       if (l < s.L) {
         if (keep_z) dst[e] = v;
-        v = j < nout ? silu(v) : 0.0f;
+        v = j < nout ? act_fn(s.act, v) : 0.0f;
       }
       lds[t.act[l] + e] = v;
     }
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(64) void k_mlp_grad(MlpShape s, const float* __rest
       __syncthreads();
       for (int e = lane; e < kChunk * pin; e += 64) {
         const int j = e % pin;
-        nxt[e] = j < nin ? nxt[e] * silu_grad(lds[t.z[l - 1] + e]) : 0.0f;
+        nxt[e] = j < nin ? nxt[e] * act_grad(s.act, lds[t.z[l - 1] + e]) : 0.0f;
       }
       cur ^= 1;
     }

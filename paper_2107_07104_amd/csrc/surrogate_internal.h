@@ -18,9 +18,10 @@ constexpr int kSurMaxStates = 64;
 // fragments of 64 lanes x 8 BF16 (512 elements), fragment (ob, kb) at
 // index frag_off[l] + ob * (pad_in[l]/32) + kb; its biases (padded to
 // pad_out[l]) start at bias_off[l].  w_off / b_off locate the layer in the
-// flat FP32 parameters.
+// flat FP32 parameters.  act: hidden activation (FIB_ACT_*).
 struct SurrogateNet {
   int L;
+  int act;
   int n_in[kSurMaxLayers + 2], n_out[kSurMaxLayers + 2];
   int pad_in[kSurMaxLayers + 2], pad_out[kSurMaxLayers + 2];
   int w_off[kSurMaxLayers + 2], b_off[kSurMaxLayers + 2];
@@ -30,28 +31,29 @@ struct SurrogateNet {
   int bias_elems;
 };
 
-// Input x_k = (u_k - in_shift_k) in_scale_k for the states, plus the
-// stimulus flag I * flag_scale when the network has S + 1 inputs; output
-// du_k = out_shift_k + out_scale_k o_k; residual scale 1 / s_k.
+// Per-state tables of the surrogate step (device memory, kSurTabs rows of
+// kSurMaxStates floats): input x_k = (u_k - in_shift_k) in_scale_k, output
+// du_k = out_shift_k + out_scale_k o_k, acceptance |du1_k - du_k| inv_res_k
+// <= tol, and the resting state the offsets u are taken from.
+enum { kTabInShift = 0, kTabInScale, kTabOutShift, kTabOutScale, kTabInvRes, kTabRest, kSurTabs };
+
+// Scalars of the step: network inputs (n_states, or n_states + 1 with the
+// stimulus flag I * flag_scale) and the acceptance tolerance.
 struct SurrogateScales {
   int n_in;
   float flag_scale;
   float tol;
-  float in_shift[kSurMaxStates], in_scale[kSurMaxStates];
-  float out_shift[kSurMaxStates], out_scale[kSurMaxStates];
-  float inv_res[kSurMaxStates];
 };
 
 hipError_t launch_pack(const SurrogateNet& net, const float* params, __bf16* frags, float* biases,
                        hipStream_t s);
 size_t surrogate_lds_bytes(int model, const SurrogateNet& net);
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
-                                 const __bf16* frags, const float* biases,
+                                 const __bf16* frags, const float* biases, const float* tab,
                                  const SurrogateScales& sc, int32_t step_a, int* list, int* count,
                                  int grid, hipStream_t s);
-
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
-                                    const __bf16* frags, const float* biases,
+                                    const __bf16* frags, const float* biases, const float* tab,
                                     const SurrogateScales& sc, int32_t step_a, float* pred,
                                     int grid, hipStream_t s);
 

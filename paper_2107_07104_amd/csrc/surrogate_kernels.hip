@@ -5,27 +5,39 @@
 // R(dt/2) of step n+1, by one implicit-midpoint step of width dt,
 //   du* = dt G(y + du*/2, I),
 // solved by fixed-point iteration from the network's prediction du:
-//   du1 = dt G(y + du/2, I),   du2 = dt G(y + du1/2, I).
-// The iteration contracts by q = dt |dG/dy| / 2 (a few percent at the
-// split steps used here), so |du1 - du| measures the network's error and
-// du2 lies within about q^2 |du1 - du| of du*.  A node keeps du2 only if
+//   du1 = dt G(y + du/2, I),   du2 = dt G(y + du1/2, I), ...
+// The iteration contracts by q = dt |dG/dy| / 2 (about 0.02 for
+// Hodgkin-Huxley at dt = 5e-3 ms, up to 0.26 for ST57 at dt = 5e-4 ms), so
+// |du1 - du| measures the network's error and the c-th iterate lies within
+// about q^c |du1 - du| / (1 - q) of du*.  Hodgkin-Huxley takes two
+// iterations (its right-hand side is cheap), ST57 one (its right-hand side
+// is most of the step's arithmetic).  A node keeps the last iterate only if
 // |du1 - du|_k <= tol * atol_k for every state k; every other node -- and
 // every node whose stimulus changes between the two halves -- is appended
 // to a compacted list that the fallback kernel advances with the plain
 // Heun substeps.  The state at the end of step n, which the pair never
-// forms, is taken as the midpoint y + du2/2 for the activation-time
-// observable; steps that write V_m samples run the plain path everywhere.
+// forms, is taken as the midpoint y + du_c/2 of the last iterate du_c for
+// the activation-time observable; steps that write V_m samples run the
+// plain path everywhere.
 //
-// Network on the matrix cores, one wave per 64 nodes: nodes are the N
-// dimension of v_mfma_f32_16x16x32_bf16 (16 nodes per instruction, four
-// groups per wave) and the weights are the A operand, pre-packed in BF16
-// fragments that the workgroup stages in LDS.  A layer's output D holds, in
-// lane l, features 16 ob + 4 (l / 16) + j of node l % 16; the next layer
-// takes its K-block kb from the output blocks 2 kb and 2 kb + 1 of the same
-// lane, so activations stay in registers and the weight packing absorbs the
+// Network on the matrix cores, one wave per tile of 64 nodes (lane = node
+// for everything outside the network): nodes are the N dimension of
+// v_mfma_f32_16x16x32_bf16 (16 nodes per instruction, four node groups per
+// tile) and the weights are the A operand, pre-packed in BF16 fragments
+// that the workgroup stages in LDS once; every fragment read from LDS
+// serves the four groups.  A layer's output D holds, in lane l, features
+// 16 ob + 4 (l / 16) + j of node l % 16 of the group; the next layer takes
+// its K-block kb from the output blocks 2 kb and 2 kb + 1 of the same lane,
+// so activations stay in registers and the weight packing absorbs the
 // implied permutation of the K index:
 //   K index 8 g + i  <->  feature 32 kb + 4 g + i          (i < 4)
 //                          feature 32 kb + 16 + 4 g + i - 4 (i >= 4).
+// The node-major network inputs (BF16) and outputs (FP16) pass through a
+// per-wave LDS region whose row strides (KIN_PAD + 8 and OUT_PAD + 4
+// elements) spread 16-byte row accesses of consecutive lanes over all
+// banks; the outputs overwrite the inputs, which are all in registers by
+// then.  Biases initialise the accumulators.
+#include "../../include/fib.h"
 #include "fib_internal.h"
 #include "hh_model.h"
 #include "st57_model.h"
@@ -71,8 +83,37 @@ __global__ __launch_bounds__(256) void k_pack(SurrogateNet net, const float* __r
   }
 }
 
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
+typedef short v2s __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
+typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+
 __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
+}
+
+// Hidden activation of two pre-activations, packed as two BF16 values.
+// ReLU acts on the packed BF16 bits: as 16-bit integers, negative BF16
+// values (sign bit set) are negative, so max(bits, 0) is ReLU exactly.
+template <int ACT>
+__device__ __forceinline__ unsigned act_pack(float a, float b) {
+  if constexpr (ACT == FIB_ACT_RELU) {
+    const v2bf p = __builtin_convertvector((v2f){a, b}, v2bf);
+    const v2s m = __builtin_elementwise_max(__builtin_bit_cast(v2s, p), (v2s){0, 0});
+    return __builtin_bit_cast(unsigned, m);
+  } else {
+    const v2bf p = __builtin_convertvector((v2f){silu_fast(a), silu_fast(b)}, v2bf);
+    return __builtin_bit_cast(unsigned, p);
+  }
+}
+
+__device__ __forceinline__ unsigned pack_bf16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){a, b}, v2bf));
+}
+
+__device__ __forceinline__ unsigned pack_f16(float a, float b) {
+  return __builtin_bit_cast(unsigned, __builtin_convertvector((v2f){a, b}, v2h));
 }
 
 // Model adapters: number of states, offsets -> increments of one Heun step.
@@ -110,8 +151,21 @@ struct SurST57 {
   }
 };
 
-// Observables at the end of split step `step` from V offset v1 (see
-// k_react in fib_kernels.hip for the same rules).
+// Walks the S columns of the state array at one node: the column stride
+// n_total is added to a pointer held in a vector register and hidden from
+// the optimizer, which would otherwise keep all S 64-bit column offsets in
+// scalar registers across the persistent loop (hundreds for ST57).
+struct Column {
+  const float* p;
+  int64_t stride;
+  __device__ __forceinline__ void next() {
+    p += stride;
+    __asm__("" : "+v"(p));
+  }
+};
+
+// Observables at the end of split step `step` from V offset v1 (the same
+// rules as the plain reaction kernel).
 __device__ __forceinline__ void observe(const KArgs& A, int64_t i, int32_t step, float v1) {
   const float v0 = A.v_prev[i];
   const float uth = A.v_th - A.rest[0];
@@ -121,132 +175,157 @@ __device__ __forceinline__ void observe(const KArgs& A, int64_t i, int32_t step,
   if (!isfinite(v1)) atomicOr(A.flag, 1);
 }
 
-// One wave of 64 nodes through the network.  X: LDS staging [64][KIN_PAD]
-// (BF16, node-major); O: LDS staging [64][OUT_PAD] (FP32).  The packed
-// weights and biases are in LDS (wfr, wb).
-template <int KIN_PAD, int H, int NHID, int OUT_PAD>
-__device__ __forceinline__ void wave_network(const __bf16* X, float* O, const __bf16* wfr,
-                                             const float* wb, const SurrogateNet& net,
+template <int KIN_PAD, int OUT_PAD>
+struct Stage {
+  static constexpr int XS = KIN_PAD + 8;  // BF16 elements per input row
+  static constexpr int OS = OUT_PAD + 4;  // FP16 elements per output row
+  static constexpr int kBytes = 64 * XS * 2 > 64 * OS * 2 ? 64 * XS * 2 : 64 * OS * 2;
+  static_assert(kBytes % 16 == 0, "stage alignment");
+};
+
+// The network for the 64 nodes of one tile: inputs from the wave's stage
+// (rows of XS BF16), outputs back to the same stage (rows of OS FP16).
+// The four node groups go through in passes of NG groups; each weight
+// fragment read from LDS serves the NG groups of a pass (NG = 4 needs the
+// most registers, NG = 1 reads every fragment four times).
+template <int KIN_PAD, int H, int NHID, int OUT_PAD, int ACT, int NG>
+__device__ __forceinline__ void wave_network(char* stage, const v8bf* __restrict__ frag,
+                                             const float* __restrict__ wb, const SurrogateNet& net,
                                              int lane) {
-  constexpr int HB = H / 16;         // output blocks of a hidden layer
+  using St = Stage<KIN_PAD, OUT_PAD>;
   constexpr int KB0 = KIN_PAD / 32;  // K-blocks of the input layer
-  constexpr int KBH = H / 32;        // K-blocks of a hidden-to-next layer
+  constexpr int HB = H / 16;         // output blocks of a hidden layer
+  constexpr int KBH = H / 32;        // K-blocks of a layer fed by a hidden layer
   constexpr int OB = OUT_PAD / 16;   // output blocks of the last layer
+  static_assert(4 % NG == 0, "groups per pass");
   const int r = lane & 15, g = lane >> 4;
-  const v8bf* frag = reinterpret_cast<const v8bf*>(wfr);
-  for (int grp = 0; grp < 4; ++grp) {
-    const int node = 16 * grp + r;
-    // input layer
-    v8bf b0[KB0];
+  const __bf16* X = reinterpret_cast<const __bf16*>(stage);
+  _Float16* O = reinterpret_cast<_Float16*>(stage);
+
+  // all inputs of the tile to registers first: the outputs overwrite them
+  v8bf bin[4][KB0];
+#pragma unroll
+  for (int grp = 0; grp < 4; ++grp)
 #pragma unroll
     for (int kb = 0; kb < KB0; ++kb)
-      b0[kb] = *reinterpret_cast<const v8bf*>(X + node * KIN_PAD + 32 * kb + 8 * g);
-    v4f acc[HB];
+      bin[grp][kb] = *reinterpret_cast<const v8bf*>(X + (16 * grp + r) * St::XS + 32 * kb + 8 * g);
+  __builtin_amdgcn_wave_barrier();
+
+#pragma unroll
+  for (int pass = 0; pass < 4 / NG; ++pass) {
+    v4f acc[NG][HB];
 #pragma unroll
     for (int ob = 0; ob < HB; ++ob) {
-      v4f c = {0.0f, 0.0f, 0.0f, 0.0f};
+      const v4f bias = *reinterpret_cast<const v4f*>(wb + net.bias_off[1] + 16 * ob + 4 * g);
 #pragma unroll
-      for (int kb = 0; kb < KB0; ++kb)
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(frag[(net.frag_off[1] + ob * KB0 + kb) * 64 + lane],
-                                                    b0[kb], c, 0, 0, 0);
-      acc[ob] = c;
-    }
-    // hidden layers 2..NHID (hidden to hidden), then the output layer
-    int layer = 1;
+      for (int q = 0; q < NG; ++q) acc[q][ob] = bias;
 #pragma unroll
-    for (int hl = 0; hl < NHID; ++hl, ++layer) {
-      // bias + SiLU, pack to the next layer's B operands
-      v8bf b[KBH];
+      for (int kb = 0; kb < KB0; ++kb) {
+        const v8bf a = frag[(net.frag_off[1] + ob * KB0 + kb) * 64 + lane];
 #pragma unroll
-      for (int ob = 0; ob < HB; ++ob) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const float z = acc[ob][j] + wb[net.bias_off[layer] + 16 * ob + 4 * g + j];
-          b[ob >> 1][(ob & 1) * 4 + j] = (__bf16)silu_fast(z);
-        }
+        for (int q = 0; q < NG; ++q)
+          acc[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bin[pass * NG + q][kb], acc[q][ob],
+                                                               0, 0, 0);
       }
+    }
+#pragma unroll
+    for (int hl = 0; hl < NHID; ++hl) {
+      // activation of hidden layer hl + 1, packed into the next layer's B operands
+      v8bf b[NG][KBH];
+#pragma unroll
+      for (int q = 0; q < NG; ++q)
+#pragma unroll
+        for (int kb = 0; kb < KBH; ++kb) {
+          const v4f lo = acc[q][2 * kb], hi = acc[q][2 * kb + 1];
+          const v4u w = {act_pack<ACT>(lo[0], lo[1]), act_pack<ACT>(lo[2], lo[3]),
+                         act_pack<ACT>(hi[0], hi[1]), act_pack<ACT>(hi[2], hi[3])};
+          b[q][kb] = __builtin_bit_cast(v8bf, w);
+        }
+      const int layer = hl + 2;
       if (hl + 1 < NHID) {
 #pragma unroll
         for (int ob = 0; ob < HB; ++ob) {
-          v4f c = {0.0f, 0.0f, 0.0f, 0.0f};
+          const v4f bias = *reinterpret_cast<const v4f*>(wb + net.bias_off[layer] + 16 * ob + 4 * g);
 #pragma unroll
-          for (int kb = 0; kb < KBH; ++kb)
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                frag[(net.frag_off[layer + 1] + ob * KBH + kb) * 64 + lane], b[kb], c, 0, 0, 0);
-          acc[ob] = c;
+          for (int q = 0; q < NG; ++q) acc[q][ob] = bias;
+#pragma unroll
+          for (int kb = 0; kb < KBH; ++kb) {
+            const v8bf a = frag[(net.frag_off[layer] + ob * KBH + kb) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+              acc[q][ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][kb], acc[q][ob], 0, 0, 0);
+          }
         }
       } else {
-        // output layer
 #pragma unroll
         for (int ob = 0; ob < OB; ++ob) {
-          v4f c = {0.0f, 0.0f, 0.0f, 0.0f};
+          const v4f bias = *reinterpret_cast<const v4f*>(wb + net.bias_off[layer] + 16 * ob + 4 * g);
+          v4f out[NG];
 #pragma unroll
-          for (int kb = 0; kb < KBH; ++kb)
-            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                frag[(net.frag_off[layer + 1] + ob * KBH + kb) * 64 + lane], b[kb], c, 0, 0, 0);
+          for (int q = 0; q < NG; ++q) out[q] = bias;
 #pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int f = 16 * ob + 4 * g + j;
-            O[node * OUT_PAD + f] = c[j] + wb[net.bias_off[layer + 1] + f];
+          for (int kb = 0; kb < KBH; ++kb) {
+            const v8bf a = frag[(net.frag_off[layer] + ob * KBH + kb) * 64 + lane];
+#pragma unroll
+            for (int q = 0; q < NG; ++q)
+              out[q] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[q][kb], out[q], 0, 0, 0);
+          }
+#pragma unroll
+          for (int q = 0; q < NG; ++q) {
+            const uint2 v = {pack_f16(out[q][0], out[q][1]), pack_f16(out[q][2], out[q][3])};
+            *reinterpret_cast<uint2*>(O + (16 * (pass * NG + q) + r) * St::OS + 16 * ob + 4 * g) = v;
           }
         }
       }
     }
   }
+  __builtin_amdgcn_wave_barrier();
 }
-
-// Staging of one wave in LDS: the FP32 network outputs O [64][OUT_PAD] and,
-// aliased into the same region, the BF16 inputs X [64][KIN_PAD] at byte
-// offset XOFF.  Group g (nodes 16 g .. 16 g + 15) reads its X rows before
-// it writes its O rows, and its O rows never reach the X rows of a later
-// group.
-template <int KIN_PAD, int OUT_PAD>
-struct Staging {
-  static constexpr int kOBytes = 64 * OUT_PAD * 4;
-  static constexpr int kXBytes = 64 * KIN_PAD * 2;
-  static constexpr int kGap = 3 * 16 * (OUT_PAD * 4 - KIN_PAD * 2);
-  static constexpr int kXOff = kGap > 0 ? (kGap + 15) / 16 * 16 : 0;
-  static constexpr int kBytes = (kOBytes > kXOff + kXBytes ? kOBytes : kXOff + kXBytes);
-};
 
 // Surrogate reaction pair for every node: finishes step `step_a` and
 // starts step `step_a + 1`.  Rejected nodes are appended to list[] through
 // count[0] (one atomic per wave).  With `pred` set, the kernel only writes
 // the predicted increments du ([S][n_total]) and changes no state.
 // Persistent: each wave walks the 64-node tiles tile = wave_id,
-// wave_id + waves, ...  Launch: 256 threads.
-template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD>
-__global__ __launch_bounds__(256) void k_surrogate(KArgs A, SurrogateNet net,
-                                                   const __bf16* __restrict__ frags,
-                                                   const float* __restrict__ biases,
-                                                   SurrogateScales sc, int32_t step_a,
-                                                   int* __restrict__ list,
-                                                   int* __restrict__ count,
-                                                   float* __restrict__ pred) {
+// wave_id + waves, ...  Launch: 64 WAVES threads.
+template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD, int ACT, int WAVES, int NG,
+          int NCORR>
+__global__ __launch_bounds__(64 * WAVES) void k_surrogate(
+    KArgs A, SurrogateNet net, const __bf16* __restrict__ frags, const float* __restrict__ biases,
+    const float* __restrict__ tab_g, SurrogateScales sc, int32_t step_a, int* __restrict__ list,
+    int* __restrict__ count, float* __restrict__ pred) {
   extern __shared__ float lds_f[];
-  using St = Staging<KIN_PAD, OUT_PAD>;
+  using St = Stage<KIN_PAD, OUT_PAD>;
   constexpr int S = M::S;
-  __bf16* wfr = reinterpret_cast<__bf16*>(lds_f);
+  constexpr int T = kSurMaxStates;
+  v8bf* wfr = reinterpret_cast<v8bf*>(lds_f);
   float* wb = lds_f + net.frag_elems / 2;
-  char* stage = reinterpret_cast<char*>(wb + net.bias_elems);
+  float* tab = wb + net.bias_elems;
+  char* stage_base = reinterpret_cast<char*>(tab + kSurTabs * T);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  float* O = reinterpret_cast<float*>(stage + wave * St::kBytes);
-  __bf16* X = reinterpret_cast<__bf16*>(stage + wave * St::kBytes + St::kXOff);
+  char* stage = stage_base + wave * St::kBytes;
 
   {
     const uint4* src = reinterpret_cast<const uint4*>(frags);
     uint4* dst = reinterpret_cast<uint4*>(wfr);
-    for (int e = threadIdx.x; e < net.frag_elems / 8; e += 256) dst[e] = src[e];
-    for (int e = threadIdx.x; e < net.bias_elems; e += 256) wb[e] = biases[e];
+    for (int e = threadIdx.x; e < net.frag_elems / 8; e += 64 * WAVES) dst[e] = src[e];
+    for (int e = threadIdx.x; e < net.bias_elems; e += 64 * WAVES) wb[e] = biases[e];
+    for (int e = threadIdx.x; e < kSurTabs * T; e += 64 * WAVES) tab[e] = tab_g[e];
   }
   __syncthreads();
+  const float* in_shift = tab + kTabInShift * T;
+  const float* in_scale = tab + kTabInScale * T;
+  const float* out_shift = tab + kTabOutShift * T;
+  const float* out_scale = tab + kTabOutScale * T;
+  const float* inv_res = tab + kTabInvRes * T;
+  const float* rest = tab + kTabRest * T;
 
   const int64_t nt = A.n_total;
   const int64_t tiles = (nt + 63) / 64;
   const int32_t step_b = step_a + 1;
   const float span = 2.0f * A.tau * (float)A.n_sub;
-  for (int64_t tile = (int64_t)blockIdx.x * 4 + wave; tile < tiles;
-       tile += (int64_t)gridDim.x * 4) {
+  for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < tiles;
+       tile += (int64_t)gridDim.x * WAVES) {
     const int64_t i = tile * 64 + lane;
     const bool real = i < nt;
     float Ia = 0.0f, Ib = 0.0f;
@@ -255,57 +334,85 @@ __global__ __launch_bounds__(256) void k_surrogate(KArgs A, SurrogateNet net,
       Ia = stim_current(sid, A.stim, step_a);
       Ib = stim_current(sid, A.stim, step_b);
     }
-    // network inputs of this lane's node
+    // this lane's node: offsets in registers for the whole tile
+    float u[S];
+    {
+      Column col{A.state + (real ? i : 0), nt};
 #pragma unroll
-    for (int k = 0; k < KIN_PAD; ++k) {
-      float x = 0.0f;
-      if (k < S && k < sc.n_in) {
-        const float u = real ? A.state[k * nt + i] : 0.0f;
-        x = (u - sc.in_shift[k]) * sc.in_scale[k];
-      } else if (k == S && k < sc.n_in) {
-        x = Ia * sc.flag_scale;
+      for (int k = 0; k < S; ++k) {
+        u[k] = real ? *col.p : 0.0f;
+        col.next();
       }
-      X[lane * KIN_PAD + k] = (__bf16)x;
     }
-    wave_network<KIN_PAD, H, NHID, OUT_PAD>(X, O, wfr, wb, net, lane);
+    // network inputs, one 16-byte row chunk at a time
+    {
+      __bf16* X = reinterpret_cast<__bf16*>(stage);
+#pragma unroll
+      for (int q = 0; q < KIN_PAD / 8; ++q) {
+        float x[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int k = 8 * q + e;
+          x[e] = 0.0f;
+          if (k < S) x[e] = (u[k] - in_shift[k]) * in_scale[k];
+          else if (k == S) x[e] = sc.n_in > S ? Ia * sc.flag_scale : 0.0f;
+        }
+        const v4u w = {pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]),
+                       pack_bf16(x[6], x[7])};
+        *reinterpret_cast<v4u*>(X + lane * St::XS + 8 * q) = w;
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    wave_network<KIN_PAD, H, NHID, OUT_PAD, ACT, NG>(stage, wfr, wb, net, lane);
+    const _Float16* O = reinterpret_cast<const _Float16*>(stage) + lane * St::OS;
+
     if (pred) {
       if (real) {
+        Column col{pred + i, nt};
 #pragma unroll
-        for (int k = 0; k < S; ++k)
-          pred[k * nt + i] = fmaf(O[lane * OUT_PAD + k], sc.out_scale[k], sc.out_shift[k]);
+        for (int k = 0; k < S; ++k) {
+          const_cast<float*>(col.p)[0] = fmaf((float)O[k], out_scale[k], out_shift[k]);
+          col.next();
+        }
       }
+      __builtin_amdgcn_wave_barrier();
       continue;
     }
 
-    // residual of the prediction at the midpoint y + du / 2
+    // fixed-point iterations of the implicit midpoint rule from the
+    // prediction; the first one decides acceptance
     bool ok = false;
     if (real) {
-      float ym[S], G[S];
+      float y[S], G[S];
 #pragma unroll
-      for (int k = 0; k < S; ++k) {
-        const float du = fmaf(O[lane * OUT_PAD + k], sc.out_scale[k], sc.out_shift[k]);
-        ym[k] = fmaf(0.5f, du, A.state[k * nt + i]);
-      }
-      M::rhs(ym, A.rest, Ia, A.inv_cm, G);
+      for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * out_scale[k], (float)O[k], fmaf(0.5f, out_shift[k], u[k]));
+      M::rhs(y, rest, Ia, A.inv_cm, G);
       // a comparison with NaN is false: a non-finite prediction is rejected
       bool within = true;
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float du = fmaf(O[lane * OUT_PAD + k], sc.out_scale[k], sc.out_shift[k]);
-        const float du1 = span * G[k];
-        within &= fabsf(du1 - du) * sc.inv_res[k] <= sc.tol;
-        ym[k] = fmaf(0.5f * span, G[k], A.state[k * nt + i]);
+        const float du = fmaf((float)O[k], out_scale[k], out_shift[k]);
+        within &= fabsf(fmaf(span, G[k], -du)) * inv_res[k] <= sc.tol;
       }
       const bool flag_ok = sc.n_in > S || Ia == 0.0f;
       ok = within && flag_ok && Ia == Ib;
       if (ok) {
-        M::rhs(ym, A.rest, Ia, A.inv_cm, G);
-        const float u0 = A.state[i];
-        observe(A, i, step_a, fmaf(0.5f * span, G[0], u0));
 #pragma unroll
-        for (int k = 0; k < S; ++k) A.state[k * nt + i] = fmaf(span, G[k], A.state[k * nt + i]);
+        for (int c = 1; c < NCORR; ++c) {
+#pragma unroll
+          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]);
+          M::rhs(y, rest, Ia, A.inv_cm, G);
+        }
+        observe(A, i, step_a, fmaf(0.5f * span, G[0], u[0]));
+        Column col{A.state + i, nt};
+#pragma unroll
+        for (int k = 0; k < S; ++k) {
+          const_cast<float*>(col.p)[0] = fmaf(span, G[k], u[k]);
+          col.next();
+        }
       }
     }
+    __builtin_amdgcn_wave_barrier();
     // compaction of the rejected nodes: one atomic per wave
     const bool reject = real && !ok;
     const uint64_t mask = __ballot(reject);
@@ -361,66 +468,96 @@ hipError_t launch_pack(const SurrogateNet& net, const float* params, __bf16* fra
   return hipGetLastError();
 }
 
-template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD>
+// Kernel configurations: Hodgkin-Huxley 4|5 -> 64 -> 64 -> 64 -> 4 with
+// four waves per workgroup (three workgroups fit one CU's LDS), all four
+// node groups per weight fragment and two corrector iterations; ST57
+// 57|58 -> 128 -> 128 -> 57 with eight waves per workgroup (the 64 KB of
+// weights in LDS allow one workgroup per CU, and eight waves keep two per
+// SIMD within 256 VGPRs), two node groups per weight fragment and one
+// corrector iteration.  Measured on 400 x 1481 ST57 nodes: four waves per
+// workgroup (one per SIMD) ran 1.6x slower.
+template <class M> struct SurCfg;
+template <> struct SurCfg<SurHH> {
+  static constexpr int KIN_PAD = 32, H = 64, NHID = 3, OUT_PAD = 16, WAVES = 4, NG = 4, NCORR = 2;
+};
+#ifndef FIB_SUR_ST57_WAVES
+#define FIB_SUR_ST57_WAVES 8
+#endif
+#ifndef FIB_SUR_ST57_NG
+#define FIB_SUR_ST57_NG 2
+#endif
+#ifndef FIB_SUR_ST57_NCORR
+#define FIB_SUR_ST57_NCORR 1
+#endif
+template <> struct SurCfg<SurST57> {
+  static constexpr int KIN_PAD = 64, H = 128, NHID = 2, OUT_PAD = 64;
+  static constexpr int WAVES = FIB_SUR_ST57_WAVES, NG = FIB_SUR_ST57_NG,
+                       NCORR = FIB_SUR_ST57_NCORR;
+};
+
+template <class M>
 static size_t sur_lds(const SurrogateNet& net) {
+  using C = SurCfg<M>;
   return (size_t)net.frag_elems * 2 + (size_t)net.bias_elems * 4 +
-         (size_t)4 * Staging<KIN_PAD, OUT_PAD>::kBytes;
+         (size_t)kSurTabs * kSurMaxStates * 4 +
+         (size_t)C::WAVES * Stage<C::KIN_PAD, C::OUT_PAD>::kBytes;
 }
 
-template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD>
-static hipError_t sur_step(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
-                           const float* biases, const SurrogateScales& sc, int32_t step_a,
-                           int* list, int* count, int grid, hipStream_t s) {
-  const size_t lds = sur_lds<M, KIN_PAD, H, NHID, OUT_PAD>(net);
+template <class M, int ACT>
+static hipError_t sur_launch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
+                             const float* biases, const float* tab, const SurrogateScales& sc,
+                             int32_t step_a, int* list, int* count, float* pred, int grid,
+                             hipStream_t s) {
+  using C = SurCfg<M>;
+  const size_t lds = sur_lds<M>(net);
   const int64_t tiles = (a.n_total + 63) / 64;
-  const int64_t need = (tiles + 3) / 4;
+  const int64_t need = (tiles + C::WAVES - 1) / C::WAVES;
   const unsigned blocks = (unsigned)(need < grid ? need : grid);
-  hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, count);
-  hipLaunchKernelGGL((k_surrogate<M, KIN_PAD, H, NHID, OUT_PAD>), dim3(blocks), dim3(256), lds, s,
-                     a, net, frags, biases, sc, step_a, list, count, nullptr);
+  if (!pred) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, count);
+  hipLaunchKernelGGL((k_surrogate<M, C::KIN_PAD, C::H, C::NHID, C::OUT_PAD, ACT, C::WAVES, C::NG,
+                                  C::NCORR>),
+                     dim3(blocks), dim3(64 * C::WAVES), lds, s, a, net, frags, biases, tab, sc,
+                     step_a, list, count, pred);
   hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
+  if (e != hipSuccess || pred) return e;
   hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, count, step_a);
   return hipGetLastError();
 }
 
-template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD>
-static hipError_t sur_predict(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
-                              const float* biases, const SurrogateScales& sc, int32_t step_a,
-                              float* pred, int grid, hipStream_t s) {
-  const size_t lds = sur_lds<M, KIN_PAD, H, NHID, OUT_PAD>(net);
-  const int64_t tiles = (a.n_total + 63) / 64;
-  const int64_t need = (tiles + 3) / 4;
-  const unsigned blocks = (unsigned)(need < grid ? need : grid);
-  hipLaunchKernelGGL((k_surrogate<M, KIN_PAD, H, NHID, OUT_PAD>), dim3(blocks), dim3(256), lds, s,
-                     a, net, frags, biases, sc, step_a, nullptr, nullptr, pred);
-  return hipGetLastError();
+template <class M>
+static hipError_t sur_dispatch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
+                               const float* biases, const float* tab, const SurrogateScales& sc,
+                               int32_t step_a, int* list, int* count, float* pred, int grid,
+                               hipStream_t s) {
+  if (net.act == FIB_ACT_RELU)
+    return sur_launch<M, FIB_ACT_RELU>(a, net, frags, biases, tab, sc, step_a, list, count, pred,
+                                       grid, s);
+  return sur_launch<M, FIB_ACT_SILU>(a, net, frags, biases, tab, sc, step_a, list, count, pred,
+                                     grid, s);
 }
 
 size_t surrogate_lds_bytes(int model, const SurrogateNet& net) {
-  if (model == 0) return sur_lds<SurHH, 32, 64, 3, 16>(net);
-  return sur_lds<SurST57, 64, 128, 2, 64>(net);
+  return model == 0 ? sur_lds<SurHH>(net) : sur_lds<SurST57>(net);
 }
 
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
-                                 const __bf16* frags, const float* biases,
+                                 const __bf16* frags, const float* biases, const float* tab,
                                  const SurrogateScales& sc, int32_t step_a, int* list, int* count,
                                  int grid, hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
-  if (model == 0)  // 5 -> 64 -> 64 -> 64 -> 4
-    return sur_step<SurHH, 32, 64, 3, 16>(a, net, frags, biases, sc, step_a, list, count, grid, s);
-  // 57 -> 128 -> 128 -> 57
-  return sur_step<SurST57, 64, 128, 2, 64>(a, net, frags, biases, sc, step_a, list, count, grid, s);
+  if (model == 0)
+    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, list, count, nullptr, grid, s);
+  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, list, count, nullptr, grid, s);
 }
 
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
-                                    const __bf16* frags, const float* biases,
+                                    const __bf16* frags, const float* biases, const float* tab,
                                     const SurrogateScales& sc, int32_t step_a, float* pred,
                                     int grid, hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
   if (model == 0)
-    return sur_predict<SurHH, 32, 64, 3, 16>(a, net, frags, biases, sc, step_a, pred, grid, s);
-  return sur_predict<SurST57, 64, 128, 2, 64>(a, net, frags, biases, sc, step_a, pred, grid, s);
+    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, pred, grid, s);
+  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, pred, grid, s);
 }
 
 }  // namespace fib

@@ -28,6 +28,9 @@ FIB_EUNSUPPORTED = -6
 
 FIB_MODEL_HH = 0
 FIB_MODEL_ST57 = 1
+FIB_ACT_SILU = 0
+FIB_ACT_RELU = 1
+ACTS = {"silu": FIB_ACT_SILU, "relu": FIB_ACT_RELU}
 FIB_SCHED_AUTO = 0
 FIB_SCHED_FUSED = 1
 FIB_SCHED_SPLIT = 2
@@ -106,7 +109,7 @@ def lib():
                                   _i32p, _i32p, C.POINTER(C.c_int64)], C.c_int),
         }
         sig.update({
-            "fib_mlp_create": ([C.c_int32, _i32p, _vp, C.POINTER(_vp)], C.c_int),
+            "fib_mlp_create": ([C.c_int32, _i32p, C.c_int32, _vp, C.POINTER(_vp)], C.c_int),
             "fib_mlp_destroy": ([_vp], None),
             "fib_mlp_n_params": ([_vp], C.c_int64),
             "fib_mlp_set_params": ([_vp, _fp, C.c_int64], C.c_int),
@@ -265,10 +268,10 @@ def fib_plan_preview(params: fib_params, n_nodes, compute_units: int = 256):
                 max_load=mx.value)
 
 
-def fib_mlp_create(sizes, stream=None) -> int:
+def fib_mlp_create(sizes, stream=None, act: str = "silu") -> int:
     sz = np.ascontiguousarray(sizes, dtype=np.int32)
     out = _vp()
-    _check(lib().fib_mlp_create(len(sz) - 1, sz.ctypes.data_as(_i32p),
+    _check(lib().fib_mlp_create(len(sz) - 1, sz.ctypes.data_as(_i32p), ACTS[act],
                                 _vp(stream) if stream else None, C.byref(out)))
     return out.value
 
@@ -340,13 +343,14 @@ def fib_surrogate_last_fallbacks(ctx) -> int:
 class Mlp:
     """Owns one surrogate network; data arrays are torch CUDA tensors."""
 
-    def __init__(self, sizes, stream=None):
+    def __init__(self, sizes, stream=None, act: str = "silu"):
         import torch
         self.torch = torch
         self.sizes = list(sizes)
+        self.act = act
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
-        self.net = fib_mlp_create(self.sizes, stream)
+        self.net = fib_mlp_create(self.sizes, stream, act)
 
     def close(self):
         if self.net:

@@ -151,19 +151,22 @@ def batched_hh(n_fibers: int = 1369, n_min: int = 1000, n_max: int = 1500,
 
 def st57_bundle(n_fibers: int = 400, n_nodes: int = 1481, t_end: float = 5.0,
                 dt_0D: float = 1e-4, dt_split: float = 5e-4, amp: float = AMP_SUPRA,
-                onset_max: float = 2.0, period_ms: float = 0.0) -> Workload:
+                onset_max: float = 2.0, period_ms: float = 0.0,
+                realization: int = 0) -> Workload:
     """ST57 fibers of equal length: every state starts at rest times
     (1 + 0.01 N(0, 1)) (seed 5); each fiber is stimulated for 0.1 ms on three
     nodes around a node drawn from the central 10 % (seed 3) at a time drawn
     from [0, onset_max] ms (seed 4), repeating every period_ms if > 0.
-    dt_0D = 1e-4 ms, dt_1D = dt_split = 5e-4 ms."""
+    dt_0D = 1e-4 ms, dt_1D = dt_split = 5e-4 ms.  `realization` > 0 shifts
+    every seed by 100 per realization."""
     S = 57
+    shift = 100 * int(realization)
     lengths = np.full(n_fibers, n_nodes, dtype=np.int32)
     n_total = int(lengths.sum())
-    rel = _normal(SEED_REL_NOISE, S * n_total, 0.01).reshape(S, n_total)
-    g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE))
+    rel = _normal(SEED_REL_NOISE + shift, S * n_total, 0.01).reshape(S, n_total)
+    g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE + shift))
     u_node = g_node.random(n_fibers)
-    g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME))
+    g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME + shift))
     u_time = g_time.random(n_fibers)
     pulse = int(round(0.1 / dt_split))
     period = int(round(period_ms / dt_split)) if period_ms > 0 else 0

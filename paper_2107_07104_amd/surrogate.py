@@ -30,7 +30,15 @@ import numpy as np
 from . import fib as F
 from . import inputs as I
 
+# Network of each model: layer widths and hidden activation.  The
+# Hodgkin-Huxley network takes the four states and the stimulus flag, three
+# hidden SiLU layers of 64; the ST57 network maps the 57 states through two
+# hidden layers of 128 with ReLU, whose cost on the vector units is one
+# packed integer max per two BF16 values (SiLU needs an exponential and a
+# reciprocal per value, which at this width costs as much as the plain
+# subcellular update the network replaces).
 SHAPES = {I.MODEL_HH: [5, 64, 64, 64, 4], I.MODEL_ST57: [57, 128, 128, 57]}
+ACTIVATION = {I.MODEL_HH: "silu", I.MODEL_ST57: "relu"}
 
 
 @dataclass
@@ -41,9 +49,10 @@ class Surrogate:
     scales: dict              # in_shift, in_scale, out_shift, out_scale, res_scale, flag_scale
     dt_split: float
     info: dict
+    act: str = "silu"
 
     def network(self):
-        net = F.Mlp(self.sizes)
+        net = F.Mlp(self.sizes, act=self.act)
         net.set_params(self.params)
         return net
 
@@ -144,11 +153,12 @@ def _init_params(sizes, seed):
 def train_surrogate(model: int, w: I.Workload, snapshot_steps, steps: int = 20000,
                     batch: int = 8192, lr: float = 2e-3, lr_end: float = 2e-5,
                     flag_share: float = 0.1, amp: float = I.AMP_SUPRA, seed: int = 7,
-                    log=print) -> Surrogate:
+                    act=None, log=print) -> Surrogate:
     """Collects data from `w`, trains the network of SHAPES[model] with the
     library's Adam kernels and returns it with its scalings."""
     import torch
     sizes = SHAPES[model]
+    act = ACTIVATION[model] if act is None else act
     t0 = time.time()
     U = collect_states(w, snapshot_steps, log=log)
     S = U.shape[1]
@@ -181,7 +191,7 @@ def train_surrogate(model: int, w: I.Workload, snapshot_steps, steps: int = 2000
     X = X.float().contiguous()
     T = T.float().contiguous()
     del Uall, dUall
-    net = F.Mlp(sizes)
+    net = F.Mlp(sizes, act=act)
     net.set_params(_init_params(sizes, seed))
     g = torch.Generator(device=U.device.type).manual_seed(seed)
     n = X.shape[0]
@@ -211,13 +221,14 @@ def train_surrogate(model: int, w: I.Workload, snapshot_steps, steps: int = 2000
                 train_seconds=time.time() - t1, workload=w.name,
                 snapshots=[int(s) for s in snapshot_steps])
     return Surrogate(model=model, sizes=sizes, params=params, scales=scales,
-                     dt_split=w.dt_split, info=info)
+                     dt_split=w.dt_split, info=info, act=act)
 
 
 def save(path: str, sur: Surrogate) -> None:
     np.savez(path, model=np.int32(sur.model), sizes=np.asarray(sur.sizes, dtype=np.int32),
              params=sur.params.astype(np.float32), dt_split=np.float64(sur.dt_split),
              flag_scale=np.float64(sur.scales["flag_scale"]),
+             act=np.int32(F.ACTS[sur.act]),
              **{k: np.asarray(v, dtype=np.float32) for k, v in sur.scales.items()
                 if k != "flag_scale"})
 
@@ -226,8 +237,10 @@ def load(path: str) -> Surrogate:
     z = np.load(path, allow_pickle=False)
     scales = {k: z[k] for k in ("in_shift", "in_scale", "out_shift", "out_scale", "res_scale")}
     scales["flag_scale"] = float(z["flag_scale"])
+    act = {v: k for k, v in F.ACTS.items()}[int(z["act"])] if "act" in z else "silu"
     return Surrogate(model=int(z["model"]), sizes=[int(v) for v in z["sizes"]],
-                     params=z["params"], scales=scales, dt_split=float(z["dt_split"]), info={})
+                     params=z["params"], scales=scales, dt_split=float(z["dt_split"]), info={},
+                     act=act)
 
 
 def hh_training_workload() -> I.Workload:

@@ -18,6 +18,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 SHAPES = [[5, 64, 64, 64, 4], [57, 128, 128, 57], [3, 40, 7]]
+CASES = [(s, "silu") for s in SHAPES] + [([57, 128, 128, 57], "relu"), ([3, 40, 7], "relu")]
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -27,24 +28,24 @@ def _need_gpu():
     F.lib()
 
 
-def _net(sizes, seed):
+def _net(sizes, seed, act="silu"):
     params = M.init_params(sizes, seed)
     rng = np.random.default_rng(seed)
     params = [(W, 0.1 * rng.standard_normal(b.shape)) for W, b in params]
-    net = F.Mlp(sizes)
+    net = F.Mlp(sizes, act=act)
     net.set_params(M.flatten(params).astype(np.float32))
     return net, params
 
 
-@pytest.mark.parametrize("sizes", SHAPES)
-def test_forward_matches_reference(sizes):
-    say(f"[mlp forward] {sizes}")
-    net, params = _net(sizes, 5)
+@pytest.mark.parametrize("sizes,act", CASES)
+def test_forward_matches_reference(sizes, act):
+    say(f"[mlp forward] {sizes} {act}")
+    net, params = _net(sizes, 5, act)
     rng = np.random.default_rng(6)
     B = 1000  # several chunks and a ragged last chunk
     X = rng.standard_normal((B, sizes[0]))
     O = net.forward(torch.as_tensor(X, dtype=torch.float32, device="cuda")).cpu().numpy()
-    ref, _ = M.forward(params, X)
+    ref, _ = M.forward(params, X, act)
     err = np.max(np.abs(O - ref)) / np.max(np.abs(ref))
     say("   rel err", err)
     assert err < 3e-2
@@ -52,10 +53,10 @@ def test_forward_matches_reference(sizes):
     net.close()
 
 
-@pytest.mark.parametrize("sizes", SHAPES)
-def test_gradient_matches_reference(sizes):
-    say(f"[mlp gradient] {sizes}")
-    net, params = _net(sizes, 7)
+@pytest.mark.parametrize("sizes,act", CASES)
+def test_gradient_matches_reference(sizes, act):
+    say(f"[mlp gradient] {sizes} {act}")
+    net, params = _net(sizes, 7, act)
     rng = np.random.default_rng(8)
     B = 777
     X = rng.standard_normal((B, sizes[0]))
@@ -63,11 +64,12 @@ def test_gradient_matches_reference(sizes):
     g, loss = net.gradient(torch.as_tensor(X, dtype=torch.float32, device="cuda"),
                            torch.as_tensor(T, dtype=torch.float32, device="cuda"))
     g = g.cpu().numpy()
-    ref = M.flatten(M.backward(params, X, T))
+    ref = M.flatten(M.backward(params, X, T, act))
     err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
-    say("   rel err", err, "loss", float(loss.item()), M.loss(params, X, T))
+    ref_loss = M.loss(params, X, T, act)
+    say("   rel err", err, "loss", float(loss.item()), ref_loss)
     assert err < 3e-2
-    assert abs(float(loss.item()) - M.loss(params, X, T)) < 3e-2 * M.loss(params, X, T)
+    assert abs(float(loss.item()) - ref_loss) < 3e-2 * ref_loss
     # deterministic: the same call gives the same bits
     g2, _ = net.gradient(torch.as_tensor(X, dtype=torch.float32, device="cuda"),
                          torch.as_tensor(T, dtype=torch.float32, device="cuda"))

@@ -6,16 +6,18 @@
   node count with a ragged last tile;
 * with every node accepted, the corrected update is the FP64 fixed-point
   iteration du1 = dt G(y + du/2), du2 = dt G(y + du1/2) of the implicit
-  midpoint rule started from the FP64 prediction, G from the oracle;
+  midpoint rule started from the FP64 prediction, G from the oracle (two
+  iterations for Hodgkin-Huxley, one for ST57);
 * with every node rejected, a surrogate run is bitwise the plain split run
   (the fallback is the plain Heun pair);
 * a network trained on the GPU from plain runs keeps a batched run within
   the V_m and activation-time tolerances of the FP64 oracle while it takes
   the step for most nodes (end-to-end, with the oracle on a subset).
 
-The corrector's sensitivity to the prediction is (dt |dG/dy| / 2)^2, so
-the BF16 error of the prediction does not reach the corrected states: the
-second check uses FP32 tolerances.
+The corrector's sensitivity to the prediction is (dt |dG/dy| / 2)^c after
+c iterations (about 0.02^2 for Hodgkin-Huxley, 0.26 for ST57), so the
+second check bounds the BF16 error of the prediction times that factor on
+top of FP32 tolerances.
 """
 import numpy as np
 import pytest
@@ -26,7 +28,9 @@ from paper_2107_07104_amd import fib as F
 from paper_2107_07104_amd import inputs as I
 from paper_2107_07104_amd import surrogate as SU
 
-from gpu_helpers import compare_runs, gpu_solver, oracle_run, say
+from gpu_helpers import gpu_solver, say
+
+ITERATIONS = {I.MODEL_HH: 2, I.MODEL_ST57: 1}
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -146,15 +150,23 @@ def test_accepted_step_is_the_midpoint_iteration(model):
     o = _reference_prediction(model, params, sc, y, I_stim, sizes[0])
     du = (sc["out_shift"] + sc["out_scale"] * o).T
     dt = w.dt_split
-    du1 = dt * _rhs(model, y + 0.5 * du, I_stim, w.Cm)
-    du2 = dt * _rhs(model, y + 0.5 * du1, I_stim, w.Cm)
-    y_ref = y + du2
-    # FP32 state rounding plus FP32 evaluation of G: relative 1e-5 of the
-    # increment and the usual FP32 ulps of the state
-    tol = 1e-5 * np.abs(y).max(axis=1, keepdims=True) + 2e-3 * np.abs(du2).max(axis=1, keepdims=True)
+    duc = du
+    for _ in range(ITERATIONS[model]):
+        duc = dt * _rhs(model, y + 0.5 * duc, I_stim, w.Cm)
+    y_ref = y + duc
+    # FP32 rounding of the states and of G (relative 1e-5 of the state and
+    # 2e-3 of the increment), and the BF16 error of the prediction (up to
+    # 3e-2 of du) times the corrector's sensitivity: for one iteration its
+    # effect is dt/2 dG/dy times that error, taken from the FP64 map
+    eps = 3e-2 * np.abs(du).max(axis=1, keepdims=True)
+    sens = np.zeros_like(duc)
+    if ITERATIONS[model] == 1:
+        sens = np.abs(dt * _rhs(model, y + 0.5 * (du + eps * np.sign(du)), I_stim, w.Cm) - duc)
+    tol = (1e-5 * np.abs(y).max(axis=1, keepdims=True) + 2e-3 * np.abs(duc).max(axis=1, keepdims=True)
+           + 2.0 * np.max(sens, axis=1, keepdims=True) + 1e-30)
     err = np.abs(y_dev - y_ref)
     worst = np.argmax((err / tol).max(axis=1))
-    say(f"   max |du2| V {np.abs(du2[0]).max():.3e}; worst state {worst}: err "
+    say(f"   max |du_c| V {np.abs(duc[0]).max():.3e}; worst state {worst}: err "
         f"{err[worst].max():.3e} vs tol {tol[worst, 0]:.3e}; V err {err[0].max():.3e}")
     assert np.all(err <= tol)
     s.close()

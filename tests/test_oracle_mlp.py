@@ -7,7 +7,11 @@
 * a hand-computed two-layer example;
 * backpropagation of the full network against central finite differences;
 * the first Adam step moves every parameter by lr * sign(g) (bias-corrected
-  moments give m/sqrt(v) = g/|g| at t = 1).
+  moments give m/sqrt(v) = g/|g| at t = 1);
+* ReLU: closed forms, a ReLU network whose pre-activations are all positive
+  is the product of its affine maps, one whose hidden pre-activations are
+  all negative outputs its last bias, and its backpropagation matches
+  central differences away from the kinks.
 """
 import numpy as np
 import pytest
@@ -83,3 +87,51 @@ def test_first_adam_step_moves_by_lr_times_sign():
 def test_param_count_of_the_surrogate_shapes():
     assert M.n_params([5, 64, 64, 64, 4]) == 8964
     assert M.n_params([57, 128, 128, 57]) == 31289
+
+
+def test_relu_closed_forms():
+    assert M.relu(-1.5) == 0.0 and M.relu(2.5) == 2.5 and M.relu(0.0) == 0.0
+    assert M.relu_grad(-1.5) == 0.0 and M.relu_grad(2.5) == 1.0 and M.relu_grad(0.0) == 0.0
+
+
+def test_relu_network_in_its_linear_region_is_the_product_of_affine_maps():
+    rng = np.random.default_rng(4)
+    sizes = [3, 6, 5, 2]
+    # positive weights and inputs keep every pre-activation positive
+    params = [(rng.uniform(0.1, 1.0, (sizes[i + 1], sizes[i])), rng.uniform(0.1, 1.0, sizes[i + 1]))
+              for i in range(3)]
+    X = rng.uniform(0.1, 1.0, (4, 3))
+    O, (zs, _) = M.forward(params, X, "relu")
+    assert all((z > 0).all() for z in zs[:-1])
+    (W1, b1), (W2, b2), (W3, b3) = params
+    A = W3 @ W2 @ W1
+    c = W3 @ (W2 @ b1 + b2) + b3
+    np.testing.assert_allclose(O, X @ A.T + c, rtol=1e-13)
+    # negative first-layer biases switch every hidden unit off: output = b3
+    params_off = [(W1, -10.0 * np.ones(6)), (W2, b2), (W3, b3)]
+    O_off, _ = M.forward(params_off, X, "relu")
+    z2 = np.maximum(b2, 0.0)
+    np.testing.assert_allclose(O_off, np.tile(W3 @ z2 + b3, (4, 1)), rtol=1e-13)
+
+
+def test_relu_backprop_matches_central_differences():
+    sizes = [5, 8, 8, 4]
+    rng = np.random.default_rng(12)
+    params = M.init_params(sizes, seed=13)
+    params = [(W, 0.2 * rng.standard_normal(b.shape)) for W, b in params]
+    X = rng.standard_normal((9, sizes[0]))
+    T = rng.standard_normal((9, sizes[-1]))
+    _, (zs, _) = M.forward(params, X, "relu")
+    h = 1e-7
+    # no hidden pre-activation within reach of a kink for steps of size h
+    assert min(np.min(np.abs(z)) for z in zs[:-1]) > 1e-4
+    g = M.flatten(M.backward(params, X, T, "relu"))
+    theta = M.flatten(params)
+    num = np.zeros_like(theta)
+    for i in range(theta.size):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        num[i] = (M.loss(M.unflatten(tp, sizes), X, T, "relu") -
+                  M.loss(M.unflatten(tm, sizes), X, T, "relu")) / (2 * h)
+    np.testing.assert_allclose(g, num, rtol=1e-5, atol=1e-9)
