@@ -273,7 +273,9 @@ struct fib_ctx {
   float* d_sur_bias = nullptr;
   float* d_sur_tab = nullptr;
   int* d_sur_list = nullptr;
-  int* d_sur_count = nullptr;
+  int* d_sur_count = nullptr;  // two counters, alternated between surrogate steps
+  int sur_slot = 0;             // counter of the next surrogate step
+  int sur_last_slot = -1;       // counter of the last one (-1: none yet)
   int sur_grid = 0;
 };
 
@@ -884,7 +886,10 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     if (c->sur_on && !last && !sample) {
       HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags,
                                          c->d_sur_bias, c->d_sur_tab, c->sur_sc, (int32_t)n,
-                                         c->d_sur_list, c->d_sur_count, c->sur_grid, c->stream));
+                                         c->d_sur_list, c->d_sur_count, c->sur_slot, c->sur_grid,
+                                         c->stream));
+      c->sur_last_slot = c->sur_slot;
+      c->sur_slot ^= 1;
     } else {
       const int flags = 1 | 2 | (last ? 0 : 4);
       HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
@@ -937,20 +942,19 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   sc.n_in = ms.size[0];
   sc.flag_scale = (float)flag_scale;
   sc.tol = (float)tol;
-  constexpr int T = fib::kSurMaxStates;
-  std::vector<float> tab((size_t)fib::kSurTabs * T, 0.0f);
+  std::vector<float> tab((size_t)fib::kSurTabFloats, 0.0f);
   const KArgs a0 = base_args(c);
   for (int k = 0; k < S; ++k) {
     if (!(in_scale[k] > 0.0f) || !(out_scale[k] > 0.0f) || !(res_scale[k] > 0.0f) ||
         !std::isfinite(in_shift[k]) || !std::isfinite(out_shift[k]) ||
         !std::isfinite(in_scale[k]) || !std::isfinite(out_scale[k]) || !std::isfinite(res_scale[k]))
       return fail(FIB_EINVAL, "state %d: scales must be finite and > 0", k);
-    tab[fib::kTabInShift * T + k] = in_shift[k];
-    tab[fib::kTabInScale * T + k] = in_scale[k];
-    tab[fib::kTabOutShift * T + k] = out_shift[k];
-    tab[fib::kTabOutScale * T + k] = out_scale[k];
-    tab[fib::kTabInvRes * T + k] = 1.0f / res_scale[k];
-    tab[fib::kTabRest * T + k] = a0.rest[k];
+    tab[fib::kTabIn + 2 * k] = in_scale[k];
+    tab[fib::kTabIn + 2 * k + 1] = -in_shift[k] * in_scale[k];
+    tab[fib::kTabOut + 4 * k] = out_scale[k];
+    tab[fib::kTabOut + 4 * k + 1] = out_shift[k];
+    tab[fib::kTabOut + 4 * k + 2] = 1.0f / res_scale[k];
+    tab[fib::kTabOut + 4 * k + 3] = a0.rest[k];
   }
   const size_t lds = fib::surrogate_lds_bytes(c->p.model, sn);
   if (lds > c->max_lds) return fail(FIB_EUNSUPPORTED, "surrogate needs %zu bytes of LDS", lds);
@@ -969,9 +973,14 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   HIP_TRY(hipMemcpy(c->d_sur_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
   if (!c->d_sur_list) {
     if (hipMalloc(&c->d_sur_list, sizeof(int) * (size_t)std::max<int64_t>(c->n_total, 1)) != hipSuccess ||
-        hipMalloc(&c->d_sur_count, sizeof(int)) != hipSuccess)
+        hipMalloc(&c->d_sur_count, 2 * sizeof(int)) != hipSuccess)
       return fail(FIB_ENOMEM, "device allocation failed");
   }
+  // both rejection counters start at zero; each surrogate step clears the
+  // one the next step uses
+  HIP_TRY(hipMemset(c->d_sur_count, 0, 2 * sizeof(int)));
+  c->sur_slot = 0;
+  c->sur_last_slot = -1;
   HIP_TRY(fib::launch_pack(sn, fib::mlp_device_params(net), c->d_sur_frags, c->d_sur_bias, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, c->max_lds / lds));
@@ -993,7 +1002,9 @@ int fib_step_surrogate(fib_t* c, int64_t step) {
   a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
   HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
                                      c->d_sur_tab, c->sur_sc, (int32_t)step, c->d_sur_list,
-                                     c->d_sur_count, c->sur_grid, c->stream));
+                                     c->d_sur_count, c->sur_slot, c->sur_grid, c->stream));
+  c->sur_last_slot = c->sur_slot;
+  c->sur_slot ^= 1;
   return FIB_OK;
 }
 
@@ -1020,10 +1031,10 @@ int fib_surrogate_last_fallbacks(fib_t* c, int64_t* n) {
   if (int rc = check_ctx(c)) return rc;
   if (!n) return fail(FIB_EINVAL, "null output");
   *n = 0;
-  if (!c->d_sur_count) return FIB_OK;
+  if (!c->d_sur_count || c->sur_last_slot < 0) return FIB_OK;
   int v = 0;
   HIP_TRY(hipStreamSynchronize(c->stream));
-  HIP_TRY(hipMemcpy(&v, c->d_sur_count, sizeof(int), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(&v, c->d_sur_count + c->sur_last_slot, sizeof(int), hipMemcpyDeviceToHost));
   *n = v;
   return FIB_OK;
 }

@@ -66,15 +66,11 @@ __host__ __device__ __forceinline__ void hh_gates(T V, T m, T h, T n, T& dm, T& 
   dn = fma_(-(an + bn), n, an);
 }
 
-// Right-hand side: d = G(ref + u) with stimulus current I (uA/cm^2).
-// `ref` points at S values (kernel arguments, uniform across lanes).
+// Right-hand side at absolute states y: d = G(y) with stimulus current I
+// (uA/cm^2).
 template <typename T>
-__host__ __device__ __forceinline__ void rhs(const T (&u)[S], const T* __restrict__ ref, T I,
-                                             T inv_cm, T (&d)[S]) {
+__host__ __device__ __forceinline__ void rhs_abs(const T (&y)[S], T I, T inv_cm, T (&d)[S]) {
   using F = T;
-  T y[S];
-#pragma unroll
-  for (int k = 0; k < S; ++k) y[k] = u[k] + ref[k];
 
   const F V = y[0], m = y[1], h = y[2], n = y[3];
   const F Vt = y[4], mt = y[5], ht = y[6], nt = y[7];
@@ -210,6 +206,17 @@ __host__ __device__ __forceinline__ void rhs(const T (&u)[S], const T* __restric
     d[55] = fma_(F(1.1) - Ls, F(0.05), -F(0.02) * Fn);
     d[56] = (Fn - y[56]) * F(0.2);
   }
+}
+
+// Right-hand side at offsets: d = G(ref + u).  `ref` points at S values
+// (kernel arguments, uniform across lanes).
+template <typename T>
+__host__ __device__ __forceinline__ void rhs(const T (&u)[S], const T* __restrict__ ref, T I,
+                                             T inv_cm, T (&d)[S]) {
+  T y[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) y[k] = u[k] + ref[k];
+  rhs_abs(y, I, inv_cm, d);
 }
 
 // One Heun step of width tau on the offsets u (eq. heun).  The update is

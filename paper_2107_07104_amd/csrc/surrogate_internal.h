@@ -31,11 +31,15 @@ struct SurrogateNet {
   int bias_elems;
 };
 
-// Per-state tables of the surrogate step (device memory, kSurTabs rows of
-// kSurMaxStates floats): input x_k = (u_k - in_shift_k) in_scale_k, output
-// du_k = out_shift_k + out_scale_k o_k, acceptance |du1_k - du_k| inv_res_k
-// <= tol, and the resting state the offsets u are taken from.
-enum { kTabInShift = 0, kTabInScale, kTabOutShift, kTabOutScale, kTabInvRes, kTabRest, kSurTabs };
+// Per-state tables of the surrogate step (device memory, kSurTabFloats
+// floats): from kTabIn, a float2 per state (in_scale_k, -in_shift_k
+// in_scale_k), so the input is x_k = u_k in_scale_k - in_shift_k in_scale_k;
+// from kTabOut, a float4 per state (out_scale_k, out_shift_k, 1 / res_k,
+// rest_k): the prediction du_k = out_shift_k + out_scale_k o_k, the
+// acceptance scale and the resting state the offsets u are taken from.
+constexpr int kTabIn = 0;
+constexpr int kTabOut = 2 * kSurMaxStates;
+constexpr int kSurTabFloats = 6 * kSurMaxStates;
 
 // Scalars of the step: network inputs (n_states, or n_states + 1 with the
 // stimulus flag I * flag_scale) and the acceptance tolerance.
@@ -48,10 +52,13 @@ struct SurrogateScales {
 hipError_t launch_pack(const SurrogateNet& net, const float* params, __bf16* frags, float* biases,
                        hipStream_t s);
 size_t surrogate_lds_bytes(int model, const SurrogateNet& net);
+// One surrogate step: appends rejected nodes to list through counts[slot]
+// and clears counts[slot ^ 1] for the next step (the caller alternates the
+// slot between launches; both counters start at zero).
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
                                  const __bf16* frags, const float* biases, const float* tab,
-                                 const SurrogateScales& sc, int32_t step_a, int* list, int* count,
-                                 int grid, hipStream_t s);
+                                 const SurrogateScales& sc, int32_t step_a, int* list, int* counts,
+                                 int slot, int grid, hipStream_t s);
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
                                     const __bf16* frags, const float* biases, const float* tab,
                                     const SurrogateScales& sc, int32_t step_a, float* pred,

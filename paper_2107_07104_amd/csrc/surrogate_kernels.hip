@@ -88,6 +88,7 @@ typedef __bf16 v2bf __attribute__((ext_vector_type(2)));
 typedef short v2s __attribute__((ext_vector_type(2)));
 typedef float v2f __attribute__((ext_vector_type(2)));
 typedef _Float16 v2h __attribute__((ext_vector_type(2)));
+typedef _Float16 v4h __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float silu_fast(float z) {
   return z * __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(-1.4426950408889634f * z));
@@ -119,6 +120,14 @@ __device__ __forceinline__ unsigned pack_f16(float a, float b) {
 // Model adapters: number of states, offsets -> increments of one Heun step.
 struct SurHH {
   static constexpr int S = 4;
+  __device__ static void rhs_abs(const float (&y)[S], float I, float inv_cm, float (&d)[S]) {
+    const hh::State g = hh::rhs(hh::State{y[0], y[1], y[2], y[3]}, I, inv_cm,
+                                hh::Ref{0.0f, 0.0f, 0.0f, 0.0f});
+    d[0] = g.V;
+    d[1] = g.m;
+    d[2] = g.h;
+    d[3] = g.n;
+  }
   __device__ static void rhs(const float (&u)[S], const float* ref, float I, float inv_cm,
                              float (&d)[S]) {
     const hh::State y{u[0], u[1], u[2], u[3]};
@@ -142,6 +151,9 @@ struct SurHH {
 
 struct SurST57 {
   static constexpr int S = st57::S;
+  __device__ static void rhs_abs(const float (&y)[S], float I, float inv_cm, float (&d)[S]) {
+    st57::rhs_abs<float>(y, I, inv_cm, d);
+  }
   __device__ static void rhs(const float (&u)[S], const float* ref, float I, float inv_cm,
                              float (&d)[S]) {
     st57::rhs<float>(u, ref, I, inv_cm, d);
@@ -284,7 +296,8 @@ __device__ __forceinline__ void wave_network(char* stage, const v8bf* __restrict
 
 // Surrogate reaction pair for every node: finishes step `step_a` and
 // starts step `step_a + 1`.  Rejected nodes are appended to list[] through
-// count[0] (one atomic per wave).  With `pred` set, the kernel only writes
+// count[slot] (one atomic per wave); the kernel clears count[slot ^ 1],
+// which the next surrogate step uses, so no separate reset is launched.  With `pred` set, the kernel only writes
 // the predicted increments du ([S][n_total]) and changes no state.
 // Persistent: each wave walks the 64-node tiles tile = wave_id,
 // wave_id + waves, ...  Launch: 64 WAVES threads.
@@ -293,15 +306,14 @@ template <class M, int KIN_PAD, int H, int NHID, int OUT_PAD, int ACT, int WAVES
 __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     KArgs A, SurrogateNet net, const __bf16* __restrict__ frags, const float* __restrict__ biases,
     const float* __restrict__ tab_g, SurrogateScales sc, int32_t step_a, int* __restrict__ list,
-    int* __restrict__ count, float* __restrict__ pred) {
+    int* __restrict__ counts, int slot, float* __restrict__ pred) {
   extern __shared__ float lds_f[];
   using St = Stage<KIN_PAD, OUT_PAD>;
   constexpr int S = M::S;
-  constexpr int T = kSurMaxStates;
   v8bf* wfr = reinterpret_cast<v8bf*>(lds_f);
   float* wb = lds_f + net.frag_elems / 2;
   float* tab = wb + net.bias_elems;
-  char* stage_base = reinterpret_cast<char*>(tab + kSurTabs * T);
+  char* stage_base = reinterpret_cast<char*>(tab + kSurTabFloats);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   char* stage = stage_base + wave * St::kBytes;
 
@@ -310,15 +322,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     uint4* dst = reinterpret_cast<uint4*>(wfr);
     for (int e = threadIdx.x; e < net.frag_elems / 8; e += 64 * WAVES) dst[e] = src[e];
     for (int e = threadIdx.x; e < net.bias_elems; e += 64 * WAVES) wb[e] = biases[e];
-    for (int e = threadIdx.x; e < kSurTabs * T; e += 64 * WAVES) tab[e] = tab_g[e];
+    for (int e = threadIdx.x; e < kSurTabFloats; e += 64 * WAVES) tab[e] = tab_g[e];
   }
   __syncthreads();
-  const float* in_shift = tab + kTabInShift * T;
-  const float* in_scale = tab + kTabInScale * T;
-  const float* out_shift = tab + kTabOutShift * T;
-  const float* out_scale = tab + kTabOutScale * T;
-  const float* inv_res = tab + kTabInvRes * T;
-  const float* rest = tab + kTabRest * T;
+  int* count = counts ? counts + slot : nullptr;
+  if (counts && blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
+  const float2* tin = reinterpret_cast<const float2*>(tab + kTabIn);    // scale, bias
+  const float4* tout = reinterpret_cast<const float4*>(tab + kTabOut);  // scale, shift, 1/res, rest
 
   const int64_t nt = A.n_total;
   const int64_t tiles = (nt + 63) / 64;
@@ -328,19 +338,21 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
        tile += (int64_t)gridDim.x * WAVES) {
     const int64_t i = tile * 64 + lane;
     const bool real = i < nt;
+    // lanes past the end read the last node (their results are dropped)
+    const int64_t ic = real ? i : nt - 1;
     float Ia = 0.0f, Ib = 0.0f;
-    if (real) {
-      const uint32_t sid = (uint32_t)A.node_stim[i];
+    {
+      const uint32_t sid = (uint32_t)A.node_stim[ic];
       Ia = stim_current(sid, A.stim, step_a);
       Ib = stim_current(sid, A.stim, step_b);
     }
     // this lane's node: offsets in registers for the whole tile
     float u[S];
     {
-      Column col{A.state + (real ? i : 0), nt};
+      Column col{A.state + ic, nt};
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        u[k] = real ? *col.p : 0.0f;
+        u[k] = *col.p;
         col.next();
       }
     }
@@ -354,8 +366,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         for (int e = 0; e < 8; ++e) {
           const int k = 8 * q + e;
           x[e] = 0.0f;
-          if (k < S) x[e] = (u[k] - in_shift[k]) * in_scale[k];
-          else if (k == S) x[e] = sc.n_in > S ? Ia * sc.flag_scale : 0.0f;
+          if (k < S) {
+            const float2 t = tin[k];
+            x[e] = fmaf(u[k], t.x, t.y);
+          } else if (k == S) {
+            x[e] = sc.n_in > S ? Ia * sc.flag_scale : 0.0f;
+          }
         }
         const v4u w = {pack_bf16(x[0], x[1]), pack_bf16(x[2], x[3]), pack_bf16(x[4], x[5]),
                        pack_bf16(x[6], x[7])};
@@ -364,14 +380,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     }
     __builtin_amdgcn_wave_barrier();
     wave_network<KIN_PAD, H, NHID, OUT_PAD, ACT, NG>(stage, wfr, wb, net, lane);
-    const _Float16* O = reinterpret_cast<const _Float16*>(stage) + lane * St::OS;
+    // this lane's network outputs, four FP16 values per LDS read
+    const v4h* O4 = reinterpret_cast<const v4h*>(reinterpret_cast<const _Float16*>(stage) + lane * St::OS);
+    auto out = [&](int k) { return (float)O4[k >> 2][k & 3]; };
 
     if (pred) {
       if (real) {
         Column col{pred + i, nt};
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-          const_cast<float*>(col.p)[0] = fmaf((float)O[k], out_scale[k], out_shift[k]);
+          const float4 t = tout[k];
+          const_cast<float*>(col.p)[0] = fmaf(out(k), t.x, t.y);
           col.next();
         }
       }
@@ -385,14 +404,18 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     if (real) {
       float y[S], G[S];
 #pragma unroll
-      for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * out_scale[k], (float)O[k], fmaf(0.5f, out_shift[k], u[k]));
-      M::rhs(y, rest, Ia, A.inv_cm, G);
+      for (int k = 0; k < S; ++k) {
+        const float4 t = tout[k];
+        y[k] = fmaf(0.5f, fmaf(out(k), t.x, t.y), u[k]) + t.w;  // rest + u + du / 2
+      }
+      M::rhs_abs(y, Ia, A.inv_cm, G);
       // a comparison with NaN is false: a non-finite prediction is rejected
       bool within = true;
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float du = fmaf((float)O[k], out_scale[k], out_shift[k]);
-        within &= fabsf(fmaf(span, G[k], -du)) * inv_res[k] <= sc.tol;
+        const float4 t = tout[k];
+        const float du = fmaf(out(k), t.x, t.y);
+        within &= fabsf(fmaf(span, G[k], -du)) * t.z <= sc.tol;
       }
       const bool flag_ok = sc.n_in > S || Ia == 0.0f;
       ok = within && flag_ok && Ia == Ib;
@@ -400,8 +423,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
 #pragma unroll
         for (int c = 1; c < NCORR; ++c) {
 #pragma unroll
-          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]);
-          M::rhs(y, rest, Ia, A.inv_cm, G);
+          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tout[k].w;
+          M::rhs_abs(y, Ia, A.inv_cm, G);
         }
         observe(A, i, step_a, fmaf(0.5f * span, G[0], u[0]));
         Column col{A.state + i, nt};
@@ -454,8 +477,6 @@ __global__ __launch_bounds__(256) void k_fallback(KArgs A, const int* __restrict
   }
 }
 
-__global__ void k_zero_int(int* p) { *p = 0; }
-
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
@@ -499,41 +520,41 @@ template <class M>
 static size_t sur_lds(const SurrogateNet& net) {
   using C = SurCfg<M>;
   return (size_t)net.frag_elems * 2 + (size_t)net.bias_elems * 4 +
-         (size_t)kSurTabs * kSurMaxStates * 4 +
+         (size_t)kSurTabFloats * 4 +
          (size_t)C::WAVES * Stage<C::KIN_PAD, C::OUT_PAD>::kBytes;
 }
 
 template <class M, int ACT>
 static hipError_t sur_launch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
                              const float* biases, const float* tab, const SurrogateScales& sc,
-                             int32_t step_a, int* list, int* count, float* pred, int grid,
-                             hipStream_t s) {
+                             int32_t step_a, int* list, int* counts, int slot, float* pred,
+                             int grid, hipStream_t s) {
   using C = SurCfg<M>;
   const size_t lds = sur_lds<M>(net);
   const int64_t tiles = (a.n_total + 63) / 64;
   const int64_t need = (tiles + C::WAVES - 1) / C::WAVES;
   const unsigned blocks = (unsigned)(need < grid ? need : grid);
-  if (!pred) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(1), 0, s, count);
   hipLaunchKernelGGL((k_surrogate<M, C::KIN_PAD, C::H, C::NHID, C::OUT_PAD, ACT, C::WAVES, C::NG,
                                   C::NCORR>),
                      dim3(blocks), dim3(64 * C::WAVES), lds, s, a, net, frags, biases, tab, sc,
-                     step_a, list, count, pred);
+                     step_a, list, counts, slot, pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pred) return e;
-  hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, count, step_a);
+  hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, counts + slot,
+                     step_a);
   return hipGetLastError();
 }
 
 template <class M>
 static hipError_t sur_dispatch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
                                const float* biases, const float* tab, const SurrogateScales& sc,
-                               int32_t step_a, int* list, int* count, float* pred, int grid,
-                               hipStream_t s) {
+                               int32_t step_a, int* list, int* counts, int slot, float* pred,
+                               int grid, hipStream_t s) {
   if (net.act == FIB_ACT_RELU)
-    return sur_launch<M, FIB_ACT_RELU>(a, net, frags, biases, tab, sc, step_a, list, count, pred,
-                                       grid, s);
-  return sur_launch<M, FIB_ACT_SILU>(a, net, frags, biases, tab, sc, step_a, list, count, pred,
-                                     grid, s);
+    return sur_launch<M, FIB_ACT_RELU>(a, net, frags, biases, tab, sc, step_a, list, counts, slot,
+                                       pred, grid, s);
+  return sur_launch<M, FIB_ACT_SILU>(a, net, frags, biases, tab, sc, step_a, list, counts, slot,
+                                     pred, grid, s);
 }
 
 size_t surrogate_lds_bytes(int model, const SurrogateNet& net) {
@@ -542,12 +563,14 @@ size_t surrogate_lds_bytes(int model, const SurrogateNet& net) {
 
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
                                  const __bf16* frags, const float* biases, const float* tab,
-                                 const SurrogateScales& sc, int32_t step_a, int* list, int* count,
-                                 int grid, hipStream_t s) {
+                                 const SurrogateScales& sc, int32_t step_a, int* list, int* counts,
+                                 int slot, int grid, hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
   if (model == 0)
-    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, list, count, nullptr, grid, s);
-  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, list, count, nullptr, grid, s);
+    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, list, counts, slot, nullptr,
+                               grid, s);
+  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, list, counts, slot, nullptr,
+                               grid, s);
 }
 
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
@@ -556,8 +579,10 @@ hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNe
                                     int grid, hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
   if (model == 0)
-    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, pred, grid, s);
-  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, pred, grid, s);
+    return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, 0, pred,
+                               grid, s);
+  return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, 0, pred,
+                               grid, s);
 }
 
 }  // namespace fib

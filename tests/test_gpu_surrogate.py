@@ -196,3 +196,24 @@ def test_all_rejected_is_bitwise_the_plain_split_run(model):
     np.testing.assert_array_equal(tb, ta)
     b.close()
     net.close()
+
+
+def test_rejection_counts_of_consecutive_steps():
+    """Each surrogate step counts its own rejections (the two alternating
+    counters are cleared one step ahead), also across re-attachment."""
+    say("[surrogate rejection counts]")
+    w, s, y, steps = _active_state(I.MODEL_HH)
+    sizes, params, net = _random_net(I.MODEL_HH, 41)
+    sc = _scales(I.MODEL_HH, y, w, 6, _out_mag(I.MODEL_HH, w, y))
+    s.set_surrogate(net, sc, 1e-30)          # every node rejected
+    for j in range(5):
+        s.step_surrogate(steps + j)
+        s.sync()
+        assert s.last_fallbacks() == w.n_total
+    s.set_surrogate(net, sc, 1e30)           # every unstimulated node accepted
+    for j in range(3):
+        s.step_surrogate(steps + 5 + j)
+        s.sync()
+        assert s.last_fallbacks() == 0
+    s.close()
+    net.close()
