@@ -18,6 +18,20 @@ achieved VALU issue rate from its algorithmic op count against the chip's
 FP32 VALU issue peak; `cpu_baseline` times the FP64 oracle on a bounded
 subset of the same fibers on the host cores and doubles as a parity check
 of those fibers.
+
+`surrogate` (skipped with --no-surrogate) compares the plain FP32 method
+with the learned surrogate step on the two surrogate workloads, each
+network trained here on the GPU by the library's own kernels from plain
+runs of a training realization and evaluated on an independent one:
+  hh:   1369 x 1481 Hodgkin-Huxley nodes, dt_split 5e-3 ms (three Heun
+        substeps of each half), 20 ms; network 5 -> 64 -> 64 -> 64 -> 4 SiLU;
+  st57: 10000 x 2000 ST57 nodes (2e7), stimuli at 100 Hz from seeded onsets
+        in [0, 10) ms, dt_split 5e-4 ms; network 57 -> 128 -> 128 -> 57
+        ReLU; a bounded window of --st57-ms simulated ms is timed.
+For each: node-steps/s of the plain path(s) and of the surrogate path over
+the same run, the V_m / activation-time differences between them, the
+rejected (fallback) share, and the FP64 oracle's V_m / activation-time
+errors of the surrogate run on sampled fibers.
 """
 from __future__ import annotations
 
@@ -60,6 +74,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fibers", type=int, default=0,
                     help="fibers in the oracle sample (default: 2 per host thread)")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--sur-train-steps", type=int, default=20000)
+    ap.add_argument("--sur-tol", type=float, default=1e-2)
+    ap.add_argument("--st57-ms", type=float, default=1.0,
+                    help="simulated ms of the large ST57 bundle timed per path")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB before the timed "
                          "region, as the known-size reference for HBM byte counters")
@@ -115,6 +134,180 @@ def cpu_baseline(w, gpu_samples, gpu_tact, fibers):
     return sub.node_steps() / dt, dict(fibers=fibers, nodes=n, seconds=dt, vm_max_err_mV=vm_err,
                                        tact_max_err_ms=tact_err, tact_mismatch=mismatch,
                                        activated=int(both.sum()))
+
+
+def _log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
+
+
+def _timed_run(s, w, init, sample_every):
+    """Initial state, then one fib_run over the whole workload with V_m
+    samples; returns (seconds, samples [rows, n_total] on the device, t_act)."""
+    import torch
+    rows = w.n_steps // sample_every
+    samples = torch.empty((rows, w.n_total), device="cuda")
+    init()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.run(0, w.n_steps, sample_every, samples)
+    s.sync()
+    torch.cuda.synchronize()
+    return time.perf_counter() - t0, samples, s.tact()
+
+
+def _compare(sa, ta, sb, tb, dt_split):
+    """V_m and activation-time differences of run b against run a."""
+    dv = float((sa - sb).abs().max().item()) if sa.numel() else 0.0
+    fa, fb = np.isfinite(ta), np.isfinite(tb)
+    both = fa & fb
+    return dict(vm_max_diff_mV=dv,
+                tact_max_diff_ms=float(np.max(np.abs(ta[both] - tb[both]))) if both.any() else 0.0,
+                tact_mismatch=int(np.sum(fa != fb)), activated=int(both.sum()),
+                dt_split_ms=dt_split)
+
+
+def _oracle_parity(w, fibers, y0_cols, gpu_samples, gpu_tact, n_steps):
+    """FP64 oracle on the listed fibers over the first n_steps split steps,
+    against the GPU samples and activation times of the same nodes."""
+    from oracle import oracle as O
+    sub = w.subset(fibers).with_steps(n_steps)
+    cfg = O.Config(model=sub.model, dt_0D=sub.dt_0D, dt_1D=sub.dt_1D, dt_split=sub.dt_split,
+                   v_th=sub.v_th, Cm=sub.Cm, Am=sub.Am, sigma=sub.sigma, h=sub.h)
+    t0 = time.perf_counter()
+    yo, so, to = O.run(cfg, sub.n_nodes, y0_cols, sub.stims, n_steps, sample_every=w.sample_every)
+    secs = time.perf_counter() - t0
+    import torch
+    off = w.offsets
+    cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+    rows = n_steps // w.sample_every
+    ci = torch.as_tensor(cols, device=gpu_samples.device)
+    gs = gpu_samples[:rows].index_select(1, ci).cpu().numpy().astype(np.float64)
+    tg = gpu_tact[cols].astype(np.float64)
+    # activation times only count within the oracle's window
+    tg = np.where(tg <= n_steps * w.dt_split, tg, np.inf)
+    both = np.isfinite(tg) & np.isfinite(to)
+    return dict(fibers=[int(f) for f in fibers], nodes=int(len(cols)), split_steps=int(n_steps),
+                vm_max_err_mV=float(np.max(np.abs(gs - so))) if rows else 0.0,
+                tact_max_err_ms=float(np.max(np.abs(tg[both] - to[both]))) if both.any() else 0.0,
+                tact_mismatch=int(np.sum(np.isfinite(tg) != np.isfinite(to))),
+                activated=int(both.sum()), oracle_seconds=secs)
+
+
+def surrogate_hh(args):
+    """Hodgkin-Huxley surrogate workload: train, then plain fused, plain
+    split and surrogate runs of an independent realization."""
+    from dataclasses import replace
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+    from paper_2107_07104_amd import surrogate as SU
+    wt = SU.hh_training_workload()
+    snaps = [int(round(t / wt.dt_split)) for t in (1.0, 3.0, 5.0, 7.0, 10.0)]
+    t0 = time.perf_counter()
+    sur = SU.train_surrogate(I.MODEL_HH, wt, snaps, steps=args.sur_train_steps,
+                             log=lambda m: _log("hh surrogate:" + m))
+    train_s = time.perf_counter() - t0
+    w = replace(I.batched_hh(n_min=1481, n_max=1481, dt=5e-3, realization=1), dt_0D=1e-3,
+                name="hh_surrogate_eval_1369x1481")
+    vm = w.vm_noise.astype(np.float32)
+    res = {}
+    runs = {}
+    for path, sched in (("plain_fused", F.FIB_SCHED_FUSED), ("plain_split", F.FIB_SCHED_SPLIT),
+                        ("surrogate", F.FIB_SCHED_SPLIT)):
+        s = SU._solver(w, schedule=sched)
+        s.set_stimulus(w.stims)
+        net = None
+        if path == "surrogate":
+            net = sur.network()
+            s.set_surrogate(net, sur.scales, args.sur_tol)
+        _timed_run(s, w.with_steps(40), lambda: s.init_state(vm_noise=vm), w.sample_every)
+        secs, smp, ta = _timed_run(s, w, lambda: s.init_state(vm_noise=vm), w.sample_every)
+        runs[path] = (smp, ta)
+        res[path] = dict(value=w.node_steps() / secs, seconds=secs)
+        if net is not None:
+            res[path]["fallbacks_last_step"] = int(s.last_fallbacks())
+            net.close()
+        s.close()
+        _log(f"hh {path}: {res[path]['value']:.3e} node-steps/s")
+    sp, tp = runs["plain_split"]
+    ss, ts = runs["surrogate"]
+    fibers = [0, 1, 2, 3]
+    off = w.offsets
+    from oracle import oracle as O
+    cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+    y0 = np.tile(O.rest_state(I.MODEL_HH)[:, None], (1, len(cols)))
+    y0[0] += vm[cols]
+    parity = _oracle_parity(w, fibers, y0, ss, ts, w.n_steps)
+    best_plain = max(res["plain_fused"]["value"], res["plain_split"]["value"])
+    return dict(workload=w.name, fibers=int(len(w.n_nodes)), nodes=int(w.n_total),
+                split_steps=int(w.n_steps), dt_split_ms=w.dt_split, dt_0D_ms=w.dt_0D,
+                network="5-64-64-64-4 SiLU, BF16 MFMA", tol=args.sur_tol,
+                train=dict(pairs=sur.info["pairs"], adam_steps=sur.info["steps"],
+                           final_loss=sur.info["losses"][-1][1], seconds=train_s,
+                           workload="realization 0 of the same bundle"),
+                **res, surrogate_over_best_plain=res["surrogate"]["value"] / best_plain,
+                surrogate_vs_plain_split=_compare(sp, tp, ss, ts, w.dt_split),
+                surrogate_vs_oracle=parity)
+
+
+def surrogate_st57(args):
+    """Large ST57 bundle: train on the 400 x 1481 bundle, then time the
+    plain split path and the surrogate path on 10000 x 2000 nodes."""
+    import torch
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+    from paper_2107_07104_amd import surrogate as SU
+    wt = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0)
+    snaps = [int(round(t / wt.dt_split)) for t in (0.5, 1.5, 2.5, 3.5, 4.5)]
+    t0 = time.perf_counter()
+    sur = SU.train_surrogate(I.MODEL_ST57, wt, snaps, steps=args.sur_train_steps,
+                             log=lambda m: _log("st57 surrogate:" + m))
+    train_s = time.perf_counter() - t0
+    w = I.st57_bundle(n_fibers=10000, n_nodes=2000, t_end=args.st57_ms, onset_max=10.0,
+                      period_ms=10.0, realization=2, host_noise=False)
+    rel = I.device_rel_noise(w)
+    res = {}
+    runs = {}
+    for path in ("plain_split", "surrogate"):
+        s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
+        s.set_stimulus(w.stims)
+        net = None
+        if path == "surrogate":
+            net = sur.network()
+            s.set_surrogate(net, sur.scales, args.sur_tol)
+        _timed_run(s, w.with_steps(20), lambda: s.init_state(rel_noise=rel), w.sample_every)
+        secs, smp, ta = _timed_run(s, w, lambda: s.init_state(rel_noise=rel), w.sample_every)
+        runs[path] = (smp, ta)
+        res[path] = dict(value=w.node_steps() / secs, seconds=secs)
+        if net is not None:
+            res[path]["fallbacks_last_step"] = int(s.last_fallbacks())
+            net.close()
+        s.close()
+        _log(f"st57 {path}: {res[path]['value']:.3e} node-steps/s")
+    sp, tp = runs["plain_split"]
+    ss, ts = runs["surrogate"]
+    cmp_plain = _compare(sp, tp, ss, ts, w.dt_split)
+    # oracle on the fibers stimulated first (activity inside the window)
+    onsets = np.array([st["step_on"] for st in w.stims])
+    fibers = sorted(int(f) for f in np.argsort(onsets, kind="stable")[:8])
+    off = w.offsets
+    from oracle import oracle as O
+    cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+    relc = rel[:, torch.as_tensor(cols, device="cuda")].cpu().numpy().astype(np.float64)
+    y0 = O.rest_state(I.MODEL_ST57)[:, None] * (1.0 + relc)
+    n_or = w.n_steps
+    parity = _oracle_parity(w, fibers, y0, ss, ts, n_or)
+    del rel, runs, sp, ss
+    torch.cuda.empty_cache()
+    return dict(workload=f"st57_10000x2000_100Hz_{args.st57_ms:g}ms", fibers=int(len(w.n_nodes)),
+                nodes=int(w.n_total), split_steps=int(w.n_steps), dt_split_ms=w.dt_split,
+                dt_0D_ms=w.dt_0D, network="57-128-128-57 ReLU, BF16 MFMA", tol=args.sur_tol,
+                train=dict(pairs=sur.info["pairs"], adam_steps=sur.info["steps"],
+                           final_loss=sur.info["losses"][-1][1], seconds=train_s,
+                           workload="st57 400 x 1481 bundle, 5 ms"),
+                **res, surrogate_over_plain=res["surrogate"]["value"] / res["plain_split"]["value"],
+                surrogate_vs_plain_split=cmp_plain, surrogate_vs_oracle=parity)
 
 
 def main():
@@ -209,6 +402,12 @@ def main():
         print(f"# oracle: {rate:.3e} node-steps/s on {threads} threads; parity {parity}",
               file=sys.stderr, flush=True)
 
+    sur = None
+    if not args.no_surrogate:
+        s.close()
+        s = None
+        sur = {"hh": surrogate_hh(args), "st57": surrogate_st57(args)}
+
     out = {
         "metric": METRIC,
         "value": value,
@@ -229,8 +428,10 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
+        "surrogate": sur,
     }
-    s.close()
+    if s is not None:
+        s.close()
     print(json.dumps(out), flush=True)
 
 

@@ -421,11 +421,23 @@ class Solver:
             pass
 
     def init_state(self, vm_noise=None, rel_noise=None):
+        """Resting state times (1 + rel_noise) plus vm_noise on V_m; the noise
+        arrays are host arrays or float32 CUDA tensors ([n_total], [S, n_total])."""
         t = self.torch
-        self._vm = (t.as_tensor(np.asarray(vm_noise, dtype=np.float32), device="cuda")
-                    if vm_noise is not None else None)
-        self._rel = (t.as_tensor(np.asarray(rel_noise, dtype=np.float32), device="cuda")
-                     if rel_noise is not None else None)
+
+        def dev(a):
+            if a is None:
+                return None
+            if isinstance(a, t.Tensor):
+                return a.to(device="cuda", dtype=t.float32).contiguous()
+            return t.as_tensor(np.asarray(a, dtype=np.float32), device="cuda")
+        self._vm = dev(vm_noise)
+        self._rel = dev(rel_noise)
+        # the kernel reads n_total and S * n_total values: check before launching
+        if self._vm is not None and self._vm.numel() != self.n_total:
+            raise ValueError(f"vm_noise has {self._vm.numel()} values, expected {self.n_total}")
+        if self._rel is not None and self._rel.numel() != self.S * self.n_total:
+            raise ValueError(f"rel_noise has {self._rel.numel()} values, expected {self.S} x {self.n_total}")
         fib_init_state(self.ctx, self._vm.data_ptr() if self._vm is not None else 0,
                        self._rel.data_ptr() if self._rel is not None else 0)
 

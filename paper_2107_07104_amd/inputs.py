@@ -152,18 +152,21 @@ def batched_hh(n_fibers: int = 1369, n_min: int = 1000, n_max: int = 1500,
 def st57_bundle(n_fibers: int = 400, n_nodes: int = 1481, t_end: float = 5.0,
                 dt_0D: float = 1e-4, dt_split: float = 5e-4, amp: float = AMP_SUPRA,
                 onset_max: float = 2.0, period_ms: float = 0.0,
-                realization: int = 0) -> Workload:
+                realization: int = 0, host_noise: bool = True) -> Workload:
     """ST57 fibers of equal length: every state starts at rest times
     (1 + 0.01 N(0, 1)) (seed 5); each fiber is stimulated for 0.1 ms on three
     nodes around a node drawn from the central 10 % (seed 3) at a time drawn
     from [0, onset_max] ms (seed 4), repeating every period_ms if > 0.
     dt_0D = 1e-4 ms, dt_1D = dt_split = 5e-4 ms.  `realization` > 0 shifts
-    every seed by 100 per realization."""
+    every seed by 100 per realization.  With host_noise False the
+    perturbation is not drawn here (rel_noise None) but on the device by
+    device_rel_noise(), for bundles too large for a host copy."""
     S = 57
     shift = 100 * int(realization)
     lengths = np.full(n_fibers, n_nodes, dtype=np.int32)
     n_total = int(lengths.sum())
-    rel = _normal(SEED_REL_NOISE + shift, S * n_total, 0.01).reshape(S, n_total)
+    rel = (_normal(SEED_REL_NOISE + shift, S * n_total, 0.01).reshape(S, n_total)
+           if host_noise else None)
     g_node = np.random.Generator(np.random.PCG64(SEED_STIM_NODE + shift))
     u_node = g_node.random(n_fibers)
     g_time = np.random.Generator(np.random.PCG64(SEED_STIM_TIME + shift))
@@ -181,7 +184,23 @@ def st57_bundle(n_fibers: int = 400, n_nodes: int = 1481, t_end: float = 5.0,
         name=f"st57_{n_fibers}x{n_nodes}", model=MODEL_ST57, n_nodes=lengths,
         vm_noise=np.zeros(n_total), rel_noise=rel, stims=stims,
         n_steps=int(round(t_end / dt_split)), sample_every=int(round(0.1 / dt_split)),
-        dt_0D=dt_0D, dt_1D=dt_split, dt_split=dt_split)
+        dt_0D=dt_0D, dt_1D=dt_split, dt_split=dt_split,
+        extra=dict(rel_seed=SEED_REL_NOISE + shift))
+
+
+def device_rel_noise(w: Workload, scale: float = 0.01):
+    """Multiplicative perturbation N(0, scale) of every state of every node,
+    drawn on the device (torch CUDA generator seeded from the workload) as a
+    float32 tensor [S, n_total]; for fibers used in host-side checks, copy
+    their columns back."""
+    import torch
+    S = 57 if w.model == MODEL_ST57 else 4
+    g = torch.Generator(device="cuda")
+    g.manual_seed(int(w.extra.get("rel_seed", SEED_REL_NOISE)))
+    out = torch.empty((S, w.n_total), dtype=torch.float32, device="cuda")
+    for k in range(S):
+        out[k].normal_(0.0, scale, generator=g)
+    return out
 
 
 def stim_array(stims: List[dict]) -> np.ndarray:
