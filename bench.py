@@ -89,26 +89,41 @@ KERNEL_SOURCES = ("paper_2107_07104_amd/csrc/fib_kernels.hip",
                   "paper_2107_07104_amd/csrc/hh_model.h",
                   "paper_2107_07104_amd/csrc/fib_internal.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_run_hh.json")
+SUR_SOURCES = ("paper_2107_07104_amd/csrc/surrogate_kernels.hip",
+               "paper_2107_07104_amd/csrc/surrogate_internal.h",
+               "paper_2107_07104_amd/csrc/st57_model.h",
+               "paper_2107_07104_amd/csrc/hh_model.h",
+               "paper_2107_07104_amd/csrc/fib_internal.h")
+SUR_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_surrogate_st57.json")
+# Algorithmic HBM bytes per node of one ST57 surrogate step: read and write
+# the 57 FP32 states (456), the node's stimulus entry (4), the previous V_m
+# for the activation test (read and write, 8) and the activation time (4).
+SUR_ST57_BYTES_PER_NODE = 472
+HBM_PEAK = 8.0e12
+MFMA_BF16_PEAK = 2.5e15
+# Matrix-core work per node of the ST57 network as the kernel runs it
+# (inputs padded to 64, outputs to 64): 2 (64 x 128 + 128 x 128 + 128 x 64)
+SUR_ST57_FLOP_PER_NODE = 65536
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(sources=KERNEL_SOURCES) -> str:
     import hashlib
     h = hashlib.sha256()
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(ROOT, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per launch of the fused kernel from the committed rocprofv3
-    counter runs, or None if the kernel sources changed since they were taken."""
+def measured_traffic(path=TRAFFIC_FILE, sources=KERNEL_SOURCES):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    runs, or None if the kernel sources changed since they were taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             rec = json.load(f)
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != kernel_source_hash():
+    if rec.get("kernel_source_sha256") != kernel_source_hash(sources):
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -285,6 +300,35 @@ def surrogate_st57(args):
             net.close()
         s.close()
         _log(f"st57 {path}: {res[path]['value']:.3e} node-steps/s")
+    # the surrogate step kernel alone, timed with HIP events on the library's
+    # stream (each step also launches the fallback kernel, a few percent)
+    s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
+    s.set_stimulus(w.stims)
+    net = sur.network()
+    s.set_surrogate(net, sur.scales, args.sur_tol)
+    s.init_state(rel_noise=rel)
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(10)]
+    s.step_surrogate(0)
+    for j, (e0, e1) in enumerate(evs):
+        e0.record(stream)
+        s.step_surrogate(1 + j)
+        e1.record(stream)
+    s.sync()
+    torch.cuda.synchronize()
+    step_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    net.close()
+    s.close()
+    achieved = SUR_ST57_BYTES_PER_NODE * w.n_total / (step_ms * 1e-3)
+    roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9,
+                "unit": "GB/s", "frac": achieved / HBM_PEAK,
+                "traffic": measured_traffic(SUR_TRAFFIC_FILE, SUR_SOURCES),
+                "kernel": "k_surrogate<ST57> + k_fallback", "ms_per_step": step_ms,
+                "bytes_per_node": SUR_ST57_BYTES_PER_NODE,
+                "mfma_tflops": SUR_ST57_FLOP_PER_NODE * w.n_total / (step_ms * 1e-3) / 1e12,
+                "mfma_frac": SUR_ST57_FLOP_PER_NODE * w.n_total / (step_ms * 1e-3) / MFMA_BF16_PEAK}
+    _log(f"st57 surrogate step: {step_ms:.3f} ms, {achieved / 1e9:.0f} GB/s")
     sp, tp = runs["plain_split"]
     ss, ts = runs["surrogate"]
     cmp_plain = _compare(sp, tp, ss, ts, w.dt_split)
@@ -307,7 +351,8 @@ def surrogate_st57(args):
                            final_loss=sur.info["losses"][-1][1], seconds=train_s,
                            workload="st57 400 x 1481 bundle, 5 ms"),
                 **res, surrogate_over_plain=res["surrogate"]["value"] / res["plain_split"]["value"],
-                surrogate_vs_plain_split=cmp_plain, surrogate_vs_oracle=parity)
+                surrogate_vs_plain_split=cmp_plain, surrogate_vs_oracle=parity,
+                roofline=roofline)
 
 
 def main():
