@@ -74,6 +74,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-fibers", type=int, default=0,
                     help="fibers in the oracle sample (default: 2 per host thread)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default workgroup shape instead of measuring candidates")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-train-steps", type=int, default=20000)
     ap.add_argument("--sur-tol", type=float, default=1e-2)
@@ -170,15 +172,20 @@ def _timed_run(s, w, init, sample_every):
     return time.perf_counter() - t0, samples, s.tact()
 
 
-def _compare(sa, ta, sb, tb, dt_split):
-    """V_m and activation-time differences of run b against run a."""
+def _compare(sa, ta, sb, tb, dt_split, t_end):
+    """V_m and activation-time differences of run b against run a.  Nodes
+    that activate in one run only are reported with the earliest activation
+    time among them: within one split step of t_end, the other run would
+    activate after the window."""
     dv = float((sa - sb).abs().max().item()) if sa.numel() else 0.0
     fa, fb = np.isfinite(ta), np.isfinite(tb)
     both = fa & fb
+    one = fa != fb
+    first = float(np.min(np.where(fa, ta, tb)[one])) if one.any() else None
     return dict(vm_max_diff_mV=dv,
                 tact_max_diff_ms=float(np.max(np.abs(ta[both] - tb[both]))) if both.any() else 0.0,
-                tact_mismatch=int(np.sum(fa != fb)), activated=int(both.sum()),
-                dt_split_ms=dt_split)
+                tact_mismatch=int(one.sum()), mismatch_earliest_tact_ms=first,
+                t_end_ms=t_end, activated=int(both.sum()), dt_split_ms=dt_split)
 
 
 def _oracle_parity(w, fibers, y0_cols, gpu_samples, gpu_tact, n_steps):
@@ -261,7 +268,7 @@ def surrogate_hh(args):
                            final_loss=sur.info["losses"][-1][1], seconds=train_s,
                            workload="realization 0 of the same bundle"),
                 **res, surrogate_over_best_plain=res["surrogate"]["value"] / best_plain,
-                surrogate_vs_plain_split=_compare(sp, tp, ss, ts, w.dt_split),
+                surrogate_vs_plain_split=_compare(sp, tp, ss, ts, w.dt_split, w.n_steps * w.dt_split),
                 surrogate_vs_oracle=parity)
 
 
@@ -331,7 +338,7 @@ def surrogate_st57(args):
     _log(f"st57 surrogate step: {step_ms:.3f} ms, {achieved / 1e9:.0f} GB/s")
     sp, tp = runs["plain_split"]
     ss, ts = runs["surrogate"]
-    cmp_plain = _compare(sp, tp, ss, ts, w.dt_split)
+    cmp_plain = _compare(sp, tp, ss, ts, w.dt_split, w.n_steps * w.dt_split)
     # oracle on the fibers stimulated first (activity inside the window)
     onsets = np.array([st["step_on"] for st in w.stims])
     fibers = sorted(int(f) for f in np.argsort(onsets, kind="stable")[:8])
@@ -377,9 +384,15 @@ def main():
     vm = torch.as_tensor(w.vm_noise.astype(np.float32), device="cuda")
     rows = w.n_steps // w.sample_every
     samples = torch.empty((rows, w.n_total), device="cuda")
+    default_plan = s.plan()
+    tuned = None
+    if not args.no_autotune:
+        # workgroup shape measured on the workload itself (outside the timed region)
+        F.fib_init_state(s.ctx, vm.data_ptr(), 0)
+        tuned = s.autotune(trial_steps=200, max_candidates=8)
     plan = s.plan()
-    print(f"# workload {w.name}: {w.n_total} nodes, {w.n_steps} split steps; plan {plan}",
-          file=sys.stderr, flush=True)
+    print(f"# workload {w.name}: {w.n_total} nodes, {w.n_steps} split steps; default plan "
+          f"{default_plan}, plan {plan}", file=sys.stderr, flush=True)
 
     def step(ev=None):
         F.fib_init_state(s.ctx, vm.data_ptr(), 0)
@@ -469,7 +482,8 @@ def main():
         "config": {"workload": "hh_batched_1369_fibers_1000-1500_nodes_20ms",
                    "fibers": int(len(w.n_nodes)), "nodes": int(w.n_total),
                    "split_steps": int(w.n_steps), "dt_split_ms": w.dt_split,
-                   "schedule": "fused", "plan": plan, "path": "plain"},
+                   "schedule": "fused", "plan": plan, "default_plan": default_plan,
+                   "autotune": tuned, "path": "plain"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,

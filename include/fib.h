@@ -85,8 +85,9 @@ typedef struct {
   double v_th;        /* activation threshold of the activation-time observable, mV */
   int32_t pcr_full;   /* 0: stop the reduced-system PCR once every remaining coupling is
                          below 2^-40 of the diagonal; 1: run all log2(threads) levels */
-  int32_t threads_per_group; /* 0: automatic; else 64..1024, a power of two */
-  int32_t nodes_per_thread;  /* 0: automatic; else 2..8 */
+  int32_t threads_per_group; /* 0: automatic; else a multiple of 64 in 64..1024 (at most
+                                768 with 9 or 10 nodes per thread, 512 with 11..14) */
+  int32_t nodes_per_thread;  /* 0: automatic (2..8); else 2..14 */
   int32_t groups;            /* 0: automatic (one per compute unit); else the number of
                                 fiber bins, i.e. workgroups of the fused kernel */
 } fib_params;
@@ -207,11 +208,26 @@ int fib_reset_observables(fib_t* ctx);
  * error and FIB_ENONFINITE if a kernel flagged a non-finite V_m. */
 int fib_sync(fib_t* ctx);
 
-/* Describes the plan chosen by fib_create: workgroups (fiber bins),
- * threads per workgroup, nodes per thread, and PCR levels of the fused
- * diffusion solve.  Any pointer may be NULL. */
+/* Describes the plan chosen by fib_create (or fib_autotune): workgroups
+ * (fiber bins), threads per workgroup, nodes per thread, and PCR levels of
+ * the fused diffusion solve.  Any pointer may be NULL. */
 int fib_plan_info(const fib_t* ctx, int32_t* groups, int32_t* threads, int32_t* nodes_per_thread,
                   int32_t* pcr_levels);
+
+/* Autotuner of the workgroup shape (the batching of uneven fibers into
+ * bins of whole fibers is kept): for the current bins it ranks every
+ * (threads per workgroup, nodes per thread) that holds the heaviest bin
+ * with at most 30 % padding by the slots one SIMD sweeps per step, times
+ * the current plan and up to max_candidates - 1 of the best-ranked ones
+ * over trial_steps split steps of fib_run from the current state (HIP
+ * events on the context's stream), and keeps the fastest.  The state,
+ * activation times and previous-V_m buffers are restored afterwards, so a
+ * tuned context continues exactly where it was; results of later runs
+ * differ from the untuned plan only by FP32 rounding (the partitioned
+ * solve groups nodes differently).  ms_per_step (nullable) receives the
+ * chosen plan's trial time per split step.  Synchronous; allocates scratch
+ * for one copy of the state.  FIB_ESTATE without an initialized state. */
+int fib_autotune(fib_t* ctx, int32_t trial_steps, int32_t max_candidates, double* ms_per_step);
 
 /* ------------------------------------------------------------------------
  * Surrogate network: a multilayer perceptron with SiLU hidden layers and a

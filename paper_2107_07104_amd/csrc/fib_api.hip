@@ -226,7 +226,6 @@ int64_t ceil_steps(double span, double dt) {
   return n < 1.0 ? 1 : (int64_t)n;
 }
 
-bool is_pow2(int x) { return x > 0 && (x & (x - 1)) == 0; }
 
 }  // namespace
 
@@ -263,6 +262,7 @@ struct fib_ctx {
   int32_t* d_node_stim = nullptr;
   fib::StimDev* d_stim = nullptr;
   int32_t n_stim = 0;
+  std::vector<int32_t> node_stim;      // host copy: stimulus entry + 1 per node (0: none)
   bool state_ready = false;
 
   // surrogate
@@ -422,48 +422,9 @@ double cn_r(const fib_ctx* c, double dt_cn) {
   return c->p.sigma / (c->p.Am * c->p.Cm) * dt_cn / (c->p.h * c->p.h);
 }
 
-// Chooses bins, threads per bin and nodes per thread, and fills the slot
-// tables.
-int make_plan(fib_ctx* c) {
-  const int64_t max_len =
-      c->n_fibers ? *std::max_element(c->n_nodes.begin(), c->n_nodes.end()) : 0;
-  if (max_len > 8 * 1024)
-    return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the 8192 nodes one workgroup holds",
-                (long long)max_len);
-  int groups = c->p.groups > 0 ? c->p.groups : c->cu_count;
-  groups = (int)std::min<int64_t>(groups, std::max<int32_t>(c->n_fibers, 1));
-  for (;;) {
-    pack_bins(c, groups);
-    int64_t load = 0;
-    for (auto& b : c->bin_fibers) {
-      int64_t s = 0;
-      for (int32_t f : b) s += c->n_nodes[f];
-      load = std::max(load, s);
-    }
-    load = std::max<int64_t>(load, 1);
-    int K = c->p.nodes_per_thread;
-    int T = c->p.threads_per_group;
-    if (K == 0 && T == 0) {
-      K = (int)std::min<int64_t>(8, std::max<int64_t>(2, (load + 1023) / 1024));
-      T = 64;
-      while ((int64_t)T * K < load) T *= 2;
-    } else if (K == 0) {
-      K = (int)std::max<int64_t>(2, (load + T - 1) / T);
-    } else if (T == 0) {
-      T = 64;
-      while ((int64_t)T * K < load && T < 1024) T *= 2;
-    }
-    if (K <= 8 && T <= 1024 && (int64_t)T * K >= load) {
-      c->K = K;
-      c->threads = T;
-      c->groups = groups;
-      break;
-    }
-    if (c->p.groups > 0 || groups >= c->n_fibers)
-      return fail(FIB_EUNSUPPORTED, "cannot fit %lld nodes into %d bins with the requested shape",
-                  (long long)load, groups);
-    groups = std::min(groups * 2, c->n_fibers);
-  }
+// Fills the slot tables and the PCR level count of the current shape
+// (groups, threads, K) and bins.
+void build_tables(fib_ctx* c) {
   c->cap = c->threads * c->K;
   const size_t nslots = (size_t)c->groups * c->cap;
   c->slot_gidx.assign(nslots, -1);
@@ -489,6 +450,89 @@ int make_plan(fib_ctx* c) {
   for (int b = 0; b < c->groups; ++b)
     lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
   c->levels = lv;
+}
+
+int64_t max_bin_load(const fib_ctx* c) {
+  int64_t load = 0;
+  for (auto& b : c->bin_fibers) {
+    int64_t s = 0;
+    for (int32_t f : b) s += c->n_nodes[f];
+    load = std::max(load, s);
+  }
+  return std::max<int64_t>(load, 1);
+}
+
+// Chooses bins, threads per bin and nodes per thread, and fills the slot
+// tables.  Automatic shapes use K <= 8 nodes per thread and a power-of-two
+// workgroup; fib_autotune measures the others.
+int make_plan(fib_ctx* c) {
+  const int64_t max_len =
+      c->n_fibers ? *std::max_element(c->n_nodes.begin(), c->n_nodes.end()) : 0;
+  if (max_len > 14 * 512)
+    return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the %d nodes one workgroup holds",
+                (long long)max_len, 14 * 512);
+  int groups = c->p.groups > 0 ? c->p.groups : c->cu_count;
+  groups = (int)std::min<int64_t>(groups, std::max<int32_t>(c->n_fibers, 1));
+  for (;;) {
+    pack_bins(c, groups);
+    const int64_t load = max_bin_load(c);
+    int K = c->p.nodes_per_thread;
+    int T = c->p.threads_per_group;
+    if (K == 0 && T == 0) {
+      K = (int)std::min<int64_t>(8, std::max<int64_t>(2, (load + 1023) / 1024));
+      T = 64;
+      while ((int64_t)T * K < load) T *= 2;
+    } else if (K == 0) {
+      K = (int)std::max<int64_t>(2, (load + T - 1) / T);
+    } else if (T == 0) {
+      T = (int)std::max<int64_t>(64, (load + 64LL * K - 1) / (64LL * K) * 64);
+    }
+    const int maxT = fib::plan_max_threads(K);
+    if (maxT > 0 && T <= maxT && (int64_t)T * K >= load) {
+      c->K = K;
+      c->threads = T;
+      c->groups = groups;
+      break;
+    }
+    if (c->p.groups > 0 || groups >= c->n_fibers)
+      return fail(FIB_EUNSUPPORTED, "cannot fit %lld nodes into %d bins with the requested shape",
+                  (long long)load, groups);
+    groups = std::min(groups * 2, c->n_fibers);
+  }
+  build_tables(c);
+  return FIB_OK;
+}
+
+// Slot-info words with the stimulus entry of each real slot.
+std::vector<uint32_t> slot_info_with_stim(const fib_ctx* c) {
+  std::vector<uint32_t> info(c->slot_base);
+  if (!c->node_stim.empty())
+    for (size_t k = 0; k < info.size(); ++k)
+      if (c->slot_gidx[k] >= 0)
+        info[k] |= (uint32_t)c->node_stim[c->slot_gidx[k]] << fib::SLOT_STIM_SHIFT;
+  return info;
+}
+
+// Uploads the slot tables of the current plan (reallocating them if their
+// size changed).  The stream must be idle.
+int upload_plan(fib_ctx* c, size_t old_slots) {
+  const size_t nslots = std::max<size_t>(c->slot_gidx.size(), 1);
+  if (nslots != old_slots) {
+    (void)hipFree(c->d_slot_gidx);
+    (void)hipFree(c->d_slot_info);
+    c->d_slot_gidx = nullptr;
+    c->d_slot_info = nullptr;
+    if (hipMalloc(&c->d_slot_gidx, sizeof(int32_t) * nslots) != hipSuccess ||
+        hipMalloc(&c->d_slot_info, sizeof(uint32_t) * nslots) != hipSuccess)
+      return fail(FIB_ENOMEM, "device allocation failed");
+  }
+  const std::vector<uint32_t> info = slot_info_with_stim(c);
+  if (!c->slot_gidx.empty()) {
+    HIP_TRY(hipMemcpy(c->d_slot_gidx, c->slot_gidx.data(), sizeof(int32_t) * c->slot_gidx.size(),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(c->d_slot_info, info.data(), sizeof(uint32_t) * info.size(),
+                      hipMemcpyHostToDevice));
+  }
   return FIB_OK;
 }
 
@@ -551,10 +595,14 @@ int fib_check_params(const fib_params* p) {
     return fail(FIB_EINVAL, "time steps must be > 0");
   if (!std::isfinite(p->v_th)) return fail(FIB_EINVAL, "v_th must be finite");
   if (p->threads_per_group != 0 &&
-      (!is_pow2(p->threads_per_group) || p->threads_per_group < 64 || p->threads_per_group > 1024))
-    return fail(FIB_EINVAL, "threads_per_group must be 0 or a power of two in [64, 1024]");
-  if (p->nodes_per_thread != 0 && (p->nodes_per_thread < 2 || p->nodes_per_thread > 8))
-    return fail(FIB_EINVAL, "nodes_per_thread must be 0 or in [2, 8]");
+      (p->threads_per_group % 64 != 0 || p->threads_per_group < 64 || p->threads_per_group > 1024))
+    return fail(FIB_EINVAL, "threads_per_group must be 0 or a multiple of 64 in [64, 1024]");
+  if (p->nodes_per_thread != 0 && fib::plan_max_threads(p->nodes_per_thread) == 0)
+    return fail(FIB_EINVAL, "nodes_per_thread must be 0 or in [2, 14]");
+  if (p->threads_per_group != 0 && p->nodes_per_thread != 0 &&
+      p->threads_per_group > fib::plan_max_threads(p->nodes_per_thread))
+    return fail(FIB_EINVAL, "%d nodes per thread allow at most %d threads per group",
+                p->nodes_per_thread, fib::plan_max_threads(p->nodes_per_thread));
   if (p->groups < 0) return fail(FIB_EINVAL, "groups must be >= 0");
   if (ceil_steps(p->dt_split * 0.5, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
     return fail(FIB_EINVAL, "more than 2^20 substeps per split step");
@@ -641,20 +689,14 @@ int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, vo
   if ((rc = check_levels_fit(c, c->levels))) return bail(rc);
 
   const size_t nt = (size_t)std::max<int64_t>(total, 1);
-  const size_t nslots = std::max<size_t>(c->slot_gidx.size(), 1);
   if (hipMalloc(&c->d_state, sizeof(float) * nt * c->S) != hipSuccess ||
       hipMalloc(&c->d_tact, sizeof(float) * nt) != hipSuccess ||
       hipMalloc(&c->d_vprev, sizeof(float) * nt) != hipSuccess ||
       hipMalloc(&c->d_node_stim, sizeof(int32_t) * nt) != hipSuccess ||
-      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess ||
-      hipMalloc(&c->d_slot_gidx, sizeof(int32_t) * nslots) != hipSuccess ||
-      hipMalloc(&c->d_slot_info, sizeof(uint32_t) * nslots) != hipSuccess)
+      hipMalloc(&c->d_flag, sizeof(int)) != hipSuccess)
     return bail(fail(FIB_ENOMEM, "device allocation failed"));
-  if (hipMemcpy(c->d_slot_gidx, c->slot_gidx.data(), sizeof(int32_t) * c->slot_gidx.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(c->d_slot_info, c->slot_base.data(), sizeof(uint32_t) * c->slot_base.size(),
-                hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemset(c->d_node_stim, 0, sizeof(int32_t) * nt) != hipSuccess ||
+  if ((rc = upload_plan(c, 0))) return bail(rc);
+  if (hipMemset(c->d_node_stim, 0, sizeof(int32_t) * nt) != hipSuccess ||
       hipMemset(c->d_flag, 0, sizeof(int)) != hipSuccess)
     return bail(fail(FIB_EHIP, "device upload failed"));
   if (fib::launch_fill(c->d_tact, total, INFINITY, c->stream) != hipSuccess ||
@@ -776,10 +818,9 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
   }
   if ((int64_t)n + 1 >= ((int64_t)1 << (32 - fib::SLOT_STIM_SHIFT)))
     return fail(FIB_EINVAL, "too many stimulus entries");
-  std::vector<uint32_t> info(c->slot_base);
-  for (size_t k = 0; k < info.size(); ++k)
-    if (c->slot_gidx[k] >= 0) info[k] |= (uint32_t)node_stim[c->slot_gidx[k]] << fib::SLOT_STIM_SHIFT;
   HIP_TRY(hipStreamSynchronize(c->stream));
+  c->node_stim = node_stim;
+  const std::vector<uint32_t> info = slot_info_with_stim(c);
   (void)hipFree(c->d_stim);
   c->d_stim = nullptr;
   c->n_stim = 0;
@@ -896,6 +937,111 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     }
   }
   return FIB_OK;
+}
+
+int fib_autotune(fib_t* c, int32_t trial_steps, int32_t max_candidates, double* ms_per_step) {
+  if (int rc = check_ctx(c)) return rc;
+  if (trial_steps < 1 || trial_steps > 100000) return fail(FIB_EINVAL, "trial_steps must be in [1, 100000]");
+  if (max_candidates < 1) return fail(FIB_EINVAL, "max_candidates must be >= 1");
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (ms_per_step) *ms_per_step = 0.0;
+  if (c->n_total == 0) return FIB_OK;
+  // candidate shapes for the current bins: every workgroup size (multiple of
+  // 64) and nodes per thread that hold the heaviest bin with at most 30 %
+  // padding, ranked by the slots one SIMD sweeps per step (waves per SIMD x K)
+  const int64_t load = max_bin_load(c);
+  struct Cand { int T, K; int64_t cost; };
+  std::vector<Cand> cand;
+  for (int K = 2; K <= 14; ++K) {
+    const int maxT = fib::plan_max_threads(K);
+    for (int T = 64; T <= maxT; T += 64) {
+      const int64_t capn = (int64_t)T * K;
+      if (capn < load || capn * 10 > load * 13) continue;
+      if (fib::lds_bytes_for(T, 1) > c->max_lds) continue;
+      cand.push_back({T, K, (int64_t)((T / 64 + 3) / 4) * K});
+    }
+  }
+  std::sort(cand.begin(), cand.end(), [](const Cand& x, const Cand& y) {
+    return x.cost != y.cost ? x.cost < y.cost : x.T < y.T;
+  });
+  std::vector<Cand> trial;
+  trial.push_back({c->threads, c->K, 0});
+  for (const Cand& x : cand) {
+    if ((int)trial.size() >= max_candidates) break;
+    if (x.cost * 100 > cand[0].cost * 112) break;
+    if (x.T == c->threads && x.K == c->K) continue;
+    trial.push_back(x);
+  }
+  // the trial runs start from the current state and observables; keep copies
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t sb = sizeof(float) * (size_t)c->n_total * c->S, ob = sizeof(float) * (size_t)c->n_total;
+  float *s_state = nullptr, *s_tact = nullptr, *s_vprev = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  auto cleanup = [&]() {
+    (void)hipFree(s_state);
+    (void)hipFree(s_tact);
+    (void)hipFree(s_vprev);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+  };
+  if (hipMalloc(&s_state, sb) != hipSuccess || hipMalloc(&s_tact, ob) != hipSuccess ||
+      hipMalloc(&s_vprev, ob) != hipSuccess || hipEventCreate(&e0) != hipSuccess ||
+      hipEventCreate(&e1) != hipSuccess) {
+    cleanup();
+    return fail(FIB_ENOMEM, "autotune: scratch allocation failed");
+  }
+  auto copy_all = [&](bool save) -> hipError_t {
+    hipError_t e = hipMemcpyAsync(save ? s_state : c->d_state, save ? c->d_state : s_state, sb,
+                                  hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(save ? s_tact : c->d_tact, save ? c->d_tact : s_tact, ob,
+                         hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(save ? s_vprev : c->d_vprev, save ? c->d_vprev : s_vprev, ob,
+                         hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return e;
+  };
+  int rc = FIB_OK;
+  if (copy_all(true) != hipSuccess) rc = fail(FIB_EHIP, "autotune: state copy failed");
+  double best = -1.0;
+  Cand pick = trial[0];
+  for (const Cand& x : trial) {
+    if (rc) break;
+    const size_t old = std::max<size_t>(c->slot_gidx.size(), 1);
+    c->threads = x.T;
+    c->K = x.K;
+    build_tables(c);
+    if (fib::lds_bytes_for(c->threads, c->levels) > c->max_lds) continue;
+    if ((rc = upload_plan(c, old))) break;
+    if (copy_all(false) != hipSuccess) { rc = fail(FIB_EHIP, "autotune: state copy failed"); break; }
+    if ((rc = fib_run(c, 0, 1, 0, nullptr, 0))) break;  // warm-up (code object load)
+    if (copy_all(false) != hipSuccess) { rc = fail(FIB_EHIP, "autotune: state copy failed"); break; }
+    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(FIB_EHIP, "autotune: event failed"); break; }
+    if ((rc = fib_run(c, 0, trial_steps, 0, nullptr, 0))) break;
+    float ms = 0.0f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = fail(FIB_EHIP, "autotune: timing failed");
+      break;
+    }
+    if (best < 0.0 || ms < best) {
+      best = ms;
+      pick = x;
+    }
+  }
+  // the chosen shape, and the state and observables as before
+  if (!rc) {
+    const size_t old = std::max<size_t>(c->slot_gidx.size(), 1);
+    c->threads = pick.T;
+    c->K = pick.K;
+    build_tables(c);
+    rc = upload_plan(c, old);
+  }
+  if (copy_all(false) != hipSuccess && !rc) rc = fail(FIB_EHIP, "autotune: state copy failed");
+  cleanup();
+  if (!rc && ms_per_step) *ms_per_step = best / trial_steps;
+  return rc;
 }
 
 int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, const float* in_scale,

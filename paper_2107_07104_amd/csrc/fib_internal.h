@@ -70,6 +70,9 @@ __device__ __forceinline__ float stim_current(uint32_t sid1, const StimDev* __re
 }
 
 // Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.
+// Largest workgroup size the kernels are built for with K nodes per thread
+// (0: K not supported).
+int plan_max_threads(int K);
 hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds_bytes,
                             const KArgs& a, hipStream_t s);
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, const KArgs& a,

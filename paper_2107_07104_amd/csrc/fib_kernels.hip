@@ -222,8 +222,8 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
 // node's four states in registers: R(dt/2) D(dt) R(dt/2), then the
 // observables.  Device memory is read at the start, written at the end and
 // for samples / activation times only.
-template <int K>
-__global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
+template <int K, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
   extern __shared__ float lds[];
   const int T = blockDim.x;
   const int t = threadIdx.x;
@@ -320,8 +320,8 @@ __global__ __launch_bounds__(1024) void k_run_hh(KArgs A) {
 // Diffusion only (states in device memory)
 // ---------------------------------------------------------------------------
 
-template <int K>
-__global__ __launch_bounds__(1024) void k_diffusion(KArgs A) {
+template <int K, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
   extern __shared__ float lds[];
   const int T = blockDim.x;
   const int t = threadIdx.x;
@@ -445,45 +445,63 @@ __global__ __launch_bounds__(256) void k_check_finite(const float* p, int64_t n,
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-template <int K>
-static hipError_t run_fused_k(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_run_hh<K>, dim3(groups), dim3(threads), lds, s, a);
-  return hipGetLastError();
+// Instantiations: nodes per thread K with the largest workgroup MAXT the
+// launch may use.  A smaller MAXT gives the compiler more registers per
+// thread (1024 threads: 128 VGPRs; 768: 168; 512: 256), which the larger K
+// need; plan_fits() in the host runtime accepts exactly these pairs.
+#define FIB_FOR_EACH_PLAN(X) \
+  X(2, 1024) X(3, 1024) X(4, 1024) X(5, 1024) X(6, 1024) X(7, 1024) X(8, 1024) \
+  X(7, 768) X(8, 768) X(9, 768) X(10, 768) \
+  X(10, 512) X(11, 512) X(12, 512) X(13, 512) X(14, 512)
+
+int plan_max_threads(int K) {
+  if (K >= 2 && K <= 8) return 1024;
+  if (K >= 9 && K <= 10) return 768;
+  if (K >= 11 && K <= 14) return 512;
+  return 0;
 }
+
+// Picks the instantiation with the smallest MAXT that still holds `threads`.
+template <template <int, int> class L>
+static hipError_t dispatch_plan(int K, int threads, int groups, size_t lds, const KArgs& a,
+                                hipStream_t s) {
+  int best = 0;
+#define FIB_PICK(KK, MT) \
+  if (K == KK && threads <= MT && (best == 0 || MT < best)) best = MT;
+  FIB_FOR_EACH_PLAN(FIB_PICK)
+#undef FIB_PICK
+#define FIB_LAUNCH(KK, MT) \
+  if (K == KK && best == MT) return L<KK, MT>::go(groups, threads, lds, a, s);
+  FIB_FOR_EACH_PLAN(FIB_LAUNCH)
+#undef FIB_LAUNCH
+  return hipErrorInvalidValue;
+}
+
+template <int K, int MAXT>
+struct FusedLaunch {
+  static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_run_hh<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int K, int MAXT>
+struct DiffusionLaunch {
+  static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_diffusion<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
+    return hipGetLastError();
+  }
+};
 
 hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds,
                             const KArgs& a, hipStream_t s) {
   if (model != 0) return hipErrorInvalidValue;
-  switch (K) {
-    case 2: return run_fused_k<2>(groups, threads, lds, a, s);
-    case 3: return run_fused_k<3>(groups, threads, lds, a, s);
-    case 4: return run_fused_k<4>(groups, threads, lds, a, s);
-    case 5: return run_fused_k<5>(groups, threads, lds, a, s);
-    case 6: return run_fused_k<6>(groups, threads, lds, a, s);
-    case 7: return run_fused_k<7>(groups, threads, lds, a, s);
-    case 8: return run_fused_k<8>(groups, threads, lds, a, s);
-    default: return hipErrorInvalidValue;
-  }
-}
-
-template <int K>
-static hipError_t diffusion_k(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_diffusion<K>, dim3(groups), dim3(threads), lds, s, a);
-  return hipGetLastError();
+  return dispatch_plan<FusedLaunch>(K, threads, groups, lds, a, s);
 }
 
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KArgs& a,
                             hipStream_t s) {
-  switch (K) {
-    case 2: return diffusion_k<2>(groups, threads, lds, a, s);
-    case 3: return diffusion_k<3>(groups, threads, lds, a, s);
-    case 4: return diffusion_k<4>(groups, threads, lds, a, s);
-    case 5: return diffusion_k<5>(groups, threads, lds, a, s);
-    case 6: return diffusion_k<6>(groups, threads, lds, a, s);
-    case 7: return diffusion_k<7>(groups, threads, lds, a, s);
-    case 8: return diffusion_k<8>(groups, threads, lds, a, s);
-    default: return hipErrorInvalidValue;
-  }
+  return dispatch_plan<DiffusionLaunch>(K, threads, groups, lds, a, s);
 }
 
 hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,

@@ -45,7 +45,7 @@ EXPORTS = (
     "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
     "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate",
-    "fib_surrogate_predict",
+    "fib_surrogate_predict", "fib_autotune",
 )
 
 
@@ -105,6 +105,7 @@ def lib():
             "fib_reset_observables": ([_vp], C.c_int),
             "fib_sync": ([_vp], C.c_int),
             "fib_plan_info": ([_vp, _i32p, _i32p, _i32p, _i32p], C.c_int),
+            "fib_autotune": ([_vp, C.c_int32, C.c_int32, C.POINTER(C.c_double)], C.c_int),
             "fib_plan_preview": ([C.POINTER(fib_params), C.c_int32, _i32p, C.c_int32, _i32p, _i32p,
                                   _i32p, _i32p, C.POINTER(C.c_int64)], C.c_int),
         }
@@ -266,6 +267,12 @@ def fib_plan_preview(params: fib_params, n_nodes, compute_units: int = 256):
                                   C.byref(l), C.byref(mx)))
     return dict(groups=g.value, threads=t.value, nodes_per_thread=k.value, pcr_levels=l.value,
                 max_load=mx.value)
+
+
+def fib_autotune(ctx, trial_steps: int = 100, max_candidates: int = 8) -> float:
+    ms = C.c_double(0.0)
+    _check(lib().fib_autotune(_vp(ctx), int(trial_steps), int(max_candidates), C.byref(ms)))
+    return ms.value
 
 
 def fib_mlp_create(sizes, stream=None, act: str = "silu") -> int:
@@ -481,6 +488,14 @@ class Solver:
 
     def plan(self):
         return fib_plan_info(self.ctx)
+
+    def autotune(self, trial_steps=100, max_candidates=8):
+        """Measures candidate workgroup shapes and keeps the fastest; returns
+        the chosen plan with its trial time per split step (ms)."""
+        ms = fib_autotune(self.ctx, trial_steps, max_candidates)
+        out = dict(self.plan())
+        out["trial_ms_per_step"] = ms
+        return out
 
     def set_surrogate(self, net, scales: dict, tol: float):
         fib_set_surrogate(self.ctx, net.net, scales["in_shift"], scales["in_scale"],

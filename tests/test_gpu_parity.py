@@ -75,7 +75,11 @@ LENGTHS = [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 63, 64, 65, 100, 1000, 1481, 1500, 2,
                                    dict(threads_per_group=1024, nodes_per_thread=2, groups=3),
                                    dict(threads_per_group=1024, nodes_per_thread=3, groups=2),
                                    dict(threads_per_group=1024, nodes_per_thread=5, groups=1),
-                                   dict(pcr_full=1, threads_per_group=512, nodes_per_thread=4)])
+                                   dict(pcr_full=1, threads_per_group=512, nodes_per_thread=4),
+                                   dict(threads_per_group=768, nodes_per_thread=9),
+                                   dict(threads_per_group=960, nodes_per_thread=7),
+                                   dict(threads_per_group=512, nodes_per_thread=14),
+                                   dict(pcr_full=1, threads_per_group=704, nodes_per_thread=10)])
 @pytest.mark.parametrize("dt", [1e-3, 5e-3])
 def test_diffusion_step_matches_oracle(shape, dt):
     say(f"[diffusion] shape={shape} dt={dt}")
@@ -129,6 +133,7 @@ def _assert_parity(w, res, end_time):
     say("  ", res)
     assert res["vm_err"] <= 0.5
     assert res["tact_err"] <= 1.0 * w.dt_split
+    assert res["tact_mismatch"] == 0
 
 
 @pytest.mark.parametrize("amp", [I.AMP_AS_WRITTEN, I.AMP_SUPRA])
@@ -158,6 +163,46 @@ def test_batched_run_matches_oracle_small():
     _assert_parity(w, res, w.n_steps * w.dt_split)
     assert res["activated"] > 1000
     gpu[3].close()
+
+
+@pytest.mark.parametrize("shape", [dict(threads_per_group=768, nodes_per_thread=9),
+                                   dict(threads_per_group=512, nodes_per_thread=14, groups=16),
+                                   dict(threads_per_group=960, nodes_per_thread=7, groups=8)])
+def test_batched_run_matches_oracle_in_other_workgroup_shapes(shape):
+    """The fused kernel in the shapes only the autotuner picks by default:
+    non-power-of-two workgroups and 9-14 nodes per thread."""
+    w = I.batched_hh(n_fibers=24, t_end=4.0)
+    say(f"[run batched shape] {shape}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w, **shape)
+    plan = gpu[3].plan()
+    say("  plan", plan)
+    assert plan["threads"] == shape["threads_per_group"]
+    assert plan["nodes_per_thread"] == shape["nodes_per_thread"]
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    gpu[3].close()
+
+
+def test_autotune_restores_the_state_and_keeps_parity():
+    w = I.batched_hh(n_fibers=24, t_end=7.0)
+    say("[autotune]")
+    s = gpu_solver(w)
+    s.run(0, 500)
+    s.sync()
+    y0, t0 = s.get_state(), s.tact()
+    info = s.autotune(trial_steps=40, max_candidates=6)
+    say("  chosen", info)
+    np.testing.assert_array_equal(s.get_state(), y0)
+    np.testing.assert_array_equal(s.tact(), t0)
+    assert info["threads"] % 64 == 0 and info["trial_ms_per_step"] > 0
+    # a whole run with the tuned plan against the oracle
+    s.init_state(vm_noise=w.vm_noise.astype(np.float32))
+    ora = oracle_run(w)
+    gpu = gpu_run(w, solver=s)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    s.close()
 
 
 def test_ragged_and_degenerate_fibers_run():

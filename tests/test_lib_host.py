@@ -40,7 +40,7 @@ def test_n_states():
     ("Cm", 0.0), ("Am", -1.0), ("h", float("nan")), ("sigma", -0.1), ("dt_0D", 0.0),
     ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
     ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
-    ("nodes_per_thread", 9), ("groups", -1), ("model", 7), ("schedule", 3)])
+    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("schedule", 3)])
 def test_check_params_rejects(field, value):
     p = F.make_params()
     setattr(p, field, value)
@@ -50,6 +50,18 @@ def test_check_params_rejects(field, value):
 
 def test_check_params_accepts_defaults():
     assert F.fib_check_params(F.make_params()) == F.FIB_OK
+
+
+@pytest.mark.parametrize("threads,k,ok", [(768, 9, True), (960, 7, True), (512, 14, True),
+                                          (1024, 9, False), (832, 10, False), (576, 12, False)])
+def test_workgroup_shapes_follow_the_built_kernels(threads, k, ok):
+    """Workgroup sizes are multiples of 64; 9-10 nodes per thread allow at most
+    768 threads and 11-14 at most 512 (the kernels' register budgets)."""
+    p = F.make_params(threads_per_group=threads, nodes_per_thread=k)
+    assert (F.fib_check_params(p) == F.FIB_OK) == ok
+    if ok:
+        plan = F.fib_plan_preview(p, [threads * k // 2] * 3, 256)
+        assert plan["threads"] == threads and plan["nodes_per_thread"] == k
     assert F.fib_check_params(F.make_params(threads_per_group=64, nodes_per_thread=8)) == F.FIB_OK
 
 
