@@ -46,14 +46,15 @@ constexpr ExpCoef kXn = exp_coef(-1.0 / 10.0, 65.0, 0.0);         // exp(x_n), x
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
-// x / (exp(x) - 1) given e = exp(x).  For |x| < 0.1 the Bernoulli series
-// 1 - x/2 + x^2/12 - x^4/720 (truncation error below x^6/30240 < 4e-11)
-// replaces the quotient, whose cancellation error grows like 6e-8 / |x|.
+// x / (exp(x) - 1) given e = exp(x).  For |x| < 1e-3 the series 1 - x/2
+// (truncation error x^2/12 < 1e-7, below FP32 resolution) replaces the
+// quotient, which is 0/0 at x = 0 and whose cancellation error, about
+// 1.2e-7 / |x| relative, stays below 1.2e-4 outside that interval; the
+// rate is that inexact only within 0.01 mV of the singular voltage.
 __device__ __forceinline__ float x_over_expm1(float x, float e) {
-  float x2 = x * x;
-  float s = fmaf(x, fmaf(x, fmaf(x2, -1.0f / 720.0f, 1.0f / 12.0f), -0.5f), 1.0f);
-  float q = x * rcp(e - 1.0f);
-  return fabsf(x) < 0.1f ? s : q;
+  const float s = fmaf(x, -0.5f, 1.0f);
+  const float q = x * rcp(e - 1.0f);
+  return fabsf(x) < 1e-3f ? s : q;
 }
 
 // Every state is carried as its offset from the resting state (ref): the
