@@ -1097,10 +1097,12 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
       return fail(FIB_EINVAL, "state %d: scales must be finite and > 0", k);
     tab[fib::kTabIn + 2 * k] = in_scale[k];
     tab[fib::kTabIn + 2 * k + 1] = -in_shift[k] * in_scale[k];
-    tab[fib::kTabOut + 4 * k] = out_scale[k];
-    tab[fib::kTabOut + 4 * k + 1] = out_shift[k];
-    tab[fib::kTabOut + 4 * k + 2] = 1.0f / res_scale[k];
-    tab[fib::kTabOut + 4 * k + 3] = a0.rest[k];
+    tab[fib::kTabMid + 2 * k] = 0.5f * out_scale[k];
+    tab[fib::kTabMid + 2 * k + 1] = 0.5f * out_shift[k] + a0.rest[k];
+    tab[fib::kTabChk + 4 * k] = out_scale[k];
+    tab[fib::kTabChk + 4 * k + 1] = out_shift[k];
+    tab[fib::kTabChk + 4 * k + 2] = (float)(tol * (double)res_scale[k]);
+    tab[fib::kTabChk + 4 * k + 3] = a0.rest[k];
   }
   const size_t lds = fib::surrogate_lds_bytes(c->p.model, sn);
   if (lds > c->max_lds) return fail(FIB_EUNSUPPORTED, "surrogate needs %zu bytes of LDS", lds);

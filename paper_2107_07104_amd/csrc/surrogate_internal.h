@@ -32,14 +32,19 @@ struct SurrogateNet {
 };
 
 // Per-state tables of the surrogate step (device memory, kSurTabFloats
-// floats): from kTabIn, a float2 per state (in_scale_k, -in_shift_k
-// in_scale_k), so the input is x_k = u_k in_scale_k - in_shift_k in_scale_k;
-// from kTabOut, a float4 per state (out_scale_k, out_shift_k, 1 / res_k,
-// rest_k): the prediction du_k = out_shift_k + out_scale_k o_k, the
-// acceptance scale and the resting state the offsets u are taken from.
+// floats), laid out so one LDS read serves a state in each use:
+//   kTabIn,  float2: (in_scale_k, -in_shift_k in_scale_k), so the input is
+//            x_k = u_k in_scale_k - in_shift_k in_scale_k;
+//   kTabMid, float2: (out_scale_k / 2, out_shift_k / 2 + rest_k), so the
+//            midpoint is y_k = rest_k + u_k + du_k / 2 with
+//            du_k = out_shift_k + out_scale_k o_k;
+//   kTabChk, float4: (out_scale_k, out_shift_k, tol res_k, rest_k): the
+//            prediction, the absolute acceptance threshold and the resting
+//            state the offsets u are taken from.
 constexpr int kTabIn = 0;
-constexpr int kTabOut = 2 * kSurMaxStates;
-constexpr int kSurTabFloats = 6 * kSurMaxStates;
+constexpr int kTabMid = 2 * kSurMaxStates;
+constexpr int kTabChk = 4 * kSurMaxStates;
+constexpr int kSurTabFloats = 8 * kSurMaxStates;
 
 // Scalars of the step: network inputs (n_states, or n_states + 1 with the
 // stimulus flag I * flag_scale) and the acceptance tolerance.

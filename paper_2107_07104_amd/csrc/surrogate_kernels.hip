@@ -328,7 +328,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
   int* count = counts ? counts + slot : nullptr;
   if (counts && blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
   const float2* tin = reinterpret_cast<const float2*>(tab + kTabIn);    // scale, bias
-  const float4* tout = reinterpret_cast<const float4*>(tab + kTabOut);  // scale, shift, 1/res, rest
+  const float2* tmid = reinterpret_cast<const float2*>(tab + kTabMid);  // scale/2, shift/2 + rest
+  const float4* tchk = reinterpret_cast<const float4*>(tab + kTabChk);  // scale, shift, thr, rest
 
   const int64_t nt = A.n_total;
   const int64_t tiles = (nt + 63) / 64;
@@ -389,7 +390,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         Column col{pred + i, nt};
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-          const float4 t = tout[k];
+          const float4 t = tchk[k];
           const_cast<float*>(col.p)[0] = fmaf(out(k), t.x, t.y);
           col.next();
         }
@@ -405,17 +406,17 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
       float y[S], G[S];
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float4 t = tout[k];
-        y[k] = fmaf(0.5f, fmaf(out(k), t.x, t.y), u[k]) + t.w;  // rest + u + du / 2
+        const float2 t = tmid[k];
+        y[k] = fmaf(out(k), t.x, u[k] + t.y);  // rest + u + du / 2
       }
       M::rhs_abs(y, Ia, A.inv_cm, G);
       // a comparison with NaN is false: a non-finite prediction is rejected
       bool within = true;
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float4 t = tout[k];
+        const float4 t = tchk[k];
         const float du = fmaf(out(k), t.x, t.y);
-        within &= fabsf(fmaf(span, G[k], -du)) * t.z <= sc.tol;
+        within &= fabsf(fmaf(span, G[k], -du)) <= t.z;
       }
       const bool flag_ok = sc.n_in > S || Ia == 0.0f;
       ok = within && flag_ok && Ia == Ib;
@@ -423,7 +424,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
 #pragma unroll
         for (int c = 1; c < NCORR; ++c) {
 #pragma unroll
-          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tout[k].w;
+          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tchk[k].w;
           M::rhs_abs(y, Ia, A.inv_cm, G);
         }
         observe(A, i, step_a, fmaf(0.5f * span, G[0], u[0]));

@@ -82,8 +82,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
-                              "or python -m paper_2107_07104_amd.csrc.build")
+            raise ImportError(f"{LIB_PATH} is not built; run "
+                              "python -m paper_2107_07104_amd.csrc.build")
         L = C.CDLL(LIB_PATH)
         sig = {
             "fib_n_states": ([C.c_int32], C.c_int),
