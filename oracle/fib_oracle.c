@@ -18,7 +18,9 @@
  *     eq. monodomain_bc1;
  *   - operator splitting: eq. monodomain_strang (0D, 1D, 0D order, figure
  *     splitting_schemes), eq. monodomain_godunov;
- *   - time stepping: eq. heun (0D), eq. crank_nicolson with theta = 1/2 (1D);
+ *   - time stepping: eq. heun (0D); the theta-scheme of eq. crank_nicolson
+ *     (1D), theta = 1/2 Crank-Nicolson, theta = 1 implicit Euler
+ *     (eq. implicit_euler, lumped as in eq. lumping_implicit_euler);
  *   - 1D linear finite elements: tables stencils_laplace and
  *     stencils_mass_laplace, mass lumping (section "Using Mass Lumping for
  *     Implicit Timestepping", eq. lumping_crank_nicolson);
@@ -26,7 +28,8 @@
  *   - Thomas algorithm: section "Improved Parallel Solver Scheme using the
  *     Thomas Algorithm";
  *   - stimulation of the nodes around a neuromuscular junction: section
- *     "Specification of Stimulation Times Using Callback Functions".
+ *     "Specification of Stimulation Times Using Callback Functions", either
+ *     as an injected current or as a prescribed membrane voltage.
  */
 #include <math.h>
 #include <stdint.h>
@@ -52,17 +55,19 @@ typedef struct {
   double dt_1D;    /* largest diffusion substep, ms */
   double dt_split; /* splitting step, ms */
   double v_th;     /* activation threshold for the activation-time observable, mV */
+  double theta;    /* 1D time stepping (eq. crank_nicolson): 0.5 Crank-Nicolson,
+                      1 implicit Euler (eq. implicit_euler); values in [0.5, 1] */
 } or_params;
 
 typedef struct {
   int32_t fiber;      /* fiber index */
   int32_t node;       /* centre node j (0-based, within the fiber) */
   int32_t half_width; /* nodes j-hw .. j+hw are stimulated (clipped to the fiber) */
-  int32_t pad_;
-  int64_t step_on;    /* first split step with current on */
-  int64_t n_steps;    /* number of consecutive split steps with current on */
+  int32_t mode;       /* 0: current density `amp`; 1: V_m prescribed to `amp` */
+  int64_t step_on;    /* first split step with the stimulus on */
+  int64_t n_steps;    /* number of consecutive split steps with the stimulus on */
   int64_t period;     /* 0: one pulse; >0: the pulse repeats every `period` steps */
-  double amp;         /* current density, uA/cm^2 */
+  double amp;         /* current density in uA/cm^2 (mode 0) or voltage in mV (mode 1) */
 } or_stim;
 
 /* ------------------------------------------------------------------------ */
@@ -253,25 +258,29 @@ static void lumped_row(int64_t i, int64_t n, double* wl, double* wr) {
   *wl = 1.0; *wr = 1.0;
 }
 
-/* One Crank-Nicolson step of width dt on one fiber,
- *   (I - dt/2 c M_L^{-1} K) V+ = (I + dt/2 c M_L^{-1} K) V,
- * with c = sigma / (Am Cm) (eq. monodomain, eq. lumping_crank_nicolson).
- * The left-hand matrix is assembled row by row and solved by Thomas. */
+/* One theta-scheme step of width dt on one fiber (eq. crank_nicolson with
+ * the lumped mass of eq. lumping_crank_nicolson; theta = 1/2 is
+ * Crank-Nicolson, theta = 1 the implicit Euler of eq.
+ * lumping_implicit_euler):
+ *   (I - theta dt L) V+ = (I + (1 - theta) dt L) V,  L = c M_L^{-1} K,
+ * with c = sigma / (Am Cm) (eq. monodomain).  The left-hand matrix is
+ * assembled row by row and solved by Thomas. */
 static void cn_step(const or_params* p, int64_t n, double* V, double dt,
                     double* a, double* d, double* c, double* b, double* x, double* work) {
   double coef = p->sigma / (p->Am * p->Cm);
-  double half = 0.5 * dt * coef / (p->h * p->h);
+  double lam = dt * coef / (p->h * p->h);
+  double impl = p->theta * lam, expl = (1.0 - p->theta) * lam;
   for (int64_t i = 0; i < n; ++i) {
     double wl, wr;
     lumped_row(i, n, &wl, &wr);
     double left = (i > 0) ? V[i - 1] : 0.0;
     double right = (i < n - 1) ? V[i + 1] : 0.0;
-    /* right-hand side (I + dt/2 L) V */
-    b[i] = V[i] + half * (wl * left - (wl + wr) * V[i] + wr * right);
-    /* left-hand matrix (I - dt/2 L) */
-    a[i] = -half * wl;
-    d[i] = 1.0 + half * (wl + wr);
-    c[i] = -half * wr;
+    /* right-hand side (I + (1 - theta) dt L) V */
+    b[i] = V[i] + expl * (wl * left - (wl + wr) * V[i] + wr * right);
+    /* left-hand matrix (I - theta dt L) */
+    a[i] = -impl * wl;
+    d[i] = 1.0 + impl * (wl + wr);
+    c[i] = -impl * wr;
   }
   or_thomas(n, a, d, c, b, x, work);
   for (int64_t i = 0; i < n; ++i) V[i] = x[i];
@@ -302,15 +311,31 @@ static int stim_on(const or_stim* s, int64_t step) {
   return k < s->n_steps;
 }
 
-/* Stimulus current of every node of fiber f (local node index) at `step`. */
+/* Stimulus current of every node of fiber f (local node index) at `step`
+ * from the current-density entries (mode 0). */
 static void fiber_current(int32_t f, int64_t n, const or_stim* stim, int32_t n_stim,
                           int64_t step, double* I) {
   for (int64_t i = 0; i < n; ++i) I[i] = 0.0;
   for (int32_t e = 0; e < n_stim; ++e) {
     const or_stim* s = &stim[e];
-    if (s->fiber != f || !stim_on(s, step)) continue;
+    if (s->fiber != f || s->mode != 0 || !stim_on(s, step)) continue;
     for (int64_t j = (int64_t)s->node - s->half_width; j <= (int64_t)s->node + s->half_width; ++j)
       if (j >= 0 && j < n) I[j] += s->amp;
+  }
+}
+
+/* Prescribed-voltage entries (mode 1) on during `step`: the membrane
+ * voltage of their nodes is set to `amp` at the start of the split step
+ * (section "Specification of Stimulation Times Using Callback Functions":
+ * the callback alters the state vector between steps).  V is the fiber's
+ * voltage row. */
+static void fiber_prescribe(int32_t f, int64_t n, const or_stim* stim, int32_t n_stim,
+                            int64_t step, double* V) {
+  for (int32_t e = 0; e < n_stim; ++e) {
+    const or_stim* s = &stim[e];
+    if (s->fiber != f || s->mode != 1 || !stim_on(s, step)) continue;
+    for (int64_t j = (int64_t)s->node - s->half_width; j <= (int64_t)s->node + s->half_width; ++j)
+      if (j >= 0 && j < n) V[j] = s->amp;
   }
 }
 
@@ -332,7 +357,7 @@ int or_reaction(const or_params* p, int64_t n_total, double* y, const double* I,
  * fibers (fiber f occupies n_nodes[f] consecutive entries of V). */
 int or_diffusion(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double* V,
                  double span) {
-  if (n_fibers < 0 || !(span > 0.0)) return OR_EINVAL;
+  if (n_fibers < 0 || !(span > 0.0) || !(p->theta >= 0.5 && p->theta <= 1.0)) return OR_EINVAL;
   int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_fibers + 1));
   if (!off) return OR_ENOMEM;
   off[0] = 0;
@@ -387,7 +412,9 @@ int or_run(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double*
            const or_stim* stim, int32_t n_stim, int64_t step0, int64_t n_steps,
            int64_t sample_every, double* samples, double* t_act) {
   int S = or_n_states(p->model);
-  if (S <= 0 || n_fibers < 0 || n_steps < 0 || step0 < 0 || !(p->dt_split > 0.0)) return OR_EINVAL;
+  if (S <= 0 || n_fibers < 0 || n_steps < 0 || step0 < 0 || !(p->dt_split > 0.0) ||
+      !(p->theta >= 0.5 && p->theta <= 1.0))
+    return OR_EINVAL;
   int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_fibers + 1));
   if (!off) return OR_ENOMEM;
   off[0] = 0;
@@ -412,7 +439,10 @@ int or_run(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double*
       memcpy(yf + (size_t)k * n, y + (int64_t)k * n_total + o, sizeof(double) * n);
 
     for (int64_t step = step0; step < step0 + n_steps; ++step) {
+      /* V at the end of the previous step: the activation test spans the
+       * whole step, including a prescription at its start */
       memcpy(vprev, yf, sizeof(double) * n);
+      fiber_prescribe(f, n, stim, n_stim, step, yf);
       fiber_current(f, n, stim, n_stim, step, I);
       if (p->scheme == 0) {
         reaction_range(p, S, yf, n, 0, n, I, 0.5 * dt);

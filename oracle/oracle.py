@@ -42,12 +42,12 @@ class Params(C.Structure):
     _fields_ = [("model", C.c_int32), ("scheme", C.c_int32),
                 ("Cm", C.c_double), ("Am", C.c_double), ("sigma", C.c_double),
                 ("h", C.c_double), ("dt_0D", C.c_double), ("dt_1D", C.c_double),
-                ("dt_split", C.c_double), ("v_th", C.c_double)]
+                ("dt_split", C.c_double), ("v_th", C.c_double), ("theta", C.c_double)]
 
 
 class Stim(C.Structure):
     _fields_ = [("fiber", C.c_int32), ("node", C.c_int32), ("half_width", C.c_int32),
-                ("pad_", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
+                ("mode", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
                 ("period", C.c_int64), ("amp", C.c_double)]
 
 
@@ -106,10 +106,11 @@ class Config:
     dt_1D: float = 1e-3
     dt_split: float = 1e-3
     v_th: float = -20.0
+    theta: float = 0.5          # 1D time stepping: 0.5 Crank-Nicolson, 1 implicit Euler
 
     def c_params(self) -> Params:
         return Params(self.model, self.scheme, self.Cm, self.Am, self.sigma, self.h,
-                      self.dt_0D, self.dt_1D, self.dt_split, self.v_th)
+                      self.dt_0D, self.dt_1D, self.dt_split, self.v_th, self.theta)
 
 
 def n_states(model: int = MODEL_HH) -> int:
@@ -180,7 +181,8 @@ def _stims(stims):
     n = len(stims)
     arr = (Stim * max(n, 1))()
     for i, s in enumerate(stims):
-        arr[i] = Stim(int(s["fiber"]), int(s["node"]), int(s.get("half_width", 1)), 0,
+        arr[i] = Stim(int(s["fiber"]), int(s["node"]), int(s.get("half_width", 1)),
+                      int(s.get("mode", 0)),
                       int(s["step_on"]), int(s["n_steps"]), int(s.get("period", 0)),
                       float(s["amp"]))
     return arr, n

@@ -3,7 +3,8 @@ and of its Thomas solver.
 
 * Thomas against LAPACK's pivoted LU (numpy.linalg.solve) on random
   diagonally dominant systems and on the actual Crank-Nicolson matrices.
-* Closed-form eigenmodes: with the lumped mass matrix and no-flux ends,
+* Closed-form eigenmodes (Crank-Nicolson and implicit Euler): with the
+  lumped mass matrix and no-flux ends,
   v_k(i) = cos(k pi i / (N-1)) is an exact eigenvector of M_L^{-1} K with
   eigenvalue -(4/h^2) sin^2(k pi / (2 (N-1))), so one Crank-Nicolson step
   multiplies it by (1 + dt c lam / 2) / (1 - dt c lam / 2), c = sigma/(Am Cm).
@@ -85,6 +86,26 @@ def test_cn_cosine_eigenmodes(N, dt):
         g = (1 + 0.5 * dt * c * lam) / (1 - 0.5 * dt * c * lam)
         out = O.diffusion(cfg, [N], v, dt)
         assert np.max(np.abs(out - g * v)) < 1e-12
+
+
+@pytest.mark.parametrize("N", [2, 17, 200])
+@pytest.mark.parametrize("dt", [1e-3, 0.05])
+def test_implicit_euler_cosine_eigenmodes(N, dt):
+    """theta = 1 (eq. implicit_euler with the lumped mass): the same cosine
+    eigenvectors are damped by exactly 1 / (1 - dt c lambda_k)."""
+    cfg = O.Config(dt_0D=dt, dt_1D=dt, dt_split=dt, theta=1.0)
+    c = cfg.sigma / (cfg.Am * cfg.Cm)
+    i = np.arange(N)
+    for k in range(N):
+        v = np.cos(k * np.pi * i / (N - 1))
+        lam = -(4.0 / cfg.h ** 2) * np.sin(k * np.pi / (2 * (N - 1))) ** 2
+        out = O.diffusion(cfg, [N], v, dt)
+        assert np.max(np.abs(out - v / (1 - dt * c * lam))) < 1e-12
+
+
+def test_theta_outside_the_stable_range_is_rejected():
+    with pytest.raises(RuntimeError):
+        O.diffusion(O.Config(theta=0.4), [10], np.zeros(10), 1e-3)
 
 
 def test_cn_conserves_lumped_charge_and_max_principle():

@@ -13,6 +13,11 @@
   that travels to both ends (thesis, chapter "Introduction").
 * Chunked runs reproduce a single run bit for bit (the loop has no hidden
   state besides the step index).
+* Prescribed-voltage stimulation (section "Specification of Stimulation
+  Times Using Callback Functions"): entries of that mode carry no current,
+  set V_m of their nodes to the prescribed value at the start of each
+  stimulated step, and start an action potential whose far field matches
+  the one started by a supra-threshold current (same conduction velocity).
 """
 import numpy as np
 import pytest
@@ -106,3 +111,50 @@ def test_chunked_runs_are_bitwise_identical():
     np.testing.assert_array_equal(t1, tb)
     np.testing.assert_array_equal(s1, np.concatenate([sa, sb]))
     np.testing.assert_array_equal(s1[-1], y1[0])
+
+
+def _single(mode, amp, n_nodes=600, t_end=10.0):
+    w = I.single_fiber(amp=amp, n_nodes=n_nodes, t_end=t_end)
+    stims = [dict(st, mode=mode) for st in w.stims]
+    return w, stims
+
+
+def test_prescribed_voltage_entries_carry_no_current():
+    w, stims = _single(1, 40.0)
+    assert not O.stimulus_current(w.n_nodes, stims, 0).any()
+    w, stims = _single(0, 40.0)
+    assert O.stimulus_current(w.n_nodes, stims, 0).sum() == pytest.approx(3 * 40.0)
+
+
+def test_prescribed_voltage_is_set_at_the_start_of_the_step():
+    """With no diffusion and a one-step pulse, the state after the step is
+    the reaction from the prescribed voltage (gates untouched)."""
+    w, stims = _single(1, 40.0, n_nodes=50, t_end=0.001)
+    cfg = O.Config(dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split, v_th=w.v_th, sigma=0.0)
+    stims = [dict(st, n_steps=1) for st in stims]
+    y0 = np.tile(O.rest_state()[:, None], (1, w.n_total))
+    y, _, ta = O.run(cfg, w.n_nodes, y0, stims, 1)
+    nodes = [24, 25, 26]
+    start = y0.copy()
+    start[0, nodes] = 40.0
+    # Strang with sigma = 0: two reaction halves from the prescribed state
+    expect = O.reaction(cfg, O.reaction(cfg, start, 0.5 * w.dt_split), 0.5 * w.dt_split)
+    np.testing.assert_allclose(y, expect, rtol=0, atol=1e-12)
+    # the activation test spans the prescription: the stimulated nodes
+    # crossed -20 mV inside the step, the others did not
+    assert np.all(np.isfinite(ta[nodes])) and np.sum(np.isfinite(ta)) == 3
+
+
+def test_prescribed_voltage_and_current_give_the_same_far_field():
+    n = 600
+    w, cur = _single(0, I.AMP_SUPRA, n_nodes=n)
+    _, pre = _single(1, 40.0, n_nodes=n)
+    cfg = _cfg(w)
+    ta = {}
+    for key, st in (("current", cur), ("voltage", pre)):
+        _, _, ta[key] = O.run(cfg, w.n_nodes, _init(w), st, w.n_steps)
+    a, b = n // 2 + 50, n // 2 + 150        # the front reaches node 500 at ~7 ms
+    v_cur = (b - a) * w.h / (ta["current"][b] - ta["current"][a])
+    v_pre = (b - a) * w.h / (ta["voltage"][b] - ta["voltage"][a])
+    assert np.isfinite(v_cur) and np.isfinite(v_pre)
+    assert abs(v_pre - v_cur) < 0.01 * v_cur
