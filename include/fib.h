@@ -72,6 +72,23 @@ enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1 };
  *   AUTO:  FUSED where the model fits it (Hodgkin-Huxley), else SPLIT. */
 enum { FIB_SCHED_AUTO = 0, FIB_SCHED_FUSED = 1, FIB_SCHED_SPLIT = 2 };
 
+/* Operator splitting of a split step of width dt = dt_split.
+ *   STRANG:  R(dt/2) D(dt) R(dt/2) (eq. monodomain_strang, second order);
+ *   GODUNOV: R(dt) D(dt)           (eq. monodomain_godunov, first order).
+ * R takes ceil(span/dt_0D) equal Heun substeps over its span. */
+enum { FIB_SPLIT_STRANG = 0, FIB_SPLIT_GODUNOV = 1 };
+
+/* Time stepping of the diffusion substeps (lumped mass matrix): the
+ * theta-scheme (I - theta dt L) V+ = (I + (1 - theta) dt L) V with
+ *   CRANK_NICOLSON: theta = 1/2 (eq. lumping_crank_nicolson, second order);
+ *   IMPLICIT_EULER: theta = 1   (eq. lumping_implicit_euler, first order,
+ *                   strongly damping). */
+enum { FIB_1D_CRANK_NICOLSON = 0, FIB_1D_IMPLICIT_EULER = 1 };
+
+/* Kind of a stimulus entry (section "Specification of Stimulation Times
+ * Using Callback Functions"). */
+enum { FIB_STIM_CURRENT = 0, FIB_STIM_VOLTAGE = 1 };
+
 typedef struct {
   int32_t model;      /* FIB_MODEL_* */
   int32_t schedule;   /* FIB_SCHED_* */
@@ -90,18 +107,27 @@ typedef struct {
   int32_t nodes_per_thread;  /* 0: automatic (2..8); else 2..14 */
   int32_t groups;            /* 0: automatic (one per compute unit); else the number of
                                 fiber bins, i.e. workgroups of the fused kernel */
+  int32_t splitting;         /* FIB_SPLIT_* (0: Strang) */
+  int32_t time_1d;           /* FIB_1D_* (0: Crank-Nicolson) */
 } fib_params;
 
-/* One stimulus entry: current density `amp` on nodes node-half_width ..
- * node+half_width of fiber `fiber` (clipped to the fiber), during split
- * steps n with n >= step_on and (n - step_on) mod period < n_steps
- * (period = 0: only step_on <= n < step_on + n_steps).  A node may be
- * covered by at most one entry.  Step indices must be below 2^31. */
+/* One stimulus entry on nodes node-half_width .. node+half_width of fiber
+ * `fiber` (clipped to the fiber), on during split steps n with
+ * n >= step_on and (n - step_on) mod period < n_steps (period = 0: only
+ * step_on <= n < step_on + n_steps).
+ *   FIB_STIM_CURRENT: current density `amp` (uA/cm^2) in every reaction
+ *     substep of a step it is on in;
+ *   FIB_STIM_VOLTAGE: V_m of the covered nodes is set to `amp` (mV) at the
+ *     start of every split step it is on in, before the step's first
+ *     reaction part; the activation-time test spans the whole step, from
+ *     the voltage before the prescription.  Applied by fib_run only.
+ * A node may be covered by at most one entry.  Step indices must be below
+ * 2^31. */
 typedef struct {
   int32_t fiber;
   int32_t node;
   int32_t half_width;
-  int32_t pad_;
+  int32_t mode;      /* FIB_STIM_* */
   int64_t step_on;
   int64_t n_steps;
   int64_t period;
@@ -176,11 +202,12 @@ int fib_state_device(fib_t* ctx, float** state, double* ref);
 int fib_set_stimulus(fib_t* ctx, const fib_stim* stim, int32_t n);
 
 /* Reaction part only: ceil(span/dt_0D) equal Heun substeps on every node,
- * with the stimulus current of split step `step`.  One kernel launch. */
+ * with the stimulus current of split step `step` (voltage entries are not
+ * applied).  One kernel launch. */
 int fib_step_reaction(fib_t* ctx, int64_t step, double span);
 
-/* Diffusion part only: ceil(span/dt_1D) equal Crank-Nicolson substeps on
- * every fiber.  One kernel launch. */
+/* Diffusion part only: ceil(span/dt_1D) equal substeps of the time_1d
+ * scheme on every fiber.  One kernel launch. */
 int fib_step_diffusion(fib_t* ctx, double span);
 
 /* Split steps step0 .. step0 + n_steps - 1 (step n covers the time
@@ -292,9 +319,11 @@ int fib_mlp_reset_optimizer(fib_mlp_t* net);
  *   implicit midpoint rule started from the prediction: two for
  *   Hodgkin-Huxley, one for ST57, whose right-hand side dominates the cost).
  * A node takes the last iterate du_c only if |du1 - du|_k <= tol * res_scale[k] for every
- * state k (absolute tolerances), its stimulus is the same in both halves,
+ * state k (absolute tolerances), its stimulus current is the same in both
+ * halves, no voltage entry prescribes its V_m at the start of step n+1,
  * and (for networks without the flag input) it is not stimulated; all
- * other nodes take the plain Heun substeps.  Steps that write V_m samples,
+ * other nodes take the plain Heun substeps.  Strang splitting only
+ * (FIB_EUNSUPPORTED with Godunov).  Steps that write V_m samples,
  * and the last step of a call, run the plain path for every node.  For
  * kept nodes the activation-time test uses the midpoint y + du_c/2 as the
  * state at the end of step n.  The surrogate is an addition of this

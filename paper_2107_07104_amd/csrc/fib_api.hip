@@ -422,6 +422,17 @@ double cn_r(const fib_ctx* c, double dt_cn) {
   return c->p.sigma / (c->p.Am * c->p.Cm) * dt_cn / (c->p.h * c->p.h);
 }
 
+// theta of the diffusion substeps' theta-scheme
+double theta_of(const fib_params& p) { return p.time_1d == FIB_1D_IMPLICIT_EULER ? 1.0 : 0.5; }
+
+// Diffusion coefficients of a launch with substep dt_cn: r for the
+// right-hand side dt L V, r_mat = 2 theta r for the matrix I - theta dt L.
+void set_diffusion(const fib_ctx* c, double dt_cn, KArgs& a) {
+  const double r = cn_r(c, dt_cn);
+  a.r = (float)r;
+  a.r_mat = (float)(2.0 * theta_of(c->p) * r);
+}
+
 // Fills the slot tables and the PCR level count of the current shape
 // (groups, threads, K) and bins.
 void build_tables(fib_ctx* c) {
@@ -443,9 +454,9 @@ void build_tables(fib_ctx* c) {
       }
     }
   }
-  // PCR levels for the split step's diffusion substep
+  // PCR levels for the matrix of the split step's diffusion substep
   const int64_t n_cn = ceil_steps(c->p.dt_split, c->p.dt_1D);
-  const double r = cn_r(c, c->p.dt_split / (double)n_cn);
+  const double r = 2.0 * theta_of(c->p) * cn_r(c, c->p.dt_split / (double)n_cn);
   int lv = 0;
   for (int b = 0; b < c->groups; ++b)
     lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
@@ -604,7 +615,11 @@ int fib_check_params(const fib_params* p) {
     return fail(FIB_EINVAL, "%d nodes per thread allow at most %d threads per group",
                 p->nodes_per_thread, fib::plan_max_threads(p->nodes_per_thread));
   if (p->groups < 0) return fail(FIB_EINVAL, "groups must be >= 0");
-  if (ceil_steps(p->dt_split * 0.5, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
+  if (p->splitting != FIB_SPLIT_STRANG && p->splitting != FIB_SPLIT_GODUNOV)
+    return fail(FIB_EINVAL, "unknown splitting %d", p->splitting);
+  if (p->time_1d != FIB_1D_CRANK_NICOLSON && p->time_1d != FIB_1D_IMPLICIT_EULER)
+    return fail(FIB_EINVAL, "unknown 1D time stepping %d", p->time_1d);
+  if (ceil_steps(p->dt_split, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
     return fail(FIB_EINVAL, "more than 2^20 substeps per split step");
   return FIB_OK;
 }
@@ -806,7 +821,13 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
         x.period > lim)
       return fail(FIB_EINVAL, "entry %d: step indices must lie in [0, 2^31)", e);
     if (!std::isfinite(x.amp)) return fail(FIB_EINVAL, "entry %d: non-finite amplitude", e);
-    tab[e] = fib::StimDev{(int32_t)x.step_on, (int32_t)x.n_steps, (int32_t)x.period, (float)x.amp};
+    if (x.mode != FIB_STIM_CURRENT && x.mode != FIB_STIM_VOLTAGE)
+      return fail(FIB_EINVAL, "entry %d: unknown mode %d", e, x.mode);
+    // voltage entries hold the prescribed value as the device state does:
+    // the offset from the resting V_m
+    const bool volt = x.mode == FIB_STIM_VOLTAGE;
+    tab[e] = fib::StimDev{(int32_t)x.step_on, (int32_t)x.n_steps, (int32_t)x.period,
+                          (float)(volt ? x.amp - (double)(float)c->rest[0] : x.amp), volt ? 1 : 0};
     const int64_t n_f = c->n_nodes[x.fiber];
     for (int64_t j = (int64_t)x.node - x.half_width; j <= (int64_t)x.node + x.half_width; ++j) {
       if (j < 0 || j >= n_f) continue;
@@ -862,11 +883,11 @@ int fib_step_diffusion(fib_t* c, double span) {
   const int64_t m = ceil_steps(span, c->p.dt_1D);
   if (m > (1 << 20)) return fail(FIB_EINVAL, "more than 2^20 substeps");
   a.n_cn = (int32_t)m;
-  const double r = cn_r(c, span / (double)m);
-  a.r = (float)r;
+  set_diffusion(c, span / (double)m, a);
+  const double r_mat = 2.0 * theta_of(c->p) * cn_r(c, span / (double)m);
   int lv = 0;
   for (int b = 0; b < c->groups; ++b)
-    lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
+    lv = std::max(lv, pcr_levels_needed(c, b, r_mat, c->p.pcr_full != 0));
   if (int rc = check_levels_fit(c, lv)) return rc;
   a.pcr_levels = lv;
   HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, fib::lds_bytes_for(c->threads, lv),
@@ -893,12 +914,17 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     a.sample_row0 = step0 / sample_every;
     a.sample_rows = sample_rows;
   }
-  const int64_t ns = ceil_steps(0.5 * c->p.dt_split, c->p.dt_0D);
+  // reaction span before the diffusion: half a split step (Strang) or the
+  // whole step (Godunov)
+  const bool godunov = c->p.splitting == FIB_SPLIT_GODUNOV;
+  const double span = godunov ? c->p.dt_split : 0.5 * c->p.dt_split;
+  const int64_t ns = ceil_steps(span, c->p.dt_0D);
   const int64_t nc = ceil_steps(c->p.dt_split, c->p.dt_1D);
   a.n_sub = (int32_t)ns;
-  a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
+  a.n_sub2 = godunov ? 0 : (int32_t)ns;
+  a.tau = (float)(span / (double)ns);
   a.n_cn = (int32_t)nc;
-  a.r = (float)cn_r(c, c->p.dt_split / (double)nc);
+  set_diffusion(c, c->p.dt_split / (double)nc, a);
   a.pcr_levels = c->levels;
   a.step0 = (int32_t)step0;
   a.n_steps = (int32_t)n_steps;
@@ -913,12 +939,25 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
                                   fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
     return FIB_OK;
   }
-  // SPLIT: per split step one diffusion launch and one reaction launch that
-  // finishes step n (second half, observables) and starts step n+1 (first half)
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
                          hipMemcpyDeviceToDevice, c->stream));
   const size_t lds = fib::lds_bytes_for(c->threads, c->levels);
   const int64_t end = step0 + n_steps;
+  if (godunov) {
+    // SPLIT, Godunov: per split step one reaction launch (observables of
+    // step n-1, then step n's prescriptions and its whole reaction) and one
+    // diffusion launch; the observables of the last step follow the loop
+    for (int64_t n = step0; n < end; ++n) {
+      const int flags = (n > step0 ? 2 : 0) | 4;
+      HIP_TRY(fib::launch_react(c->p.model, (int32_t)(n - 1), (int32_t)n, flags, a, c->stream));
+      HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+    }
+    HIP_TRY(fib::launch_react(c->p.model, (int32_t)(end - 1), 0, 2, a, c->stream));
+    return FIB_OK;
+  }
+  // SPLIT, Strang: per split step one diffusion launch and one reaction
+  // launch that finishes step n (second half, observables) and starts step
+  // n+1 (prescriptions, first half)
   HIP_TRY(fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
   for (int64_t n = step0; n < end; ++n) {
     HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
@@ -1051,6 +1090,8 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   if (!net || !in_shift || !in_scale || !out_shift || !out_scale || !res_scale)
     return fail(FIB_EINVAL, "null argument");
   if (!(tol > 0.0) || !std::isfinite(flag_scale)) return fail(FIB_EINVAL, "bad tolerance or flag scale");
+  if (c->p.splitting != FIB_SPLIT_STRANG)
+    return fail(FIB_EUNSUPPORTED, "the surrogate step replaces Strang reaction halves");
   const fib::MlpShape& ms = fib::mlp_shape(net);
   const int S = c->S;
   // supported shapes: the kernels are compiled for them

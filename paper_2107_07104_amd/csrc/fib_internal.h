@@ -10,10 +10,11 @@ namespace fib {
 
 // Stimulus entry as the kernels see it: step indices as int32.
 struct StimDev {
-  int32_t on;      // first split step with current
-  int32_t dur;     // consecutive split steps with current
+  int32_t on;      // first split step the entry is on in
+  int32_t dur;     // consecutive split steps it stays on
   int32_t period;  // 0: single pulse
-  float amp;       // uA/cm^2
+  float amp;       // current entries: uA/cm^2; voltage entries: V_m - rest_V (mV)
+  int32_t voltage; // 0: current entry, 1: prescribed V_m
 };
 
 // Per-slot descriptor of the fused / diffusion kernels.
@@ -46,27 +47,54 @@ struct KArgs {
   int32_t cap;              // slots per group = threads * nodes_per_thread
   int32_t step0;
   int32_t n_steps;
-  int32_t n_sub;            // reaction substeps per half split step
-  int32_t n_cn;             // Crank-Nicolson substeps per split step
+  int32_t n_sub;            // reaction substeps before the diffusion (Strang: half a
+                            // split step; Godunov: the whole step) and per k_react phase
+  int32_t n_sub2;           // fused kernel: reaction substeps after the diffusion
+                            // (Strang: n_sub; Godunov: 0)
+  int32_t n_cn;             // diffusion substeps per split step
   int32_t pcr_levels;       // reduced-system PCR levels
   float dt;                 // split step (ms)
   float tau;                // reaction substep (ms)
-  float r;                  // c * dt_cn / h^2 with c = sigma / (Am Cm)
+  float r;                  // c * dt_cn / h^2 with c = sigma / (Am Cm): explicit part
+  float r_mat;              // 2 theta r: the implicit matrix I - theta dt_cn L
   float inv_cm;             // 1 / Cm
   float v_th;               // activation threshold (mV)
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
-// Current of stimulus entry `sid1 - 1` (0: none) during split step n: a
-// pulse of `dur` steps from `on`, repeated every `period` steps if > 0.
+// Whether entry e is on during split step n: a pulse of `dur` steps from
+// `on`, repeated every `period` steps if > 0.
+__device__ __forceinline__ bool stim_on(const StimDev& e, int32_t n) {
+  int32_t k = n - e.on;
+  if (k < 0) return false;
+  if (e.period > 0) k = k % e.period;
+  return k < e.dur;
+}
+
+// Current of stimulus entry `sid1 - 1` (0: none) during split step n
+// (0 for voltage entries).
 __device__ __forceinline__ float stim_current(uint32_t sid1, const StimDev* __restrict__ tab,
                                               int32_t n) {
   if (sid1 == 0) return 0.0f;
   const StimDev e = tab[sid1 - 1];
-  int32_t k = n - e.on;
-  if (k < 0) return 0.0f;
-  if (e.period > 0) k = k % e.period;
-  return k < e.dur ? e.amp : 0.0f;
+  return (!e.voltage && stim_on(e, n)) ? e.amp : 0.0f;
+}
+
+// Current of entry `sid1 - 1` during split step n, and the prescription of
+// a voltage entry: returns true with v_off = V_m - rest_V if the node's V_m
+// is set at the start of step n.
+__device__ __forceinline__ bool stim_eval(uint32_t sid1, const StimDev* __restrict__ tab,
+                                          int32_t n, float& I, float& v_off) {
+  I = 0.0f;
+  if (sid1 == 0) return false;
+  const StimDev e = tab[sid1 - 1];
+  if (!stim_on(e, n)) return false;
+  if (!e.voltage) {
+    I = e.amp;
+    return false;
+  }
+  v_off = e.amp;
+  return true;
 }
 
 // Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.
@@ -78,8 +106,9 @@ hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t ld
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, const KArgs& a,
                             hipStream_t s);
 // Reaction kernel with states in device memory; flags: 1 = reaction with the
-// stimulus of step_a, 2 = observables after step_a, 4 = reaction with the
-// stimulus of step_b (applied in that order).
+// stimulus current of step_a, 2 = observables after step_a, 4 = the start of
+// step_b: its V_m prescriptions, then reaction with its current (applied in
+// that order).
 hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,
                         hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,

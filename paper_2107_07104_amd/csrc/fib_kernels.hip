@@ -161,8 +161,9 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
   const float* s_al = lds + 6 * T;
   const float* s_ga = s_al + levels * T;
 
-  // Increment form: with A = I - dt/2 L the step V+ = A^{-1} (I + dt/2 L) V
-  // equals V + d where A d = dt L V.  The right-hand side is built from
+  // Increment form: with A = I - theta dt L the step
+  // V+ = A^{-1} (I + (1 - theta) dt L) V equals V + d where A d = dt L V
+  // (cc holds the factors of A; `r` gives dt L).  The right-hand side is built from
   // neighbour differences, so a constant field gives d = 0 exactly and the
   // rounding error of the solve scales with the increment, not with |V|.
   s_vf[t] = V[0];
@@ -219,8 +220,8 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
 // ---------------------------------------------------------------------------
 
 // One workgroup per bin runs split steps step0 .. step0+n_steps-1 with every
-// node's four states in registers: R(dt/2) D(dt) R(dt/2), then the
-// observables.  Device memory is read at the start, written at the end and
+// node's four states in registers: V_m prescriptions of the step, R(dt/2)
+// D(dt) R(dt/2) (Godunov: R(dt) D(dt), n_sub2 = 0), then the observables.  Device memory is read at the start, written at the end and
 // for samples / activation times only.
 template <int K, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
     }
   }
   CNConst<K> cc;
-  cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
+  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);
   const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
 
   const uint32_t all = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
@@ -258,8 +259,9 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
     float I[K], v0[K];
 #pragma unroll
     for (int q = 0; q < K; ++q) {
-      I[q] = stim_current(info[q] >> SLOT_STIM_SHIFT, A.stim, n);
       v0[q] = y[q].V;
+      float vp;
+      if (stim_eval(info[q] >> SLOT_STIM_SHIFT, A.stim, n, I[q], vp)) y[q].V = vp;
     }
     for (int s = 0; s < A.n_sub; ++s) {
 #pragma unroll
@@ -273,7 +275,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
 #pragma unroll
       for (int q = 0; q < K; ++q) y[q].V = V[q];
     }
-    for (int s = 0; s < A.n_sub; ++s) {
+    for (int s = 0; s < A.n_sub2; ++s) {
 #pragma unroll
       for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, ref);
     }
@@ -336,7 +338,7 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
     V[q] = gi[q] >= 0 ? A.state[gi[q]] : 0.0f;
   }
   CNConst<K> cc;
-  cn_setup<K>(cc, info, A.r, lds, T, t, A.pcr_levels);
+  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);
   for (int c = 0; c < A.n_cn; ++c) cn_solve<K>(V, info, A.r, cc, lds, T, t, A.pcr_levels);
 #pragma unroll
   for (int q = 0; q < K; ++q)
@@ -370,9 +372,12 @@ struct ModelST57 {
 // flags bit 0: reaction with the stimulus of split step `step_a`;
 // bit 1: then the observables at the end of split step `step_a`
 //        (activation time from v_prev, samples, v_prev := V);
-// bit 2: then reaction with the stimulus of split step `step_b`.
-// The split schedule runs the second half of step n and the first half of
-// step n+1 in one launch, so the states cross HBM once per split step.
+// bit 2: then the start of split step `step_b`: its V_m prescriptions and
+//        reaction with its stimulus current.
+// The Strang split schedule runs the second half of step n and the first
+// half of step n+1 in one launch, so the states cross HBM once per split
+// step; the Godunov schedule runs the observables of step n-1 and the
+// reaction of step n.
 constexpr int REACT_A = 1, REACT_OBSERVE = 2, REACT_B = 4;
 
 template <class M>
@@ -403,7 +408,8 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
     if (!isfinite(v1)) atomicOr(A.flag, 1);
   }
   if (flags & REACT_B) {
-    const float I = stim_current(sid, A.stim, step_b);
+    float I, vp;
+    if (stim_eval(sid, A.stim, step_b, I, vp)) u[0] = vp;
     for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
   }
 #pragma unroll

@@ -13,7 +13,8 @@
 // iterations (its right-hand side is cheap), ST57 one (its right-hand side
 // is most of the step's arithmetic).  A node keeps the last iterate only if
 // |du1 - du|_k <= tol * atol_k for every state k; every other node -- and
-// every node whose stimulus changes between the two halves -- is appended
+// every node whose stimulus current changes between the two halves or whose
+// V_m is prescribed at the start of step n+1 -- is appended
 // to a compacted list that the fallback kernel advances with the plain
 // Heun substeps.  The state at the end of step n, which the pair never
 // forms, is taken as the midpoint y + du_c/2 of the last iterate du_c for
@@ -342,10 +343,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     // lanes past the end read the last node (their results are dropped)
     const int64_t ic = real ? i : nt - 1;
     float Ia = 0.0f, Ib = 0.0f;
+    bool pres_b = false;  // V_m prescribed at the start of step_b: plain path
     {
       const uint32_t sid = (uint32_t)A.node_stim[ic];
+      float vp;
       Ia = stim_current(sid, A.stim, step_a);
-      Ib = stim_current(sid, A.stim, step_b);
+      pres_b = stim_eval(sid, A.stim, step_b, Ib, vp);
     }
     // this lane's node: offsets in registers for the whole tile
     float u[S];
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         within &= fabsf(fmaf(span, G[k], -du)) <= t.z;
       }
       const bool flag_ok = sc.n_in > S || Ia == 0.0f;
-      ok = within && flag_ok && Ia == Ib;
+      ok = within && flag_ok && Ia == Ib && !pres_b;
       if (ok) {
 #pragma unroll
         for (int c = 1; c < NCORR; ++c) {
@@ -453,8 +456,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
   }
 }
 
-// Plain reaction pair (second half of step_a, observables, first half of
-// step_a + 1) for the nodes in list[0..count).  Grid-stride loop, so the
+// Plain reaction pair (second half of step_a, observables, then the start of
+// step_a + 1: its V_m prescription and first half) for the nodes in
+// list[0..count).  Grid-stride loop, so the
 // grid does not depend on the count.
 template <class M>
 __global__ __launch_bounds__(256) void k_fallback(KArgs A, const int* __restrict__ list,
@@ -471,7 +475,8 @@ __global__ __launch_bounds__(256) void k_fallback(KArgs A, const int* __restrict
     const float Ia = stim_current(sid, A.stim, step_a);
     for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, Ia, A.tau, A.inv_cm);
     observe(A, i, step_a, u[0]);
-    const float Ib = stim_current(sid, A.stim, step_a + 1);
+    float Ib, vp;
+    if (stim_eval(sid, A.stim, step_a + 1, Ib, vp)) u[0] = vp;
     for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, Ib, A.tau, A.inv_cm);
 #pragma unroll
     for (int k = 0; k < S; ++k) A.state[k * nt + i] = u[k];

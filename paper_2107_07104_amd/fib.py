@@ -34,6 +34,12 @@ ACTS = {"silu": FIB_ACT_SILU, "relu": FIB_ACT_RELU}
 FIB_SCHED_AUTO = 0
 FIB_SCHED_FUSED = 1
 FIB_SCHED_SPLIT = 2
+FIB_SPLIT_STRANG = 0
+FIB_SPLIT_GODUNOV = 1
+FIB_1D_CRANK_NICOLSON = 0
+FIB_1D_IMPLICIT_EULER = 1
+FIB_STIM_CURRENT = 0
+FIB_STIM_VOLTAGE = 1
 
 # Every function the header declares, for the export check.
 EXPORTS = (
@@ -55,12 +61,12 @@ class fib_params(C.Structure):
                 ("dt_0D", C.c_double), ("dt_1D", C.c_double), ("dt_split", C.c_double),
                 ("v_th", C.c_double), ("pcr_full", C.c_int32),
                 ("threads_per_group", C.c_int32), ("nodes_per_thread", C.c_int32),
-                ("groups", C.c_int32)]
+                ("groups", C.c_int32), ("splitting", C.c_int32), ("time_1d", C.c_int32)]
 
 
 class fib_stim(C.Structure):
     _fields_ = [("fiber", C.c_int32), ("node", C.c_int32), ("half_width", C.c_int32),
-                ("pad_", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
+                ("mode", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
                 ("period", C.c_int64), ("amp", C.c_double)]
 
 
@@ -142,15 +148,18 @@ def _check(rc):
 
 def make_params(model=FIB_MODEL_HH, schedule=FIB_SCHED_AUTO, Cm=1.0, Am=500.0, sigma=3.828,
                 h=0.01, dt_0D=1e-3, dt_1D=1e-3, dt_split=1e-3, v_th=-20.0, pcr_full=0,
-                threads_per_group=0, nodes_per_thread=0, groups=0) -> fib_params:
+                threads_per_group=0, nodes_per_thread=0, groups=0, splitting=0,
+                time_1d=0) -> fib_params:
     return fib_params(model, schedule, Cm, Am, sigma, h, dt_0D, dt_1D, dt_split, v_th,
-                      pcr_full, threads_per_group, nodes_per_thread, groups)
+                      pcr_full, threads_per_group, nodes_per_thread, groups, splitting,
+                      time_1d)
 
 
 def _stim_array(stims):
     arr = (fib_stim * max(len(stims), 1))()
     for i, s in enumerate(stims):
-        arr[i] = fib_stim(int(s["fiber"]), int(s["node"]), int(s.get("half_width", 1)), 0,
+        arr[i] = fib_stim(int(s["fiber"]), int(s["node"]), int(s.get("half_width", 1)),
+                          int(s.get("mode", FIB_STIM_CURRENT)),
                           int(s["step_on"]), int(s["n_steps"]), int(s.get("period", 0)),
                           float(s["amp"]))
     return arr

@@ -16,9 +16,10 @@ def say(*a):
     sys.stdout.flush()
 
 
-def oracle_cfg(w: I.Workload, scheme=O.SCHEME_STRANG) -> O.Config:
+def oracle_cfg(w: I.Workload, scheme=O.SCHEME_STRANG, theta=0.5) -> O.Config:
     return O.Config(model=w.model, scheme=scheme, Cm=w.Cm, Am=w.Am, sigma=w.sigma, h=w.h,
-                    dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split, v_th=w.v_th)
+                    dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split, v_th=w.v_th,
+                    theta=theta)
 
 
 def oracle_init(w: I.Workload) -> np.ndarray:
@@ -32,11 +33,12 @@ def oracle_init(w: I.Workload) -> np.ndarray:
     return y
 
 
-def oracle_run(w: I.Workload, n_steps=None, sample_every=None, y0=None):
+def oracle_run(w: I.Workload, n_steps=None, sample_every=None, y0=None, cfg=None):
     n_steps = w.n_steps if n_steps is None else n_steps
     se = w.sample_every if sample_every is None else sample_every
     y0 = oracle_init(w) if y0 is None else y0
-    return O.run(oracle_cfg(w), w.n_nodes, y0, w.stims, n_steps, sample_every=se)
+    cfg = oracle_cfg(w) if cfg is None else cfg
+    return O.run(cfg, w.n_nodes, y0, w.stims, n_steps, sample_every=se)
 
 
 def gpu_solver(w: I.Workload, **kw) -> F.Solver:

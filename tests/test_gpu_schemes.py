@@ -1,0 +1,226 @@
+"""Scheme variants of the GPU path against the FP64 oracle.
+
+* implicit-Euler diffusion steps (the theta-scheme at theta = 1 with the
+  lumped mass matrix) in several workgroup shapes, to the 1e-4 mV bound of
+  the Crank-Nicolson step test;
+* whole runs with Godunov splitting R(dt) D(dt) and/or implicit-Euler
+  diffusion in both schedules, to the method's budget (0.5 mV over all
+  samples and the final state, activation times within one split step);
+* prescribed-voltage stimulus entries, alone and mixed with current
+  entries, in both schedules, to the same budget;
+* the surrogate step with voltage entries: every node whose V_m is
+  prescribed at the start of the next step takes the plain path, which
+  applies the prescription exactly as the plain schedule does (an
+  all-rejected surrogate run is bitwise the plain split run);
+* the requests the library refuses: a surrogate under Godunov splitting,
+  unknown stimulus modes.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+from oracle import oracle as O
+from paper_2107_07104_amd import fib as F
+from paper_2107_07104_amd import inputs as I
+from paper_2107_07104_amd import surrogate as SU
+
+from gpu_helpers import compare_runs, gpu_run, gpu_solver, oracle_cfg, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+LENGTHS = [1, 2, 3, 4, 5, 7, 8, 9, 16, 17, 63, 64, 65, 100, 1000, 1481, 1500, 2, 1, 333]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.lib()
+
+
+def _assert_parity(w, res):
+    say("  ", res)
+    assert res["vm_err"] <= 0.5
+    assert res["tact_err"] <= 1.0 * w.dt_split
+    assert res["tact_mismatch"] == 0
+
+
+@pytest.mark.parametrize("shape", [dict(), dict(threads_per_group=768, nodes_per_thread=9),
+                                   dict(threads_per_group=1024, nodes_per_thread=2, groups=3),
+                                   dict(pcr_full=1, threads_per_group=512, nodes_per_thread=4)])
+@pytest.mark.parametrize("dt", [1e-3, 5e-2])
+def test_implicit_euler_diffusion_step_matches_oracle(shape, dt):
+    say(f"[diffusion IE] shape={shape} dt={dt}")
+    rng = np.random.default_rng(14)
+    n = LENGTHS
+    V = rng.uniform(-85.0, 35.0, sum(n))
+    y0 = np.vstack([V[None], np.full((3, sum(n)), 0.5)])
+    s = F.Solver(n, dt_1D=dt, dt_split=dt, time_1d=F.FIB_1D_IMPLICIT_EULER, **shape)
+    say("  plan", s.plan())
+    s.set_state(y0)
+    y0f = s.get_state()
+    cfg = O.Config(dt_1D=dt, dt_split=dt, theta=1.0)
+    s.step_diffusion(dt)
+    s.sync()
+    yg = s.get_state()
+    vo = O.diffusion(cfg, n, y0f[0], dt)
+    say(f"  err {np.max(np.abs(yg[0] - vo)):.2e}")
+    assert np.max(np.abs(yg[0] - vo)) < 1e-4
+    np.testing.assert_array_equal(yg[1:], y0f[1:])
+    s.step_diffusion(3 * dt)
+    s.sync()
+    vo = O.diffusion(cfg, n, vo, 3 * dt)
+    assert np.max(np.abs(s.get_state()[0] - vo)) < 2e-4
+    s.close()
+
+
+VARIANTS = [(F.FIB_SPLIT_GODUNOV, F.FIB_1D_CRANK_NICOLSON),
+            (F.FIB_SPLIT_STRANG, F.FIB_1D_IMPLICIT_EULER),
+            (F.FIB_SPLIT_GODUNOV, F.FIB_1D_IMPLICIT_EULER)]
+
+
+def _variant_workload():
+    """Split step 5e-3 ms (reaction substeps 1e-3 ms): there every variant
+    differs from Strang + Crank-Nicolson by several mV, far above the parity
+    budget, so the parity check also shows that the variant was taken."""
+    w = I.batched_hh(n_fibers=24, t_end=4.0, dt=5e-3)
+    return replace(w, dt_0D=1e-3)
+
+
+@pytest.mark.parametrize("splitting,time_1d", VARIANTS)
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_scheme_variants_match_oracle(splitting, time_1d, schedule):
+    w = _variant_workload()
+    say(f"[scheme] splitting={splitting} time_1d={time_1d} schedule={schedule} "
+        f"steps={w.n_steps}")
+    cfg = oracle_cfg(w, scheme=O.SCHEME_GODUNOV if splitting == F.FIB_SPLIT_GODUNOV
+                     else O.SCHEME_STRANG,
+                     theta=1.0 if time_1d == F.FIB_1D_IMPLICIT_EULER else 0.5)
+    ora = oracle_run(w, cfg=cfg)
+    default = oracle_run(w)
+    gap = float(np.max(np.abs(ora[1] - default[1])))
+    say(f"  oracle: variant vs Strang + Crank-Nicolson {gap:.2f} mV")
+    assert gap > 1.0
+    gpu = gpu_run(w, schedule=schedule, splitting=splitting, time_1d=time_1d)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res)
+    assert res["activated"] > 500
+    gpu[3].close()
+
+
+def _voltage_workload(mixed):
+    w = I.batched_hh(n_fibers=24, t_end=4.0)
+    stims = []
+    for j, st in enumerate(w.stims):
+        if not mixed or j % 2 == 0:
+            st = dict(st, mode=F.FIB_STIM_VOLTAGE, amp=20.0)
+        stims.append(st)
+    return replace(w, stims=stims)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_prescribed_voltage_stimulus_matches_oracle(mixed, schedule):
+    w = _voltage_workload(mixed)
+    if schedule == F.FIB_SCHED_SPLIT:
+        w = w.with_steps(2500)
+    say(f"[voltage stimulus] mixed={mixed} schedule={schedule} steps={w.n_steps}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w, schedule=schedule)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res)
+    assert res["activated"] > (500 if schedule == F.FIB_SCHED_FUSED else 200)
+    gpu[3].close()
+
+
+def test_prescribed_voltage_single_fiber_godunov_implicit_euler():
+    w = I.single_fiber(amp=20.0)
+    w = replace(w, stims=[dict(st, mode=F.FIB_STIM_VOLTAGE) for st in w.stims])
+    say("[voltage stimulus single fiber, Godunov + implicit Euler]")
+    ora = oracle_run(w, cfg=oracle_cfg(w, scheme=O.SCHEME_GODUNOV, theta=1.0))
+    gpu = gpu_run(w, splitting=F.FIB_SPLIT_GODUNOV, time_1d=F.FIB_1D_IMPLICIT_EULER)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res)
+    assert res["activated"] > 300
+    gpu[3].close()
+
+
+def _surrogate_net():
+    sizes = SU.SHAPES[I.MODEL_HH]
+    params = M.init_params(sizes, 5)
+    net = F.Mlp(sizes, act=SU.ACTIVATION[I.MODEL_HH])
+    net.set_params(M.flatten(params).astype(np.float32))
+    S = sizes[-1]
+    sc = dict(in_shift=np.zeros(S, np.float32), in_scale=np.ones(S, np.float32),
+              out_shift=np.zeros(S, np.float32), out_scale=np.full(S, 1e-3, np.float32),
+              res_scale=np.ones(S, np.float32), flag_scale=1.0 / I.AMP_SUPRA)
+    return net, sc
+
+
+def _voltage_surrogate_workload():
+    w = I.batched_hh(n_fibers=6, n_min=600, n_max=700, dt=5e-3, onset_max=1.0)
+    w = replace(w, dt_0D=1e-3, stims=[dict(st, mode=F.FIB_STIM_VOLTAGE, amp=20.0)
+                                      for st in w.stims])
+    return w
+
+
+def test_surrogate_rejects_prescribed_nodes_and_falls_back_exactly():
+    w = _voltage_surrogate_workload()
+    n = 300
+    say("[surrogate + voltage entries] all rejected vs plain")
+    a = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    a.run(0, n)
+    a.sync()
+    ya, ta = a.get_state(), a.tact()
+    a.close()
+    net, sc = _surrogate_net()
+    b = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    b.set_surrogate(net, sc, 1e-30)
+    b.run(0, n)
+    b.sync()
+    np.testing.assert_array_equal(b.get_state(), ya)
+    np.testing.assert_array_equal(b.tact(), ta)
+    assert np.isfinite(ta).sum() > 100
+    b.close()
+    # every other node accepted: the rejected ones are exactly the nodes
+    # whose V_m is prescribed at the start of the next step
+    say("[surrogate + voltage entries] rejection count")
+    s = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    s.set_surrogate(net, sc, 1e30)
+    offs = w.offsets
+    for st in w.stims[:3]:
+        step = int(st["step_on"]) - 1 if st["step_on"] > 0 else int(st["step_on"])
+        covered = np.zeros(w.n_total, bool)
+        for e in w.stims:
+            if O.stimulus_current(w.n_nodes, [dict(e, mode=0, amp=1.0)], step + 1).any():
+                lo = max(int(e["node"]) - int(e["half_width"]), 0)
+                hi = min(int(e["node"]) + int(e["half_width"]), int(w.n_nodes[e["fiber"]]) - 1)
+                covered[offs[e["fiber"]] + lo:offs[e["fiber"]] + hi + 1] = True
+        s.step_surrogate(step)
+        s.sync()
+        say(f"   step {step}: {s.last_fallbacks()} fallbacks, {int(covered.sum())} prescribed")
+        assert covered.sum() >= 3
+        assert s.last_fallbacks() == int(covered.sum())
+    s.close()
+    net.close()
+
+
+def test_refused_requests():
+    w = _voltage_surrogate_workload()
+    net, sc = _surrogate_net()
+    s = gpu_solver(w, splitting=F.FIB_SPLIT_GODUNOV)
+    with pytest.raises(F.FibError) as e:
+        s.set_surrogate(net, sc, 1e-2)
+    assert e.value.code == F.FIB_EUNSUPPORTED
+    with pytest.raises(F.FibError) as e:
+        s.set_stimulus([dict(w.stims[0], mode=2)])
+    assert e.value.code == F.FIB_EINVAL
+    # the refused table left the old one in place: the run still matches
+    s.run(0, 10)
+    s.sync()
+    s.close()
+    net.close()

@@ -40,7 +40,8 @@ def test_n_states():
     ("Cm", 0.0), ("Am", -1.0), ("h", float("nan")), ("sigma", -0.1), ("dt_0D", 0.0),
     ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
     ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
-    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("schedule", 3)])
+    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("schedule", 3),
+    ("splitting", 2), ("time_1d", 2), ("time_1d", -1)])
 def test_check_params_rejects(field, value):
     p = F.make_params()
     setattr(p, field, value)
@@ -50,6 +51,22 @@ def test_check_params_rejects(field, value):
 
 def test_check_params_accepts_defaults():
     assert F.fib_check_params(F.make_params()) == F.FIB_OK
+    for split in (F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV):
+        for t1 in (F.FIB_1D_CRANK_NICOLSON, F.FIB_1D_IMPLICIT_EULER):
+            assert F.fib_check_params(F.make_params(splitting=split, time_1d=t1)) == F.FIB_OK
+
+
+def test_implicit_euler_matrix_couples_more_strongly():
+    """The implicit-Euler matrix I - dt L has twice the off-diagonal weight of
+    the Crank-Nicolson matrix I - dt L / 2, so the reduced system keeps its
+    couplings above 2^-40 over at least as many PCR levels."""
+    n = [1000] * 8
+    for dt in (1e-3, 0.05, 0.5):
+        p = dict(dt_split=dt, dt_1D=dt, nodes_per_thread=2)
+        cn = F.fib_plan_preview(F.make_params(**p), n, 8)
+        ie = F.fib_plan_preview(F.make_params(time_1d=F.FIB_1D_IMPLICIT_EULER, **p), n, 8)
+        assert ie["pcr_levels"] >= cn["pcr_levels"] > 0
+    assert ie["pcr_levels"] > cn["pcr_levels"]   # dt = 0.5 ms: one more level
 
 
 @pytest.mark.parametrize("threads,k,ok", [(768, 9, True), (960, 7, True), (512, 14, True),
