@@ -5,7 +5,8 @@
   the Crank-Nicolson step test;
 * whole runs with Godunov splitting R(dt) D(dt) and/or implicit-Euler
   diffusion in both schedules, to the method's budget (0.5 mV over all
-  samples and the final state, activation times within one split step);
+  samples and the final state, activation times within one split step),
+  and with four diffusion substeps per split step;
 * prescribed-voltage stimulus entries, alone and mixed with current
   entries, in both schedules, to the same budget;
 * the surrogate step with voltage entries: every node whose V_m is
@@ -109,6 +110,23 @@ def test_scheme_variants_match_oracle(splitting, time_1d, schedule):
     res = compare_runs(w, gpu, ora)
     _assert_parity(w, res)
     assert res["activated"] > 500
+    gpu[3].close()
+
+
+@pytest.mark.parametrize("time_1d", [F.FIB_1D_CRANK_NICOLSON, F.FIB_1D_IMPLICIT_EULER])
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_diffusion_subcycling_matches_oracle(time_1d, schedule):
+    """dt_1D = dt_split / 4: four diffusion substeps per split step."""
+    w = replace(_variant_workload(), dt_1D=1.25e-3)
+    say(f"[subcycling] time_1d={time_1d} schedule={schedule}")
+    theta = 1.0 if time_1d == F.FIB_1D_IMPLICIT_EULER else 0.5
+    ora = oracle_run(w, cfg=oracle_cfg(w, theta=theta))
+    one = oracle_run(replace(w, dt_1D=w.dt_split), cfg=oracle_cfg(replace(w, dt_1D=w.dt_split),
+                                                                 theta=theta))
+    say(f"  oracle: four substeps vs one {np.max(np.abs(ora[1] - one[1])):.2f} mV")
+    gpu = gpu_run(w, schedule=schedule, time_1d=time_1d)
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res)
     gpu[3].close()
 
 
