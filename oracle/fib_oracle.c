@@ -472,3 +472,181 @@ int or_run(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double*
   free(off);
   return err;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Adaptive computation (section sec:adaptive_computation_for_fiber_based)   */
+/* ------------------------------------------------------------------------ */
+
+/* Point states of the adaptive scheme (figure state_chart). */
+#define OR_PT_ACTIVE 0   /* not in equilibrium: solved in the next step */
+#define OR_PT_INACTIVE 1 /* in equilibrium: not solved */
+#define OR_PT_NEIGHBOR 2 /* a neighbour is active: solved and checked in the next step */
+
+/* Marks every inactive point of a fiber with an active neighbour as
+ * "neighbor is active": in one step a point can influence only its two
+ * neighbours through the linear-element stencil. */
+static void mark_neighbors(int64_t n, uint8_t* pt) {
+  for (int64_t i = 0; i < n; ++i) {
+    if (pt[i] != OR_PT_INACTIVE) continue;
+    if ((i > 0 && pt[i - 1] == OR_PT_ACTIVE) || (i + 1 < n && pt[i + 1] == OR_PT_ACTIVE))
+      pt[i] = OR_PT_NEIGHBOR;
+  }
+}
+
+/* Reaction part over `span` for the points of one fiber that are not
+ * inactive (SoA state yf[k * n + i] of the fiber). */
+static void reaction_points(const or_params* p, int S, double* yf, int64_t n, const uint8_t* pt,
+                            const double* I, double span) {
+  int64_t nsub = or_n_substeps(span, p->dt_0D);
+  double tau = span / (double)nsub;
+  double yn[OR_MAX_STATES];
+  for (int64_t i = 0; i < n; ++i) {
+    if (pt[i] == OR_PT_INACTIVE) continue;
+    for (int k = 0; k < S; ++k) yn[k] = yf[(int64_t)k * n + i];
+    for (int64_t s = 0; s < nsub; ++s) heun_step(p->model, S, p->Cm, yn, I[i], tau);
+    for (int k = 0; k < S; ++k) yf[(int64_t)k * n + i] = yn[k];
+  }
+}
+
+/* Equilibrium check of the solved points: moved[i] = 1 if the relative
+ * change |y_k - before_k| > tol |before_k| for any state k. */
+static void check_points(int S, const double* yf, const double* before, int64_t n,
+                         const uint8_t* pt, double tol, uint8_t* moved) {
+  for (int64_t i = 0; i < n; ++i) {
+    moved[i] = 0;
+    if (pt[i] == OR_PT_INACTIVE) continue;
+    for (int k = 0; k < S; ++k) {
+      const double a = before[(int64_t)k * n + i], b = yf[(int64_t)k * n + i];
+      if (fabs(b - a) > tol * fabs(a)) moved[i] = 1;
+    }
+  }
+}
+
+/* Split steps step0 .. step0+n_steps-1 with adaptive computation.  Same
+ * arguments and observables as or_run, plus
+ *
+ * tol       relative change that separates equilibrium from activity;
+ * pt        nullable, in/out: per node OR_PT_*; null starts every node
+ *           active (the scheme's initial state);
+ * computed  nullable, out: number of node-steps whose reaction was solved.
+ *
+ * Per fiber and split step, in this order:
+ *  1. a fiber is left out of the step (neither reaction nor diffusion)
+ *     before the first step in which one of its stimulus entries is on
+ *     (from the table, whatever step the run starts at); from that step on
+ *     it is always part of the computation;
+ *  2. V_m prescriptions and currents of the step as in or_run; every point
+ *     covered by an entry that is on becomes active, and inactive points
+ *     next to an active point become "neighbor is active";
+ *  3. the reaction parts of the splitting run on the points that are not
+ *     inactive; the diffusion part runs on the whole fiber if any point is
+ *     not inactive, else it is skipped;
+ *  4. every point solved in the step compares its state before and after
+ *     the step's last reaction part (the Heun solve): if the relative change
+ *     |y_k+ - y_k| > tol |y_k| for any state k it is active, else inactive;
+ *     then inactive points next to an active point become "neighbor is
+ *     active" again;
+ *  5. observables as in or_run.
+ * Points are single nodes (the thesis groups SIMD-vector-sized runs of
+ * nodes into one point; the granularity does not enter the definition). */
+int or_run_adaptive(const or_params* p, int32_t n_fibers, const int32_t* n_nodes, double* y,
+                    const or_stim* stim, int32_t n_stim, int64_t step0, int64_t n_steps,
+                    int64_t sample_every, double* samples, double* t_act, double tol,
+                    uint8_t* pt, int64_t* computed) {
+  int S = or_n_states(p->model);
+  if (S <= 0 || n_fibers < 0 || n_steps < 0 || step0 < 0 || !(p->dt_split > 0.0) ||
+      !(p->theta >= 0.5 && p->theta <= 1.0) || !(tol >= 0.0))
+    return OR_EINVAL;
+  int64_t* off = (int64_t*)malloc(sizeof(int64_t) * ((size_t)n_fibers + 1));
+  if (!off) return OR_ENOMEM;
+  off[0] = 0;
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    if (n_nodes[f] < 1) { free(off); return OR_EINVAL; }
+    off[f + 1] = off[f] + n_nodes[f];
+  }
+  const int64_t n_total = off[n_fibers];
+  const double dt = p->dt_split;
+  int err = OR_OK;
+  int64_t total = 0;
+
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+  for (int32_t f = 0; f < n_fibers; ++f) {
+    const int64_t n = n_nodes[f], o = off[f];
+    double* buf = (double*)malloc(sizeof(double) * (2 * (size_t)S * n + 9 * (size_t)n));
+    uint8_t* ptf = (uint8_t*)malloc(2 * (size_t)n);
+    if (!buf || !ptf) { err = OR_ENOMEM; free(buf); free(ptf); continue; }
+    uint8_t* moved = ptf + n;
+    double* yf = buf;                   /* SoA state of this fiber */
+    double* before = yf + (size_t)S * n; /* state before the last reaction part */
+    double* I = before + (size_t)S * n;
+    double* vprev = I + n;
+    double* scratch = vprev + n;
+    for (int k = 0; k < S; ++k)
+      memcpy(yf + (size_t)k * n, y + (int64_t)k * n_total + o, sizeof(double) * n);
+    for (int64_t i = 0; i < n; ++i) ptf[i] = pt ? pt[o + i] : OR_PT_ACTIVE;
+    /* first step with a stimulus entry of this fiber on */
+    int64_t first_on = INT64_MAX;
+    for (int32_t e = 0; e < n_stim; ++e)
+      if (stim[e].fiber == f && stim[e].n_steps > 0 && stim[e].step_on < first_on)
+        first_on = stim[e].step_on;
+    int64_t cnt = 0;
+
+    for (int64_t step = step0; step < step0 + n_steps; ++step) {
+      memcpy(vprev, yf, sizeof(double) * n);
+      if (step >= first_on) {
+        fiber_prescribe(f, n, stim, n_stim, step, yf);
+        fiber_current(f, n, stim, n_stim, step, I);
+        for (int32_t e = 0; e < n_stim; ++e) {
+          const or_stim* s = &stim[e];
+          if (s->fiber != f || !stim_on(s, step)) continue;
+          for (int64_t j = (int64_t)s->node - s->half_width; j <= (int64_t)s->node + s->half_width; ++j)
+            if (j >= 0 && j < n) ptf[j] = OR_PT_ACTIVE;
+        }
+        mark_neighbors(n, ptf);
+        int any = 0;
+        for (int64_t i = 0; i < n; ++i) {
+          any |= ptf[i] != OR_PT_INACTIVE;
+          cnt += ptf[i] != OR_PT_INACTIVE;
+        }
+        if (p->scheme == 0) {
+          reaction_points(p, S, yf, n, ptf, I, 0.5 * dt);
+          if (any) diffusion_fiber(p, n, yf, dt, scratch);
+          memcpy(before, yf, sizeof(double) * (size_t)S * n);
+          reaction_points(p, S, yf, n, ptf, I, 0.5 * dt);
+          check_points(S, yf, before, n, ptf, tol, moved);
+        } else {
+          /* the check compares the ends of the reaction part, before the
+           * diffusion changes V */
+          memcpy(before, yf, sizeof(double) * (size_t)S * n);
+          reaction_points(p, S, yf, n, ptf, I, dt);
+          check_points(S, yf, before, n, ptf, tol, moved);
+          if (any) diffusion_fiber(p, n, yf, dt, scratch);
+        }
+        for (int64_t i = 0; i < n; ++i)
+          if (ptf[i] != OR_PT_INACTIVE) ptf[i] = moved[i] ? OR_PT_ACTIVE : OR_PT_INACTIVE;
+        mark_neighbors(n, ptf);
+      }
+      if (t_act) {
+        double t0 = (double)step * dt;
+        for (int64_t i = 0; i < n; ++i) {
+          double v0 = vprev[i], v1 = yf[i];
+          if (isinf(t_act[o + i]) && v0 < p->v_th && v1 >= p->v_th)
+            t_act[o + i] = t0 + dt * (p->v_th - v0) / (v1 - v0);
+        }
+      }
+      if (samples && sample_every > 0 && (step + 1) % sample_every == 0) {
+        int64_t s = (step + 1) / sample_every - 1 - step0 / sample_every;
+        memcpy(samples + s * n_total + o, yf, sizeof(double) * n);
+      }
+    }
+    for (int k = 0; k < S; ++k)
+      memcpy(y + (int64_t)k * n_total + o, yf + (size_t)k * n, sizeof(double) * n);
+    if (pt) memcpy(pt + o, ptf, (size_t)n);
+    total += cnt;
+    free(buf);
+    free(ptf);
+  }
+  free(off);
+  if (computed) *computed = total;
+  return err;
+}

@@ -54,6 +54,7 @@ class Stim(C.Structure):
 _lib = None
 _dp = C.POINTER(C.c_double)
 _ip = C.POINTER(C.c_int32)
+_u8p = C.POINTER(C.c_uint8)
 
 
 def lib():
@@ -80,6 +81,9 @@ def lib():
                                           C.c_int64, _dp]
         L.or_run.argtypes = [C.POINTER(Params), C.c_int32, _ip, _dp, C.POINTER(Stim),
                              C.c_int32, C.c_int64, C.c_int64, C.c_int64, _dp, _dp]
+        L.or_run_adaptive.argtypes = [C.POINTER(Params), C.c_int32, _ip, _dp, C.POINTER(Stim),
+                                      C.c_int32, C.c_int64, C.c_int64, C.c_int64, _dp, _dp,
+                                      C.c_double, _u8p, C.POINTER(C.c_int64)]
         _lib = L
     return _lib
 
@@ -216,6 +220,38 @@ def diffusion(cfg: Config, n_nodes, V: np.ndarray, span: float) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"or_diffusion failed ({rc})")
     return V
+
+
+PT_ACTIVE, PT_INACTIVE, PT_NEIGHBOR = 0, 1, 2
+
+
+def run_adaptive(cfg: Config, n_nodes, y0: np.ndarray, stims, n_steps: int, step0: int = 0,
+                 sample_every: int = 0, t_act=None, tol: float = 1e-5, pt=None):
+    """The splitting loop with adaptive computation (or_run_adaptive); returns
+    (y, samples or None, t_act, point states, node-steps solved)."""
+    nn = np.ascontiguousarray(n_nodes, dtype=np.int32)
+    y = np.array(y0, dtype=np.float64, order="C", copy=True)
+    n_total = int(nn.sum())
+    assert y.shape[1] == n_total
+    arr, n = _stims(stims)
+    samples = None
+    if sample_every > 0:
+        first = step0 // sample_every
+        last = (step0 + n_steps) // sample_every
+        samples = np.full((max(last - first, 0), n_total), np.nan)
+    ta = (np.full(n_total, np.inf) if t_act is None
+          else np.array(t_act, dtype=np.float64, copy=True))
+    pt = (np.full(n_total, PT_ACTIVE, dtype=np.uint8) if pt is None
+          else np.array(pt, dtype=np.uint8, copy=True))
+    cnt = C.c_int64(0)
+    p = cfg.c_params()
+    rc = lib().or_run_adaptive(C.byref(p), len(nn), nn.ctypes.data_as(_ip), _d(y), arr, n,
+                               int(step0), int(n_steps), int(sample_every),
+                               _d(samples) if samples is not None and samples.size else None,
+                               _d(ta), float(tol), pt.ctypes.data_as(_u8p), C.byref(cnt))
+    if rc != 0:
+        raise RuntimeError(f"or_run_adaptive failed ({rc})")
+    return y, samples, ta, pt, int(cnt.value)
 
 
 def run(cfg: Config, n_nodes, y0: np.ndarray, stims, n_steps: int, step0: int = 0,
