@@ -224,6 +224,40 @@ int fib_step_diffusion(fib_t* ctx, double span);
 int fib_run(fib_t* ctx, int64_t step0, int64_t n_steps, int64_t sample_every, float* samples,
             int64_t sample_rows);
 
+/* Adaptive computation of the subcellular model (section
+ * sec:adaptive_computation_for_fiber_based, figure state_chart) for
+ * fib_run.  With tol > 0 each node ("point") is active, inactive or
+ * "neighbor is active", and per split step:
+ *   - a fiber takes no part (no reaction, no diffusion) before the first
+ *     step in which one of its stimulus entries is on (by the table,
+ *     whatever step a run starts at);
+ *   - a node of a fiber that takes part is solved if the last check found
+ *     it or a neighbour in its fiber active, or a stimulus entry that is on
+ *     covers it or a neighbour; the reaction parts run on solved nodes
+ *     only, the diffusion on fibers with at least one solved node;
+ *   - each solved node checks the relative change |y_k+ - y_k| >
+ *     tol |y_k| of every state over the step's last reaction part (the
+ *     thesis uses tol = 1e-5): active if any state moved that much, else
+ *     inactive.
+ * The check runs in FP32 on the device.  Enabling (or re-enabling) resets
+ * every point to active, its initial state, and the solved-node counter to
+ * zero; fib_init_state and fib_set_state reset the points too.  tol = 0
+ * turns it off.  Split schedule only: FIB_EUNSUPPORTED with
+ * FIB_SCHED_FUSED or an attached surrogate (AUTO takes the split schedule
+ * while it is on).  fib_autotune times the plain schedule and leaves the
+ * points alone.  Blocking. */
+int fib_set_adaptive(fib_t* ctx, double tol);
+
+/* Node-steps whose reaction was solved by adaptive runs since
+ * fib_set_adaptive enabled it.  Blocking. */
+int fib_adaptive_solved(fib_t* ctx, int64_t* node_steps);
+
+/* Per node 1 if the last equilibrium check found it active (nodes of
+ * fibers that have not taken part yet keep their initial "active"), else 0,
+ * into a host array of n_total bytes.  FIB_ESTATE if adaptive computation
+ * was never enabled.  Blocking. */
+int fib_adaptive_points(fib_t* ctx, uint8_t* active, int64_t n);
+
 /* Activation times (ms, +inf where V_m has not crossed v_th) into a host
  * FP32 array of n_total values.  Blocking. */
 int fib_get_tact(fib_t* ctx, float* t_act, int64_t n);

@@ -277,6 +277,16 @@ struct fib_ctx {
   int sur_slot = 0;             // counter of the next surrogate step
   int sur_last_slot = -1;       // counter of the last one (-1: none yet)
   int sur_grid = 0;
+
+  // adaptive computation (split schedule)
+  double adapt_tol = 0.0;              // > 0: on
+  std::vector<int32_t> first_on;       // per fiber: first step with a stimulus entry on
+  int32_t* d_node_fiber = nullptr;     // [n_total]
+  int32_t* d_first_on = nullptr;       // [n_fibers]
+  uint8_t* d_pt = nullptr;             // [2][n_total] point flags by step parity
+  uint8_t* d_fiber_any = nullptr;      // [2][n_fibers] by step parity
+  unsigned long long* d_adapt_count = nullptr;  // [kAdaptCounters]
+  int adapt_par = 0;                   // parity of the buffer with the latest flags
 };
 
 namespace {
@@ -425,12 +435,13 @@ double cn_r(const fib_ctx* c, double dt_cn) {
 // theta of the diffusion substeps' theta-scheme
 double theta_of(const fib_params& p) { return p.time_1d == FIB_1D_IMPLICIT_EULER ? 1.0 : 0.5; }
 
-// Diffusion coefficients of a launch with substep dt_cn: r for the
-// right-hand side dt L V, r_mat = 2 theta r for the matrix I - theta dt L.
+// Diffusion coefficients of a launch with substep dt_cn: r_mat = 2 theta r
+// (r = c dt_cn / h^2) gives the row weights of the matrix I - theta dt L,
+// and 1 / theta times them the right-hand side dt L V.
 void set_diffusion(const fib_ctx* c, double dt_cn, KArgs& a) {
   const double r = cn_r(c, dt_cn);
-  a.r = (float)r;
   a.r_mat = (float)(2.0 * theta_of(c->p) * r);
+  a.rhs = (float)(1.0 / theta_of(c->p));
 }
 
 // Fills the slot tables and the PCR level count of the current shape
@@ -571,6 +582,69 @@ int check_ctx(const fib_ctx* c) {
   return FIB_OK;
 }
 
+// Every point of the adaptive computation back to "active" (its initial
+// state), as after a new state.
+int adapt_reset_points(fib_ctx* c) {
+  if (!c->d_pt || c->n_total == 0) return FIB_OK;
+  HIP_TRY(hipMemsetAsync(c->d_pt, fib::PT_ACTIVE, 2 * (size_t)c->n_total, c->stream));
+  return FIB_OK;
+}
+
+// fib_run with adaptive computation (split schedule).  Per Strang step n:
+// start(n) [solve set, prescriptions, first half], diffusion(n) [fibers
+// with a solved node], finish(n) [second half, check, observables]; per
+// Godunov step: start(n) [observables of n-1, solve set, reaction, check],
+// diffusion(n), and the observables of the last step after the loop.  The
+// point flags of step n live in buffer n & 1, the fiber flags likewise.
+int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
+  const int64_t nt = c->n_total, nf = c->n_fibers;
+  const int64_t end = step0 + n_steps;
+  const bool godunov = c->p.splitting == FIB_SPLIT_GODUNOV;
+  a.node_fiber = c->d_node_fiber;
+  a.fiber_first_on = c->d_first_on;
+  a.adapt_count = c->d_adapt_count;
+  a.adapt_tol = (float)c->adapt_tol;
+  auto at = [&](int64_t n) {
+    a.pt_cur = c->d_pt + (n & 1) * nt;
+    a.pt_prev = c->d_pt + ((n + 1) & 1) * nt;
+    a.fiber_any = c->d_fiber_any + (n & 1) * nf;
+    a.fiber_any_next = c->d_fiber_any + ((n + 1) & 1) * nf;
+  };
+  // the flags of step step0 - 1 must sit in buffer (step0 - 1) & 1
+  const int want = (int)((step0 + 1) & 1);
+  if (want != c->adapt_par)
+    HIP_TRY(hipMemcpyAsync(c->d_pt + want * nt, c->d_pt + c->adapt_par * nt, (size_t)nt,
+                           hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(hipMemsetAsync(c->d_fiber_any, 0, 2 * (size_t)nf, c->stream));
+  HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * nt, hipMemcpyDeviceToDevice,
+                         c->stream));
+  const size_t lds = fib::lds_bytes_for(c->threads, c->levels);
+  if (godunov) {
+    for (int64_t n = step0; n < end; ++n) {
+      at(n);
+      HIP_TRY(fib::launch_adapt_start(c->p.model, true, (int32_t)n, n > step0, a, c->stream));
+      HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+    }
+    KArgs o = a;
+    o.fiber_any = nullptr;
+    HIP_TRY(fib::launch_react(c->p.model, (int32_t)(end - 1), 0, 2, o, c->stream));
+  } else {
+    at(step0);
+    HIP_TRY(fib::launch_adapt_start(c->p.model, false, (int32_t)step0, false, a, c->stream));
+    for (int64_t n = step0; n < end; ++n) {
+      at(n);
+      HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+      HIP_TRY(fib::launch_adapt_finish(c->p.model, (int32_t)n, a, c->stream));
+      if (n + 1 < end) {
+        at(n + 1);
+        HIP_TRY(fib::launch_adapt_start(c->p.model, false, (int32_t)(n + 1), false, a, c->stream));
+      }
+    }
+  }
+  c->adapt_par = (int)((end - 1) & 1);
+  return FIB_OK;
+}
+
 int check_levels_fit(const fib_ctx* c, int levels) {
   const size_t need = fib::lds_bytes_for(c->threads, levels);
   if (need > c->max_lds)
@@ -689,6 +763,7 @@ int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, vo
   for (int32_t f = 0; f < n_fibers; ++f) c->offsets[f + 1] = c->offsets[f] + n_nodes[f];
   c->n_total = total;
   c->stream = (hipStream_t)stream;
+  c->first_on.assign(n_fibers, INT32_MAX);
 
   auto bail = [&](int code) {
     fib_destroy(c);
@@ -737,6 +812,11 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_sur_tab);
   (void)hipFree(c->d_sur_list);
   (void)hipFree(c->d_sur_count);
+  (void)hipFree(c->d_node_fiber);
+  (void)hipFree(c->d_first_on);
+  (void)hipFree(c->d_pt);
+  (void)hipFree(c->d_fiber_any);
+  (void)hipFree(c->d_adapt_count);
   delete c;
 }
 
@@ -766,6 +846,7 @@ int fib_init_state(fib_t* c, const float* vm_noise, const float* rel_noise) {
   KArgs a = base_args(c);
   HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
   HIP_TRY(fib::launch_init(c->p.model, vm_noise, rel_noise, a, c->stream));
+  if (int rc = adapt_reset_points(c)) return rc;
   c->state_ready = true;
   return FIB_OK;
 }
@@ -783,6 +864,7 @@ int fib_set_state(fib_t* c, const double* y, int64_t n_values) {
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
                          hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  if (int rc = adapt_reset_points(c)) return rc;
   HIP_TRY(hipStreamSynchronize(c->stream));
   c->state_ready = true;
   return FIB_OK;
@@ -812,6 +894,7 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
   if (n < 0 || (n > 0 && !s)) return fail(FIB_EINVAL, "bad stimulus table");
   std::vector<int32_t> node_stim(c->n_total, 0);
   std::vector<fib::StimDev> tab(n);
+  std::vector<int32_t> first_on(c->n_fibers, INT32_MAX);
   const int64_t lim = ((int64_t)1 << 31) - 1;
   for (int32_t e = 0; e < n; ++e) {
     const fib_stim& x = s[e];
@@ -826,6 +909,7 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
     // voltage entries hold the prescribed value as the device state does:
     // the offset from the resting V_m
     const bool volt = x.mode == FIB_STIM_VOLTAGE;
+    if (x.n_steps > 0) first_on[x.fiber] = std::min(first_on[x.fiber], (int32_t)x.step_on);
     tab[e] = fib::StimDev{(int32_t)x.step_on, (int32_t)x.n_steps, (int32_t)x.period,
                           (float)(volt ? x.amp - (double)(float)c->rest[0] : x.amp), volt ? 1 : 0};
     const int64_t n_f = c->n_nodes[x.fiber];
@@ -851,6 +935,10 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
     HIP_TRY(hipMemcpy(c->d_stim, tab.data(), sizeof(fib::StimDev) * n, hipMemcpyHostToDevice));
   }
   c->n_stim = n;
+  c->first_on = first_on;
+  if (c->d_first_on && c->n_fibers > 0)
+    HIP_TRY(hipMemcpy(c->d_first_on, first_on.data(), sizeof(int32_t) * c->n_fibers,
+                      hipMemcpyHostToDevice));
   if (c->n_total > 0)
     HIP_TRY(hipMemcpy(c->d_node_stim, node_stim.data(), sizeof(int32_t) * c->n_total,
                       hipMemcpyHostToDevice));
@@ -928,6 +1016,7 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   a.pcr_levels = c->levels;
   a.step0 = (int32_t)step0;
   a.n_steps = (int32_t)n_steps;
+  if (c->adapt_tol > 0.0) return run_adaptive(c, a, step0, n_steps);
   // AUTO: fused for Hodgkin-Huxley unless a surrogate is attached (the
   // surrogate step belongs to the split schedule)
   const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
@@ -978,8 +1067,19 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   return FIB_OK;
 }
 
+static int autotune_impl(fib_t* c, int32_t trial_steps, int32_t max_candidates, double* ms_per_step);
+
 int fib_autotune(fib_t* c, int32_t trial_steps, int32_t max_candidates, double* ms_per_step) {
   if (int rc = check_ctx(c)) return rc;
+  // the trials time the plain schedule; the adaptive flags stay untouched
+  const double tol = c->adapt_tol;
+  c->adapt_tol = 0.0;
+  const int rc = autotune_impl(c, trial_steps, max_candidates, ms_per_step);
+  c->adapt_tol = tol;
+  return rc;
+}
+
+static int autotune_impl(fib_t* c, int32_t trial_steps, int32_t max_candidates, double* ms_per_step) {
   if (trial_steps < 1 || trial_steps > 100000) return fail(FIB_EINVAL, "trial_steps must be in [1, 100000]");
   if (max_candidates < 1) return fail(FIB_EINVAL, "max_candidates must be >= 1");
   if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
@@ -1092,6 +1192,8 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   if (!(tol > 0.0) || !std::isfinite(flag_scale)) return fail(FIB_EINVAL, "bad tolerance or flag scale");
   if (c->p.splitting != FIB_SPLIT_STRANG)
     return fail(FIB_EUNSUPPORTED, "the surrogate step replaces Strang reaction halves");
+  if (c->adapt_tol > 0.0)
+    return fail(FIB_EUNSUPPORTED, "adaptive computation and the surrogate step do not combine");
   const fib::MlpShape& ms = fib::mlp_shape(net);
   const int S = c->S;
   // supported shapes: the kernels are compiled for them
@@ -1225,6 +1327,77 @@ int fib_surrogate_last_fallbacks(fib_t* c, int64_t* n) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(&v, c->d_sur_count + c->sur_last_slot, sizeof(int), hipMemcpyDeviceToHost));
   *n = v;
+  return FIB_OK;
+}
+
+int fib_set_adaptive(fib_t* c, double tol) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!(std::isfinite(tol) && tol >= 0.0)) return fail(FIB_EINVAL, "tol must be finite and >= 0");
+  if (tol == 0.0) {
+    c->adapt_tol = 0.0;
+    return FIB_OK;
+  }
+  if (c->p.schedule == FIB_SCHED_FUSED)
+    return fail(FIB_EUNSUPPORTED, "adaptive computation runs in the split schedule");
+  if (c->sur_on)
+    return fail(FIB_EUNSUPPORTED, "adaptive computation and the surrogate step do not combine");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const size_t nt = (size_t)std::max<int64_t>(c->n_total, 1), nf = (size_t)std::max(c->n_fibers, 1);
+  if (!c->d_pt) {
+    std::vector<int32_t> fib_of(nt, 0);
+    for (int32_t f = 0; f < c->n_fibers; ++f)
+      for (int64_t i = c->offsets[f]; i < c->offsets[f + 1]; ++i) fib_of[i] = f;
+    if (hipMalloc(&c->d_node_fiber, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc(&c->d_first_on, sizeof(int32_t) * nf) != hipSuccess ||
+        hipMalloc(&c->d_pt, 2 * nt) != hipSuccess || hipMalloc(&c->d_fiber_any, 2 * nf) != hipSuccess ||
+        hipMalloc(&c->d_adapt_count, sizeof(unsigned long long) * fib::kAdaptCounters) != hipSuccess) {
+      (void)hipFree(c->d_node_fiber);
+      (void)hipFree(c->d_first_on);
+      (void)hipFree(c->d_pt);
+      (void)hipFree(c->d_fiber_any);
+      (void)hipFree(c->d_adapt_count);
+      c->d_node_fiber = c->d_first_on = nullptr;
+      c->d_pt = c->d_fiber_any = nullptr;
+      c->d_adapt_count = nullptr;
+      return fail(FIB_ENOMEM, "device allocation failed");
+    }
+    HIP_TRY(hipMemcpy(c->d_node_fiber, fib_of.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+  }
+  if (c->n_fibers > 0)
+    HIP_TRY(hipMemcpy(c->d_first_on, c->first_on.data(), sizeof(int32_t) * c->n_fibers,
+                      hipMemcpyHostToDevice));
+  HIP_TRY(hipMemset(c->d_pt, fib::PT_ACTIVE, 2 * nt));
+  HIP_TRY(hipMemset(c->d_fiber_any, 0, 2 * nf));
+  HIP_TRY(hipMemset(c->d_adapt_count, 0, sizeof(unsigned long long) * fib::kAdaptCounters));
+  c->adapt_par = 0;
+  c->adapt_tol = tol;
+  return FIB_OK;
+}
+
+int fib_adaptive_solved(fib_t* c, int64_t* node_steps) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!node_steps) return fail(FIB_EINVAL, "null argument");
+  *node_steps = 0;
+  if (!c->d_adapt_count) return FIB_OK;
+  unsigned long long h[fib::kAdaptCounters];
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(h, c->d_adapt_count, sizeof(h), hipMemcpyDeviceToHost));
+  unsigned long long sum = 0;
+  for (unsigned long long v : h) sum += v;
+  *node_steps = (int64_t)sum;
+  return FIB_OK;
+}
+
+int fib_adaptive_points(fib_t* c, uint8_t* active, int64_t n) {
+  if (int rc = check_ctx(c)) return rc;
+  if (n != c->n_total || (n > 0 && !active)) return fail(FIB_EINVAL, "expected %lld values",
+                                                         (long long)c->n_total);
+  if (!c->d_pt) return fail(FIB_ESTATE, "adaptive computation was never enabled");
+  if (n == 0) return FIB_OK;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(active, c->d_pt + (size_t)c->adapt_par * c->n_total, (size_t)n,
+                    hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) active[i] = (active[i] & fib::PT_ACTIVE) ? 1 : 0;
   return FIB_OK;
 }
 

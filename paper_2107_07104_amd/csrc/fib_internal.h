@@ -29,6 +29,16 @@ constexpr int SLOT_STIM_SHIFT = 3;
 
 constexpr int MAX_STATES = 64;
 
+// Point flags of the adaptive computation, one byte per node and step:
+//   PT_SOLVE:  the node is solved in this step (set by the start kernel,
+//              consumed by the finish kernel of a Strang step);
+//   PT_ACTIVE: the last equilibrium check found the node active.
+constexpr uint8_t PT_SOLVE = 1u;
+constexpr uint8_t PT_ACTIVE = 2u;
+// Counters of solved node-steps (spread over addresses to keep the atomics
+// apart).
+constexpr int kAdaptCounters = 256;
+
 // Everything a kernel launch needs, passed by value.
 struct KArgs {
   float* state;             // SoA [S][n_total]
@@ -55,10 +65,20 @@ struct KArgs {
   int32_t pcr_levels;       // reduced-system PCR levels
   float dt;                 // split step (ms)
   float tau;                // reaction substep (ms)
-  float r;                  // c * dt_cn / h^2 with c = sigma / (Am Cm): explicit part
-  float r_mat;              // 2 theta r: the implicit matrix I - theta dt_cn L
+  float r_mat;              // 2 theta c dt_cn / h^2 with c = sigma / (Am Cm): the row
+                            // weights of the matrix I - theta dt_cn L
+  float rhs;                // 1 / theta: dt_cn L V from the matrix's row weights
   float inv_cm;             // 1 / Cm
   float v_th;               // activation threshold (mV)
+  // adaptive computation (split schedule; all null when off)
+  const int32_t* node_fiber;      // [n_total] fiber of each node
+  const int32_t* fiber_first_on;  // [n_fibers] first split step with a stimulus entry on
+  const uint8_t* pt_prev;         // [n_total] point flags after the previous step
+  uint8_t* pt_cur;                // [n_total] point flags of this step
+  uint8_t* fiber_any;             // [n_fibers] 1: a node of the fiber is solved in this step
+  uint8_t* fiber_any_next;        // [n_fibers] flags of the next step (cleared by the diffusion)
+  unsigned long long* adapt_count;// [kAdaptCounters] solved node-steps
+  float adapt_tol;                // relative change of an active point
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
@@ -69,6 +89,13 @@ __device__ __forceinline__ bool stim_on(const StimDev& e, int32_t n) {
   if (k < 0) return false;
   if (e.period > 0) k = k % e.period;
   return k < e.dur;
+}
+
+// Whether stimulus entry `sid1 - 1` (0: none), of either kind, is on during
+// split step n.
+__device__ __forceinline__ bool stim_any_on(uint32_t sid1, const StimDev* __restrict__ tab,
+                                            int32_t n) {
+  return sid1 != 0 && stim_on(tab[sid1 - 1], n);
 }
 
 // Current of stimulus entry `sid1 - 1` (0: none) during split step n
@@ -111,6 +138,16 @@ hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, co
 // that order).
 hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,
                         hipStream_t s);
+// Adaptive computation, split schedule.  Start of split step `step`: the
+// observables of step - 1 if observe_prev, the points to solve (from the
+// flags of the previous step and the stimulus), their V_m prescriptions and
+// the reaction part before the diffusion; with Godunov splitting (the
+// step's only reaction part) also their equilibrium check.
+hipError_t launch_adapt_start(int model, bool godunov, int32_t step, bool observe_prev,
+                              const KArgs& a, hipStream_t s);
+// End of Strang split step `step`: the second reaction half and the
+// equilibrium check of the solved points, then the observables.
+hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);

@@ -148,11 +148,13 @@ __device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, flo
 //   (I - dt/2 L) V+ = (I + dt/2 L) V,  L = c M_L^{-1} K,
 // for the whole bin.  V may hold V_m or V_m minus any constant (the step
 // commutes with adding a constant).  All threads of the workgroup must call
-// it.
+// it.  Bit q of `live` clear zeroes slot q's right-hand side: a fiber whose
+// slots are all cleared keeps its V exactly (the matrix is block diagonal
+// per fiber and every coupling across a fiber end is an exact zero).
 template <int K>
 __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K], float r,
-                                         const CNConst<K>& cc, float* lds, int T, int t,
-                                         int levels) {
+                                         float rhs, const CNConst<K>& cc, float* lds, int T,
+                                         int t, int levels, uint32_t live) {
   float* s_vf = lds;
   float* s_vl = lds + T;
   float* s_y0 = lds + 2 * T;
@@ -163,7 +165,8 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
 
   // Increment form: with A = I - theta dt L the step
   // V+ = A^{-1} (I + (1 - theta) dt L) V equals V + d where A d = dt L V
-  // (cc holds the factors of A; `r` gives dt L).  The right-hand side is built from
+  // (cc holds the factors of A, whose row weights `r` also give dt L: times
+  // rhs = 1 / theta).  The right-hand side is built from
   // neighbour differences, so a constant field gives d = 0 exactly and the
   // rounding error of the solve scales with the increment, not with |V|.
   s_vf[t] = V[0];
@@ -178,9 +181,11 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
     const float rr = (q == K - 1) ? vright : V[q == K - 1 ? K - 1 : q + 1];
     float wl, wr;
     row_weights(info[q], r, wl, wr);
-    // dt L V = 2 (wl (V_l - V) + wr (V_r - V)); a zero weight removes the
-    // (possibly unrelated) neighbour value exactly
-    b[q] = 2.0f * fmaf(wl, l - V[q], wr * (rr - V[q]));
+    // dt L V = (wl (V_l - V) + wr (V_r - V)) / theta with the matrix's
+    // weights (theta dt L); a zero weight removes the (possibly unrelated)
+    // neighbour value exactly
+    b[q] = rhs * fmaf(wl, l - V[q], wr * (rr - V[q]));
+    if (!((live >> q) & 1u)) b[q] = 0.0f;
   }
   // interior solve with the right-hand side only
   float y[K - 1];
@@ -271,7 +276,8 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
       float V[K];
 #pragma unroll
       for (int q = 0; q < K; ++q) V[q] = y[q].V;
-      for (int c = 0; c < A.n_cn; ++c) cn_solve<K>(V, info, A.r, cc, lds, T, t, A.pcr_levels);
+      for (int c = 0; c < A.n_cn; ++c)
+        cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, ~0u);
 #pragma unroll
       for (int q = 0; q < K; ++q) y[q].V = V[q];
     }
@@ -331,15 +337,24 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
   uint32_t info[K];
   int32_t gi[K];
   float V[K];
+  uint32_t live = ~0u;  // adaptive computation: slots of fibers with a solved node
+  if (A.fiber_any) live = 0u;
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     info[q] = A.slot_info[base + q];
     gi[q] = A.slot_gidx[base + q];
     V[q] = gi[q] >= 0 ? A.state[gi[q]] : 0.0f;
+    if (A.fiber_any && gi[q] >= 0) {
+      const int32_t f = A.node_fiber[gi[q]];
+      if (A.fiber_any[f]) live |= 1u << q;
+      // the fiber's first node clears its flag for the step after next
+      if (!(info[q] & SLOT_L)) A.fiber_any_next[f] = 0;
+    }
   }
   CNConst<K> cc;
   cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);
-  for (int c = 0; c < A.n_cn; ++c) cn_solve<K>(V, info, A.r, cc, lds, T, t, A.pcr_levels);
+  for (int c = 0; c < A.n_cn; ++c)
+    cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
 #pragma unroll
   for (int q = 0; q < K; ++q)
     if (gi[q] >= 0) A.state[gi[q]] = V[q];
@@ -380,6 +395,22 @@ struct ModelST57 {
 // reaction of step n.
 constexpr int REACT_A = 1, REACT_OBSERVE = 2, REACT_B = 4;
 
+// Observables at the end of split step `step` for node i with V_m offset
+// v1: activation time from v_prev, the V_m sample of sample steps, then
+// v_prev := v1.
+__device__ __forceinline__ void observe_step(const KArgs& A, int64_t i, int32_t step, float v1) {
+  const float v0 = A.v_prev[i];
+  const float uth = A.v_th - A.rest[0];
+  if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
+    A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
+  if (A.sample_every > 0 && ((int64_t)step + 1) % A.sample_every == 0) {
+    const int64_t row = ((int64_t)step + 1) / A.sample_every - 1 - A.sample_row0;
+    A.samples[row * A.n_total + i] = v1 + A.rest[0];
+  }
+  A.v_prev[i] = v1;
+  if (!isfinite(v1)) atomicOr(A.flag, 1);
+}
+
 template <class M>
 __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t step_b,
                                                int flags) {
@@ -394,19 +425,7 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
     const float I = stim_current(sid, A.stim, step_a);
     for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
   }
-  if (flags & REACT_OBSERVE) {
-    const float v1 = u[0];
-    const float v0 = A.v_prev[i];
-    const float uth = A.v_th - A.rest[0];
-    if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
-      A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step_a * A.dt);
-    if (A.sample_every > 0 && ((int64_t)step_a + 1) % A.sample_every == 0) {
-      const int64_t row = ((int64_t)step_a + 1) / A.sample_every - 1 - A.sample_row0;
-      A.samples[row * nt + i] = v1 + A.rest[0];
-    }
-    A.v_prev[i] = v1;
-    if (!isfinite(v1)) atomicOr(A.flag, 1);
-  }
+  if (flags & REACT_OBSERVE) observe_step(A, i, step_a, u[0]);
   if (flags & REACT_B) {
     float I, vp;
     if (stim_eval(sid, A.stim, step_b, I, vp)) u[0] = vp;
@@ -414,6 +433,103 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
   }
 #pragma unroll
   for (int k = 0; k < M::S; ++k) A.state[k * nt + i] = u[k];
+}
+
+// ---------------------------------------------------------------------------
+// Adaptive computation (split schedule), one node per thread
+// ---------------------------------------------------------------------------
+
+// Equilibrium check: the relative change |y_k+ - y_k| > tol |y_k| of any
+// state over the reaction part (y = offset + rest).
+template <int S>
+__device__ __forceinline__ bool point_moved(const float (&u)[S], const float (&b)[S],
+                                            const float* rest, float tol) {
+  bool m = false;
+#pragma unroll
+  for (int k = 0; k < S; ++k) m |= fabsf(u[k] - b[k]) > tol * fabsf(b[k] + rest[k]);
+  return m;
+}
+
+// Start of split step `step`.  A node of a fiber that takes part (step at or
+// after the fiber's first stimulus) is solved if the last check found it or
+// a neighbour in its fiber active, or a stimulus entry covers it or a
+// neighbour; nodes of fibers left out carry their flags.  Every wave adds
+// its solved nodes to one of the counters.
+template <class M, bool GODUNOV>
+__global__ __launch_bounds__(256) void k_adapt_start(KArgs A, int32_t step, int observe_prev) {
+  constexpr int S = M::S;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = A.n_total;
+  const bool real = i < nt;
+  bool solve = false, on = false;
+  int32_t f = 0;
+  if (real) {
+    if (observe_prev) observe_step(A, i, step - 1, A.state[i]);
+    f = A.node_fiber[i];
+    on = step >= A.fiber_first_on[f];
+    if (on) {
+      solve = (A.pt_prev[i] & PT_ACTIVE) || stim_any_on((uint32_t)A.node_stim[i], A.stim, step);
+      if (i > 0 && A.node_fiber[i - 1] == f)
+        solve = solve || (A.pt_prev[i - 1] & PT_ACTIVE) ||
+                stim_any_on((uint32_t)A.node_stim[i - 1], A.stim, step);
+      if (i + 1 < nt && A.node_fiber[i + 1] == f)
+        solve = solve || (A.pt_prev[i + 1] & PT_ACTIVE) ||
+                stim_any_on((uint32_t)A.node_stim[i + 1], A.stim, step);
+    } else {
+      A.pt_cur[i] = A.pt_prev[i];
+    }
+  }
+  const uint64_t mask = __ballot(solve);
+  if ((threadIdx.x & 63) == 0 && mask)
+    atomicAdd(&A.adapt_count[blockIdx.x % kAdaptCounters], (unsigned long long)__popcll(mask));
+  if (!real || !on) return;
+  if (!solve) {
+    A.pt_cur[i] = 0;
+    return;
+  }
+  A.fiber_any[f] = 1;
+  float u[S];
+#pragma unroll
+  for (int k = 0; k < S; ++k) u[k] = A.state[k * nt + i];
+  float I, vp;
+  if (stim_eval((uint32_t)A.node_stim[i], A.stim, step, I, vp)) u[0] = vp;
+  if (GODUNOV) {
+    float b[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) b[k] = u[k];
+    for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+    A.pt_cur[i] = point_moved<S>(u, b, A.rest, A.adapt_tol) ? PT_ACTIVE : 0;
+  } else {
+    for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+    A.pt_cur[i] = PT_SOLVE;
+  }
+#pragma unroll
+  for (int k = 0; k < S; ++k) A.state[k * nt + i] = u[k];
+}
+
+// End of Strang split step `step`: second reaction half and equilibrium
+// check of the nodes solved in the step, observables of every node.
+template <class M>
+__global__ __launch_bounds__(256) void k_adapt_finish(KArgs A, int32_t step) {
+  constexpr int S = M::S;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nt = A.n_total;
+  if (i >= nt) return;
+  float v1;
+  if (A.pt_cur[i] & PT_SOLVE) {
+    float u[S], b[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) b[k] = u[k] = A.state[k * nt + i];
+    const float I = stim_current((uint32_t)A.node_stim[i], A.stim, step);
+    for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+    A.pt_cur[i] = point_moved<S>(u, b, A.rest, A.adapt_tol) ? PT_ACTIVE : 0;
+#pragma unroll
+    for (int k = 0; k < S; ++k) A.state[k * nt + i] = u[k];
+    v1 = u[0];
+  } else {
+    v1 = A.state[i];
+  }
+  observe_step(A, i, step, v1);
 }
 
 // ---------------------------------------------------------------------------
@@ -518,6 +634,37 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
     hipLaunchKernelGGL(k_react<ModelHH>, grid, block, 0, s, a, step_a, step_b, flags);
   else if (model == 1)
     hipLaunchKernelGGL(k_react<ModelST57>, grid, block, 0, s, a, step_a, step_b, flags);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <class M>
+static hipError_t adapt_start_for(bool godunov, int32_t step, bool observe_prev, const KArgs& a,
+                                  hipStream_t s) {
+  const dim3 grid(blocks_for(a.n_total, 256)), block(256);
+  if (godunov)
+    hipLaunchKernelGGL((k_adapt_start<M, true>), grid, block, 0, s, a, step, observe_prev ? 1 : 0);
+  else
+    hipLaunchKernelGGL((k_adapt_start<M, false>), grid, block, 0, s, a, step, observe_prev ? 1 : 0);
+  return hipGetLastError();
+}
+
+hipError_t launch_adapt_start(int model, bool godunov, int32_t step, bool observe_prev,
+                              const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  if (model == 0) return adapt_start_for<ModelHH>(godunov, step, observe_prev, a, s);
+  if (model == 1) return adapt_start_for<ModelST57>(godunov, step, observe_prev, a, s);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  const dim3 grid(blocks_for(a.n_total, 256)), block(256);
+  if (model == 0)
+    hipLaunchKernelGGL(k_adapt_finish<ModelHH>, grid, block, 0, s, a, step);
+  else if (model == 1)
+    hipLaunchKernelGGL(k_adapt_finish<ModelST57>, grid, block, 0, s, a, step);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -51,7 +51,8 @@ EXPORTS = (
     "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
     "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate",
-    "fib_surrogate_predict", "fib_autotune",
+    "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
+    "fib_adaptive_points",
 )
 
 
@@ -131,6 +132,9 @@ def lib():
             "fib_step_surrogate": ([_vp, C.c_int64], C.c_int),
             "fib_surrogate_predict": ([_vp, C.c_int64, _vp], C.c_int),
             "fib_surrogate_last_fallbacks": ([_vp, C.POINTER(C.c_int64)], C.c_int),
+            "fib_set_adaptive": ([_vp, C.c_double], C.c_int),
+            "fib_adaptive_solved": ([_vp, C.POINTER(C.c_int64)], C.c_int),
+            "fib_adaptive_points": ([_vp, _vp, C.c_int64], C.c_int),
         })
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -251,6 +255,23 @@ def fib_get_tact(ctx) -> np.ndarray:
     t = np.zeros(n, dtype=np.float32)
     _check(lib().fib_get_tact(_vp(ctx), t.ctypes.data_as(_fp), n))
     return t
+
+
+def fib_set_adaptive(ctx, tol: float) -> None:
+    _check(lib().fib_set_adaptive(_vp(ctx), float(tol)))
+
+
+def fib_adaptive_solved(ctx) -> int:
+    n = C.c_int64(0)
+    _check(lib().fib_adaptive_solved(_vp(ctx), C.byref(n)))
+    return int(n.value)
+
+
+def fib_adaptive_points(ctx) -> np.ndarray:
+    n = fib_n_total(ctx)
+    a = np.zeros(max(n, 1), dtype=np.uint8)
+    _check(lib().fib_adaptive_points(_vp(ctx), a.ctypes.data_as(_vp), n))
+    return a[:n]
 
 
 def fib_reset_observables(ctx) -> None:
@@ -527,3 +548,13 @@ class Solver:
 
     def last_fallbacks(self):
         return fib_surrogate_last_fallbacks(self.ctx)
+
+    def set_adaptive(self, tol):
+        """Adaptive computation with relative tolerance tol (0: off)."""
+        fib_set_adaptive(self.ctx, tol)
+
+    def adaptive_solved(self):
+        return fib_adaptive_solved(self.ctx)
+
+    def adaptive_points(self):
+        return fib_adaptive_points(self.ctx)
