@@ -32,6 +32,18 @@ For each: node-steps/s of the plain path(s) and of the surrogate path over
 the same run, the V_m / activation-time differences between them, the
 rejected (fallback) share, and the FP64 oracle's V_m / activation-time
 errors of the surrogate run on sampled fibers.
+
+`adaptive` (skipped with --no-adaptive) compares the plain paths with the
+adaptive computation of the subcellular model (relative tolerance
+--adapt-tol) from an equilibrium start -- the scheme's premise: the same
+fibers and stimuli without the initial noise --
+  hh:   the 1369-fiber bundle above, 20 ms: plain fused vs adaptive (split);
+  st57: 400 x 1481 ST57 nodes, stimuli in [0, 2] ms, 5 ms: plain split vs
+        adaptive.
+Reported: node-steps/s over all node-steps of the run, the share of
+node-steps the adaptive run solved, and the FP64 oracle's V_m /
+activation-time errors of the adaptive run on sampled fibers (against the
+plain method).
 """
 from __future__ import annotations
 
@@ -85,6 +97,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-train-steps", type=int, default=20000)
     ap.add_argument("--sur-tol", type=float, default=1e-2)
+    ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--adapt-tol", type=float, default=1e-6)
     ap.add_argument("--st57-ms", type=float, default=1.0,
                     help="simulated ms of the large ST57 bundle timed per path")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -368,6 +382,63 @@ def surrogate_st57(args):
                 roofline=roofline)
 
 
+def adaptive_bench(args):
+    """Plain vs adaptive computation from an equilibrium start (see the
+    module docstring)."""
+    from dataclasses import replace
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+    from oracle import oracle as O
+    out = {}
+    cases = (
+        ("hh", replace(I.batched_hh(t_end=args.t_end), rel_noise=None),
+         (("plain_fused", F.FIB_SCHED_FUSED, 0.0), ("adaptive", F.FIB_SCHED_SPLIT, args.adapt_tol)),
+         [0, 1, 2, 3]),
+        ("st57", I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0, host_noise=False),
+         (("plain_split", F.FIB_SCHED_SPLIT, 0.0), ("adaptive", F.FIB_SCHED_SPLIT, args.adapt_tol)),
+         [0, 1]),
+    )
+    for name, w, paths, fibers in cases:
+        w = replace(w, vm_noise=np.zeros_like(w.vm_noise))
+        res = {}
+        runs = {}
+        for path, sched, tol in paths:
+            s = F.Solver(w.n_nodes, model=w.model, schedule=sched, Cm=w.Cm, Am=w.Am,
+                         sigma=w.sigma, h=w.h, dt_0D=w.dt_0D, dt_1D=w.dt_1D,
+                         dt_split=w.dt_split, v_th=w.v_th)
+            s.set_stimulus(w.stims)
+            if tol > 0.0:
+                s.set_adaptive(tol)
+            elif sched == F.FIB_SCHED_FUSED:
+                s.init_state()
+                s.autotune(trial_steps=200, max_candidates=8)
+            _timed_run(s, w.with_steps(50), lambda: s.init_state(), w.sample_every)
+            before = s.adaptive_solved() if tol > 0.0 else 0
+            secs, smp, ta = _timed_run(s, w, lambda: s.init_state(), w.sample_every)
+            runs[path] = (smp, ta)
+            res[path] = dict(value=w.node_steps() / secs, seconds=secs)
+            if tol > 0.0:
+                res[path]["tol"] = tol
+                res[path]["solved_share"] = (s.adaptive_solved() - before) / w.node_steps()
+            s.close()
+            _log(f"adaptive {name} {path}: {res[path]['value']:.3e} node-steps/s "
+                 f"{res[path].get('solved_share', '')}")
+        (p0, (sp, tp)), (p1, (sa, ta)) = runs.items()
+        off = w.offsets
+        cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+        y0 = np.tile(O.rest_state(w.model)[:, None], (1, len(cols)))
+        parity = _oracle_parity(w, fibers, y0, sa, ta, w.n_steps)
+        out[name] = dict(workload=f"{w.name}, equilibrium start", fibers=int(len(w.n_nodes)),
+                         nodes=int(w.n_total), split_steps=int(w.n_steps),
+                         dt_split_ms=w.dt_split, **res,
+                         adaptive_over_plain=res["adaptive"]["value"] / res[p0]["value"],
+                         adaptive_vs_plain=_compare(sp, tp, sa, ta, w.dt_split,
+                                                    w.n_steps * w.dt_split),
+                         adaptive_vs_oracle_plain=parity)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -467,10 +538,14 @@ def main():
               file=sys.stderr, flush=True)
 
     sur = None
-    if not args.no_surrogate:
+    adapt = None
+    if not args.no_surrogate or not args.no_adaptive:
         s.close()
         s = None
+    if not args.no_surrogate:
         sur = {"hh": surrogate_hh(args), "st57": surrogate_st57(args)}
+    if not args.no_adaptive:
+        adapt = adaptive_bench(args)
 
     out = {
         "metric": METRIC,
@@ -494,6 +569,7 @@ def main():
         "cpu_baseline": cpu,
         "parity_vs_oracle": parity,
         "surrogate": sur,
+        "adaptive": adapt,
     }
     if s is not None:
         s.close()
