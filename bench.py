@@ -37,9 +37,11 @@ errors of the surrogate run on sampled fibers.
 adaptive computation of the subcellular model (relative tolerance
 --adapt-tol) from an equilibrium start -- the scheme's premise: the same
 fibers and stimuli without the initial noise --
-  hh:   the 1369-fiber bundle above, 20 ms: plain fused vs adaptive (split);
+  hh:   the 1369-fiber bundle above, 20 ms: plain fused vs adaptive in the
+        fused kernel (states in LDS, solved nodes compacted per step) and in
+        the split schedule;
   st57: 400 x 1481 ST57 nodes, stimuli in [0, 2] ms, 5 ms: plain split vs
-        adaptive.
+        adaptive (split).
 Reported: node-steps/s over all node-steps of the run, the share of
 node-steps the adaptive run solved, and the FP64 oracle's V_m /
 activation-time errors of the adaptive run on sampled fibers (against the
@@ -393,7 +395,8 @@ def adaptive_bench(args):
     out = {}
     cases = (
         ("hh", replace(I.batched_hh(t_end=args.t_end), rel_noise=None),
-         (("plain_fused", F.FIB_SCHED_FUSED, 0.0), ("adaptive", F.FIB_SCHED_SPLIT, args.adapt_tol)),
+         (("plain_fused", F.FIB_SCHED_FUSED, 0.0), ("adaptive", F.FIB_SCHED_FUSED, args.adapt_tol),
+          ("adaptive_split", F.FIB_SCHED_SPLIT, args.adapt_tol)),
          [0, 1, 2, 3]),
         ("st57", I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0, host_noise=False),
          (("plain_split", F.FIB_SCHED_SPLIT, 0.0), ("adaptive", F.FIB_SCHED_SPLIT, args.adapt_tol)),
@@ -408,23 +411,25 @@ def adaptive_bench(args):
                          sigma=w.sigma, h=w.h, dt_0D=w.dt_0D, dt_1D=w.dt_1D,
                          dt_split=w.dt_split, v_th=w.v_th)
             s.set_stimulus(w.stims)
-            if tol > 0.0:
-                s.set_adaptive(tol)
-            elif sched == F.FIB_SCHED_FUSED:
+            if sched == F.FIB_SCHED_FUSED:
                 s.init_state()
                 s.autotune(trial_steps=200, max_candidates=8)
+            if tol > 0.0:
+                s.set_adaptive(tol)
             _timed_run(s, w.with_steps(50), lambda: s.init_state(), w.sample_every)
             before = s.adaptive_solved() if tol > 0.0 else 0
             secs, smp, ta = _timed_run(s, w, lambda: s.init_state(), w.sample_every)
             runs[path] = (smp, ta)
-            res[path] = dict(value=w.node_steps() / secs, seconds=secs)
+            res[path] = dict(value=w.node_steps() / secs, seconds=secs, plan=s.plan())
             if tol > 0.0:
                 res[path]["tol"] = tol
                 res[path]["solved_share"] = (s.adaptive_solved() - before) / w.node_steps()
             s.close()
             _log(f"adaptive {name} {path}: {res[path]['value']:.3e} node-steps/s "
                  f"{res[path].get('solved_share', '')}")
-        (p0, (sp, tp)), (p1, (sa, ta)) = runs.items()
+        p0 = paths[0][0]
+        sp, tp = runs[p0]
+        sa, ta = runs["adaptive"]
         off = w.offsets
         cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
         y0 = np.tile(O.rest_state(w.model)[:, None], (1, len(cols)))

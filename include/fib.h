@@ -242,10 +242,15 @@ int fib_run(fib_t* ctx, int64_t step0, int64_t n_steps, int64_t sample_every, fl
  * The check runs in FP32 on the device.  Enabling (or re-enabling) resets
  * every point to active, its initial state, and the solved-node counter to
  * zero; fib_init_state and fib_set_state reset the points too.  tol = 0
- * turns it off.  Split schedule only: FIB_EUNSUPPORTED with
- * FIB_SCHED_FUSED or an attached surrogate (AUTO takes the split schedule
- * while it is on).  fib_autotune times the plain schedule and leaves the
- * points alone.  Blocking. */
+ * turns it off.  Schedules: FUSED (Hodgkin-Huxley) runs a variant of the
+ * fused kernel that keeps each bin's states in LDS and compacts the solved
+ * nodes of every step; it takes plans with at most 64 fibers per bin whose
+ * states fit the LDS (fib_run returns FIB_EUNSUPPORTED otherwise).  SPLIT
+ * runs one start kernel, the diffusion and (Strang) one finish kernel per
+ * step, for both models.  AUTO takes the fused variant where it can, else
+ * the split schedule.  FIB_EUNSUPPORTED with an attached surrogate.
+ * fib_autotune times the plain schedule and leaves the points alone.
+ * Blocking. */
 int fib_set_adaptive(fib_t* ctx, double tol);
 
 /* Node-steps whose reaction was solved by adaptive runs since

@@ -287,6 +287,13 @@ struct fib_ctx {
   uint8_t* d_fiber_any = nullptr;      // [2][n_fibers] by step parity
   unsigned long long* d_adapt_count = nullptr;  // [kAdaptCounters]
   int adapt_par = 0;                   // parity of the buffer with the latest flags
+  // tables of the adaptive fused kernel, valid for plan / stimulus versions
+  uint8_t* d_slot_fiber = nullptr;     // [groups * cap] bin-local fiber of each slot
+  int32_t* d_bin_first_on = nullptr;   // [groups * kBinFibers]
+  size_t adapt_slots = 0, adapt_bins = 0;  // allocated sizes
+  uint64_t plan_version = 0, stim_version = 0;
+  uint64_t adapt_tables_plan = ~0ull, adapt_tables_stim = ~0ull;
+  bool adapt_fused_ok = false;
 };
 
 namespace {
@@ -447,6 +454,7 @@ void set_diffusion(const fib_ctx* c, double dt_cn, KArgs& a) {
 // Fills the slot tables and the PCR level count of the current shape
 // (groups, threads, K) and bins.
 void build_tables(fib_ctx* c) {
+  ++c->plan_version;
   c->cap = c->threads * c->K;
   const size_t nslots = (size_t)c->groups * c->cap;
   c->slot_gidx.assign(nslots, -1);
@@ -590,6 +598,83 @@ int adapt_reset_points(fib_ctx* c) {
   return FIB_OK;
 }
 
+// Tables of the adaptive fused kernel for the current plan and stimulus:
+// per slot the index of its fiber within the bin, per bin the first
+// stimulus step of each fiber.  *ok is false where the kernel cannot take
+// the plan (a bin with more than kBinFibers fibers, or not enough LDS).
+int adapt_fused_tables(fib_ctx* c, bool* ok) {
+  if (c->adapt_tables_plan == c->plan_version && c->adapt_tables_stim == c->stim_version) {
+    *ok = c->adapt_fused_ok;
+    return FIB_OK;
+  }
+  *ok = false;
+  c->adapt_fused_ok = false;
+  c->adapt_tables_plan = c->plan_version;
+  c->adapt_tables_stim = c->stim_version;
+  const size_t need = fib::lds_bytes_for(c->threads, c->levels) + fib::adapt_lds_extra(c->cap);
+  if (need > c->max_lds) return FIB_OK;
+  for (auto& b : c->bin_fibers)
+    if ((int)b.size() > fib::kBinFibers) return FIB_OK;
+  const size_t nslots = (size_t)c->groups * c->cap, nbins = (size_t)c->groups * fib::kBinFibers;
+  std::vector<uint8_t> fib_of(std::max<size_t>(nslots, 1), 0);
+  std::vector<int32_t> first(std::max<size_t>(nbins, 1), INT32_MAX);
+  for (int b = 0; b < c->groups; ++b) {
+    size_t pos = (size_t)b * c->cap;
+    for (size_t j = 0; j < c->bin_fibers[b].size(); ++j) {
+      const int32_t f = c->bin_fibers[b][j];
+      first[(size_t)b * fib::kBinFibers + j] = c->first_on[f];
+      for (int32_t i = 0; i < c->n_nodes[f]; ++i) fib_of[pos++] = (uint8_t)j;
+    }
+  }
+  if (c->adapt_slots < fib_of.size() || c->adapt_bins < first.size()) {
+    (void)hipFree(c->d_slot_fiber);
+    (void)hipFree(c->d_bin_first_on);
+    c->d_slot_fiber = nullptr;
+    c->d_bin_first_on = nullptr;
+    c->adapt_slots = c->adapt_bins = 0;
+    if (hipMalloc(&c->d_slot_fiber, fib_of.size()) != hipSuccess ||
+        hipMalloc(&c->d_bin_first_on, sizeof(int32_t) * first.size()) != hipSuccess) {
+      c->adapt_tables_plan = ~0ull;
+      return fail(FIB_ENOMEM, "device allocation failed");
+    }
+    c->adapt_slots = fib_of.size();
+    c->adapt_bins = first.size();
+  }
+  HIP_TRY(hipMemcpy(c->d_slot_fiber, fib_of.data(), fib_of.size(), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(c->d_bin_first_on, first.data(), sizeof(int32_t) * first.size(),
+                    hipMemcpyHostToDevice));
+  c->adapt_fused_ok = true;
+  *ok = true;
+  return FIB_OK;
+}
+
+// The point flags of step step0 - 1 must sit in buffer (step0 - 1) & 1.
+int adapt_align_flags(fib_ctx* c, int64_t step0) {
+  const int want = (int)((step0 + 1) & 1);
+  if (want != c->adapt_par)
+    HIP_TRY(hipMemcpyAsync(c->d_pt + want * c->n_total, c->d_pt + c->adapt_par * c->n_total,
+                           (size_t)c->n_total, hipMemcpyDeviceToDevice, c->stream));
+  c->adapt_par = want;
+  return FIB_OK;
+}
+
+// fib_run with adaptive computation in the fused kernel: one launch; the
+// point flags of step0 - 1 in, those of the last step out.
+int run_adaptive_fused(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
+  if (int rc = adapt_align_flags(c, step0)) return rc;
+  const int64_t end = step0 + n_steps;
+  a.pt_prev = c->d_pt + ((step0 + 1) & 1) * c->n_total;
+  a.pt_cur = c->d_pt + ((end - 1) & 1) * c->n_total;
+  a.adapt_count = c->d_adapt_count;
+  a.adapt_tol = (float)c->adapt_tol;
+  a.slot_fiber = c->d_slot_fiber;
+  a.bin_first_on = c->d_bin_first_on;
+  const size_t lds = fib::lds_bytes_for(c->threads, c->levels) + fib::adapt_lds_extra(c->cap);
+  HIP_TRY(fib::launch_run_fused_adaptive(c->K, c->groups, c->threads, lds, a, c->stream));
+  c->adapt_par = (int)((end - 1) & 1);
+  return FIB_OK;
+}
+
 // fib_run with adaptive computation (split schedule).  Per Strang step n:
 // start(n) [solve set, prescriptions, first half], diffusion(n) [fibers
 // with a solved node], finish(n) [second half, check, observables]; per
@@ -610,11 +695,7 @@ int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
     a.fiber_any = c->d_fiber_any + (n & 1) * nf;
     a.fiber_any_next = c->d_fiber_any + ((n + 1) & 1) * nf;
   };
-  // the flags of step step0 - 1 must sit in buffer (step0 - 1) & 1
-  const int want = (int)((step0 + 1) & 1);
-  if (want != c->adapt_par)
-    HIP_TRY(hipMemcpyAsync(c->d_pt + want * nt, c->d_pt + c->adapt_par * nt, (size_t)nt,
-                           hipMemcpyDeviceToDevice, c->stream));
+  if (int rc = adapt_align_flags(c, step0)) return rc;
   HIP_TRY(hipMemsetAsync(c->d_fiber_any, 0, 2 * (size_t)nf, c->stream));
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * nt, hipMemcpyDeviceToDevice,
                          c->stream));
@@ -817,6 +898,8 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_pt);
   (void)hipFree(c->d_fiber_any);
   (void)hipFree(c->d_adapt_count);
+  (void)hipFree(c->d_slot_fiber);
+  (void)hipFree(c->d_bin_first_on);
   delete c;
 }
 
@@ -936,6 +1019,7 @@ int fib_set_stimulus(fib_t* c, const fib_stim* s, int32_t n) {
   }
   c->n_stim = n;
   c->first_on = first_on;
+  ++c->stim_version;
   if (c->d_first_on && c->n_fibers > 0)
     HIP_TRY(hipMemcpy(c->d_first_on, first_on.data(), sizeof(int32_t) * c->n_fibers,
                       hipMemcpyHostToDevice));
@@ -1016,7 +1100,22 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   a.pcr_levels = c->levels;
   a.step0 = (int32_t)step0;
   a.n_steps = (int32_t)n_steps;
-  if (c->adapt_tol > 0.0) return run_adaptive(c, a, step0, n_steps);
+  if (c->adapt_tol > 0.0) {
+    // fused where the model and the plan allow it, else split
+    const bool want_fused = c->p.schedule == FIB_SCHED_FUSED ||
+                            (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH);
+    if (want_fused) {
+      if (c->p.model != FIB_MODEL_HH)
+        return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
+      bool ok = false;
+      if (int rc = adapt_fused_tables(c, &ok)) return rc;
+      if (ok) return run_adaptive_fused(c, a, step0, n_steps);
+      if (c->p.schedule == FIB_SCHED_FUSED)
+        return fail(FIB_EUNSUPPORTED, "the plan does not fit the adaptive fused kernel (at most "
+                    "%d fibers per bin, its states in LDS)", fib::kBinFibers);
+    }
+    return run_adaptive(c, a, step0, n_steps);
+  }
   // AUTO: fused for Hodgkin-Huxley unless a surrogate is attached (the
   // surrogate step belongs to the split schedule)
   const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
@@ -1337,8 +1436,6 @@ int fib_set_adaptive(fib_t* c, double tol) {
     c->adapt_tol = 0.0;
     return FIB_OK;
   }
-  if (c->p.schedule == FIB_SCHED_FUSED)
-    return fail(FIB_EUNSUPPORTED, "adaptive computation runs in the split schedule");
   if (c->sur_on)
     return fail(FIB_EUNSUPPORTED, "adaptive computation and the surrogate step do not combine");
   HIP_TRY(hipStreamSynchronize(c->stream));

@@ -38,6 +38,8 @@ constexpr uint8_t PT_ACTIVE = 2u;
 // Counters of solved node-steps (spread over addresses to keep the atomics
 // apart).
 constexpr int kAdaptCounters = 256;
+// Fibers a bin may hold for the fused kernel with adaptive computation.
+constexpr int kBinFibers = 64;
 
 // Everything a kernel launch needs, passed by value.
 struct KArgs {
@@ -79,6 +81,8 @@ struct KArgs {
   uint8_t* fiber_any_next;        // [n_fibers] flags of the next step (cleared by the diffusion)
   unsigned long long* adapt_count;// [kAdaptCounters] solved node-steps
   float adapt_tol;                // relative change of an active point
+  const uint8_t* slot_fiber;      // fused: [groups * cap] bin-local fiber of each slot
+  const int32_t* bin_first_on;    // fused: [groups * kBinFibers] first stimulus step
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
@@ -130,6 +134,10 @@ __device__ __forceinline__ bool stim_eval(uint32_t sid1, const StimDev* __restri
 int plan_max_threads(int K);
 hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds_bytes,
                             const KArgs& a, hipStream_t s);
+// Fused kernel with adaptive computation (Hodgkin-Huxley); lds_bytes =
+// lds_bytes_for(threads, levels) + adapt_lds_extra(cap).
+hipError_t launch_run_fused_adaptive(int K, int groups, int threads, size_t lds_bytes,
+                                     const KArgs& a, hipStream_t s);
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds_bytes, const KArgs& a,
                             hipStream_t s);
 // Reaction kernel with states in device memory; flags: 1 = reaction with the
@@ -157,6 +165,15 @@ hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t
 // `levels` PCR levels.
 inline size_t lds_bytes_for(int threads, int levels) {
   return sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
+}
+
+// LDS the adaptive fused kernel needs beyond the Crank-Nicolson region for
+// a bin of `cap` slots (a multiple of 64): the states (4 cap floats), the
+// compacted list of solved slots (cap uint16), the bin-local fiber of each
+// slot (cap bytes), the verdict bits (cap / 32 + 2 words), the per-fiber
+// flags of two steps, and two list lengths and two flags.
+inline size_t adapt_lds_extra(int cap) {
+  return (size_t)cap * (16 + 2 + 1) + 4 * ((size_t)cap / 32 + 2) + 2 * kBinFibers + 4 * 4;
 }
 
 }  // namespace fib

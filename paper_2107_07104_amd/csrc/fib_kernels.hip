@@ -325,6 +325,310 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
 }
 
 // ---------------------------------------------------------------------------
+// Fused persistent kernel with adaptive computation (Hodgkin-Huxley)
+// ---------------------------------------------------------------------------
+
+// Equilibrium check: the relative change |y_k+ - y_k| > tol |y_k| of any
+// state over the reaction part (y = offset + rest).
+template <int S>
+__device__ __forceinline__ bool point_moved(const float (&u)[S], const float (&b)[S],
+                                            const float* rest, float tol) {
+  bool m = false;
+#pragma unroll
+  for (int k = 0; k < S; ++k) m |= fabsf(u[k] - b[k]) > tol * fabsf(b[k] + rest[k]);
+  return m;
+}
+
+
+
+// The same split steps as k_run_hh with the adaptive computation of the
+// reaction: the bin's states live in LDS (offsets from rest, one row per
+// state) instead of the owners' registers, so that each step can compact the
+// slots it solves into a list that all threads share.  Per split step:
+//   1. each thread decides for its slots whether they are solved (the last
+//      check found the slot or a neighbour in its fiber active, or a
+//      stimulus covers one of them; fibers take part from their first
+//      stimulus on) with bit masks over a window of the bin's bit-packed
+//      verdicts, applies V_m prescriptions and flags the fibers that have a
+//      solved slot;
+//   2. one LDS atomic per wave reserves list positions for the solved slots
+//      (their order in the list does not matter: every slot is solved on
+//      its own) -- except slots with a stimulus current, which their owners
+//      solve themselves (a handful per fiber), so that the list carries no
+//      current;
+//   3. the first reaction part runs over the list, T slots at a time, and on
+//      the owners' current-stimulated slots (Godunov: the only part, with
+//      the equilibrium check);
+//   4. the owners run the diffusion on their slots, with a zero right-hand
+//      side on fibers without a solved slot (which keeps them exact);
+//   5. Strang: the second reaction half and the check, as in 3;
+//   6. the owners take the observables of their slots.
+// A bin with no slot to solve in a step skips 3-5: its diffusion would have
+// a zero right-hand side everywhere.  The point flags come from and go back
+// to device memory (one byte per node: PT_ACTIVE), as in the split schedule.
+template <int K, int MAXT>
+__global__ __launch_bounds__(MAXT) void k_run_hh_adapt(KArgs A) {
+  extern __shared__ float lds[];
+  const int T = blockDim.x;
+  const int t = threadIdx.x;
+  const int cap = A.cap;
+  const int64_t bslot = (int64_t)blockIdx.x * cap;  // the bin's first slot
+  const int s0 = t * K;                              // this thread's first slot in the bin
+  const int64_t nt = A.n_total;
+  float* s_y = lds + (size_t)T * (6 + 2 * A.pcr_levels);
+  uint16_t* s_list = reinterpret_cast<uint16_t*>(s_y + 4 * (size_t)cap);
+  uint8_t* s_fib = reinterpret_cast<uint8_t*>(s_list + cap);    // bin-local fiber per slot
+  uint32_t* s_act = reinterpret_cast<uint32_t*>(s_fib + cap);   // verdict bits, cap / 32 + 2 words
+  const int n_words = cap / 32 + 2;
+  uint8_t* s_fany = reinterpret_cast<uint8_t*>(s_act + n_words);  // [2][kBinFibers]
+  int32_t* s_cnt = reinterpret_cast<int32_t*>(s_fany + 2 * kBinFibers);  // [2] list lengths
+  int32_t* s_any = s_cnt + 2;                                            // [2] anything solved
+  const int lane = t & 63;
+  const int32_t* first_on = A.bin_first_on + (int64_t)blockIdx.x * kBinFibers;
+  constexpr uint32_t allK = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
+
+  for (int j = t; j < n_words; j += T) s_act[j] = 0u;
+  for (int j = t; j < kBinFibers; j += T) {
+    s_fany[j] = 0;
+    s_fany[kBinFibers + j] = 0;
+  }
+  if (t < 2) {
+    s_cnt[t] = 0;
+    s_any[t] = 0;
+  }
+  uint32_t info[K];
+  float vcur[K];        // V of each slot at the end of the previous step
+  uint32_t done = 0;    // slots that need no activation-time update
+  uint32_t act0 = 0;    // verdicts of the previous step (for the setup only)
+  uint32_t lmask = 0, rmask = 0, smask = 0;  // left / right neighbour in the fiber; stimulus entry
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int sl = s0 + q;
+    info[q] = A.slot_info[bslot + sl];
+    const int32_t g = A.slot_gidx[bslot + sl];
+    if (info[q] & SLOT_L) lmask |= 1u << q;
+    if (info[q] & SLOT_R) rmask |= 1u << q;
+    if (info[q] >> SLOT_STIM_SHIFT) smask |= 1u << q;
+    if (g >= 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s_y[k * cap + sl] = A.state[k * nt + g];
+      s_fib[sl] = A.slot_fiber[bslot + sl];
+      if (A.pt_prev[g] & PT_ACTIVE) act0 |= 1u << q;
+      if (!isinf(A.t_act[g])) done |= 1u << q;
+      vcur[q] = A.state[g];
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) s_y[k * cap + sl] = 0.0f;
+      s_fib[sl] = 0;
+      done |= 1u << q;
+      vcur[q] = 0.0f;
+    }
+  }
+  // slots of fibers that take part, and the next step at which one more of
+  // this thread's fibers joins (rare: recomputed then)
+  uint32_t onmask = 0;
+  int32_t next_on = INT32_MAX;
+  auto update_on = [&](int32_t n) {
+    onmask = 0;
+    next_on = INT32_MAX;
+    for (int q = 0; q < K; ++q) {
+      if (!(info[q] & SLOT_REAL)) continue;
+      const int32_t f1 = first_on[A.slot_fiber[bslot + s0 + q]];
+      if (n >= f1) onmask |= 1u << q;
+      else next_on = f1 < next_on ? f1 : next_on;
+    }
+  };
+  update_on(A.step0);
+  // stimulus entries of the slots next to this thread's first and last
+  const uint32_t sid_l = t > 0 ? (A.slot_info[bslot + s0 - 1] >> SLOT_STIM_SHIFT) : 0u;
+  const uint32_t sid_r = t + 1 < T ? (A.slot_info[bslot + s0 + K] >> SLOT_STIM_SHIFT) : 0u;
+  CNConst<K> cc;
+  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);  // its barriers order the clears above
+  for (uint32_t m = act0; m; m &= m - 1u) {
+    const int sl = s0 + __builtin_ctz(m);
+    atomicOr(&s_act[sl >> 5], 1u << (sl & 31));
+  }
+  __syncthreads();
+  const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
+
+  // verdict of slot sl into the bit array
+  auto set_verdict = [&](int sl, bool moved) {
+    const uint32_t bit = 1u << (sl & 31);
+    if (moved)
+      atomicOr(&s_act[sl >> 5], bit);
+    else
+      atomicAnd(&s_act[sl >> 5], ~bit);
+  };
+  // reaction part of n_s substeps on slot sl with current I; with `check`
+  // the equilibrium verdict goes to the bit array
+  auto react = [&](int sl, float I, int n_s, bool check) {
+    hh::State y{s_y[sl], s_y[cap + sl], s_y[2 * cap + sl], s_y[3 * cap + sl]};
+    const hh::State b = y;
+    for (int s = 0; s < n_s; ++s) hh::heun(y, I, A.tau, A.inv_cm, ref);
+    s_y[sl] = y.V;
+    s_y[cap + sl] = y.m;
+    s_y[2 * cap + sl] = y.h;
+    s_y[3 * cap + sl] = y.n;
+    if (check) {
+      const float u[4] = {y.V, y.m, y.h, y.n}, ub[4] = {b.V, b.m, b.h, b.n};
+      set_verdict(sl, point_moved<4>(u, ub, A.rest, A.adapt_tol));
+    }
+  };
+
+  const int32_t n_end = A.step0 + A.n_steps;
+  unsigned long long solved = 0;
+  for (int32_t n = A.step0; n < n_end; ++n) {
+    const int par = n & 1;
+    if (n >= next_on) update_on(n);
+    // 1. slots to solve: a window of verdict bits from slot s0 - 1 to s0 + K
+    uint32_t solve, cur = 0;  // cur: solved slots with a stimulus current
+    {
+      uint64_t win;
+      if (t > 0) {
+        const int w = (s0 - 1) >> 5;
+        win = ((uint64_t)s_act[w] | ((uint64_t)s_act[w + 1] << 32)) >> ((s0 - 1) & 31);
+      } else {
+        win = ((uint64_t)s_act[0] | ((uint64_t)s_act[1] << 32)) << 1;
+      }
+      uint32_t hot = (uint32_t)(win >> 1) & allK;  // active, or stimulated now
+      for (uint32_t m = smask; m; m &= m - 1u) {
+        const int q = __builtin_ctz(m);
+        if (stim_any_on(A.slot_info[bslot + s0 + q] >> SLOT_STIM_SHIFT, A.stim, n)) hot |= 1u << q;
+      }
+      const uint32_t hot_l = t > 0 && ((win & 1u) || stim_any_on(sid_l, A.stim, n)) ? 1u : 0u;
+      const uint32_t hot_r =
+          t + 1 < T && (((win >> (K + 1)) & 1u) || stim_any_on(sid_r, A.stim, n)) ? 1u : 0u;
+      const uint32_t hw = hot_l | (hot << 1) | (hot_r << (K + 1));  // bit q + 1: slot q
+      solve = onmask & (hot | (hw & lmask) | ((hw >> 2) & rmask));
+      // prescriptions and currents of the solved stimulated slots
+      for (uint32_t m = solve & smask; m; m &= m - 1u) {
+        const int q = __builtin_ctz(m);
+        float I, vp;
+        if (stim_eval(A.slot_info[bslot + s0 + q] >> SLOT_STIM_SHIFT, A.stim, n, I, vp))
+          s_y[s0 + q] = vp;
+        if (I != 0.0f) cur |= 1u << q;
+      }
+      // one flag per fiber run of solved slots (a fiber starts at a slot
+      // without a left neighbour)
+      const uint32_t starts = ~lmask & allK;
+      for (uint32_t m = solve; m;) {
+        const int q = __builtin_ctz(m);
+        s_fany[par * kBinFibers + s_fib[s0 + q]] = 1;
+        const uint32_t later = starts & ~((2u << q) - 1u);  // fiber starts after q
+        m &= later ? ~((1u << __builtin_ctz(later)) - 1u) : 0u;
+      }
+    }
+    // 2. list positions: a wave-level prefix of the counts from one ballot
+    // per bit of the count, and one LDS atomic per wave
+    const uint32_t listed = solve & ~cur;
+    const int cnt = __popc(listed);
+    solved += (unsigned)__popc(solve);
+    const uint64_t below = (1ull << lane) - 1ull;
+    int excl = 0, wave_total = 0;
+#pragma unroll
+    for (int b = 0; (1 << b) <= K; ++b) {
+      const uint64_t bits = __ballot((cnt >> b) & 1);
+      excl += __popcll(bits & below) << b;
+      wave_total += __popcll(bits) << b;
+    }
+    int base = 0;
+    if (lane == 0 && wave_total > 0) base = atomicAdd(&s_cnt[par], wave_total);
+    base = __builtin_amdgcn_readfirstlane(base);
+    int pos = base + excl;
+    for (uint32_t m = listed; m; m &= m - 1u) s_list[pos++] = (uint16_t)(s0 + __builtin_ctz(m));
+    if (solve) s_any[par] = 1;
+    // the other parity's counters and fiber flags were last read in the
+    // previous step; clear them for the next one
+    if (t == 0) {
+      s_cnt[par ^ 1] = 0;
+      s_any[par ^ 1] = 0;
+    }
+    for (int j = t; j < kBinFibers; j += T) s_fany[(par ^ 1) * kBinFibers + j] = 0;
+    __syncthreads();
+    const int total = s_cnt[par];
+
+    if (s_any[par]) {
+      uint32_t live = 0;  // slots of fibers with a solved slot
+#pragma unroll
+      for (int q = 0; q < K; ++q)
+        if (s_fany[par * kBinFibers + s_fib[s0 + q]]) live |= 1u << q;
+      // 3. first reaction part (Godunov: the only one, checked)
+      const bool check_first = A.n_sub2 == 0;
+      for (int j = t; j < total; j += T) react(s_list[j], 0.0f, A.n_sub, check_first);
+      for (uint32_t m = cur; m; m &= m - 1u) {
+        const int sl = s0 + __builtin_ctz(m);
+        react(sl, stim_current(A.slot_info[bslot + sl] >> SLOT_STIM_SHIFT, A.stim, n), A.n_sub,
+              check_first);
+      }
+      __syncthreads();
+      // 4. diffusion on the fibers with a solved slot
+      {
+        float V[K];
+#pragma unroll
+        for (int q = 0; q < K; ++q) V[q] = s_y[s0 + q];
+        for (int c = 0; c < A.n_cn; ++c)
+          cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
+#pragma unroll
+        for (int q = 0; q < K; ++q) s_y[s0 + q] = V[q];
+      }
+      __syncthreads();
+      // 5. Strang: second reaction half and the equilibrium check
+      if (!check_first) {
+        for (int j = t; j < total; j += T) react(s_list[j], 0.0f, A.n_sub2, true);
+        for (uint32_t m = cur; m; m &= m - 1u) {
+          const int sl = s0 + __builtin_ctz(m);
+          react(sl, stim_current(A.slot_info[bslot + sl] >> SLOT_STIM_SHIFT, A.stim, n), A.n_sub2,
+                true);
+        }
+        __syncthreads();
+      }
+    }
+
+    // 6. observables of this thread's slots
+    {
+      const float t0 = (float)n * A.dt;
+      const float uth = A.v_th - A.rest[0];
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const float v1 = s_y[s0 + q];
+        if (!((done >> q) & 1u) && vcur[q] < uth && v1 >= uth) {
+          const int32_t g = A.slot_gidx[bslot + s0 + q];
+          A.t_act[g] = fmaf(A.dt, (uth - vcur[q]) / (v1 - vcur[q]), t0);
+          done |= 1u << q;
+        }
+        vcur[q] = v1;
+      }
+    }
+    if (A.sample_every > 0 && ((int64_t)n + 1) % A.sample_every == 0) {
+      const int64_t row = ((int64_t)n + 1) / A.sample_every - 1 - A.sample_row0;
+#pragma unroll
+      for (int q = 0; q < K; ++q) {
+        const int32_t g = A.slot_gidx[bslot + s0 + q];
+        if (g >= 0) A.samples[row * nt + g] = vcur[q] + A.rest[0];
+      }
+    }
+  }
+
+  bool bad = false;
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const int sl = s0 + q;
+    const int32_t g = A.slot_gidx[bslot + sl];
+    if (g >= 0) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const float v = s_y[k * cap + sl];
+        A.state[k * nt + g] = v;
+        bad |= !isfinite(v);
+      }
+      A.pt_cur[g] = ((s_act[sl >> 5] >> (sl & 31)) & 1u) ? PT_ACTIVE : 0;
+    }
+  }
+  if (bad) atomicOr(A.flag, 1);
+  if (solved) atomicAdd(&A.adapt_count[blockIdx.x % kAdaptCounters], solved);
+}
+
+// ---------------------------------------------------------------------------
 // Diffusion only (states in device memory)
 // ---------------------------------------------------------------------------
 
@@ -438,17 +742,6 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
 // ---------------------------------------------------------------------------
 // Adaptive computation (split schedule), one node per thread
 // ---------------------------------------------------------------------------
-
-// Equilibrium check: the relative change |y_k+ - y_k| > tol |y_k| of any
-// state over the reaction part (y = offset + rest).
-template <int S>
-__device__ __forceinline__ bool point_moved(const float (&u)[S], const float (&b)[S],
-                                            const float* rest, float tol) {
-  bool m = false;
-#pragma unroll
-  for (int k = 0; k < S; ++k) m |= fabsf(u[k] - b[k]) > tol * fabsf(b[k] + rest[k]);
-  return m;
-}
 
 // Start of split step `step`.  A node of a fiber that takes part (step at or
 // after the fiber's first stimulus) is solved if the last check found it or
@@ -608,6 +901,14 @@ struct FusedLaunch {
 };
 
 template <int K, int MAXT>
+struct FusedAdaptLaunch {
+  static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_run_hh_adapt<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int K, int MAXT>
 struct DiffusionLaunch {
   static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
     hipLaunchKernelGGL((k_diffusion<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
@@ -619,6 +920,11 @@ hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t ld
                             const KArgs& a, hipStream_t s) {
   if (model != 0) return hipErrorInvalidValue;
   return dispatch_plan<FusedLaunch>(K, threads, groups, lds, a, s);
+}
+
+hipError_t launch_run_fused_adaptive(int K, int groups, int threads, size_t lds,
+                                     const KArgs& a, hipStream_t s) {
+  return dispatch_plan<FusedAdaptLaunch>(K, threads, groups, lds, a, s);
 }
 
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KArgs& a,

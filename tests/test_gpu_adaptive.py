@@ -1,7 +1,8 @@
 """Adaptive computation on the GPU against the FP64 oracle's adaptive loop.
 
 * a vanishing tolerance keeps every point active: the adaptive kernels
-  reproduce the plain split schedule bit for bit and count every node-step;
+  reproduce the plain schedule bit for bit (fused and split) and count every
+  node-step;
 * an infinite tolerance solves exactly the stimulated points and their
   neighbours after the first step (solved counts equal the oracle's, an
   integer result, bit-exact), and freezes the state once the stimulus is off;
@@ -51,8 +52,8 @@ def _run(s, w, n_steps, step0=0):
     return (s.get_state(), samples[:rows].cpu().numpy().astype(np.float64), s.tact().astype(np.float64))
 
 
-def _adaptive_gpu(w, tol, n_steps=None, **kw):
-    s = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT, **kw)
+def _adaptive_gpu(w, tol, n_steps=None, schedule=F.FIB_SCHED_SPLIT, **kw):
+    s = gpu_solver(w, schedule=schedule, **kw)
     s.set_adaptive(tol)
     out = _run(s, w, w.n_steps if n_steps is None else n_steps)
     return out + (s,)
@@ -62,14 +63,18 @@ def _at_zero(w):
     return replace(w, stims=[dict(st, step_on=0) for st in w.stims])
 
 
+SCHEDULES = [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT]
+
+
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("splitting", [F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV])
-def test_vanishing_tolerance_is_the_plain_split_schedule(splitting):
+def test_vanishing_tolerance_is_the_plain_schedule(splitting, schedule):
     w = _at_zero(I.batched_hh(n_fibers=6, n_min=300, n_max=400, t_end=1.0))
-    say(f"[adaptive tol->0] splitting={splitting}")
-    plain = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT, splitting=splitting)
+    say(f"[adaptive tol->0] splitting={splitting} schedule={schedule}")
+    plain = gpu_solver(w, schedule=schedule, splitting=splitting)
     yp, sp, tp = _run(plain, w, w.n_steps)
     plain.close()
-    ya, sa, ta, s = _adaptive_gpu(w, 1e-30, splitting=splitting)
+    ya, sa, ta, s = _adaptive_gpu(w, 1e-30, schedule=schedule, splitting=splitting)
     np.testing.assert_array_equal(ya, yp)
     np.testing.assert_array_equal(sa, sp)
     np.testing.assert_array_equal(ta, tp)
@@ -78,14 +83,15 @@ def test_vanishing_tolerance_is_the_plain_split_schedule(splitting):
     s.close()
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("splitting", [F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV])
-def test_infinite_tolerance_counts_match_the_oracle(splitting):
+def test_infinite_tolerance_counts_match_the_oracle(splitting, schedule):
     w = _quiet(I.batched_hh(n_fibers=5, n_min=40, n_max=90, t_end=0.3, onset_max=0.05))
     w.stims[1]["node"] = 0                      # clipped at the fiber's first node
     w.stims[2]["node"] = int(w.n_nodes[2]) - 1  # and at its last
     scheme = O.SCHEME_GODUNOV if splitting == F.FIB_SPLIT_GODUNOV else O.SCHEME_STRANG
     cfg = oracle_cfg(w, scheme=scheme)
-    s = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT, splitting=splitting)
+    s = gpu_solver(w, schedule=schedule, splitting=splitting)
     s.set_adaptive(1e30)
     y = oracle_init(w)
     pt = None
@@ -108,11 +114,12 @@ def test_infinite_tolerance_counts_match_the_oracle(splitting):
     s.close()
 
 
-def test_fibers_untouched_before_their_first_stimulus():
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_fibers_untouched_before_their_first_stimulus(schedule):
     w = I.batched_hh(n_fibers=6, n_min=200, n_max=300, t_end=1.0, onset_max=0.2)
     w.stims[2]["step_on"] = 600
     w.stims[4]["step_on"] = 10 ** 6
-    s = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    s = gpu_solver(w, schedule=schedule)
     y0 = s.get_state()
     s.set_adaptive(1e-6)
     s.run(0, 600)
@@ -128,14 +135,14 @@ def test_fibers_untouched_before_their_first_stimulus():
     s.close()
 
 
-def _parity(w, tol, splitting=F.FIB_SPLIT_STRANG):
+def _parity(w, tol, splitting=F.FIB_SPLIT_STRANG, schedule=F.FIB_SCHED_SPLIT):
     scheme = O.SCHEME_GODUNOV if splitting == F.FIB_SPLIT_GODUNOV else O.SCHEME_STRANG
     cfg = oracle_cfg(w, scheme=scheme)
     y0 = oracle_init(w)
     ya, sa, ta, pta, cnt = O.run_adaptive(cfg, w.n_nodes, y0, w.stims, w.n_steps,
                                           sample_every=w.sample_every, tol=tol)
     plain = O.run(cfg, w.n_nodes, y0, w.stims, w.n_steps, sample_every=w.sample_every)
-    yg, sg, tg, s = _adaptive_gpu(w, tol, splitting=splitting)
+    yg, sg, tg, s = _adaptive_gpu(w, tol, schedule=schedule, splitting=splitting)
     got = s.adaptive_solved()
     total = w.n_total * w.n_steps
     res_a = compare_runs(w, (yg, sg, tg, s), (ya, sa, ta))
@@ -152,11 +159,12 @@ def _parity(w, tol, splitting=F.FIB_SPLIT_STRANG):
     return got / total
 
 
+@pytest.mark.parametrize("schedule", SCHEDULES)
 @pytest.mark.parametrize("splitting", [F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV])
-def test_hh_batch_matches_oracle(splitting):
+def test_hh_batch_matches_oracle(splitting, schedule):
     w = _quiet(I.batched_hh(n_fibers=24, t_end=7.0))
-    say(f"[adaptive HH] splitting={splitting} steps={w.n_steps}")
-    share = _parity(w, 1e-6, splitting)
+    say(f"[adaptive HH] splitting={splitting} schedule={schedule} steps={w.n_steps}")
+    share = _parity(w, 1e-6, splitting, schedule)
     assert share < 0.6
 
 
@@ -167,12 +175,13 @@ def test_st57_bundle_matches_oracle():
     assert share < 0.8
 
 
-def test_chunked_adaptive_runs_are_bitwise_identical():
+@pytest.mark.parametrize("schedule", SCHEDULES)
+def test_chunked_adaptive_runs_are_bitwise_identical(schedule):
     w = _quiet(I.batched_hh(n_fibers=5, n_min=200, n_max=300, t_end=2.0, onset_max=0.5))
-    ys, ss, ts, s = _adaptive_gpu(w, 1e-6)
+    ys, ss, ts, s = _adaptive_gpu(w, 1e-6, schedule=schedule)
     n1 = s.adaptive_solved()
     s.close()
-    c = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    c = gpu_solver(w, schedule=schedule)
     c.set_adaptive(1e-6)
     for a, b in ((0, 351), (351, 1000), (1000, 1433), (1433, 2000)):
         c.run(a, b - a)
@@ -183,11 +192,29 @@ def test_chunked_adaptive_runs_are_bitwise_identical():
     c.close()
 
 
+def test_fused_and_split_adaptive_agree():
+    """The fused kernel (states in LDS, compacted solve list) and the split
+    schedule take the same decisions: equal solved counts and states within
+    FP32 rounding."""
+    w = _quiet(I.batched_hh(n_fibers=12, n_min=600, n_max=900, t_end=3.0, onset_max=1.0))
+    a = _adaptive_gpu(w, 1e-6, schedule=F.FIB_SCHED_FUSED)
+    b = _adaptive_gpu(w, 1e-6, schedule=F.FIB_SCHED_SPLIT)
+    na, nb = a[3].adaptive_solved(), b[3].adaptive_solved()
+    say(f"   solved fused {na}, split {nb}; V diff {np.max(np.abs(a[0][0] - b[0][0])):.2e}")
+    assert abs(na - nb) <= 0.01 * nb
+    assert np.max(np.abs(a[1] - b[1])) < 0.05
+    a[3].close()
+    b[3].close()
+
+
 def test_refused_requests():
     w = I.batched_hh(n_fibers=3, n_min=100, n_max=120, t_end=0.1)
-    s = gpu_solver(w, schedule=F.FIB_SCHED_FUSED)
+    # ST57 states do not fit the fused kernel
+    ws = I.st57_bundle(n_fibers=2, n_nodes=64, t_end=0.01)
+    s = gpu_solver(ws, schedule=F.FIB_SCHED_FUSED)
+    s.set_adaptive(1e-5)
     with pytest.raises(F.FibError) as e:
-        s.set_adaptive(1e-5)
+        s.run(0, 2)
     assert e.value.code == F.FIB_EUNSUPPORTED
     s.close()
     s = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
