@@ -13,7 +13,8 @@
  *   - subcellular model: section "Subcellular Model", eqs. subcellular_model_
  *     helper3-5 and subcellular; the Hodgkin-Huxley rate functions in the
  *     -75 mV resting-potential convention fixed by the generated-code excerpt
- *     in section "Computation of CellML Models" (Hodgkin & Huxley 1952);
+ *     in section "Computation of CellML Models" (Hodgkin & Huxley 1952); the
+ *     same membrane with exp replaced by the exp* of eq. apx-e-function;
  *   - monodomain equation on a fiber: eq. monodomain, no-flux ends
  *     eq. monodomain_bc1;
  *   - operator splitting: eq. monodomain_strang (0D, 1D, 0D order, figure
@@ -45,7 +46,8 @@
 /* ------------------------------------------------------------------------ */
 
 typedef struct {
-  int32_t model;   /* 0: Hodgkin-Huxley (4 states), 1: ST57 (57 states) */
+  int32_t model;   /* 0: Hodgkin-Huxley (4 states), 1: ST57 (57 states),
+                      2: Hodgkin-Huxley with exp* (eq. apx-e-function) */
   int32_t scheme;  /* 0: Strang  R(dt/2) D(dt) R(dt/2);  1: Godunov R(dt) D(dt) */
   double Cm;       /* membrane capacitance, uF/cm^2 */
   double Am;       /* surface-to-volume ratio, 1/cm */
@@ -82,28 +84,52 @@ typedef struct {
 #define HH_EK (HH_ER - 12.0)
 #define HH_EL (HH_ER + 10.613)
 
+/* The approximate exponential of eq. apx-e-function,
+ *   exp*(x) = (1 + x/n)^n  with n = 1024 = 2^10,
+ * evaluated as the thesis does: one division by n, one addition and ten
+ * squarings. */
+double or_exp_star(double x) {
+  double u = 1.0 + x / 1024.0;
+  for (int i = 0; i < 10; ++i) u *= u;
+  return u;
+}
+
 /* x / (exp(x) - 1), the shape of alpha_m and alpha_n; removable singularity
  * at x = 0 where the value is 1.  Near 0 the Taylor series 1 - x/2 + x^2/12
- * is used (its truncation error x^4/720 is below 1e-18 for |x| < 1e-4). */
-static double x_over_expm1(double x) {
-  if (fabs(x) < 1e-4) return 1.0 - 0.5 * x + x * x / 12.0;
-  return x / expm1(x);
+ * is used (its truncation error x^4/720 is below 1e-18 for |x| < 1e-4).
+ * With apx, exp is exp*: (1 + x/n)^n - 1 = x + a' x^2 + b' x^3 + ... with
+ * a' = (n-1)/(2n), b' = (n-1)(n-2)/(6 n^2), so the quotient is
+ * 1 - a' x + (a'^2 - b') x^2 + O(x^3) near 0. */
+static double x_over_expm1(int apx, double x) {
+  if (!apx) {
+    if (fabs(x) < 1e-4) return 1.0 - 0.5 * x + x * x / 12.0;
+    return x / expm1(x);
+  }
+  const double n = 1024.0, a = (n - 1.0) / (2.0 * n), b = (n - 1.0) * (n - 2.0) / (6.0 * n * n);
+  if (fabs(x) < 1e-4) return 1.0 - a * x + (a * a - b) * x * x;
+  return x / (or_exp_star(x) - 1.0);
 }
+
+static double hh_exp(int apx, double x) { return apx ? or_exp_star(x) : exp(x); }
 
 /* Rate constants (1/ms) of the three gates at membrane voltage V (mV).
  * With v = V - E_R the classic forms are
  *   alpha_m = 0.1 (25-v)/(exp((25-v)/10)-1),  beta_m = 4 exp(-v/18),
  *   alpha_h = 0.07 exp(-v/20),                beta_h = 1/(exp((30-v)/10)+1),
- *   alpha_n = 0.01 (10-v)/(exp((10-v)/10)-1), beta_n = 0.125 exp(-v/80). */
-void or_hh_gate_rates(double V, double ab[6]) {
+ *   alpha_n = 0.01 (10-v)/(exp((10-v)/10)-1), beta_n = 0.125 exp(-v/80);
+ * with apx every exp is the exp* of eq. apx-e-function. */
+static void hh_rates(int apx, double V, double ab[6]) {
   double v = V - HH_ER;
-  ab[0] = x_over_expm1((25.0 - v) / 10.0);
-  ab[1] = 4.0 * exp(-v / 18.0);
-  ab[2] = 0.07 * exp(-v / 20.0);
-  ab[3] = 1.0 / (exp((30.0 - v) / 10.0) + 1.0);
-  ab[4] = 0.1 * x_over_expm1((10.0 - v) / 10.0);
-  ab[5] = 0.125 * exp(-v / 80.0);
+  ab[0] = x_over_expm1(apx, (25.0 - v) / 10.0);
+  ab[1] = 4.0 * hh_exp(apx, -v / 18.0);
+  ab[2] = 0.07 * hh_exp(apx, -v / 20.0);
+  ab[3] = 1.0 / (hh_exp(apx, (30.0 - v) / 10.0) + 1.0);
+  ab[4] = 0.1 * x_over_expm1(apx, (10.0 - v) / 10.0);
+  ab[5] = 0.125 * hh_exp(apx, -v / 80.0);
 }
+
+void or_hh_gate_rates(double V, double ab[6]) { hh_rates(0, V, ab); }
+void or_hh_apx_gate_rates(double V, double ab[6]) { hh_rates(1, V, ab); }
 
 /* Ionic current density I_ion (uA/cm^2), eq. subcellular_model_helper5 with
  * g_Na = gbar_Na m^3 h and g_K = gbar_K n^4. */
@@ -117,20 +143,29 @@ double or_hh_iion(const double y[4]) {
 /* Right-hand side G(y) of the subcellular model, eq. subcellular:
  *   Cm dV/dt = -I_ion + I_stim           (eq. subcellular_model_helper3)
  *   dy/dt    = alpha (1 - y) - beta y    for y in {m, h, n}. */
-void or_hh_rhs(double Cm, const double y[4], double I_stim, double dydt[4]) {
+static void hh_rhs(int apx, double Cm, const double y[4], double I_stim, double dydt[4]) {
   double ab[6];
-  or_hh_gate_rates(y[0], ab);
+  hh_rates(apx, y[0], ab);
   dydt[0] = (-or_hh_iion(y) + I_stim) / Cm;
   dydt[1] = ab[0] * (1.0 - y[1]) - ab[1] * y[1];
   dydt[2] = ab[2] * (1.0 - y[2]) - ab[3] * y[2];
   dydt[3] = ab[4] * (1.0 - y[3]) - ab[5] * y[3];
 }
 
+void or_hh_rhs(double Cm, const double y[4], double I_stim, double dydt[4]) {
+  hh_rhs(0, Cm, y, I_stim, dydt);
+}
+
+/* The same membrane with exp replaced by exp* (eq. apx-e-function). */
+void or_hh_apx_rhs(double Cm, const double y[4], double I_stim, double dydt[4]) {
+  hh_rhs(1, Cm, y, I_stim, dydt);
+}
+
 /* Steady-state ionic current with every gate at its equilibrium
  * y_inf = alpha / (alpha + beta) (the frozen-voltage limit of the gate ODE). */
-static double hh_iss(double V) {
+static double hh_iss(int apx, double V) {
   double ab[6], y[4];
-  or_hh_gate_rates(V, ab);
+  hh_rates(apx, V, ab);
   y[0] = V;
   y[1] = ab[0] / (ab[0] + ab[1]);
   y[2] = ab[2] / (ab[2] + ab[3]);
@@ -141,24 +176,27 @@ static double hh_iss(double V) {
 /* Resting state of the membrane: the voltage where the steady-state current
  * vanishes, found by bisection on [-80, -70] mV (I_ss changes sign there)
  * followed by secant polishing; gates at their equilibria. */
-int or_hh_rest(double y[4]) {
-  double lo = -80.0, hi = -70.0, flo = hh_iss(lo), fhi = hh_iss(hi);
+static int hh_rest(int apx, double y[4]) {
+  double lo = -80.0, hi = -70.0, flo = hh_iss(apx, lo), fhi = hh_iss(apx, hi);
   if (!(flo < 0.0 && fhi > 0.0)) return OR_EINVAL;
   for (int it = 0; it < 200; ++it) {
-    double mid = 0.5 * (lo + hi), fm = hh_iss(mid);
+    double mid = 0.5 * (lo + hi), fm = hh_iss(apx, mid);
     if (fm == 0.0) { lo = hi = mid; break; }
     if (fm < 0.0) lo = mid; else hi = mid;
     if (hi - lo < 1e-15) break;
   }
   double V = 0.5 * (lo + hi);
   double ab[6];
-  or_hh_gate_rates(V, ab);
+  hh_rates(apx, V, ab);
   y[0] = V;
   y[1] = ab[0] / (ab[0] + ab[1]);
   y[2] = ab[2] / (ab[2] + ab[3]);
   y[3] = ab[4] / (ab[4] + ab[5]);
   return OR_OK;
 }
+
+int or_hh_rest(double y[4]) { return hh_rest(0, y); }
+int or_hh_apx_rest(double y[4]) { return hh_rest(1, y); }
 
 /* ------------------------------------------------------------------------ */
 /* Model dispatch                                                            */
@@ -168,8 +206,10 @@ int or_hh_rest(double y[4]) {
 int or_st57_n_states(void);
 void or_st57_rhs(double Cm, const double* y, double I, double* dydt);
 
+/* Models: 0 Hodgkin-Huxley, 1 ST57, 2 Hodgkin-Huxley with exp* in its
+ * rates (eq. apx-e-function). */
 int or_n_states(int model) {
-  if (model == 0) return 4;
+  if (model == 0 || model == 2) return 4;
   if (model == 1) return or_st57_n_states();
   return -1;
 }
@@ -178,7 +218,7 @@ static void model_rhs(int model, double Cm, const double* y, double I, double* d
   if (model == 1)
     or_st57_rhs(Cm, y, I, dydt);
   else
-    or_hh_rhs(Cm, y, I, dydt);
+    hh_rhs(model == 2, Cm, y, I, dydt);
 }
 
 /* ------------------------------------------------------------------------ */

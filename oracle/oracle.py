@@ -24,6 +24,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 MODEL_HH = 0
 MODEL_ST57 = 1
+MODEL_HH_APX_EXP = 2   # Hodgkin-Huxley with exp* (eq. apx-e-function) in its rates
 SCHEME_STRANG = 0
 SCHEME_GODUNOV = 1
 
@@ -68,6 +69,11 @@ def lib():
         L.or_hh_iion.restype = C.c_double
         L.or_hh_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
         L.or_hh_rest.argtypes = [_dp]
+        L.or_hh_apx_rest.argtypes = [_dp]
+        L.or_hh_apx_gate_rates.argtypes = [C.c_double, _dp]
+        L.or_hh_apx_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
+        L.or_exp_star.argtypes = [C.c_double]
+        L.or_exp_star.restype = C.c_double
         L.or_n_states.argtypes = [C.c_int]
         L.or_st57_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
         L.or_st57_invariants.argtypes = [_dp, _dp]
@@ -143,6 +149,8 @@ def rest_state(model: int = MODEL_HH) -> np.ndarray:
     y = np.zeros(n_states(model))
     if model == MODEL_HH:
         rc = lib().or_hh_rest(_d(y))
+    elif model == MODEL_HH_APX_EXP:
+        rc = lib().or_hh_apx_rest(_d(y))
     elif model == MODEL_ST57:
         it = C.c_int(0)
         rc = lib().or_st57_rest(_d(y), C.byref(it))
@@ -151,6 +159,24 @@ def rest_state(model: int = MODEL_HH) -> np.ndarray:
     if rc != 0:
         raise RuntimeError("rest state search failed")
     return y
+
+
+def exp_star(x: float) -> float:
+    """exp*(x) = (1 + x/1024)^1024 (eq. apx-e-function)."""
+    return lib().or_exp_star(float(x))
+
+
+def hh_apx_rates(V: float) -> np.ndarray:
+    ab = np.zeros(6)
+    lib().or_hh_apx_gate_rates(float(V), _d(ab))
+    return ab
+
+
+def hh_apx_rhs(y, I_stim: float = 0.0, Cm: float = 1.0) -> np.ndarray:
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    d = np.zeros(4)
+    lib().or_hh_apx_rhs(float(Cm), _d(y), float(I_stim), _d(d))
+    return d
 
 
 def st57_rhs(y, I_stim: float = 0.0, Cm: float = 1.0) -> np.ndarray:

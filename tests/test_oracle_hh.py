@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as O
+from paper_2107_07104_amd import inputs as I
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden", "hh_rest_textbook.json")
 
@@ -143,3 +144,60 @@ def test_gates_stay_in_unit_interval_during_ap():
     for k in range(6):
         y, _, _ = O.run(cfg, w.n_nodes, y, w.stims, 1000, step0=1000 * k)
         assert np.all(y[1:] >= 0.0) and np.all(y[1:] <= 1.0)
+
+
+# ---- Hodgkin-Huxley with the approximate exponential (eq. apx-e-function) ----
+
+def _exp_star_closed(x, n=1024):
+    """(1 + x/n)^n through log1p and exp: a route independent of the
+    oracle's ten squarings."""
+    return np.exp(n * np.log1p(x / n))
+
+
+def test_exp_star_relative_error_bound_printed_in_the_thesis():
+    # the thesis bounds the relative error at |x| = 12 by 0.07
+    for x in (12.0, -12.0):
+        e = O.exp_star(x)
+        rel = abs(e - np.exp(x)) / np.exp(x)
+        assert 0.06 < rel < 0.07
+        assert e == pytest.approx(_exp_star_closed(x), rel=1e-12)
+    assert O.exp_star(0.0) == 1.0
+    # (1 + x/n)^n < e^x for x != 0, and it converges to e^x as x/n -> 0
+    xs = np.linspace(-20.0, 20.0, 81)
+    es = np.array([O.exp_star(x) for x in xs])
+    assert np.all(es[xs != 0.0] < np.exp(xs[xs != 0.0]))
+    np.testing.assert_allclose(es, _exp_star_closed(xs), rtol=1e-11)
+
+
+@pytest.mark.parametrize("V", [-50.0 + d for d in (-1e-2, -1e-3, -2e-5, 0.0, 2e-5, 1e-3, 1e-2)]
+                         + [-65.0 + d for d in (-1e-3, -2e-5, 0.0, 2e-5, 1e-3)])
+def test_exp_star_rates_near_the_removable_singularities(V):
+    """alpha_m and alpha_n with exp* against x / expm1(n log1p(x / n)), and
+    the limit 1 (times the prefactor) at x = 0."""
+    ab = O.hh_apx_rates(V)
+    for k, shift, pre in ((0, 50.0, 1.0), (4, 65.0, 0.1)):
+        x = -(V + shift) / 10.0
+        want = pre * (1.0 if x == 0.0 else x / np.expm1(1024 * np.log1p(x / 1024)))
+        assert ab[k] == pytest.approx(want, rel=1e-9)
+
+
+def test_exp_star_rates_and_rest_state():
+    V = np.linspace(-100.0, 40.0, 57)
+    for v in V:
+        ex, apx = O.hh_gate_rates(v), O.hh_apx_rates(v)
+        # every rate moves by at most the exp* error at its largest argument
+        # on this range (|x| <= 15: relative 0.1)
+        np.testing.assert_allclose(apx, ex, rtol=0.11)
+    y = O.rest_state(O.MODEL_HH_APX_EXP)
+    y_exact = O.rest_state(O.MODEL_HH)
+    assert np.max(np.abs(O.hh_apx_rhs(y))) < 1e-10
+    assert 1e-6 < abs(y[0] - y_exact[0]) < 0.5
+
+
+def test_exp_star_membrane_fires_and_propagates():
+    w = I.single_fiber(amp=I.AMP_SUPRA, n_nodes=200, t_end=8.0)
+    cfg = O.Config(model=O.MODEL_HH_APX_EXP, dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split)
+    y0 = np.tile(O.rest_state(O.MODEL_HH_APX_EXP)[:, None], (1, w.n_total))
+    y, s, ta = O.run(cfg, w.n_nodes, y0, w.stims, w.n_steps, sample_every=w.sample_every)
+    assert np.all(np.isfinite(ta))
+    assert np.nanmax(s) > 20.0
