@@ -46,6 +46,13 @@ Reported: node-steps/s over all node-steps of the run, the share of
 node-steps the adaptive run solved, and the FP64 oracle's V_m /
 activation-time errors of the adaptive run on sampled fibers (against the
 plain method).
+
+`exp_approx` (skipped with --no-exp-approx) runs the headline workload with
+the membrane whose exponentials are exp*(x) = (1 + x/1024)^1024 (the
+thesis's approximation; on gfx950 the native exponential is one FMA and one
+v_exp_f32, exp* an FMA and ten squarings): node-steps/s of the fused kernel,
+its FP64-oracle parity against the exp* model, and how far that model lies
+from the exact membrane, on sampled fibers.
 """
 from __future__ import annotations
 
@@ -100,6 +107,7 @@ def parse():
     ap.add_argument("--sur-train-steps", type=int, default=20000)
     ap.add_argument("--sur-tol", type=float, default=1e-2)
     ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-exp-approx", action="store_true")
     ap.add_argument("--adapt-tol", type=float, default=1e-6)
     ap.add_argument("--st57-ms", type=float, default=1.0,
                     help="simulated ms of the large ST57 bundle timed per path")
@@ -444,6 +452,39 @@ def adaptive_bench(args):
     return out
 
 
+def exp_approx_bench(args):
+    """The headline workload with the exp* membrane (see the module docstring)."""
+    from dataclasses import replace
+
+    import torch
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+    from oracle import oracle as O
+    w = replace(I.batched_hh(t_end=args.t_end), model=F.FIB_MODEL_HH_APX_EXP)
+    s = F.Solver(w.n_nodes, model=w.model, dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split)
+    s.set_stimulus(w.stims)
+    vm = torch.as_tensor(w.vm_noise.astype(np.float32), device="cuda")
+    s.init_state(vm_noise=vm)
+    s.autotune(trial_steps=200, max_candidates=8)
+    _timed_run(s, w.with_steps(50), lambda: s.init_state(vm_noise=vm), w.sample_every)
+    secs, smp, ta = _timed_run(s, w, lambda: s.init_state(vm_noise=vm), w.sample_every)
+    plan = s.plan()
+    s.close()
+    _log(f"exp* membrane: {w.node_steps() / secs:.3e} node-steps/s")
+    fibers = [0, 1, 2, 3]
+    off = w.offsets
+    cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+    out = dict(workload=f"{w.name}, exp* membrane", value=w.node_steps() / secs, seconds=secs,
+               plan=plan)
+    for model, key in ((F.FIB_MODEL_HH_APX_EXP, "vs_oracle_exp_star"),
+                       (F.FIB_MODEL_HH, "vs_oracle_exact_membrane")):
+        y0 = np.tile(O.rest_state(model)[:, None], (1, len(cols)))
+        y0[0] += w.vm_noise[cols].astype(np.float32)
+        out[key] = _oracle_parity(replace(w, model=model), fibers, y0, smp, ta, w.n_steps)
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -544,13 +585,17 @@ def main():
 
     sur = None
     adapt = None
-    if not args.no_surrogate or not args.no_adaptive:
+    expx = None
+    if not args.no_surrogate or not args.no_adaptive or not args.no_exp_approx:
         s.close()
         s = None
     if not args.no_surrogate:
         sur = {"hh": surrogate_hh(args), "st57": surrogate_st57(args)}
     if not args.no_adaptive:
         adapt = adaptive_bench(args)
+    if not args.no_exp_approx:
+        expx = exp_approx_bench(args)
+        expx["over_plain"] = expx["value"] / value
 
     out = {
         "metric": METRIC,
@@ -575,6 +620,7 @@ def main():
         "parity_vs_oracle": parity,
         "surrogate": sur,
         "adaptive": adapt,
+        "exp_approx": expx,
     }
     if s is not None:
         s.close()

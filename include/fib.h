@@ -62,7 +62,13 @@ typedef enum {
   FIB_EUNSUPPORTED = -6  /* valid request that this build cannot serve */
 } fib_status;
 
-enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1 };
+/* Subcellular models: Hodgkin-Huxley (4 states), the 57-state ST57 stand-in
+ * for the Shorten model, and Hodgkin-Huxley with every exponential of its
+ * rates replaced by the approximation exp*(x) = (1 + x/1024)^1024 of
+ * eq. apx-e-function (4 states; its own resting state).  The fused schedule,
+ * the adaptive fused kernel and the surrogate step take Hodgkin-Huxley only
+ * (HH_APX_EXP: the fused schedule and the split schedule). */
+enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1, FIB_MODEL_HH_APX_EXP = 2 };
 
 /* Execution schedule of fib_run.
  *   FUSED: one persistent kernel keeps every node's states in registers and

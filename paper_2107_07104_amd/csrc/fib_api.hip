@@ -55,7 +55,7 @@ int fail(int code, const char* fmt, ...) {
   } while (0)
 
 int n_states_of(int model) {
-  if (model == FIB_MODEL_HH) return 4;
+  if (model == FIB_MODEL_HH || model == FIB_MODEL_HH_APX_EXP) return 4;
   if (model == FIB_MODEL_ST57) return fib::st57::S;
   return -1;
 }
@@ -64,16 +64,19 @@ int n_states_of(int model) {
 // Hodgkin-Huxley resting state on the host (FP64)
 // ---------------------------------------------------------------------------
 
-// Equilibrium gate values at voltage V and the ionic current they carry.
-double hh_steady_current(double V, double gates[3]) {
+// Equilibrium gate values at voltage V and the ionic current they carry
+// (apx: exp replaced by exp*(x) = (1 + x/1024)^1024 = exp(1024 log1p(x/1024))).
+double hh_steady_current(double V, double gates[3], bool apx = false) {
   const double v = V + 75.0;
-  auto lin = [](double x) { return std::fabs(x) < 1e-6 ? 1.0 - 0.5 * x : x / std::expm1(x); };
+  auto ex = [apx](double x) { return apx ? std::exp(1024.0 * std::log1p(x / 1024.0)) : std::exp(x); };
+  auto em1 = [apx](double x) { return apx ? std::expm1(1024.0 * std::log1p(x / 1024.0)) : std::expm1(x); };
+  auto lin = [&](double x) { return std::fabs(x) < 1e-6 ? 1.0 - 0.5 * x : x / em1(x); };
   const double am = lin((25.0 - v) / 10.0);
-  const double bm = 4.0 * std::exp(-v / 18.0);
-  const double ah = 0.07 * std::exp(-v / 20.0);
-  const double bh = 1.0 / (std::exp((30.0 - v) / 10.0) + 1.0);
+  const double bm = 4.0 * ex(-v / 18.0);
+  const double ah = 0.07 * ex(-v / 20.0);
+  const double bh = 1.0 / (ex((30.0 - v) / 10.0) + 1.0);
   const double an = 0.1 * lin((10.0 - v) / 10.0);
-  const double bn = 0.125 * std::exp(-v / 80.0);
+  const double bn = 0.125 * ex(-v / 80.0);
   const double m = am / (am + bm), h = ah / (ah + bh), n = an / (an + bn);
   gates[0] = m;
   gates[1] = h;
@@ -84,19 +87,20 @@ double hh_steady_current(double V, double gates[3]) {
 
 // Newton's method on the steady-state current with a central-difference
 // derivative, started at the nominal resting potential of -75 mV.
-int hh_rest(double* y) {
+int hh_rest(double* y, bool apx = false) {
   double g[3];
   double V = -75.0;
   for (int it = 0; it < 50; ++it) {
-    const double f = hh_steady_current(V, g);
+    const double f = hh_steady_current(V, g, apx);
     const double e = 1e-6;
-    const double df = (hh_steady_current(V + e, g) - hh_steady_current(V - e, g)) / (2 * e);
+    const double df =
+        (hh_steady_current(V + e, g, apx) - hh_steady_current(V - e, g, apx)) / (2 * e);
     if (!(df > 0.0)) return fail(FIB_EINVAL, "resting-state search: non-positive slope");
     const double dV = f / df;
     V -= dV;
     if (std::fabs(dV) < 1e-13) break;
   }
-  hh_steady_current(V, g);
+  hh_steady_current(V, g, apx);
   y[0] = V;
   y[1] = g[0];
   y[2] = g[1];
@@ -816,6 +820,7 @@ int fib_plan_preview(const fib_params* p, int32_t n_fibers, const int32_t* n_nod
 int fib_rest_state(const fib_params* p, double* y_out) {
   if (!p || !y_out) return fail(FIB_EINVAL, "null argument");
   if (p->model == FIB_MODEL_HH) return hh_rest(y_out);
+  if (p->model == FIB_MODEL_HH_APX_EXP) return hh_rest(y_out, true);
   if (p->model == FIB_MODEL_ST57) return st57_rest(y_out);
   return fail(FIB_EINVAL, "unknown model %d", p->model);
 }
@@ -1104,6 +1109,9 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     // fused where the model and the plan allow it, else split
     const bool want_fused = c->p.schedule == FIB_SCHED_FUSED ||
                             (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH);
+    if (c->p.schedule == FIB_SCHED_FUSED && c->p.model == FIB_MODEL_HH_APX_EXP)
+      return fail(FIB_EUNSUPPORTED, "the adaptive fused kernel holds the exact Hodgkin-Huxley "
+                  "membrane only");
     if (want_fused) {
       if (c->p.model != FIB_MODEL_HH)
         return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
@@ -1118,10 +1126,11 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   }
   // AUTO: fused for Hodgkin-Huxley unless a surrogate is attached (the
   // surrogate step belongs to the split schedule)
+  const bool hh_like = c->p.model == FIB_MODEL_HH || c->p.model == FIB_MODEL_HH_APX_EXP;
   const bool fused = c->p.schedule == FIB_SCHED_FUSED ||
-                     (c->p.schedule == FIB_SCHED_AUTO && c->p.model == FIB_MODEL_HH && !c->sur_on);
+                     (c->p.schedule == FIB_SCHED_AUTO && hh_like && !c->sur_on);
   if (fused) {
-    if (c->p.model != FIB_MODEL_HH)
+    if (!hh_like)
       return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
     HIP_TRY(fib::launch_run_fused(c->p.model, c->K, c->groups, c->threads,
                                   fib::lds_bytes_for(c->threads, c->levels), a, c->stream));

@@ -228,7 +228,8 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
 // node's four states in registers: V_m prescriptions of the step, R(dt/2)
 // D(dt) R(dt/2) (Godunov: R(dt) D(dt), n_sub2 = 0), then the observables.  Device memory is read at the start, written at the end and
 // for samples / activation times only.
-template <int K, int MAXT>
+// APX: the membrane with exp* in its rates (model FIB_MODEL_HH_APX_EXP).
+template <int K, int MAXT, bool APX>
 __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
   extern __shared__ float lds[];
   const int T = blockDim.x;
@@ -270,7 +271,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
     }
     for (int s = 0; s < A.n_sub; ++s) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, ref);
+      for (int q = 0; q < K; ++q) hh::heun<APX>(y[q], I[q], A.tau, A.inv_cm, ref);
     }
     {
       float V[K];
@@ -283,7 +284,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
     }
     for (int s = 0; s < A.n_sub2; ++s) {
 #pragma unroll
-      for (int q = 0; q < K; ++q) hh::heun(y[q], I[q], A.tau, A.inv_cm, ref);
+      for (int q = 0; q < K; ++q) hh::heun<APX>(y[q], I[q], A.tau, A.inv_cm, ref);
     }
     // activation times: first upward crossing of v_th between step ends
     // (the voltage offsets cross v_th - rest_V)
@@ -668,18 +669,21 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
 // Reaction with states in device memory, one node per thread
 // ---------------------------------------------------------------------------
 
-struct ModelHH {
+template <bool APX>
+struct ModelHHT {
   static constexpr int S = 4;
   __device__ static void heun(float (&u)[S], const float* ref, float I, float tau, float inv_cm) {
     hh::State y{u[0], u[1], u[2], u[3]};
     const hh::Ref r{ref[0], ref[1], ref[2], ref[3]};
-    hh::heun(y, I, tau, inv_cm, r);
+    hh::heun<APX>(y, I, tau, inv_cm, r);
     u[0] = y.V;
     u[1] = y.m;
     u[2] = y.h;
     u[3] = y.n;
   }
 };
+using ModelHH = ModelHHT<false>;
+using ModelHHApx = ModelHHT<true>;
 
 struct ModelST57 {
   static constexpr int S = st57::S;
@@ -895,7 +899,15 @@ static hipError_t dispatch_plan(int K, int threads, int groups, size_t lds, cons
 template <int K, int MAXT>
 struct FusedLaunch {
   static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_run_hh<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
+    hipLaunchKernelGGL((k_run_hh<K, MAXT, false>), dim3(groups), dim3(threads), lds, s, a);
+    return hipGetLastError();
+  }
+};
+
+template <int K, int MAXT>
+struct FusedApxLaunch {
+  static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL((k_run_hh<K, MAXT, true>), dim3(groups), dim3(threads), lds, s, a);
     return hipGetLastError();
   }
 };
@@ -918,8 +930,9 @@ struct DiffusionLaunch {
 
 hipError_t launch_run_fused(int model, int K, int groups, int threads, size_t lds,
                             const KArgs& a, hipStream_t s) {
-  if (model != 0) return hipErrorInvalidValue;
-  return dispatch_plan<FusedLaunch>(K, threads, groups, lds, a, s);
+  if (model == 0) return dispatch_plan<FusedLaunch>(K, threads, groups, lds, a, s);
+  if (model == 2) return dispatch_plan<FusedApxLaunch>(K, threads, groups, lds, a, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_run_fused_adaptive(int K, int groups, int threads, size_t lds,
@@ -938,6 +951,8 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
   const dim3 grid(blocks_for(a.n_total, 256)), block(256);
   if (model == 0)
     hipLaunchKernelGGL(k_react<ModelHH>, grid, block, 0, s, a, step_a, step_b, flags);
+  else if (model == 2)
+    hipLaunchKernelGGL(k_react<ModelHHApx>, grid, block, 0, s, a, step_a, step_b, flags);
   else if (model == 1)
     hipLaunchKernelGGL(k_react<ModelST57>, grid, block, 0, s, a, step_a, step_b, flags);
   else
@@ -960,6 +975,7 @@ hipError_t launch_adapt_start(int model, bool godunov, int32_t step, bool observ
                               const KArgs& a, hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
   if (model == 0) return adapt_start_for<ModelHH>(godunov, step, observe_prev, a, s);
+  if (model == 2) return adapt_start_for<ModelHHApx>(godunov, step, observe_prev, a, s);
   if (model == 1) return adapt_start_for<ModelST57>(godunov, step, observe_prev, a, s);
   return hipErrorInvalidValue;
 }
@@ -969,6 +985,8 @@ hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStrea
   const dim3 grid(blocks_for(a.n_total, 256)), block(256);
   if (model == 0)
     hipLaunchKernelGGL(k_adapt_finish<ModelHH>, grid, block, 0, s, a, step);
+  else if (model == 2)
+    hipLaunchKernelGGL(k_adapt_finish<ModelHHApx>, grid, block, 0, s, a, step);
   else if (model == 1)
     hipLaunchKernelGGL(k_adapt_finish<ModelST57>, grid, block, 0, s, a, step);
   else
@@ -978,7 +996,7 @@ hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStrea
 
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s) {
-  const int S = (model == 0) ? ModelHH::S : (model == 1) ? ModelST57::S : 0;
+  const int S = (model == 0 || model == 2) ? ModelHH::S : (model == 1) ? ModelST57::S : 0;
   if (S == 0) return hipErrorInvalidValue;
   if (a.n_total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, S, vm_noise,

@@ -14,6 +14,13 @@
 // V: the 1/ln 2 factor, the 1/10, 1/18, 1/20, 1/80 slopes, the +75 shift and
 // the prefactors 4, 0.07, 0.125 (as +log2 of the prefactor) are folded into
 // the FMA's constants.
+//
+// The APX variant replaces every exponential by exp*(x) = (1 + x/n)^n,
+// n = 1024 (eq. apx-e-function).  Ten squarings of 1 + x/n in FP32 would
+// multiply the rounding error of 1 + x/n by 1024 (6e-5 relative); instead
+// d = exp*(x) - 1 is carried through the ten squarings as d <- d (d + 2),
+// starting from d = x/n (one FMA in V), which keeps it to a few ulp and
+// gives x / (exp*(x) - 1) = x / d without cancellation.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -25,10 +32,14 @@ constexpr double kL2E = 1.4426950408889634074;  // 1 / ln 2
 
 // exp(s * (V + shift)) * pre  ==  2^(V * K1 + K0)
 struct ExpCoef {
-  float k1, k0;
+  float k1, k0;  // 2^(V k1 + k0)
+  float a1, a0;  // x / n = V a1 + a0 (exp* variant)
+  float pre;     // prefactor (exp* variant)
 };
-constexpr ExpCoef exp_coef(double slope, double shift, double log2_pre) {
-  return ExpCoef{(float)(slope * kL2E), (float)(slope * shift * kL2E + log2_pre)};
+// pre exp(slope (V + shift)), log2_pre = log2(pre)
+constexpr ExpCoef exp_coef(double slope, double shift, double pre, double log2_pre) {
+  return ExpCoef{(float)(slope * kL2E), (float)(slope * shift * kL2E + log2_pre),
+                 (float)(slope / 1024.0), (float)(slope * shift / 1024.0), (float)pre};
 }
 
 // log2 of the prefactors
@@ -36,15 +47,24 @@ constexpr double kLog2_4 = 2.0;
 constexpr double kLog2_007 = -3.8365012677171206;  // log2(0.07)
 constexpr double kLog2_0125 = -3.0;
 
-constexpr ExpCoef kBm = exp_coef(-1.0 / 18.0, 75.0, kLog2_4);     // 4 exp(-v/18)
-constexpr ExpCoef kAh = exp_coef(-1.0 / 20.0, 75.0, kLog2_007);   // 0.07 exp(-v/20)
-constexpr ExpCoef kBh = exp_coef(-1.0 / 10.0, 45.0, 0.0);         // exp((30-v)/10)
-constexpr ExpCoef kBn = exp_coef(-1.0 / 80.0, 75.0, kLog2_0125);  // 0.125 exp(-v/80)
-constexpr ExpCoef kXm = exp_coef(-1.0 / 10.0, 50.0, 0.0);         // exp(x_m), x_m = (25-v)/10
-constexpr ExpCoef kXn = exp_coef(-1.0 / 10.0, 65.0, 0.0);         // exp(x_n), x_n = (10-v)/10
+constexpr ExpCoef kBm = exp_coef(-1.0 / 18.0, 75.0, 4.0, kLog2_4);       // 4 exp(-v/18)
+constexpr ExpCoef kAh = exp_coef(-1.0 / 20.0, 75.0, 0.07, kLog2_007);    // 0.07 exp(-v/20)
+constexpr ExpCoef kBh = exp_coef(-1.0 / 10.0, 45.0, 1.0, 0.0);           // exp((30-v)/10)
+constexpr ExpCoef kBn = exp_coef(-1.0 / 80.0, 75.0, 0.125, kLog2_0125);  // 0.125 exp(-v/80)
+constexpr ExpCoef kXm = exp_coef(-1.0 / 10.0, 50.0, 1.0, 0.0);  // exp(x_m), x_m = (25-v)/10
+constexpr ExpCoef kXn = exp_coef(-1.0 / 10.0, 65.0, 1.0, 0.0);  // exp(x_n), x_n = (10-v)/10
 
 __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// exp*(x) - 1 for x / n = V a1 + a0: ten squarings of 1 + x/n in the form
+// d <- d (d + 2).
+__device__ __forceinline__ float exp_star_m1(float V, const ExpCoef& c) {
+  float d = fmaf(V, c.a1, c.a0);
+#pragma unroll
+  for (int i = 0; i < 10; ++i) d = fmaf(d, d, d + d);
+  return d;
+}
 
 // x / (exp(x) - 1) given e = exp(x).  For |x| < 1e-3 the series 1 - x/2
 // (truncation error x^2/12 < 1e-7, below FP32 resolution) replaces the
@@ -69,7 +89,9 @@ struct Ref {
   float V, m, h, n;  // resting state
 };
 
-// Right-hand side G(y) of the membrane model with stimulus current I.
+// Right-hand side G(y) of the membrane model with stimulus current I
+// (APX: with exp* in the rates).
+template <bool APX = false>
 __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, const Ref& ref) {
   const float V = y.V + ref.V;
   const float m = y.m + ref.m;
@@ -77,14 +99,28 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
   const float n = y.n + ref.n;
   const float xm = fmaf(V, -0.1f, -5.0f);   // (25 - v)/10 = -(V + 50)/10
   const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
-  const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
-  const float en = ex2(fmaf(V, kXn.k1, kXn.k0));
-  const float am = x_over_expm1(xm, em);
-  const float an = 0.1f * x_over_expm1(xn, en);
-  const float bm = ex2(fmaf(V, kBm.k1, kBm.k0));
-  const float ah = ex2(fmaf(V, kAh.k1, kAh.k0));
-  const float bh = rcp(ex2(fmaf(V, kBh.k1, kBh.k0)) + 1.0f);
-  const float bn = ex2(fmaf(V, kBn.k1, kBn.k0));
+  float am, an, bm, ah, bh, bn;
+  if constexpr (!APX) {
+    const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
+    const float en = ex2(fmaf(V, kXn.k1, kXn.k0));
+    am = x_over_expm1(xm, em);
+    an = 0.1f * x_over_expm1(xn, en);
+    bm = ex2(fmaf(V, kBm.k1, kBm.k0));
+    ah = ex2(fmaf(V, kAh.k1, kAh.k0));
+    bh = rcp(ex2(fmaf(V, kBh.k1, kBh.k0)) + 1.0f);
+    bn = ex2(fmaf(V, kBn.k1, kBn.k0));
+  } else {
+    // x / (exp*(x) - 1) = x / d; near x = 0 its series 1 - (n-1)/(2n) x
+    // (truncation below 1e-7 for |x| < 1e-3)
+    constexpr float kA = 1023.0f / 2048.0f;
+    const float dm = exp_star_m1(V, kXm), dn = exp_star_m1(V, kXn);
+    am = fabsf(xm) < 1e-3f ? fmaf(xm, -kA, 1.0f) : xm * rcp(dm);
+    an = 0.1f * (fabsf(xn) < 1e-3f ? fmaf(xn, -kA, 1.0f) : xn * rcp(dn));
+    bm = kBm.pre * (exp_star_m1(V, kBm) + 1.0f);
+    ah = kAh.pre * (exp_star_m1(V, kAh) + 1.0f);
+    bh = rcp(exp_star_m1(V, kBh) + 2.0f);
+    bn = kBn.pre * (exp_star_m1(V, kBn) + 1.0f);
+  }
 
   const float m2 = m * m;
   const float m3h = m2 * (m * h);
@@ -105,14 +141,15 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
 
 // One Heun step of width tau (eq. heun):
 //   y+ = y + tau/2 (G(y) + G(y + tau G(y))).
+template <bool APX = false>
 __device__ __forceinline__ void heun(State& y, float I, float tau, float inv_cm, const Ref& ref) {
-  const State k1 = rhs(y, I, inv_cm, ref);
+  const State k1 = rhs<APX>(y, I, inv_cm, ref);
   State yt;
   yt.V = fmaf(tau, k1.V, y.V);
   yt.m = fmaf(tau, k1.m, y.m);
   yt.h = fmaf(tau, k1.h, y.h);
   yt.n = fmaf(tau, k1.n, y.n);
-  const State k2 = rhs(yt, I, inv_cm, ref);
+  const State k2 = rhs<APX>(yt, I, inv_cm, ref);
   const float ht = 0.5f * tau;
   y.V = fmaf(ht, k1.V + k2.V, y.V);
   y.m = fmaf(ht, k1.m + k2.m, y.m);

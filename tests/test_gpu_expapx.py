@@ -1,0 +1,76 @@
+"""Hodgkin-Huxley with the approximate exponential exp*(x) = (1 + x/1024)^1024
+(eq. apx-e-function) on the GPU against the FP64 oracle of the same model.
+
+* single-fiber and batched runs in both schedules stay within the method's
+  budget (0.5 mV over all samples and the final state, activation times
+  within one split step) of the oracle's exp* model;
+* the exp* model itself departs from the exact membrane by more than that
+  budget on the same workload (the oracle against the oracle), so these
+  checks also show that the approximate rates are the ones computed.
+"""
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2107_07104_amd import fib as F
+from paper_2107_07104_amd import inputs as I
+
+from gpu_helpers import compare_runs, gpu_run, oracle_cfg, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+APX = F.FIB_MODEL_HH_APX_EXP
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.lib()
+
+
+def _apx(w):
+    return replace(w, model=APX)
+
+
+def _oracle(w, model=APX):
+    cfg = replace(oracle_cfg(w), model=model)
+    y0 = np.tile(O.rest_state(model)[:, None], (1, w.n_total))
+    y0[0] += w.vm_noise.astype(np.float32).astype(np.float64)
+    return O.run(cfg, w.n_nodes, y0, w.stims, w.n_steps, sample_every=w.sample_every)
+
+
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_single_fiber_matches_oracle(schedule):
+    w = _apx(I.single_fiber(amp=I.AMP_SUPRA))
+    if schedule == F.FIB_SCHED_SPLIT:
+        w = w.with_steps(3000)
+    say(f"[exp* single fiber] schedule={schedule} steps={w.n_steps}")
+    ora = _oracle(w)
+    gpu = gpu_run(w, schedule=schedule)
+    res = compare_runs(w, gpu, ora)
+    say("  ", res)
+    assert res["vm_err"] <= 0.5 and res["tact_err"] <= w.dt_split and res["tact_mismatch"] == 0
+    assert res["activated"] > 100
+    gpu[3].close()
+
+
+def test_batched_matches_oracle_and_departs_from_the_exact_membrane():
+    w = _apx(I.batched_hh(n_fibers=24, t_end=7.0))
+    say(f"[exp* batched] steps={w.n_steps}")
+    ora = _oracle(w)
+    exact = _oracle(w, model=O.MODEL_HH)
+    gpu = gpu_run(w)
+    assert gpu[3].plan()["threads"] > 0
+    res = compare_runs(w, gpu, ora)
+    gap = compare_runs(w, gpu, exact)
+    say("   vs oracle exp*  ", res)
+    say("   vs oracle exact ", gap)
+    assert res["vm_err"] <= 0.5 and res["tact_err"] <= w.dt_split and res["tact_mismatch"] == 0
+    assert res["activated"] > 1000
+    assert gap["vm_err"] > 0.5
+    gpu[3].close()

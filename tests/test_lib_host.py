@@ -40,7 +40,7 @@ def test_n_states():
     ("Cm", 0.0), ("Am", -1.0), ("h", float("nan")), ("sigma", -0.1), ("dt_0D", 0.0),
     ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
     ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
-    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("schedule", 3),
+    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("model", 3), ("schedule", 3),
     ("splitting", 2), ("time_1d", 2), ("time_1d", -1)])
 def test_check_params_rejects(field, value):
     p = F.make_params()
@@ -86,6 +86,10 @@ def test_rest_state_agrees_with_oracle():
     y_lib = F.fib_rest_state(F.make_params())
     y_or = O.rest_state()
     np.testing.assert_allclose(y_lib, y_or, rtol=0, atol=1e-10)
+    # the membrane with exp* (eq. apx-e-function) has a rest state of its own
+    y_apx = F.fib_rest_state(F.make_params(model=F.FIB_MODEL_HH_APX_EXP))
+    np.testing.assert_allclose(y_apx, O.rest_state(O.MODEL_HH_APX_EXP), rtol=0, atol=1e-10)
+    assert abs(y_apx[0] - y_lib[0]) > 1e-5
 
 
 def test_create_rejects_bad_fibers_without_touching_the_gpu():
