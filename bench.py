@@ -109,6 +109,10 @@ def parse():
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-exp-approx", action="store_true")
     ap.add_argument("--adapt-tol", type=float, default=1e-6)
+    ap.add_argument("--adapt-cases", default="hh,st57",
+                    help="comma-separated adaptive cases to run (hh, st57)")
+    ap.add_argument("--no-adapt-parity", action="store_true",
+                    help="skip the oracle parity of the adaptive runs")
     ap.add_argument("--st57-ms", type=float, default=1.0,
                     help="simulated ms of the large ST57 bundle timed per path")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -410,7 +414,10 @@ def adaptive_bench(args):
          (("plain_split", F.FIB_SCHED_SPLIT, 0.0), ("adaptive", F.FIB_SCHED_SPLIT, args.adapt_tol)),
          [0, 1]),
     )
+    wanted = set(args.adapt_cases.split(","))
     for name, w, paths, fibers in cases:
+        if name not in wanted:
+            continue
         w = replace(w, vm_noise=np.zeros_like(w.vm_noise))
         res = {}
         runs = {}
@@ -441,7 +448,8 @@ def adaptive_bench(args):
         off = w.offsets
         cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
         y0 = np.tile(O.rest_state(w.model)[:, None], (1, len(cols)))
-        parity = _oracle_parity(w, fibers, y0, sa, ta, w.n_steps)
+        parity = (None if args.no_adapt_parity
+                  else _oracle_parity(w, fibers, y0, sa, ta, w.n_steps))
         out[name] = dict(workload=f"{w.name}, equilibrium start", fibers=int(len(w.n_nodes)),
                          nodes=int(w.n_total), split_steps=int(w.n_steps),
                          dt_split_ms=w.dt_split, **res,
