@@ -401,6 +401,55 @@ int fib_clear_surrogate(fib_t* ctx);
  * (blocking). */
 int fib_surrogate_last_fallbacks(fib_t* ctx, int64_t* n);
 
+/* ------------------------------------------------------------------------
+ * EMG: the static bidomain step on the 3D mesh (eq. discretized_fibers_2 and
+ * eq. discretized_fibers_3, the first bidomain equation eq. bidomain1 with
+ * the homogeneous Neumann conditions of eq. monodomain_bc):
+ *   V_3D = P V_m,   K_{sigma_i + sigma_e} phi_e = -K_{sigma_i} V_3D.
+ * The context's fibers form a bundle of nx x ny parallel fibers of equal
+ * length n along z, fiber f = j nx + i at (i hx, j hy); the 3D mesh of
+ * trilinear hexahedra has the fiber nodes 0, m, 2m, ... as its nodes
+ * (nz = (n - 1) / m + 1 layers, layer spacing m h), so P is the injection
+ * of those nodes.  3D node (i, j, k) has index (k ny + j) nx + i.
+ * sigma_i = sigma_i e_z e_z^T (conduction along the fibers only) and
+ * sigma_e = diag(sigma_et, sigma_et, sigma_el).
+ * ------------------------------------------------------------------------ */
+typedef struct fib_emg fib_emg_t;
+
+typedef struct {
+  int32_t nx, ny;    /* fibers along x and y (each >= 2); n_fibers = nx ny */
+  int32_t stride;    /* m >= 1; (n - 1) must be a multiple of m and (n - 1) / m >= 1 */
+  double hx, hy;     /* fiber spacing (cm, > 0) */
+  double sigma_i;    /* intracellular conductivity along the fibers (mS/cm, > 0) */
+  double sigma_el;   /* extracellular conductivity along the fibers (mS/cm, > 0) */
+  double sigma_et;   /* extracellular conductivity across the fibers (mS/cm, > 0) */
+} fib_emg_params;
+
+/* Sets up the EMG solve for a context (which must outlive it); FIB_EINVAL
+ * if the fibers do not form the bundle described above.  phi_e starts at
+ * zero.  Hodgkin-Huxley models only (V_m is state row 0). */
+int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out);
+void fib_emg_destroy(fib_emg_t* emg);
+int fib_emg_dims(const fib_emg_t* emg, int32_t* nx, int32_t* ny, int32_t* nz);
+
+/* One static bidomain solve from the context's current V_m, on its stream:
+ * right-hand side b = -K_{sigma_i} P V_m (V_m taken relative to the
+ * resting potential, which K_{sigma_i} annihilates), projected to zero mean;
+ * then conjugate gradients with the diagonal of K_{sigma_i + sigma_e} as
+ * preconditioner, started from the last phi_e, until
+ * ||r||_2 <= tol ||b||_2 or max_iter iterations; phi_e is returned to zero
+ * mean.  FP32 vectors, FP64 reductions.  iters and rel_res (nullable)
+ * receive the iterations taken and ||r|| / ||b|| (0 if b = 0).  Blocking. */
+int fib_emg_solve(fib_emg_t* emg, double tol, int32_t max_iter, int32_t* iters,
+                  double* rel_res);
+
+/* phi_e (mV) of the last solve into a host array of nx ny nz values. */
+int fib_emg_get_phi(fib_emg_t* emg, double* phi, int64_t n);
+
+/* The right-hand side -K_{sigma_i} P V_m of the last solve, before its
+ * zero-mean projection, into a host array of nx ny nz values. */
+int fib_emg_get_rhs(fib_emg_t* emg, double* rhs, int64_t n);
+
 #ifdef __cplusplus
 }
 #endif

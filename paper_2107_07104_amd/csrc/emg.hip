@@ -1,0 +1,488 @@
+// EMG step: the static bidomain solve on the structured 3D mesh (gfx950).
+//
+// The mesh nodes are every m-th node of an nx x ny bundle of equal fibers
+// (thesis eq. discretized_fibers_2: V_3D = P V_m is an injection), and the
+// elements are trilinear hexahedra with widths (hx, hy, m h).  For a
+// diagonal conduction tensor D the Q1 stiffness matrix is
+//   K_D = dx Kx (x) My (x) Mz + dy Mx (x) Ky (x) Mz + dz Mx (x) My (x) Kz
+// with the 1D linear-element stiffness K and consistent mass M, so a row of
+// K_D is a 27-point stencil whose weights are products of three 1D weights
+// (each 1D factor knows whether its neighbour exists: that is the Neumann
+// boundary).  The operator is applied matrix-free: no matrix is stored, the
+// weights of a node are formed from its (i, j, k) in registers.
+//
+// The solve (eq. discretized_fibers_3) is preconditioned conjugate gradients
+// with the diagonal of K_{sigma_i + sigma_e}.  Each iteration is two
+// launches over the nodes:
+//   k_cg_q:  p <- z + beta p (the previous p in the other buffer; the
+//            stencil reads the neighbours' z + beta p_old itself), q = A p,
+//            partial sums of p.q;
+//   k_cg_x:  x += alpha p, r -= alpha q, z = r / diag(A), partial sums of
+//            r.z and r.r.
+// Partial sums are per block in FP64; the last block of a launch (the one
+// whose arrival on a counter completes it) adds them in block order -- the
+// same order every time -- and updates the scalars (alpha, beta, the
+// convergence flag) that the next launch reads.  Converged iterations
+// return at once, so the host enqueues batches and checks the flag between
+// them.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <vector>
+
+#include "../../include/fib.h"
+#include "fib_internal.h"
+
+namespace {
+
+constexpr int kB = 256;  // threads per block (four waves)
+
+struct Grid3 {
+  int nx, ny, nz;
+  float hx, hy, hz;
+  int64_t n;
+};
+
+// Scalars of the solve, in device memory.
+struct Scal {
+  double mean_b;  // mean of the raw right-hand side
+  double bb;      // ||b||^2 after the projection
+  double rz;      // r.z of the current iterate
+  double rr;      // r.r of the current iterate
+  double alpha, beta;
+  double tol2;    // tol^2
+  int32_t it, max_it, done;
+  uint32_t counter[4];  // arrivals of the blocks of one launch, per kernel
+};
+
+// 1D linear-element stiffness and mass weights of node i (of n, spacing h)
+// towards its neighbours i - 1, i, i + 1; a missing neighbour weighs 0.
+__device__ __forceinline__ void weights_1d(int i, int n, float h, float (&K)[3], float (&M)[3]) {
+  const float lo = i > 0 ? 1.0f : 0.0f, hi = i + 1 < n ? 1.0f : 0.0f;
+  const float ih = 1.0f / h;
+  K[0] = -lo * ih;
+  K[1] = (lo + hi) * ih;
+  K[2] = -hi * ih;
+  M[0] = lo * h * (1.0f / 6.0f);
+  M[1] = (lo + hi) * h * (1.0f / 3.0f);
+  M[2] = hi * h * (1.0f / 6.0f);
+}
+
+// Row (i, j, k) of K_D applied to the field `get` (a functor of the node
+// index); diag receives the diagonal weight.
+template <class Get>
+__device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, float dz, int i,
+                                           int j, int k, Get get, float& diag) {
+  float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
+  weights_1d(i, g.nx, g.hx, Kx, Mx);
+  weights_1d(j, g.ny, g.hy, Ky, My);
+  weights_1d(k, g.nz, g.hz, Kz, Mz);
+  float acc = 0.0f;
+  diag = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    if (Mz[c] == 0.0f) continue;  // no neighbour layer
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      if (My[b] == 0.0f) continue;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        if (Mx[a] == 0.0f) continue;
+        const float w = dx * Kx[a] * My[b] * Mz[c] + dy * Mx[a] * Ky[b] * Mz[c] +
+                        dz * Mx[a] * My[b] * Kz[c];
+        const int64_t idx = ((int64_t)(k + c - 1) * g.ny + (j + b - 1)) * g.nx + (i + a - 1);
+        acc = fmaf(w, get(idx), acc);
+        if (a == 1 && b == 1 && c == 1) diag = w;
+      }
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ void node_ijk(const Grid3& g, int64_t t, int& i, int& j, int& k) {
+  i = (int)(t % g.nx);
+  const int64_t r = t / g.nx;
+  j = (int)(r % g.ny);
+  k = (int)(r / g.ny);
+}
+
+// Block sums of NV doubles into partials[v * nblocks + block]; returns true
+// in every thread of the block that arrives last, with the totals (summed
+// in block order) in tot.
+template <int NV>
+__device__ bool reduce_last(double (&v)[NV], double* partials, uint32_t* counter,
+                            double (&tot)[NV]) {
+  __shared__ double sh[NV][kB / 64];
+  __shared__ bool last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nblocks = (int)gridDim.x;
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double x = v[q];
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x += __shfl_down(x, d);
+    if (lane == 0) sh[q][wave] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      double x = 0.0;
+      for (int w = 0; w < kB / 64; ++w) x += sh[q][w];
+      partials[q * nblocks + blockIdx.x] = x;
+    }
+    __threadfence();
+    const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    last = prev == (uint32_t)nblocks - 1u;
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  // the last block: every thread adds a fixed strided subset, then a fixed tree
+  __shared__ double acc[NV][kB];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) {
+    double x = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kB)
+      x += __builtin_nontemporal_load(&partials[q * nblocks + b]);
+    acc[q][threadIdx.x] = x;
+  }
+  __syncthreads();
+  for (int s = kB / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) acc[q][threadIdx.x] += acc[q][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < NV; ++q) tot[q] = acc[q][0];
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+// b = -K_{sigma_i} P V_m from the fiber state (row 0: V_m - rest, which the
+// zero row sums of K remove), and the mean of b.
+__global__ __launch_bounds__(kB) void k_emg_rhs(Grid3 g, const float* __restrict__ vm,
+                                                int32_t n_fib, int32_t m, float sigma_i,
+                                                float* __restrict__ b, double* partials,
+                                                Scal* s) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  double v[1] = {0.0};
+  if (t < g.n) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    // node (i', j', k') is fiber j' nx + i' at its node k' m
+    auto get = [&](int64_t idx) {
+      const int64_t ii = idx % g.nx, rr = idx / g.nx;
+      const int64_t jj = rr % g.ny, kk = rr / g.ny;
+      return vm[(jj * g.nx + ii) * (int64_t)n_fib + kk * m];
+    };
+    float d;
+    const float val = -apply_row(g, 0.0f, 0.0f, sigma_i, i, j, k, get, d);
+    b[t] = val;
+    v[0] = val;
+  }
+  double tot[1];
+  if (reduce_last<1>(v, partials, &s->counter[0], tot) && threadIdx.x == 0)
+    s->mean_b = tot[0] / (double)g.n;
+}
+
+// Start of CG from the last solution x: bp = b - mean(b), r = bp - A x,
+// z = r / diag, and the sums r.z, bp.bp, r.r.
+__global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, float dz,
+                                                  const float* __restrict__ b,
+                                                  const float* __restrict__ x,
+                                                  float* __restrict__ r, float* __restrict__ z,
+                                                  double* partials, Scal* s) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  double v[3] = {0.0, 0.0, 0.0};
+  if (t < g.n) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    float d;
+    const float ax = apply_row(g, dx, dy, dz, i, j, k, [&](int64_t q) { return x[q]; }, d);
+    const float bp = b[t] - (float)s->mean_b;
+    const float rt = bp - ax;
+    const float zt = rt / d;
+    r[t] = rt;
+    z[t] = zt;
+    v[0] = (double)rt * zt;
+    v[1] = (double)bp * bp;
+    v[2] = (double)rt * rt;
+  }
+  double tot[3];
+  if (reduce_last<3>(v, partials, &s->counter[1], tot) && threadIdx.x == 0) {
+    s->rz = tot[0];
+    s->bb = tot[1];
+    s->rr = tot[2];
+    s->beta = 0.0;
+    s->it = 0;
+    s->done = (tot[1] == 0.0 || tot[2] <= s->tol2 * tot[1]) ? 1 : 0;
+  }
+}
+
+// p_new = z + beta p_old and q = A p_new; the sum p.q and alpha = r.z / p.q.
+__global__ __launch_bounds__(kB) void k_cg_q(Grid3 g, float dx, float dy, float dz,
+                                             const float* __restrict__ z,
+                                             const float* __restrict__ p_old,
+                                             float* __restrict__ p_new, float* __restrict__ q,
+                                             double* partials, Scal* s) {
+  if (s->done) return;
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const float beta = (float)s->beta;
+  double v[1] = {0.0};
+  if (t < g.n) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    float d;
+    const float qt = apply_row(g, dx, dy, dz, i, j, k,
+                               [&](int64_t n) { return fmaf(beta, p_old[n], z[n]); }, d);
+    const float pt = fmaf(beta, p_old[t], z[t]);
+    p_new[t] = pt;
+    q[t] = qt;
+    v[0] = (double)pt * qt;
+  }
+  double tot[1];
+  if (reduce_last<1>(v, partials, &s->counter[2], tot) && threadIdx.x == 0)
+    s->alpha = tot[0] > 0.0 ? s->rz / tot[0] : 0.0;
+}
+
+// x += alpha p, r -= alpha q, z = r / diag; the sums r.z and r.r, beta and
+// the convergence test.
+__global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, float dx, float dy, float dz,
+                                             const float* __restrict__ p,
+                                             const float* __restrict__ q, float* __restrict__ x,
+                                             float* __restrict__ r, float* __restrict__ z,
+                                             double* partials, Scal* s) {
+  if (s->done) return;
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  const float alpha = (float)s->alpha;
+  double v[2] = {0.0, 0.0};
+  if (t < g.n) {
+    int i, j, k;
+    node_ijk(g, t, i, j, k);
+    float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
+    weights_1d(i, g.nx, g.hx, Kx, Mx);
+    weights_1d(j, g.ny, g.hy, Ky, My);
+    weights_1d(k, g.nz, g.hz, Kz, Mz);
+    const float d = dx * Kx[1] * My[1] * Mz[1] + dy * Mx[1] * Ky[1] * Mz[1] +
+                    dz * Mx[1] * My[1] * Kz[1];
+    x[t] = fmaf(alpha, p[t], x[t]);
+    const float rt = fmaf(-alpha, q[t], r[t]);
+    const float zt = rt / d;
+    r[t] = rt;
+    z[t] = zt;
+    v[0] = (double)rt * zt;
+    v[1] = (double)rt * rt;
+  }
+  double tot[2];
+  if (reduce_last<2>(v, partials, &s->counter[3], tot) && threadIdx.x == 0) {
+    s->beta = s->rz > 0.0 ? tot[0] / s->rz : 0.0;
+    s->rz = tot[0];
+    s->rr = tot[1];
+    s->it += 1;
+    s->done = (tot[1] <= s->tol2 * s->bb || s->it >= s->max_it) ? 1 : 0;
+  }
+}
+
+// x -= mean(x) in two launches: the sum, then the subtraction.
+__global__ __launch_bounds__(kB) void k_emg_sum(Grid3 g, const float* __restrict__ x,
+                                                double* partials, Scal* s) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  double v[1] = {t < g.n ? (double)x[t] : 0.0};
+  double tot[1];
+  if (reduce_last<1>(v, partials, &s->counter[0], tot) && threadIdx.x == 0)
+    s->mean_b = tot[0] / (double)g.n;  // reused: the mean of x
+}
+
+__global__ __launch_bounds__(kB) void k_emg_shift(Grid3 g, float* __restrict__ x, const Scal* s) {
+  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+  if (t < g.n) x[t] -= (float)s->mean_b;
+}
+
+int efail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  return fib::set_error(code, buf);
+}
+
+#define EHIP(expr)                                                                    \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return efail(FIB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+}  // namespace
+
+struct fib_emg {
+  fib_t* ctx = nullptr;
+  fib_emg_params p{};
+  Grid3 g{};
+  int32_t n_fib = 0;          // nodes per fiber
+  float* d_vec = nullptr;     // b, x, r, z, p0, p1, q (n each)
+  double* d_part = nullptr;   // 3 x blocks partial sums
+  Scal* d_s = nullptr;
+  Scal* h_s = nullptr;        // pinned copy of the scalars
+  unsigned blocks = 0;
+  float* b() const { return d_vec; }
+  float* x() const { return d_vec + g.n; }
+  float* r() const { return d_vec + 2 * g.n; }
+  float* z() const { return d_vec + 3 * g.n; }
+  float* pb(int i) const { return d_vec + (4 + i) * g.n; }
+  float* q() const { return d_vec + 6 * g.n; }
+};
+
+extern "C" {
+
+int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
+  if (!out) return efail(FIB_EINVAL, "null output pointer");
+  *out = nullptr;
+  if (!ctx || !p) return efail(FIB_EINVAL, "null argument");
+  const fib::CtxView v = fib::ctx_view(ctx);
+  if (v.model != FIB_MODEL_HH && v.model != FIB_MODEL_HH_APX_EXP)
+    return efail(FIB_EUNSUPPORTED, "EMG takes the Hodgkin-Huxley models");
+  if (p->nx < 2 || p->ny < 2 || p->stride < 1)
+    return efail(FIB_EINVAL, "nx, ny must be >= 2 and the stride >= 1");
+  auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };
+  if (!pos(p->hx) || !pos(p->hy) || !pos(p->sigma_i) || !pos(p->sigma_el) || !pos(p->sigma_et))
+    return efail(FIB_EINVAL, "spacings and conductivities must be > 0");
+  if ((int64_t)p->nx * p->ny != v.n_fibers)
+    return efail(FIB_EINVAL, "%d x %d fibers expected, the context has %d", p->nx, p->ny,
+                 v.n_fibers);
+  const int32_t n = v.n_nodes[0];
+  for (int32_t f = 1; f < v.n_fibers; ++f)
+    if (v.n_nodes[f] != n) return efail(FIB_EINVAL, "fibers of unequal length");
+  if (n < 2 || (n - 1) % p->stride != 0)
+    return efail(FIB_EINVAL, "fiber length %d: (n - 1) must be a positive multiple of %d", n,
+                 p->stride);
+  fib_emg* e = new (std::nothrow) fib_emg();
+  if (!e) return efail(FIB_ENOMEM, "host allocation failed");
+  e->ctx = ctx;
+  e->p = *p;
+  e->n_fib = n;
+  e->g.nx = p->nx;
+  e->g.ny = p->ny;
+  e->g.nz = (n - 1) / p->stride + 1;
+  e->g.hx = (float)p->hx;
+  e->g.hy = (float)p->hy;
+  e->g.hz = (float)(p->stride * v.h);
+  e->g.n = (int64_t)e->g.nx * e->g.ny * e->g.nz;
+  e->blocks = (unsigned)((e->g.n + kB - 1) / kB);
+  const size_t nv = (size_t)e->g.n * 7;
+  if (hipMalloc(&e->d_vec, sizeof(float) * nv) != hipSuccess ||
+      hipMalloc(&e->d_part, sizeof(double) * 3 * e->blocks) != hipSuccess ||
+      hipMalloc(&e->d_s, sizeof(Scal)) != hipSuccess ||
+      hipHostMalloc(&e->h_s, sizeof(Scal)) != hipSuccess) {
+    fib_emg_destroy(e);
+    return efail(FIB_ENOMEM, "device allocation failed");
+  }
+  if (hipMemset(e->d_vec, 0, sizeof(float) * nv) != hipSuccess ||
+      hipMemset(e->d_s, 0, sizeof(Scal)) != hipSuccess) {
+    fib_emg_destroy(e);
+    return efail(FIB_EHIP, "device initialisation failed");
+  }
+  *out = e;
+  return FIB_OK;
+}
+
+void fib_emg_destroy(fib_emg_t* e) {
+  if (!e) return;
+  (void)hipFree(e->d_vec);
+  (void)hipFree(e->d_part);
+  (void)hipFree(e->d_s);
+  if (e->h_s) (void)hipHostFree(e->h_s);
+  delete e;
+}
+
+int fib_emg_dims(const fib_emg_t* e, int32_t* nx, int32_t* ny, int32_t* nz) {
+  if (!e) return efail(FIB_EINVAL, "null EMG handle");
+  if (nx) *nx = e->g.nx;
+  if (ny) *ny = e->g.ny;
+  if (nz) *nz = e->g.nz;
+  return FIB_OK;
+}
+
+int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, double* rel_res) {
+  if (!e) return efail(FIB_EINVAL, "null EMG handle");
+  if (!(std::isfinite(tol) && tol > 0.0) || max_iter < 0)
+    return efail(FIB_EINVAL, "tol must be > 0 and max_iter >= 0");
+  const fib::CtxView v = fib::ctx_view(e->ctx);
+  if (!v.state_ready) return efail(FIB_ESTATE, "state not initialized");
+  hipStream_t st = v.stream;
+  const Grid3 g = e->g;
+  const float dx = (float)e->p.sigma_et, dy = (float)e->p.sigma_et,
+              dz = (float)(e->p.sigma_el + e->p.sigma_i);
+  const dim3 grid(e->blocks), block(kB);
+  // scalars: tolerance and iteration limit
+  e->h_s->tol2 = tol * tol;
+  e->h_s->max_it = max_iter;
+  EHIP(hipMemcpyAsync(&e->d_s->tol2, &e->h_s->tol2, sizeof(double), hipMemcpyHostToDevice, st));
+  EHIP(hipMemcpyAsync(&e->d_s->max_it, &e->h_s->max_it, sizeof(int32_t), hipMemcpyHostToDevice,
+                      st));
+  hipLaunchKernelGGL(k_emg_rhs, grid, block, 0, st, g, v.d_state, e->n_fib, e->p.stride,
+                     (float)e->p.sigma_i, e->b(), e->d_part, e->d_s);
+  EHIP(hipGetLastError());
+  hipLaunchKernelGGL(k_emg_start, grid, block, 0, st, g, dx, dy, dz, e->b(), e->x(), e->r(),
+                     e->z(), e->d_part, e->d_s);
+  EHIP(hipGetLastError());
+  int par = 0;
+  int32_t done_it = 0;
+  const int batch = 16;
+  for (int32_t it = 0;; it += batch) {
+    EHIP(hipMemcpyAsync(e->h_s, e->d_s, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    EHIP(hipStreamSynchronize(st));
+    if (e->h_s->done || it >= max_iter) break;
+    const int nb = std::min(batch, max_iter - it);
+    for (int b = 0; b < nb; ++b) {
+      hipLaunchKernelGGL(k_cg_q, grid, block, 0, st, g, dx, dy, dz, e->z(), e->pb(par),
+                         e->pb(par ^ 1), e->q(), e->d_part, e->d_s);
+      hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, dx, dy, dz, e->pb(par ^ 1), e->q(),
+                         e->x(), e->r(), e->z(), e->d_part, e->d_s);
+      par ^= 1;
+    }
+    EHIP(hipGetLastError());
+  }
+  done_it = e->h_s->it;
+  if (e->h_s->bb == 0.0) {
+    // b = 0: phi_e is a constant, zero after the projection
+    EHIP(hipMemsetAsync(e->x(), 0, sizeof(float) * g.n, st));
+  } else {
+    hipLaunchKernelGGL(k_emg_sum, grid, block, 0, st, g, e->x(), e->d_part, e->d_s);
+    hipLaunchKernelGGL(k_emg_shift, grid, block, 0, st, g, e->x(), e->d_s);
+    EHIP(hipGetLastError());
+  }
+  EHIP(hipStreamSynchronize(st));
+  if (iters) *iters = done_it;
+  if (rel_res) *rel_res = e->h_s->bb > 0.0 ? std::sqrt(e->h_s->rr / e->h_s->bb) : 0.0;
+  return FIB_OK;
+}
+
+int fib_emg_get_phi(fib_emg_t* e, double* phi, int64_t n) {
+  if (!e) return efail(FIB_EINVAL, "null EMG handle");
+  if (n != e->g.n || !phi) return efail(FIB_EINVAL, "expected %lld values", (long long)e->g.n);
+  std::vector<float> h(n);
+  EHIP(hipStreamSynchronize(fib::ctx_view(e->ctx).stream));
+  EHIP(hipMemcpy(h.data(), e->x(), sizeof(float) * n, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) phi[i] = h[i];
+  return FIB_OK;
+}
+
+int fib_emg_get_rhs(fib_emg_t* e, double* rhs, int64_t n) {
+  if (!e) return efail(FIB_EINVAL, "null EMG handle");
+  if (n != e->g.n || !rhs) return efail(FIB_EINVAL, "expected %lld values", (long long)e->g.n);
+  std::vector<float> h(n);
+  EHIP(hipStreamSynchronize(fib::ctx_view(e->ctx).stream));
+  EHIP(hipMemcpy(h.data(), e->b(), sizeof(float) * n, hipMemcpyDeviceToHost));
+  for (int64_t i = 0; i < n; ++i) rhs[i] = h[i];
+  return FIB_OK;
+}
+
+}  // extern "C"

@@ -300,6 +300,21 @@ struct fib_ctx {
   bool adapt_fused_ok = false;
 };
 
+namespace fib {
+CtxView ctx_view(const fib_ctx* c) {
+  CtxView v{};
+  v.n_fibers = c->n_fibers;
+  v.n_nodes = c->n_nodes.data();
+  v.n_total = c->n_total;
+  v.d_state = c->d_state;
+  v.h = c->p.h;
+  v.stream = c->stream;
+  v.state_ready = c->state_ready;
+  v.model = c->p.model;
+  return v;
+}
+}  // namespace fib
+
 namespace {
 
 // Packs fibers into `groups` bins: longest-processing-time-first (fibers in

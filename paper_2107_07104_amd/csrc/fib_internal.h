@@ -128,6 +128,23 @@ __device__ __forceinline__ bool stim_eval(uint32_t sid1, const StimDev* __restri
   return true;
 }
 
+// Read-only view of a context for the EMG module (emg.hip).
+struct CtxView {
+  int32_t n_fibers;
+  const int32_t* n_nodes;  // host, n_fibers entries
+  int64_t n_total;
+  float* d_state;          // device state; row 0 holds V_m - rest_V
+  double h;                // node spacing along the fibers (cm)
+  hipStream_t stream;
+  bool state_ready;
+  int model;
+};
+}  // namespace fib
+struct fib_ctx;
+namespace fib {
+CtxView ctx_view(const fib_ctx* c);
+int set_error(int code, const char* msg);
+
 // Launchers (fib_kernels.hip).  Each returns the hipError_t of the launch.
 // Largest workgroup size the kernels are built for with K nodes per thread
 // (0: K not supported).

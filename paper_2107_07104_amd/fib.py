@@ -53,7 +53,8 @@ EXPORTS = (
     "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate",
     "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
-    "fib_adaptive_points",
+    "fib_adaptive_points", "fib_emg_create", "fib_emg_destroy", "fib_emg_dims",
+    "fib_emg_solve", "fib_emg_get_phi", "fib_emg_get_rhs",
 )
 
 
@@ -70,6 +71,12 @@ class fib_stim(C.Structure):
     _fields_ = [("fiber", C.c_int32), ("node", C.c_int32), ("half_width", C.c_int32),
                 ("mode", C.c_int32), ("step_on", C.c_int64), ("n_steps", C.c_int64),
                 ("period", C.c_int64), ("amp", C.c_double)]
+
+
+class fib_emg_params(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("stride", C.c_int32),
+                ("hx", C.c_double), ("hy", C.c_double), ("sigma_i", C.c_double),
+                ("sigma_el", C.c_double), ("sigma_et", C.c_double)]
 
 
 class FibError(RuntimeError):
@@ -136,6 +143,13 @@ def lib():
             "fib_set_adaptive": ([_vp, C.c_double], C.c_int),
             "fib_adaptive_solved": ([_vp, C.POINTER(C.c_int64)], C.c_int),
             "fib_adaptive_points": ([_vp, _vp, C.c_int64], C.c_int),
+            "fib_emg_create": ([_vp, C.POINTER(fib_emg_params), C.POINTER(_vp)], C.c_int),
+            "fib_emg_destroy": ([_vp], None),
+            "fib_emg_dims": ([_vp, _i32p, _i32p, _i32p], C.c_int),
+            "fib_emg_solve": ([_vp, C.c_double, C.c_int32, _i32p, C.POINTER(C.c_double)],
+                              C.c_int),
+            "fib_emg_get_phi": ([_vp, _dp, C.c_int64], C.c_int),
+            "fib_emg_get_rhs": ([_vp, _dp, C.c_int64], C.c_int),
         })
         for name, (args, res) in sig.items():
             f = getattr(L, name)
@@ -273,6 +287,74 @@ def fib_adaptive_points(ctx) -> np.ndarray:
     a = np.zeros(max(n, 1), dtype=np.uint8)
     _check(lib().fib_adaptive_points(_vp(ctx), a.ctypes.data_as(_vp), n))
     return a[:n]
+
+
+def fib_emg_create(ctx, nx, ny, stride, hx, hy, sigma_i, sigma_el, sigma_et):
+    p = fib_emg_params(int(nx), int(ny), int(stride), float(hx), float(hy), float(sigma_i),
+                       float(sigma_el), float(sigma_et))
+    out = _vp()
+    _check(lib().fib_emg_create(_vp(ctx), C.byref(p), C.byref(out)))
+    return out
+
+
+def fib_emg_destroy(emg) -> None:
+    lib().fib_emg_destroy(emg)
+
+
+def fib_emg_dims(emg):
+    a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+    _check(lib().fib_emg_dims(emg, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def fib_emg_solve(emg, tol: float, max_iter: int):
+    it, rr = C.c_int32(0), C.c_double(0.0)
+    _check(lib().fib_emg_solve(emg, float(tol), int(max_iter), C.byref(it), C.byref(rr)))
+    return it.value, rr.value
+
+
+def fib_emg_get_phi(emg, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    _check(lib().fib_emg_get_phi(emg, out.ctypes.data_as(_dp), n))
+    return out
+
+
+def fib_emg_get_rhs(emg, n: int) -> np.ndarray:
+    out = np.zeros(n)
+    _check(lib().fib_emg_get_rhs(emg, out.ctypes.data_as(_dp), n))
+    return out
+
+
+class Emg:
+    """Static bidomain (EMG) solve attached to a Solver's fiber bundle."""
+
+    def __init__(self, solver, nx, ny, stride, hx, hy, sigma_i=8.93, sigma_el=6.7,
+                 sigma_et=3.35):
+        self.solver = solver
+        self.h = fib_emg_create(solver.ctx, nx, ny, stride, hx, hy, sigma_i, sigma_el, sigma_et)
+        self.dims = fib_emg_dims(self.h)
+        self.n = self.dims[0] * self.dims[1] * self.dims[2]
+
+    def solve(self, tol=1e-6, max_iter=2000):
+        """Returns (iterations, relative residual)."""
+        return fib_emg_solve(self.h, tol, max_iter)
+
+    def phi(self):
+        return fib_emg_get_phi(self.h, self.n)
+
+    def rhs(self):
+        return fib_emg_get_rhs(self.h, self.n)
+
+    def close(self):
+        if self.h:
+            fib_emg_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def fib_reset_observables(ctx) -> None:
