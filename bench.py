@@ -47,6 +47,16 @@ node-steps the adaptive run solved, and the FP64 oracle's V_m /
 activation-time errors of the adaptive run on sampled fibers (against the
 plain method).
 
+`emg` (skipped with --no-emg) couples the static bidomain step to the fiber
+solve: 37 x 37 fibers of 1481 nodes (the headline's stimulus recipe), a 3D
+mesh of every 10th fiber node (37 x 37 x 149 nodes, 0.05 cm between fibers,
+sigma_i 8.93, sigma_e 6.7 along / 3.35 across the fibers, mS/cm), and one
+phi_e solve (CG to a relative residual of 1e-6, warm-started) every
+--emg-every split steps (default 500: 0.5 ms, the 2 kHz sampling of an EMG
+recording) over 20 ms: node-steps/s of the coupled run, the
+share of time in the EMG solves, CG iterations and time per iteration, and
+the FP64 residual of the last phi_e with the oracle's matrices.
+
 `exp_approx` (skipped with --no-exp-approx) runs the headline workload with
 the membrane whose exponentials are exp*(x) = (1 + x/1024)^1024 (the
 thesis's approximation; on gfx950 the native exponential is one FMA and one
@@ -108,6 +118,9 @@ def parse():
     ap.add_argument("--sur-tol", type=float, default=1e-2)
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-exp-approx", action="store_true")
+    ap.add_argument("--no-emg", action="store_true")
+    ap.add_argument("--emg-every", type=int, default=500,
+                    help="split steps between two EMG solves (500: a 2 kHz EMG sampling)")
     ap.add_argument("--adapt-tol", type=float, default=1e-6)
     ap.add_argument("--adapt-cases", default="hh,st57",
                     help="comma-separated adaptive cases to run (hh, st57)")
@@ -460,6 +473,67 @@ def adaptive_bench(args):
     return out
 
 
+def emg_bench(args):
+    """The fiber solve coupled to the static bidomain step (module docstring)."""
+    import torch
+
+    from paper_2107_07104_amd import fib as F
+    from paper_2107_07104_amd import inputs as I
+    from oracle import emg as E
+    nf, n, m, hxy = 37, 1481, 10, 0.05
+    sig = dict(sigma_i=8.93, sigma_el=6.7, sigma_et=3.35)
+    w = I.batched_hh(n_fibers=nf * nf, n_min=n, n_max=n, t_end=args.t_end)
+    s = F.Solver(w.n_nodes, dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split)
+    s.set_stimulus(w.stims)
+    vm = torch.as_tensor(w.vm_noise.astype(np.float32), device="cuda")
+    s.init_state(vm_noise=vm)
+    s.autotune(trial_steps=200, max_candidates=8)
+    emg = F.Emg(s, nf, nf, m, hxy, hxy, **sig)
+    every = args.emg_every
+
+    def run(timed):
+        s.init_state(vm_noise=vm)
+        its, t_emg = [], 0.0
+        t0 = time.perf_counter()
+        for c in range(0, w.n_steps, every):
+            s.run(c, min(every, w.n_steps - c))
+            if timed:
+                s.sync()
+                t1 = time.perf_counter()
+            it, rel = emg.solve(tol=1e-6, max_iter=5000)
+            if timed:
+                t_emg += time.perf_counter() - t1
+            its.append(it)
+        s.sync()
+        return time.perf_counter() - t0, its, t_emg
+
+    run(False)                                   # warm-up (code objects, first solves)
+    secs, its, _ = run(False)
+    _, _, t_emg = run(True)                       # EMG share with a sync around each solve
+    phi = emg.phi()
+    V3 = E.prolongate(s.get_state()[0], nf, nf, n, m)
+    g = E.Grid(nf, nf, (n - 1) // m + 1, hxy, hxy, m * w.h)
+    Ki = E.stiffness_3d(g, (0.0, 0.0, sig["sigma_i"]))
+    Kt = E.stiffness_3d(g, (sig["sigma_et"], sig["sigma_et"], sig["sigma_el"] + sig["sigma_i"]))
+    b = -(Ki @ V3)
+    b -= b.mean()
+    res = float(np.linalg.norm(b - Kt @ phi) / np.linalg.norm(b))
+    plan = s.plan()
+    emg.close()
+    s.close()
+    n_solves = len(its)
+    tot_it = int(sum(its))
+    out = dict(workload=f"hh_emg_{nf}x{nf}x{n}, 3D mesh {nf}x{nf}x{g.nz}, solve every {every} "
+                        f"split steps", value=w.node_steps() / secs, seconds=secs, plan=plan,
+               emg_solves=n_solves, cg_iterations_mean=tot_it / n_solves,
+               cg_iterations_max=int(max(its)), emg_seconds=t_emg,
+               emg_share=t_emg / secs, ms_per_cg_iteration=(t_emg / max(tot_it, 1)) * 1e3,
+               last_phi_fp64_relative_residual=res, mesh_nodes=int(g.n))
+    _log(f"emg: {out['value']:.3e} node-steps/s, {n_solves} solves, {tot_it / n_solves:.1f} "
+         f"CG iterations each, EMG share {out['emg_share']:.2f}, residual {res:.1e}")
+    return out
+
+
 def exp_approx_bench(args):
     """The headline workload with the exp* membrane (see the module docstring)."""
     from dataclasses import replace
@@ -594,13 +668,18 @@ def main():
     sur = None
     adapt = None
     expx = None
-    if not args.no_surrogate or not args.no_adaptive or not args.no_exp_approx:
+    emg = None
+    if (not args.no_surrogate or not args.no_adaptive or not args.no_exp_approx
+            or not args.no_emg):
         s.close()
         s = None
     if not args.no_surrogate:
         sur = {"hh": surrogate_hh(args), "st57": surrogate_st57(args)}
     if not args.no_adaptive:
         adapt = adaptive_bench(args)
+    if not args.no_emg:
+        emg = emg_bench(args)
+        emg["over_plain"] = emg["value"] / value
     if not args.no_exp_approx:
         expx = exp_approx_bench(args)
         expx["over_plain"] = expx["value"] / value
@@ -629,6 +708,7 @@ def main():
         "surrogate": sur,
         "adaptive": adapt,
         "exp_approx": expx,
+        "emg": emg,
     }
     if s is not None:
         s.close()

@@ -12,21 +12,24 @@
 // weights of a node are formed from its (i, j, k) in registers.
 //
 // The solve (eq. discretized_fibers_3) is preconditioned conjugate gradients
-// with the diagonal of K_{sigma_i + sigma_e}.  Each iteration is two
-// launches over the nodes:
+// with the diagonal of K_{sigma_i + sigma_e}.  Each iteration is four
+// launches:
 //   k_cg_q:  p <- z + beta p (the previous p in the other buffer; the
 //            stencil reads the neighbours' z + beta p_old itself), q = A p,
-//            partial sums of p.q;
-//   k_cg_x:  x += alpha p, r -= alpha q, z = r / diag(A), partial sums of
-//            r.z and r.r.
-// Partial sums are per block in FP64; the last block of a launch (the one
-// whose arrival on a counter completes it) adds them in block order -- the
-// same order every time -- and updates the scalars (alpha, beta, the
-// convergence flag) that the next launch reads.  Converged iterations
-// return at once, so the host enqueues batches and checks the flag between
-// them.
+//            per-block sums of p.q;
+//   k_cg_alpha (one block): alpha = r.z / p.q;
+//   k_cg_x:  x += alpha p, r -= alpha q, z = r / diag(A), per-block sums of
+//            r.z and r.r;
+//   k_cg_beta (one block): beta, the convergence test.
+// The per-block sums are FP64 and added in block order by the one-block
+// kernels, so every solve is deterministic; the kernel boundaries order the
+// partial sums and the scalars without device-wide fences.  Converged
+// iterations return at once, so the host enqueues batches and checks the
+// flag between them.  The grid is (blocks per layer, layers): a thread
+// finds (i, j) from its index in the layer and k from the block row.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -55,7 +58,6 @@ struct Scal {
   double alpha, beta;
   double tol2;    // tol^2
   int32_t it, max_it, done;
-  uint32_t counter[4];  // arrivals of the blocks of one launch, per kernel
 };
 
 // 1D linear-element stiffness and mass weights of node i (of n, spacing h)
@@ -102,23 +104,26 @@ __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, f
   return acc;
 }
 
-__device__ __forceinline__ void node_ijk(const Grid3& g, int64_t t, int& i, int& j, int& k) {
-  i = (int)(t % g.nx);
-  const int64_t r = t / g.nx;
-  j = (int)(r % g.ny);
-  k = (int)(r / g.ny);
+// Node of this thread in the (blocks per layer, layers) grid; false past
+// the end of its layer.
+__device__ __forceinline__ bool node_of(const Grid3& g, int& i, int& j, int& k, int64_t& t) {
+  const int tl = (int)blockIdx.x * kB + (int)threadIdx.x;  // index in the layer
+  if (tl >= g.nx * g.ny) return false;
+  i = tl % g.nx;
+  j = tl / g.nx;
+  k = (int)blockIdx.y;
+  t = (int64_t)k * g.nx * g.ny + tl;
+  return true;
 }
 
-// Block sums of NV doubles into partials[v * nblocks + block]; returns true
-// in every thread of the block that arrives last, with the totals (summed
-// in block order) in tot.
+// Per-block sums of NV doubles into partials[v * nblocks + block], in a
+// fixed order (waves by shuffles, then the four waves in order).
 template <int NV>
-__device__ bool reduce_last(double (&v)[NV], double* partials, uint32_t* counter,
-                            double (&tot)[NV]) {
+__device__ __forceinline__ void block_sums(double (&v)[NV], double* partials) {
   __shared__ double sh[NV][kB / 64];
-  __shared__ bool last;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nblocks = (int)gridDim.x;
+  const int nblocks = (int)(gridDim.x * gridDim.y);
+  const int blk = (int)(blockIdx.y * gridDim.x + blockIdx.x);
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double x = v[q];
@@ -127,28 +132,22 @@ __device__ bool reduce_last(double (&v)[NV], double* partials, uint32_t* counter
     if (lane == 0) sh[q][wave] = x;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int q = 0; q < NV; ++q) {
-      double x = 0.0;
-      for (int w = 0; w < kB / 64; ++w) x += sh[q][w];
-      partials[q * nblocks + blockIdx.x] = x;
-    }
-    __threadfence();
-    const uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    last = prev == (uint32_t)nblocks - 1u;
+  if (threadIdx.x < NV) {
+    double x = 0.0;
+    for (int w = 0; w < kB / 64; ++w) x += sh[threadIdx.x][w];
+    partials[threadIdx.x * nblocks + blk] = x;
   }
-  __syncthreads();
-  if (!last) return false;
-  __threadfence();
-  // the last block: every thread adds a fixed strided subset, then a fixed tree
+}
+
+// Totals of the per-block sums, in block order (one block of kB threads:
+// a fixed strided subset per thread, then a fixed tree).
+template <int NV>
+__device__ __forceinline__ void total_sums(const double* partials, int nblocks, double (&tot)[NV]) {
   __shared__ double acc[NV][kB];
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
     double x = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kB)
-      x += __builtin_nontemporal_load(&partials[q * nblocks + b]);
+    for (int b = threadIdx.x; b < nblocks; b += kB) x += partials[q * nblocks + b];
     acc[q][threadIdx.x] = x;
   }
   __syncthreads();
@@ -161,49 +160,49 @@ __device__ bool reduce_last(double (&v)[NV], double* partials, uint32_t* counter
   }
 #pragma unroll
   for (int q = 0; q < NV; ++q) tot[q] = acc[q][0];
-  if (threadIdx.x == 0) *counter = 0u;
-  return true;
 }
 
 // b = -K_{sigma_i} P V_m from the fiber state (row 0: V_m - rest, which the
-// zero row sums of K remove), and the mean of b.
+// zero row sums of K remove); per-block sums of b.
 __global__ __launch_bounds__(kB) void k_emg_rhs(Grid3 g, const float* __restrict__ vm,
                                                 int32_t n_fib, int32_t m, float sigma_i,
-                                                float* __restrict__ b, double* partials,
-                                                Scal* s) {
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+                                                float* __restrict__ b, double* partials) {
+  int i, j, k;
+  int64_t t;
   double v[1] = {0.0};
-  if (t < g.n) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
-    // node (i', j', k') is fiber j' nx + i' at its node k' m
+  if (node_of(g, i, j, k, t)) {
+    // 3D node (i', j', k') is fiber j' nx + i' at its node k' m
+    const int nxy = g.nx * g.ny;
     auto get = [&](int64_t idx) {
-      const int64_t ii = idx % g.nx, rr = idx / g.nx;
-      const int64_t jj = rr % g.ny, kk = rr / g.ny;
-      return vm[(jj * g.nx + ii) * (int64_t)n_fib + kk * m];
+      const int kk = (int)(idx / nxy), f = (int)(idx - (int64_t)kk * nxy);
+      return vm[(int64_t)f * n_fib + (int64_t)kk * m];
     };
     float d;
     const float val = -apply_row(g, 0.0f, 0.0f, sigma_i, i, j, k, get, d);
     b[t] = val;
     v[0] = val;
   }
+  block_sums<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kB) void k_emg_mean(const double* partials, int nblocks, int64_t n,
+                                                 Scal* s) {
   double tot[1];
-  if (reduce_last<1>(v, partials, &s->counter[0], tot) && threadIdx.x == 0)
-    s->mean_b = tot[0] / (double)g.n;
+  total_sums<1>(partials, nblocks, tot);
+  if (threadIdx.x == 0) s->mean_b = tot[0] / (double)n;
 }
 
 // Start of CG from the last solution x: bp = b - mean(b), r = bp - A x,
-// z = r / diag, and the sums r.z, bp.bp, r.r.
+// z = r / diag; per-block sums of r.z, bp.bp, r.r.
 __global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, float dz,
                                                   const float* __restrict__ b,
                                                   const float* __restrict__ x,
                                                   float* __restrict__ r, float* __restrict__ z,
-                                                  double* partials, Scal* s) {
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
+                                                  double* partials, const Scal* s) {
+  int i, j, k;
+  int64_t t;
   double v[3] = {0.0, 0.0, 0.0};
-  if (t < g.n) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
+  if (node_of(g, i, j, k, t)) {
     float d;
     const float ax = apply_row(g, dx, dy, dz, i, j, k, [&](int64_t q) { return x[q]; }, d);
     const float bp = b[t] - (float)s->mean_b;
@@ -215,8 +214,14 @@ __global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, f
     v[1] = (double)bp * bp;
     v[2] = (double)rt * rt;
   }
+  block_sums<3>(v, partials);
+}
+
+__global__ __launch_bounds__(kB) void k_emg_started(const double* partials, int nblocks,
+                                                    Scal* s) {
   double tot[3];
-  if (reduce_last<3>(v, partials, &s->counter[1], tot) && threadIdx.x == 0) {
+  total_sums<3>(partials, nblocks, tot);
+  if (threadIdx.x == 0) {
     s->rz = tot[0];
     s->bb = tot[1];
     s->rr = tot[2];
@@ -226,19 +231,18 @@ __global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, f
   }
 }
 
-// p_new = z + beta p_old and q = A p_new; the sum p.q and alpha = r.z / p.q.
+// p_new = z + beta p_old and q = A p_new; per-block sums of p.q.
 __global__ __launch_bounds__(kB) void k_cg_q(Grid3 g, float dx, float dy, float dz,
                                              const float* __restrict__ z,
                                              const float* __restrict__ p_old,
                                              float* __restrict__ p_new, float* __restrict__ q,
-                                             double* partials, Scal* s) {
+                                             double* partials, const Scal* s) {
   if (s->done) return;
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
   const float beta = (float)s->beta;
+  int i, j, k;
+  int64_t t;
   double v[1] = {0.0};
-  if (t < g.n) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
+  if (node_of(g, i, j, k, t)) {
     float d;
     const float qt = apply_row(g, dx, dy, dz, i, j, k,
                                [&](int64_t n) { return fmaf(beta, p_old[n], z[n]); }, d);
@@ -247,25 +251,28 @@ __global__ __launch_bounds__(kB) void k_cg_q(Grid3 g, float dx, float dy, float 
     q[t] = qt;
     v[0] = (double)pt * qt;
   }
-  double tot[1];
-  if (reduce_last<1>(v, partials, &s->counter[2], tot) && threadIdx.x == 0)
-    s->alpha = tot[0] > 0.0 ? s->rz / tot[0] : 0.0;
+  block_sums<1>(v, partials);
 }
 
-// x += alpha p, r -= alpha q, z = r / diag; the sums r.z and r.r, beta and
-// the convergence test.
+__global__ __launch_bounds__(kB) void k_cg_alpha(const double* partials, int nblocks, Scal* s) {
+  if (s->done) return;
+  double tot[1];
+  total_sums<1>(partials, nblocks, tot);
+  if (threadIdx.x == 0) s->alpha = tot[0] > 0.0 ? s->rz / tot[0] : 0.0;
+}
+
+// x += alpha p, r -= alpha q, z = r / diag; per-block sums of r.z and r.r.
 __global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, float dx, float dy, float dz,
                                              const float* __restrict__ p,
                                              const float* __restrict__ q, float* __restrict__ x,
                                              float* __restrict__ r, float* __restrict__ z,
-                                             double* partials, Scal* s) {
+                                             double* partials, const Scal* s) {
   if (s->done) return;
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
   const float alpha = (float)s->alpha;
+  int i, j, k;
+  int64_t t;
   double v[2] = {0.0, 0.0};
-  if (t < g.n) {
-    int i, j, k;
-    node_ijk(g, t, i, j, k);
+  if (node_of(g, i, j, k, t)) {
     float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
     weights_1d(i, g.nx, g.hx, Kx, Mx);
     weights_1d(j, g.ny, g.hy, Ky, My);
@@ -280,8 +287,14 @@ __global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, float dx, float dy, float 
     v[0] = (double)rt * zt;
     v[1] = (double)rt * rt;
   }
+  block_sums<2>(v, partials);
+}
+
+__global__ __launch_bounds__(kB) void k_cg_beta(const double* partials, int nblocks, Scal* s) {
+  if (s->done) return;
   double tot[2];
-  if (reduce_last<2>(v, partials, &s->counter[3], tot) && threadIdx.x == 0) {
+  total_sums<2>(partials, nblocks, tot);
+  if (threadIdx.x == 0) {
     s->beta = s->rz > 0.0 ? tot[0] / s->rz : 0.0;
     s->rz = tot[0];
     s->rr = tot[1];
@@ -290,19 +303,19 @@ __global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, float dx, float dy, float 
   }
 }
 
-// x -= mean(x) in two launches: the sum, then the subtraction.
+// x -= mean(x): the per-block sums, the mean, the subtraction.
 __global__ __launch_bounds__(kB) void k_emg_sum(Grid3 g, const float* __restrict__ x,
-                                                double* partials, Scal* s) {
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
-  double v[1] = {t < g.n ? (double)x[t] : 0.0};
-  double tot[1];
-  if (reduce_last<1>(v, partials, &s->counter[0], tot) && threadIdx.x == 0)
-    s->mean_b = tot[0] / (double)g.n;  // reused: the mean of x
+                                                double* partials) {
+  int i, j, k;
+  int64_t t;
+  double v[1] = {node_of(g, i, j, k, t) ? (double)x[t] : 0.0};
+  block_sums<1>(v, partials);
 }
 
 __global__ __launch_bounds__(kB) void k_emg_shift(Grid3 g, float* __restrict__ x, const Scal* s) {
-  const int64_t t = (int64_t)blockIdx.x * kB + threadIdx.x;
-  if (t < g.n) x[t] -= (float)s->mean_b;
+  int i, j, k;
+  int64_t t;
+  if (node_of(g, i, j, k, t)) x[t] -= (float)s->mean_b;
 }
 
 int efail(int code, const char* fmt, ...) {
@@ -331,7 +344,8 @@ struct fib_emg {
   double* d_part = nullptr;   // 3 x blocks partial sums
   Scal* d_s = nullptr;
   Scal* h_s = nullptr;        // pinned copy of the scalars
-  unsigned blocks = 0;
+  dim3 grid;                  // (blocks per layer, layers)
+  int nblocks = 0;
   float* b() const { return d_vec; }
   float* x() const { return d_vec + g.n; }
   float* r() const { return d_vec + 2 * g.n; }
@@ -375,10 +389,11 @@ int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
   e->g.hy = (float)p->hy;
   e->g.hz = (float)(p->stride * v.h);
   e->g.n = (int64_t)e->g.nx * e->g.ny * e->g.nz;
-  e->blocks = (unsigned)((e->g.n + kB - 1) / kB);
+  e->grid = dim3((unsigned)((e->g.nx * e->g.ny + kB - 1) / kB), (unsigned)e->g.nz);
+  e->nblocks = (int)(e->grid.x * e->grid.y);
   const size_t nv = (size_t)e->g.n * 7;
   if (hipMalloc(&e->d_vec, sizeof(float) * nv) != hipSuccess ||
-      hipMalloc(&e->d_part, sizeof(double) * 3 * e->blocks) != hipSuccess ||
+      hipMalloc(&e->d_part, sizeof(double) * 3 * e->nblocks) != hipSuccess ||
       hipMalloc(&e->d_s, sizeof(Scal)) != hipSuccess ||
       hipHostMalloc(&e->h_s, sizeof(Scal)) != hipSuccess) {
     fib_emg_destroy(e);
@@ -420,7 +435,8 @@ int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, do
   const Grid3 g = e->g;
   const float dx = (float)e->p.sigma_et, dy = (float)e->p.sigma_et,
               dz = (float)(e->p.sigma_el + e->p.sigma_i);
-  const dim3 grid(e->blocks), block(kB);
+  const dim3 grid = e->grid, block(kB), one(1);
+  const int nb = e->nblocks;
   // scalars: tolerance and iteration limit
   e->h_s->tol2 = tol * tol;
   e->h_s->max_it = max_iter;
@@ -428,34 +444,41 @@ int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, do
   EHIP(hipMemcpyAsync(&e->d_s->max_it, &e->h_s->max_it, sizeof(int32_t), hipMemcpyHostToDevice,
                       st));
   hipLaunchKernelGGL(k_emg_rhs, grid, block, 0, st, g, v.d_state, e->n_fib, e->p.stride,
-                     (float)e->p.sigma_i, e->b(), e->d_part, e->d_s);
-  EHIP(hipGetLastError());
+                     (float)e->p.sigma_i, e->b(), e->d_part);
+  hipLaunchKernelGGL(k_emg_mean, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
   hipLaunchKernelGGL(k_emg_start, grid, block, 0, st, g, dx, dy, dz, e->b(), e->x(), e->r(),
                      e->z(), e->d_part, e->d_s);
+  hipLaunchKernelGGL(k_emg_started, one, block, 0, st, e->d_part, nb, e->d_s);
   EHIP(hipGetLastError());
   int par = 0;
-  int32_t done_it = 0;
-  const int batch = 16;
-  for (int32_t it = 0;; it += batch) {
+  // batches grow from 8 iterations, so that a converged solve wastes few
+  // no-op launches and a long one few host round trips
+  int batch = 8;
+  for (int32_t it = 0;;) {
     EHIP(hipMemcpyAsync(e->h_s, e->d_s, sizeof(Scal), hipMemcpyDeviceToHost, st));
     EHIP(hipStreamSynchronize(st));
     if (e->h_s->done || it >= max_iter) break;
-    const int nb = std::min(batch, max_iter - it);
-    for (int b = 0; b < nb; ++b) {
+    const int n_it = std::min(batch, max_iter - it);
+    for (int b = 0; b < n_it; ++b) {
       hipLaunchKernelGGL(k_cg_q, grid, block, 0, st, g, dx, dy, dz, e->z(), e->pb(par),
                          e->pb(par ^ 1), e->q(), e->d_part, e->d_s);
+      hipLaunchKernelGGL(k_cg_alpha, one, block, 0, st, e->d_part, nb, e->d_s);
       hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, dx, dy, dz, e->pb(par ^ 1), e->q(),
                          e->x(), e->r(), e->z(), e->d_part, e->d_s);
+      hipLaunchKernelGGL(k_cg_beta, one, block, 0, st, e->d_part, nb, e->d_s);
       par ^= 1;
     }
     EHIP(hipGetLastError());
+    it += n_it;
+    batch = std::min(2 * batch, 64);
   }
-  done_it = e->h_s->it;
+  const int32_t done_it = e->h_s->it;
   if (e->h_s->bb == 0.0) {
     // b = 0: phi_e is a constant, zero after the projection
     EHIP(hipMemsetAsync(e->x(), 0, sizeof(float) * g.n, st));
   } else {
-    hipLaunchKernelGGL(k_emg_sum, grid, block, 0, st, g, e->x(), e->d_part, e->d_s);
+    hipLaunchKernelGGL(k_emg_sum, grid, block, 0, st, g, e->x(), e->d_part);
+    hipLaunchKernelGGL(k_emg_mean, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
     hipLaunchKernelGGL(k_emg_shift, grid, block, 0, st, g, e->x(), e->d_s);
     EHIP(hipGetLastError());
   }
