@@ -13,7 +13,10 @@
 // Every exponential is one v_exp_f32 (2^x) whose argument is a single FMA in
 // V: the 1/ln 2 factor, the 1/10, 1/18, 1/20, 1/80 slopes, the +75 shift and
 // the prefactors 4, 0.07, 0.125 (as +log2 of the prefactor) are folded into
-// the FMA's constants.
+// the FMA's constants.  The three exponentials of slope -1/10 differ only by
+// constant factors, exp(-(V+65)/10) = exp(-(V+50)/10) e^-1.5 and
+// exp(-(V+45)/10) = exp(-(V+50)/10) e^0.5, so they take one v_exp_f32 and
+// two multiplications.
 //
 // The APX variant replaces every exponential by exp*(x) = (1 + x/n)^n,
 // n = 1024 (eq. apx-e-function).  Ten squarings of 1 + x/n in FP32 would
@@ -101,13 +104,15 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
   const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
   float am, an, bm, ah, bh, bn;
   if constexpr (!APX) {
+    constexpr float kEm15 = 0.22313016014842982893f;  // e^-1.5
+    constexpr float kE05 = 1.6487212707001281468f;    // e^0.5
     const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
-    const float en = ex2(fmaf(V, kXn.k1, kXn.k0));
+    const float en = em * kEm15;                      // exp(x_n)
     am = x_over_expm1(xm, em);
     an = 0.1f * x_over_expm1(xn, en);
     bm = ex2(fmaf(V, kBm.k1, kBm.k0));
     ah = ex2(fmaf(V, kAh.k1, kAh.k0));
-    bh = rcp(ex2(fmaf(V, kBh.k1, kBh.k0)) + 1.0f);
+    bh = rcp(fmaf(em, kE05, 1.0f));                   // 1 / (exp((30-v)/10) + 1)
     bn = ex2(fmaf(V, kBn.k1, kBn.k0));
   } else {
     // x / (exp*(x) - 1) = x / d; near x = 0 its series 1 - (n-1)/(2n) x
