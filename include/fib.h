@@ -436,9 +436,11 @@ int fib_emg_dims(const fib_emg_t* emg, int32_t* nx, int32_t* ny, int32_t* nz);
  * right-hand side b = -K_{sigma_i} P V_m (V_m taken relative to the
  * resting potential, which K_{sigma_i} annihilates), projected to zero mean;
  * then conjugate gradients with the diagonal of K_{sigma_i + sigma_e} as
- * preconditioner, started from the last phi_e, until
- * ||r||_2 <= tol ||b||_2 or max_iter iterations; phi_e is returned to zero
- * mean.  FP32 vectors, FP64 reductions.  iters and rel_res (nullable)
+ * preconditioner, started from the last phi_e, with the residual kept at
+ * zero mean (the range of the singular Neumann operator) in every
+ * iteration, until ||r||_2 <= tol ||b||_2 or max_iter iterations; phi_e is
+ * returned to zero mean.  FP32 vectors, FP64 reductions; tolerances down to
+ * about 1e-9 are reachable.  iters and rel_res (nullable)
  * receive the iterations taken and ||r|| / ||b|| (0 if b = 0).  Blocking. */
 int fib_emg_solve(fib_emg_t* emg, double tol, int32_t max_iter, int32_t* iters,
                   double* rel_res);

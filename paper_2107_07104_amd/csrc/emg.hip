@@ -11,16 +11,32 @@
 // boundary).  The operator is applied matrix-free: no matrix is stored, the
 // weights of a node are formed from its (i, j, k) in registers.
 //
+// A row is applied as sum_{j != t} w_tj (u_j - u_t): K_D u with the diagonal
+// taken as minus the row's off-diagonal weights, which is exact for K_D
+// (its rows sum to zero).  In FP32 this keeps the constant vector an exact
+// null vector of the operator, as it is of K_D, so the projected Neumann
+// system stays consistent and semi-definite.  Applied with the centre weight
+// rounded on its own, the operator's constant mode has an eigenvalue of the
+// size of the rounding and of either sign (about -3e-8 of the diagonal on a
+// 3 x 7 x 121 mesh), and CG diverges once it resolves that mode.
+//
 // The solve (eq. discretized_fibers_3) is preconditioned conjugate gradients
-// with the diagonal of K_{sigma_i + sigma_e}.  Each iteration is four
-// launches:
-//   k_cg_q:  p <- z + beta p (the previous p in the other buffer; the
-//            stencil reads the neighbours' z + beta p_old itself), q = A p,
+// with the diagonal of K_{sigma_i + sigma_e} on the Neumann system, kept in
+// the range of the operator: the stored residual r is the raw update, and
+// its mean c is removed wherever it is used (z = (r - c) / diag).  Rounding
+// in r -= alpha q moves the residual's sum away from zero by a random walk
+// that no CG step can reduce (the constant is the operator's null vector);
+// left in, it dominates r.z once the residual is small and CG diverges.
+// The projected scalars come from four sums of the raw r:
+//   r.z = sum r^2/d - 2 c sum r/d + c^2 sum 1/d,  r.r = sum r^2 - n c^2.
+// Each iteration is four launches:
+//   k_cg_q:  p <- (r - c)/d + beta p (the previous p in the other buffer;
+//            the stencil forms its neighbours' p itself), q = A p,
 //            per-block sums of p.q;
 //   k_cg_alpha (one block): alpha = r.z / p.q;
-//   k_cg_x:  x += alpha p, r -= alpha q, z = r / diag(A), per-block sums of
-//            r.z and r.r;
-//   k_cg_beta (one block): beta, the convergence test.
+//   k_cg_x:  x += alpha p, r <- (r - c) - alpha q, per-block sums of r,
+//            r^2, r/d, r^2/d;
+//   k_cg_beta (one block): c, r.z, r.r, beta, the convergence test.
 // The per-block sums are FP64 and added in block order by the one-block
 // kernels, so every solve is deterministic; the kernel boundaries order the
 // partial sums and the scalars without device-wide fences.  Converged
@@ -53,12 +69,23 @@ struct Grid3 {
 struct Scal {
   double mean_b;  // mean of the raw right-hand side
   double bb;      // ||b||^2 after the projection
-  double rz;      // r.z of the current iterate
-  double rr;      // r.r of the current iterate
+  double c;       // mean of the stored (raw) residual
+  double rz;      // r.z of the projected residual
+  double rr;      // r.r of the projected residual
   double alpha, beta;
+  double sd;      // sum of 1 / diag(A)
   double tol2;    // tol^2
   int32_t it, max_it, done;
 };
+
+// Projected r.z and r.r from the sums of the raw residual (S1 = sum r,
+// S2 = sum r^2, S1d = sum r/d, S2d = sum r^2/d).
+__device__ __forceinline__ void project(const double (&t)[4], int64_t n, Scal* s) {
+  const double c = t[0] / (double)n;
+  s->c = c;
+  s->rz = fmax(t[3] - 2.0 * c * t[2] + c * c * s->sd, 0.0);
+  s->rr = fmax(t[1] - (double)n * c * c, 0.0);
+}
 
 // 1D linear-element stiffness and mass weights of node i (of n, spacing h)
 // towards its neighbours i - 1, i, i + 1; a missing neighbour weighs 0.
@@ -74,7 +101,8 @@ __device__ __forceinline__ void weights_1d(int i, int n, float h, float (&K)[3],
 }
 
 // Row (i, j, k) of K_D applied to the field `get` (a functor of the node
-// index); diag receives the diagonal weight.
+// index) in the difference form sum_{j != t} w_tj (u_j - u_t); diag
+// receives the diagonal weight of K_D (the Jacobi preconditioner).
 template <class Get>
 __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, float dz, int i,
                                            int j, int k, Get get, float& diag) {
@@ -82,6 +110,7 @@ __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, f
   weights_1d(i, g.nx, g.hx, Kx, Mx);
   weights_1d(j, g.ny, g.hy, Ky, My);
   weights_1d(k, g.nz, g.hz, Kz, Mz);
+  const float uc = get(((int64_t)k * g.ny + j) * g.nx + i);
   float acc = 0.0f;
   diag = 0.0f;
 #pragma unroll
@@ -95,9 +124,12 @@ __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, f
         if (Mx[a] == 0.0f) continue;
         const float w = dx * Kx[a] * My[b] * Mz[c] + dy * Mx[a] * Ky[b] * Mz[c] +
                         dz * Mx[a] * My[b] * Kz[c];
+        if (a == 1 && b == 1 && c == 1) {
+          diag = w;
+          continue;
+        }
         const int64_t idx = ((int64_t)(k + c - 1) * g.ny + (j + b - 1)) * g.nx + (i + a - 1);
-        acc = fmaf(w, get(idx), acc);
-        if (a == 1 && b == 1 && c == 1) diag = w;
+        acc = fmaf(w, get(idx) - uc, acc);
       }
     }
   }
@@ -162,8 +194,8 @@ __device__ __forceinline__ void total_sums(const double* partials, int nblocks, 
   for (int q = 0; q < NV; ++q) tot[q] = acc[q][0];
 }
 
-// b = -K_{sigma_i} P V_m from the fiber state (row 0: V_m - rest, which the
-// zero row sums of K remove); per-block sums of b.
+// b = -K_{sigma_i} P V_m from the fiber state (row 0: V_m - rest; the
+// difference form sees only differences of V_m); per-block sums of b.
 __global__ __launch_bounds__(kB) void k_emg_rhs(Grid3 g, const float* __restrict__ vm,
                                                 int32_t n_fib, int32_t m, float sigma_i,
                                                 float* __restrict__ b, double* partials) {
@@ -192,61 +224,95 @@ __global__ __launch_bounds__(kB) void k_emg_mean(const double* partials, int nbl
   if (threadIdx.x == 0) s->mean_b = tot[0] / (double)n;
 }
 
-// Start of CG from the last solution x: bp = b - mean(b), r = bp - A x,
-// z = r / diag; per-block sums of r.z, bp.bp, r.r.
+// 1 / diag(A) of every node and per-block sums of it.
+__global__ __launch_bounds__(kB) void k_emg_invd(Grid3 g, float dx, float dy, float dz,
+                                                 float* __restrict__ invd, double* partials) {
+  int i, j, k;
+  int64_t t;
+  double v[1] = {0.0};
+  if (node_of(g, i, j, k, t)) {
+    float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
+    weights_1d(i, g.nx, g.hx, Kx, Mx);
+    weights_1d(j, g.ny, g.hy, Ky, My);
+    weights_1d(k, g.nz, g.hz, Kz, Mz);
+    const float d = dx * Kx[1] * My[1] * Mz[1] + dy * Mx[1] * Ky[1] * Mz[1] +
+                    dz * Mx[1] * My[1] * Kz[1];
+    const float w = 1.0f / d;
+    invd[t] = w;
+    v[0] = w;
+  }
+  block_sums<1>(v, partials);
+}
+
+__global__ __launch_bounds__(kB) void k_emg_sd(const double* partials, int nblocks, Scal* s) {
+  double tot[1];
+  total_sums<1>(partials, nblocks, tot);
+  if (threadIdx.x == 0) s->sd = tot[0];
+}
+
+// Sums of the raw residual rt for project(): r, r^2, r/d, r^2/d.
+__device__ __forceinline__ void residual_sums(float rt, float wd, double* v) {
+  const double r = rt, rw = (double)rt * wd;
+  v[0] = r;
+  v[1] = r * r;
+  v[2] = rw;
+  v[3] = rw * r;
+}
+
+// Start of CG from the last solution x: bp = b - mean(b), r = bp - A x;
+// per-block sums of r, r^2, r/d, r^2/d and bp.bp.
 __global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, float dz,
                                                   const float* __restrict__ b,
                                                   const float* __restrict__ x,
-                                                  float* __restrict__ r, float* __restrict__ z,
-                                                  double* partials, const Scal* s) {
+                                                  const float* __restrict__ invd,
+                                                  float* __restrict__ r, double* partials,
+                                                  const Scal* s) {
   int i, j, k;
   int64_t t;
-  double v[3] = {0.0, 0.0, 0.0};
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (node_of(g, i, j, k, t)) {
     float d;
     const float ax = apply_row(g, dx, dy, dz, i, j, k, [&](int64_t q) { return x[q]; }, d);
     const float bp = b[t] - (float)s->mean_b;
     const float rt = bp - ax;
-    const float zt = rt / d;
     r[t] = rt;
-    z[t] = zt;
-    v[0] = (double)rt * zt;
-    v[1] = (double)bp * bp;
-    v[2] = (double)rt * rt;
+    residual_sums(rt, invd[t], v);
+    v[4] = (double)bp * bp;
   }
-  block_sums<3>(v, partials);
+  block_sums<5>(v, partials);
 }
 
 __global__ __launch_bounds__(kB) void k_emg_started(const double* partials, int nblocks,
-                                                    Scal* s) {
-  double tot[3];
-  total_sums<3>(partials, nblocks, tot);
+                                                    int64_t n, Scal* s) {
+  double tot[5];
+  total_sums<5>(partials, nblocks, tot);
   if (threadIdx.x == 0) {
-    s->rz = tot[0];
-    s->bb = tot[1];
-    s->rr = tot[2];
+    const double t4[4] = {tot[0], tot[1], tot[2], tot[3]};
+    project(t4, n, s);
+    s->bb = tot[4];
     s->beta = 0.0;
     s->it = 0;
-    s->done = (tot[1] == 0.0 || tot[2] <= s->tol2 * tot[1]) ? 1 : 0;
+    s->done = (tot[4] == 0.0 || s->rr <= s->tol2 * tot[4]) ? 1 : 0;
   }
 }
 
-// p_new = z + beta p_old and q = A p_new; per-block sums of p.q.
+// p_new = (r - c)/d + beta p_old and q = A p_new; per-block sums of p.q.
 __global__ __launch_bounds__(kB) void k_cg_q(Grid3 g, float dx, float dy, float dz,
-                                             const float* __restrict__ z,
+                                             const float* __restrict__ r,
+                                             const float* __restrict__ invd,
                                              const float* __restrict__ p_old,
                                              float* __restrict__ p_new, float* __restrict__ q,
                                              double* partials, const Scal* s) {
   if (s->done) return;
-  const float beta = (float)s->beta;
+  const float beta = (float)s->beta, c = (float)s->c;
   int i, j, k;
   int64_t t;
   double v[1] = {0.0};
   if (node_of(g, i, j, k, t)) {
+    auto pn = [&](int64_t n) { return fmaf(beta, p_old[n], (r[n] - c) * invd[n]); };
     float d;
-    const float qt = apply_row(g, dx, dy, dz, i, j, k,
-                               [&](int64_t n) { return fmaf(beta, p_old[n], z[n]); }, d);
-    const float pt = fmaf(beta, p_old[t], z[t]);
+    const float qt = apply_row(g, dx, dy, dz, i, j, k, pn, d);
+    const float pt = pn(t);
     p_new[t] = pt;
     q[t] = qt;
     v[0] = (double)pt * qt;
@@ -261,45 +327,37 @@ __global__ __launch_bounds__(kB) void k_cg_alpha(const double* partials, int nbl
   if (threadIdx.x == 0) s->alpha = tot[0] > 0.0 ? s->rz / tot[0] : 0.0;
 }
 
-// x += alpha p, r -= alpha q, z = r / diag; per-block sums of r.z and r.r.
-__global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, float dx, float dy, float dz,
-                                             const float* __restrict__ p,
-                                             const float* __restrict__ q, float* __restrict__ x,
-                                             float* __restrict__ r, float* __restrict__ z,
+// x += alpha p, r <- (r - c) - alpha q; per-block sums of r, r^2, r/d, r^2/d.
+__global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, const float* __restrict__ p,
+                                             const float* __restrict__ q,
+                                             const float* __restrict__ invd,
+                                             float* __restrict__ x, float* __restrict__ r,
                                              double* partials, const Scal* s) {
   if (s->done) return;
-  const float alpha = (float)s->alpha;
+  const float alpha = (float)s->alpha, c = (float)s->c;
   int i, j, k;
   int64_t t;
-  double v[2] = {0.0, 0.0};
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (node_of(g, i, j, k, t)) {
-    float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
-    weights_1d(i, g.nx, g.hx, Kx, Mx);
-    weights_1d(j, g.ny, g.hy, Ky, My);
-    weights_1d(k, g.nz, g.hz, Kz, Mz);
-    const float d = dx * Kx[1] * My[1] * Mz[1] + dy * Mx[1] * Ky[1] * Mz[1] +
-                    dz * Mx[1] * My[1] * Kz[1];
     x[t] = fmaf(alpha, p[t], x[t]);
-    const float rt = fmaf(-alpha, q[t], r[t]);
-    const float zt = rt / d;
+    const float rt = fmaf(-alpha, q[t], r[t] - c);
     r[t] = rt;
-    z[t] = zt;
-    v[0] = (double)rt * zt;
-    v[1] = (double)rt * rt;
+    residual_sums(rt, invd[t], v);
   }
-  block_sums<2>(v, partials);
+  block_sums<4>(v, partials);
 }
 
-__global__ __launch_bounds__(kB) void k_cg_beta(const double* partials, int nblocks, Scal* s) {
+__global__ __launch_bounds__(kB) void k_cg_beta(const double* partials, int nblocks, int64_t n,
+                                                Scal* s) {
   if (s->done) return;
-  double tot[2];
-  total_sums<2>(partials, nblocks, tot);
+  double tot[4];
+  total_sums<4>(partials, nblocks, tot);
   if (threadIdx.x == 0) {
-    s->beta = s->rz > 0.0 ? tot[0] / s->rz : 0.0;
-    s->rz = tot[0];
-    s->rr = tot[1];
+    const double rz_old = s->rz;
+    project(tot, n, s);
+    s->beta = rz_old > 0.0 ? s->rz / rz_old : 0.0;
     s->it += 1;
-    s->done = (tot[1] <= s->tol2 * s->bb || s->it >= s->max_it) ? 1 : 0;
+    s->done = (s->rr <= s->tol2 * s->bb || s->it >= s->max_it) ? 1 : 0;
   }
 }
 
@@ -340,8 +398,8 @@ struct fib_emg {
   fib_emg_params p{};
   Grid3 g{};
   int32_t n_fib = 0;          // nodes per fiber
-  float* d_vec = nullptr;     // b, x, r, z, p0, p1, q (n each)
-  double* d_part = nullptr;   // 3 x blocks partial sums
+  float* d_vec = nullptr;     // b, x, r, 1/diag, p0, p1, q (n each)
+  double* d_part = nullptr;   // 5 x blocks partial sums
   Scal* d_s = nullptr;
   Scal* h_s = nullptr;        // pinned copy of the scalars
   dim3 grid;                  // (blocks per layer, layers)
@@ -349,7 +407,7 @@ struct fib_emg {
   float* b() const { return d_vec; }
   float* x() const { return d_vec + g.n; }
   float* r() const { return d_vec + 2 * g.n; }
-  float* z() const { return d_vec + 3 * g.n; }
+  float* invd() const { return d_vec + 3 * g.n; }
   float* pb(int i) const { return d_vec + (4 + i) * g.n; }
   float* q() const { return d_vec + 6 * g.n; }
 };
@@ -393,14 +451,25 @@ int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
   e->nblocks = (int)(e->grid.x * e->grid.y);
   const size_t nv = (size_t)e->g.n * 7;
   if (hipMalloc(&e->d_vec, sizeof(float) * nv) != hipSuccess ||
-      hipMalloc(&e->d_part, sizeof(double) * 3 * e->nblocks) != hipSuccess ||
+      hipMalloc(&e->d_part, sizeof(double) * 5 * e->nblocks) != hipSuccess ||
       hipMalloc(&e->d_s, sizeof(Scal)) != hipSuccess ||
       hipHostMalloc(&e->h_s, sizeof(Scal)) != hipSuccess) {
     fib_emg_destroy(e);
     return efail(FIB_ENOMEM, "device allocation failed");
   }
-  if (hipMemset(e->d_vec, 0, sizeof(float) * nv) != hipSuccess ||
-      hipMemset(e->d_s, 0, sizeof(Scal)) != hipSuccess) {
+  // zeros (x = 0 is the first solve's start), then 1/diag(A) and its sum,
+  // all on the context's stream
+  hipStream_t st = v.stream;
+  bool ok = hipMemsetAsync(e->d_vec, 0, sizeof(float) * nv, st) == hipSuccess &&
+            hipMemsetAsync(e->d_s, 0, sizeof(Scal), st) == hipSuccess;
+  if (ok) {
+    hipLaunchKernelGGL(k_emg_invd, e->grid, dim3(kB), 0, st, e->g, (float)p->sigma_et,
+                       (float)p->sigma_et, (float)(p->sigma_el + p->sigma_i), e->invd(),
+                       e->d_part);
+    hipLaunchKernelGGL(k_emg_sd, dim3(1), dim3(kB), 0, st, e->d_part, e->nblocks, e->d_s);
+    ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(st) == hipSuccess;
+  }
+  if (!ok) {
     fib_emg_destroy(e);
     return efail(FIB_EHIP, "device initialisation failed");
   }
@@ -446,9 +515,9 @@ int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, do
   hipLaunchKernelGGL(k_emg_rhs, grid, block, 0, st, g, v.d_state, e->n_fib, e->p.stride,
                      (float)e->p.sigma_i, e->b(), e->d_part);
   hipLaunchKernelGGL(k_emg_mean, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
-  hipLaunchKernelGGL(k_emg_start, grid, block, 0, st, g, dx, dy, dz, e->b(), e->x(), e->r(),
-                     e->z(), e->d_part, e->d_s);
-  hipLaunchKernelGGL(k_emg_started, one, block, 0, st, e->d_part, nb, e->d_s);
+  hipLaunchKernelGGL(k_emg_start, grid, block, 0, st, g, dx, dy, dz, e->b(), e->x(),
+                     e->invd(), e->r(), e->d_part, e->d_s);
+  hipLaunchKernelGGL(k_emg_started, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
   EHIP(hipGetLastError());
   int par = 0;
   // batches grow from 8 iterations, so that a converged solve wastes few
@@ -460,12 +529,12 @@ int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, do
     if (e->h_s->done || it >= max_iter) break;
     const int n_it = std::min(batch, max_iter - it);
     for (int b = 0; b < n_it; ++b) {
-      hipLaunchKernelGGL(k_cg_q, grid, block, 0, st, g, dx, dy, dz, e->z(), e->pb(par),
-                         e->pb(par ^ 1), e->q(), e->d_part, e->d_s);
+      hipLaunchKernelGGL(k_cg_q, grid, block, 0, st, g, dx, dy, dz, e->r(), e->invd(),
+                         e->pb(par), e->pb(par ^ 1), e->q(), e->d_part, e->d_s);
       hipLaunchKernelGGL(k_cg_alpha, one, block, 0, st, e->d_part, nb, e->d_s);
-      hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, dx, dy, dz, e->pb(par ^ 1), e->q(),
-                         e->x(), e->r(), e->z(), e->d_part, e->d_s);
-      hipLaunchKernelGGL(k_cg_beta, one, block, 0, st, e->d_part, nb, e->d_s);
+      hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, e->pb(par ^ 1), e->q(), e->invd(),
+                         e->x(), e->r(), e->d_part, e->d_s);
+      hipLaunchKernelGGL(k_cg_beta, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
       par ^= 1;
     }
     EHIP(hipGetLastError());

@@ -11,6 +11,11 @@ oracle of oracle/emg.py.
   a few hundred on these meshes, plus FP32 rounding);
 * V_m linear along the fibers gives phi_e = -sigma_i / (sigma_i + sigma_el)
   V_m up to a constant;
+* CG driven far past the FP32 accuracy of phi_e (relative residual 1e-9)
+  converges and stays at the oracle's solution: the stencil in difference
+  form keeps the constant vector an exact null vector of the FP32 operator
+  and the residual is kept at zero mean in every iteration (without either,
+  a 3 x 7 x 121 mesh diverges below a relative residual of about 1e-7);
 * a resting V_m gives phi_e = 0 without an iteration; a repeated solve from
   the same V_m starts at the previous phi_e and needs at most a few
   iterations (the true residual of the FP32 iterate sits near the tolerance);
@@ -74,6 +79,23 @@ def test_phi_matches_oracle_during_a_propagating_wave(nx, ny, n, m):
     assert eb < 1.0
     assert ep < 1e-4
     assert abs(phi.mean()) < 1e-6 * np.max(np.abs(phi_o))
+    emg.close()
+    s.close()
+
+
+@pytest.mark.parametrize("nx,ny,n,m", [(3, 7, 121, 1), (5, 4, 301, 10)])
+def test_deep_solve_converges_and_stays_at_the_solution(nx, ny, n, m):
+    w = _bundle(nx, ny, n)
+    s = gpu_solver(w)
+    s.run(0, 2500)
+    s.sync()
+    emg = F.Emg(s, nx, ny, m, 0.05, 0.05, **SIG)
+    it, rel = emg.solve(tol=1e-9, max_iter=3000)
+    (phi_o, _), _, _ = _oracle(s, nx, ny, n, m, 0.05, w.h)
+    ep = np.max(np.abs(emg.phi() - phi_o)) / np.max(np.abs(phi_o))
+    say(f"[emg deep] {nx}x{ny}x{n}/{m}: {it} iterations, residual {rel:.2e}, phi err {ep:.2e}")
+    assert rel <= 1e-9 and it < 3000
+    assert ep < 1e-4
     emg.close()
     s.close()
 
