@@ -29,18 +29,20 @@
 // left in, it dominates r.z once the residual is small and CG diverges.
 // The projected scalars come from four sums of the raw r:
 //   r.z = sum r^2/d - 2 c sum r/d + c^2 sum 1/d,  r.r = sum r^2 - n c^2.
-// Each iteration is four launches:
-//   k_cg_q:  p <- (r - c)/d + beta p (the previous p in the other buffer;
-//            the stencil forms its neighbours' p itself), q = A p,
-//            per-block sums of p.q;
-//   k_cg_alpha (one block): alpha = r.z / p.q;
-//   k_cg_x:  x += alpha p, r <- (r - c) - alpha q, per-block sums of r,
-//            r^2, r/d, r^2/d;
-//   k_cg_beta (one block): c, r.z, r.r, beta, the convergence test.
-// The per-block sums are FP64 and added in block order by the one-block
-// kernels, so every solve is deterministic; the kernel boundaries order the
-// partial sums and the scalars without device-wide fences.  Converged
-// iterations return at once, so the host enqueues batches and checks the
+// Each iteration k is two launches:
+//   k_cg_q:  the totals of the previous launch's per-block sums of r give
+//            c, r.z, r.r and the convergence test; then p <- (r - c)/d +
+//            beta p (the previous p in the other buffer; the stencil forms
+//            its neighbours' p itself), q = A p, per-block sums of p.q;
+//   k_cg_x:  alpha = r.z / p.q from the totals of those sums; x += alpha p,
+//            r <- (r - c) - alpha q, per-block sums of r, r^2, r/d, r^2/d.
+// Every block forms the totals itself, from FP64 per-block sums added in a
+// fixed order, so all blocks agree bit for bit and every solve is
+// deterministic; the kernel boundaries order the sums and scalars without
+// device-wide fences.  Sums and scalars alternate between two buffers by
+// the parity of k, so a launch never overwrites what its own blocks read.
+// Once converged, launches return at once, so the host enqueues batches and
+// checks the
 // flag between them.  The grid is (blocks per layer, layers): a thread
 // finds (i, j) from its index in the layer and k from the block row.
 #include <hip/hip_runtime.h>
@@ -65,26 +67,37 @@ struct Grid3 {
   int64_t n;
 };
 
-// Scalars of the solve, in device memory.
+// Scalars of the solve, in device memory.  slot[k & 1] holds iteration
+// k's projected scalars, written by block 0 of its k_cg_q.
+struct Slot {
+  double c;   // mean of the stored (raw) residual
+  double rz;  // r.z of the projected residual
+};
+
 struct Scal {
   double mean_b;  // mean of the raw right-hand side
   double bb;      // ||b||^2 after the projection
-  double c;       // mean of the stored (raw) residual
-  double rz;      // r.z of the projected residual
-  double rr;      // r.r of the projected residual
-  double alpha, beta;
   double sd;      // sum of 1 / diag(A)
   double tol2;    // tol^2
-  int32_t it, max_it, done;
+  double rr;      // r.r of the last residual tested
+  Slot slot[2];
+  int32_t it;     // iterations taken
+  int32_t done;   // converged (or b = 0)
 };
 
-// Projected r.z and r.r from the sums of the raw residual (S1 = sum r,
+// Projected c, r.z, r.r from the sums of the raw residual (S1 = sum r,
 // S2 = sum r^2, S1d = sum r/d, S2d = sum r^2/d).
-__device__ __forceinline__ void project(const double (&t)[4], int64_t n, Scal* s) {
+struct Proj {
+  double c, rz, rr;
+};
+
+__device__ __forceinline__ Proj project(const double* t, int64_t n, double sd) {
   const double c = t[0] / (double)n;
-  s->c = c;
-  s->rz = fmax(t[3] - 2.0 * c * t[2] + c * c * s->sd, 0.0);
-  s->rr = fmax(t[1] - (double)n * c * c, 0.0);
+  return {c, fmax(t[3] - 2.0 * c * t[2] + c * c * sd, 0.0), fmax(t[1] - (double)n * c * c, 0.0)};
+}
+
+__device__ __forceinline__ bool first_thread() {
+  return blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0;
 }
 
 // 1D linear-element stiffness and mass weights of node i (of n, spacing h)
@@ -100,9 +113,16 @@ __device__ __forceinline__ void weights_1d(int i, int n, float h, float (&K)[3],
   M[2] = hi * h * (1.0f / 6.0f);
 }
 
-// Row (i, j, k) of K_D applied to the field `get` (a functor of the node
-// index) in the difference form sum_{j != t} w_tj (u_j - u_t); diag
-// receives the diagonal weight of K_D (the Jacobi preconditioner).
+// Row (i, j, k) of K_D applied to a field u in the difference form
+// sum_{j != t} w_tj (u_j - u_t), by sum factorization over the axes:
+//     dx sum_c Mz_c sum_b My_b sum_a Kx_a du
+//   + dy sum_c Mz_c sum_b Ky_b sum_a Mx_a du
+//   + dz sum_c Kz_c sum_b My_b sum_a Mx_a du,
+// du = u(i + a - 1, j + b - 1, k + c - 1) - u(i, j, k) (the centre term is
+// zero).  get(kk, l) returns u at layer kk and in-layer index l = j' nx + i'.
+// A missing neighbour has 1D weight 0, and its offset is clamped to the node
+// itself so that every read stays in the mesh.  diag receives the diagonal
+// weight of K_D (the Jacobi preconditioner).
 template <class Get>
 __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, float dz, int i,
                                            int j, int k, Get get, float& diag) {
@@ -110,51 +130,70 @@ __device__ __forceinline__ float apply_row(const Grid3& g, float dx, float dy, f
   weights_1d(i, g.nx, g.hx, Kx, Mx);
   weights_1d(j, g.ny, g.hy, Ky, My);
   weights_1d(k, g.nz, g.hz, Kz, Mz);
-  const float uc = get(((int64_t)k * g.ny + j) * g.nx + i);
-  float acc = 0.0f;
-  diag = 0.0f;
+  diag = dx * Kx[1] * My[1] * Mz[1] + dy * Mx[1] * Ky[1] * Mz[1] + dz * Mx[1] * My[1] * Kz[1];
+  const uint32_t l0 = (uint32_t)(j * g.nx + i);
+  const uint32_t ox[3] = {i > 0 ? ~0u : 0u, 0u, i + 1 < g.nx ? 1u : 0u};
+  const uint32_t oy[3] = {j > 0 ? 0u - (uint32_t)g.nx : 0u, 0u, j + 1 < g.ny ? (uint32_t)g.nx : 0u};
+  const uint32_t kz[3] = {(uint32_t)(k > 0 ? k - 1 : k), (uint32_t)k,
+                          (uint32_t)(k + 1 < g.nz ? k + 1 : k)};
+  const float uc = get((uint32_t)k, l0);
+  float s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
 #pragma unroll
   for (int c = 0; c < 3; ++c) {
-    if (Mz[c] == 0.0f) continue;  // no neighbour layer
+    float y1 = 0.0f, y2 = 0.0f, y3 = 0.0f;
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      if (My[b] == 0.0f) continue;
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        if (Mx[a] == 0.0f) continue;
-        const float w = dx * Kx[a] * My[b] * Mz[c] + dy * Mx[a] * Ky[b] * Mz[c] +
-                        dz * Mx[a] * My[b] * Kz[c];
-        if (a == 1 && b == 1 && c == 1) {
-          diag = w;
-          continue;
-        }
-        const int64_t idx = ((int64_t)(k + c - 1) * g.ny + (j + b - 1)) * g.nx + (i + a - 1);
-        acc = fmaf(w, get(idx) - uc, acc);
-      }
+      const uint32_t l = l0 + oy[b];
+      const float d0 = get(kz[c], l + ox[0]) - uc;
+      const float d1 = get(kz[c], l) - uc;
+      const float d2 = get(kz[c], l + ox[2]) - uc;
+      const float sk = fmaf(Kx[0], d0, fmaf(Kx[1], d1, Kx[2] * d2));
+      const float sm = fmaf(Mx[0], d0, fmaf(Mx[1], d1, Mx[2] * d2));
+      y1 = fmaf(My[b], sk, y1);
+      y2 = fmaf(Ky[b], sm, y2);
+      y3 = fmaf(My[b], sm, y3);
     }
+    s1 = fmaf(Mz[c], y1, s1);
+    s2 = fmaf(Mz[c], y2, s2);
+    s3 = fmaf(Kz[c], y3, s3);
   }
-  return acc;
+  return fmaf(dx, s1, fmaf(dy, s2, dz * s3));
 }
 
 // Node of this thread in the (blocks per layer, layers) grid; false past
 // the end of its layer.
-__device__ __forceinline__ bool node_of(const Grid3& g, int& i, int& j, int& k, int64_t& t) {
+__device__ __forceinline__ bool node_of(const Grid3& g, int& i, int& j, int& k, uint32_t& t) {
   const int tl = (int)blockIdx.x * kB + (int)threadIdx.x;  // index in the layer
   if (tl >= g.nx * g.ny) return false;
   i = tl % g.nx;
   j = tl / g.nx;
   k = (int)blockIdx.y;
-  t = (int64_t)k * g.nx * g.ny + tl;
+  t = (uint32_t)k * (uint32_t)(g.nx * g.ny) + (uint32_t)tl;
   return true;
 }
 
-// Per-block sums of NV doubles into partials[v * nblocks + block], in a
-// fixed order (waves by shuffles, then the four waves in order).
+// Element idx of a vector through a 32-bit byte offset (vectors hold at
+// most 2^30 elements), so that the load takes the base address from scalar
+// registers and only the offset from a vector register.
+__device__ __forceinline__ float at(const float* __restrict__ v, uint32_t idx) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(v) + (idx << 2));
+}
+
+// Accessor of a mesh vector for apply_row.
+struct MeshVec {
+  const float* __restrict__ v;
+  uint32_t nxy;
+  __device__ __forceinline__ float operator()(uint32_t kk, uint32_t l) const {
+    return at(v, kk * nxy + l);
+  }
+};
+
+// Per-block sums of NV doubles into the block's record partials[block * NV
+// + v], in a fixed order (waves by shuffles, then the four waves in order).
 template <int NV>
 __device__ __forceinline__ void block_sums(double (&v)[NV], double* partials) {
   __shared__ double sh[NV][kB / 64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int nblocks = (int)(gridDim.x * gridDim.y);
   const int blk = (int)(blockIdx.y * gridDim.x + blockIdx.x);
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
@@ -167,31 +206,50 @@ __device__ __forceinline__ void block_sums(double (&v)[NV], double* partials) {
   if (threadIdx.x < NV) {
     double x = 0.0;
     for (int w = 0; w < kB / 64; ++w) x += sh[threadIdx.x][w];
-    partials[threadIdx.x * nblocks + blk] = x;
+    partials[(size_t)blk * NV + threadIdx.x] = x;
   }
 }
 
-// Totals of the per-block sums, in block order (one block of kB threads:
-// a fixed strided subset per thread, then a fixed tree).
+// Totals of the per-block records, the same in every block that forms them:
+// thread t adds records t, t + kB, t + 2 kB, ... in that order (loaded four
+// at a time, so one memory latency covers up to 4 kB blocks), then the
+// waves reduce by shuffles and the four wave sums are added in order.
+// Each NV has its own LDS array: one kernel must not call it twice with the
+// same NV.
 template <int NV>
 __device__ __forceinline__ void total_sums(const double* partials, int nblocks, double (&tot)[NV]) {
-  __shared__ double acc[NV][kB];
+  __shared__ double sh[NV][kB / 64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double x[NV];
+#pragma unroll
+  for (int q = 0; q < NV; ++q) x[q] = 0.0;
+  for (int b0 = threadIdx.x; b0 < nblocks; b0 += 4 * kB) {
+    double rec[4][NV];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int b = b0 + u * kB;
+#pragma unroll
+      for (int q = 0; q < NV; ++q) rec[u][q] = b < nblocks ? partials[(size_t)b * NV + q] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+#pragma unroll
+      for (int q = 0; q < NV; ++q) x[q] += rec[u][q];
+    }
+  }
 #pragma unroll
   for (int q = 0; q < NV; ++q) {
-    double x = 0.0;
-    for (int b = threadIdx.x; b < nblocks; b += kB) x += partials[q * nblocks + b];
-    acc[q][threadIdx.x] = x;
+#pragma unroll
+    for (int d = 32; d > 0; d >>= 1) x[q] += __shfl_down(x[q], d);
+    if (lane == 0) sh[q][wave] = x[q];
   }
   __syncthreads();
-  for (int s = kB / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
 #pragma unroll
-      for (int q = 0; q < NV; ++q) acc[q][threadIdx.x] += acc[q][threadIdx.x + s];
-    }
-    __syncthreads();
+  for (int q = 0; q < NV; ++q) {
+    double y = 0.0;
+    for (int w = 0; w < kB / 64; ++w) y += sh[q][w];
+    tot[q] = y;
   }
-#pragma unroll
-  for (int q = 0; q < NV; ++q) tot[q] = acc[q][0];
 }
 
 // b = -K_{sigma_i} P V_m from the fiber state (row 0: V_m - rest; the
@@ -200,14 +258,12 @@ __global__ __launch_bounds__(kB) void k_emg_rhs(Grid3 g, const float* __restrict
                                                 int32_t n_fib, int32_t m, float sigma_i,
                                                 float* __restrict__ b, double* partials) {
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   double v[1] = {0.0};
   if (node_of(g, i, j, k, t)) {
     // 3D node (i', j', k') is fiber j' nx + i' at its node k' m
-    const int nxy = g.nx * g.ny;
-    auto get = [&](int64_t idx) {
-      const int kk = (int)(idx / nxy), f = (int)(idx - (int64_t)kk * nxy);
-      return vm[(int64_t)f * n_fib + (int64_t)kk * m];
+    auto get = [&](uint32_t kk, uint32_t f) {
+      return at(vm, f * (uint32_t)n_fib + kk * (uint32_t)m);
     };
     float d;
     const float val = -apply_row(g, 0.0f, 0.0f, sigma_i, i, j, k, get, d);
@@ -228,7 +284,7 @@ __global__ __launch_bounds__(kB) void k_emg_mean(const double* partials, int nbl
 __global__ __launch_bounds__(kB) void k_emg_invd(Grid3 g, float dx, float dy, float dz,
                                                  float* __restrict__ invd, double* partials) {
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   double v[1] = {0.0};
   if (node_of(g, i, j, k, t)) {
     float Kx[3], Mx[3], Ky[3], My[3], Kz[3], Mz[3];
@@ -260,83 +316,105 @@ __device__ __forceinline__ void residual_sums(float rt, float wd, double* v) {
 }
 
 // Start of CG from the last solution x: bp = b - mean(b), r = bp - A x;
-// per-block sums of r, r^2, r/d, r^2/d and bp.bp.
+// per-block sums of r, r^2, r/d, r^2/d into part_r and of bp.bp into part_b.
 __global__ __launch_bounds__(kB) void k_emg_start(Grid3 g, float dx, float dy, float dz,
                                                   const float* __restrict__ b,
                                                   const float* __restrict__ x,
                                                   const float* __restrict__ invd,
-                                                  float* __restrict__ r, double* partials,
-                                                  const Scal* s) {
+                                                  float* __restrict__ r, double* part_r,
+                                                  double* part_b, const Scal* s) {
   int i, j, k;
-  int64_t t;
-  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  uint32_t t;
+  double v[4] = {0.0, 0.0, 0.0, 0.0}, vb[1] = {0.0};
   if (node_of(g, i, j, k, t)) {
     float d;
-    const float ax = apply_row(g, dx, dy, dz, i, j, k, [&](int64_t q) { return x[q]; }, d);
+    const float ax = apply_row(g, dx, dy, dz, i, j, k, MeshVec{x, (uint32_t)(g.nx * g.ny)}, d);
     const float bp = b[t] - (float)s->mean_b;
     const float rt = bp - ax;
     r[t] = rt;
     residual_sums(rt, invd[t], v);
-    v[4] = (double)bp * bp;
+    vb[0] = (double)bp * bp;
   }
-  block_sums<5>(v, partials);
+  block_sums<4>(v, part_r);
+  block_sums<1>(vb, part_b);
 }
 
-__global__ __launch_bounds__(kB) void k_emg_started(const double* partials, int nblocks,
-                                                    int64_t n, Scal* s) {
-  double tot[5];
-  total_sums<5>(partials, nblocks, tot);
+__global__ __launch_bounds__(kB) void k_emg_started(const double* part_r, const double* part_b,
+                                                    int nblocks, int64_t n, Scal* s) {
+  double tot[4], tb[1];
+  total_sums<4>(part_r, nblocks, tot);
+  total_sums<1>(part_b, nblocks, tb);
   if (threadIdx.x == 0) {
-    const double t4[4] = {tot[0], tot[1], tot[2], tot[3]};
-    project(t4, n, s);
-    s->bb = tot[4];
-    s->beta = 0.0;
+    const Proj pr = project(tot, n, s->sd);
+    s->bb = tb[0];
+    s->rr = pr.rr;
     s->it = 0;
-    s->done = (tot[4] == 0.0 || s->rr <= s->tol2 * tot[4]) ? 1 : 0;
+    s->slot[1].rz = INFINITY;  // beta = 0 in the first iteration
+    s->done = (tb[0] == 0.0 || pr.rr <= s->tol2 * tb[0]) ? 1 : 0;
   }
 }
 
-// p_new = (r - c)/d + beta p_old and q = A p_new; per-block sums of p.q.
+// Iteration k (parity P): the test and beta from the sums of r in part_r,
+// then p_new = (r - c)/d + beta p_old and q = A p_new; per-block sums of
+// p.q into part_pq.
 __global__ __launch_bounds__(kB) void k_cg_q(Grid3 g, float dx, float dy, float dz,
                                              const float* __restrict__ r,
                                              const float* __restrict__ invd,
                                              const float* __restrict__ p_old,
                                              float* __restrict__ p_new, float* __restrict__ q,
-                                             double* partials, const Scal* s) {
+                                             const double* part_r, double* part_pq, int nblocks,
+                                             int P, Scal* s) {
   if (s->done) return;
-  const float beta = (float)s->beta, c = (float)s->c;
+  double tot[4];
+  total_sums<4>(part_r, nblocks, tot);
+  const Proj pr = project(tot, g.n, s->sd);
+  const bool done = pr.rr <= s->tol2 * s->bb;
+  const double rz_prev = s->slot[P ^ 1].rz;
+  if (first_thread()) {
+    s->rr = pr.rr;
+    s->slot[P].c = pr.c;
+    s->slot[P].rz = pr.rz;
+    if (done) s->done = 1;
+    else s->it += 1;
+  }
+  if (done) return;
+  const float beta = (rz_prev > 0.0 && rz_prev < INFINITY) ? (float)(pr.rz / rz_prev) : 0.0f;
+  const float c = (float)pr.c;
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   double v[1] = {0.0};
   if (node_of(g, i, j, k, t)) {
-    auto pn = [&](int64_t n) { return fmaf(beta, p_old[n], (r[n] - c) * invd[n]); };
+    const uint32_t nxy = (uint32_t)(g.nx * g.ny);
+    auto pn = [&](uint32_t kk, uint32_t l) {
+      const uint32_t n = kk * nxy + l;
+      return fmaf(beta, at(p_old, n), (at(r, n) - c) * at(invd, n));
+    };
     float d;
     const float qt = apply_row(g, dx, dy, dz, i, j, k, pn, d);
-    const float pt = pn(t);
+    const float pt = fmaf(beta, p_old[t], (r[t] - c) * invd[t]);
     p_new[t] = pt;
     q[t] = qt;
     v[0] = (double)pt * qt;
   }
-  block_sums<1>(v, partials);
+  block_sums<1>(v, part_pq);
 }
 
-__global__ __launch_bounds__(kB) void k_cg_alpha(const double* partials, int nblocks, Scal* s) {
-  if (s->done) return;
-  double tot[1];
-  total_sums<1>(partials, nblocks, tot);
-  if (threadIdx.x == 0) s->alpha = tot[0] > 0.0 ? s->rz / tot[0] : 0.0;
-}
-
-// x += alpha p, r <- (r - c) - alpha q; per-block sums of r, r^2, r/d, r^2/d.
+// Iteration k (parity P): alpha from the sums of p.q, x += alpha p,
+// r <- (r - c) - alpha q; per-block sums of r, r^2, r/d, r^2/d into
+// part_r (the buffer of parity P ^ 1).
 __global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, const float* __restrict__ p,
                                              const float* __restrict__ q,
                                              const float* __restrict__ invd,
                                              float* __restrict__ x, float* __restrict__ r,
-                                             double* partials, const Scal* s) {
+                                             const double* part_pq, double* part_r, int nblocks,
+                                             int P, const Scal* s) {
   if (s->done) return;
-  const float alpha = (float)s->alpha, c = (float)s->c;
+  double tot[1];
+  total_sums<1>(part_pq, nblocks, tot);
+  const float alpha = tot[0] > 0.0 ? (float)(s->slot[P].rz / tot[0]) : 0.0f;
+  const float c = (float)s->slot[P].c;
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   if (node_of(g, i, j, k, t)) {
     x[t] = fmaf(alpha, p[t], x[t]);
@@ -344,35 +422,30 @@ __global__ __launch_bounds__(kB) void k_cg_x(Grid3 g, const float* __restrict__ 
     r[t] = rt;
     residual_sums(rt, invd[t], v);
   }
-  block_sums<4>(v, partials);
+  block_sums<4>(v, part_r);
 }
 
-__global__ __launch_bounds__(kB) void k_cg_beta(const double* partials, int nblocks, int64_t n,
-                                                Scal* s) {
+// r.r of the last iterate when the iteration limit stopped the solve.
+__global__ __launch_bounds__(kB) void k_cg_final(const double* part_r, int nblocks, int64_t n,
+                                                 Scal* s) {
   if (s->done) return;
   double tot[4];
-  total_sums<4>(partials, nblocks, tot);
-  if (threadIdx.x == 0) {
-    const double rz_old = s->rz;
-    project(tot, n, s);
-    s->beta = rz_old > 0.0 ? s->rz / rz_old : 0.0;
-    s->it += 1;
-    s->done = (s->rr <= s->tol2 * s->bb || s->it >= s->max_it) ? 1 : 0;
-  }
+  total_sums<4>(part_r, nblocks, tot);
+  if (threadIdx.x == 0) s->rr = project(tot, n, s->sd).rr;
 }
 
 // x -= mean(x): the per-block sums, the mean, the subtraction.
 __global__ __launch_bounds__(kB) void k_emg_sum(Grid3 g, const float* __restrict__ x,
                                                 double* partials) {
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   double v[1] = {node_of(g, i, j, k, t) ? (double)x[t] : 0.0};
   block_sums<1>(v, partials);
 }
 
 __global__ __launch_bounds__(kB) void k_emg_shift(Grid3 g, float* __restrict__ x, const Scal* s) {
   int i, j, k;
-  int64_t t;
+  uint32_t t;
   if (node_of(g, i, j, k, t)) x[t] -= (float)s->mean_b;
 }
 
@@ -399,7 +472,7 @@ struct fib_emg {
   Grid3 g{};
   int32_t n_fib = 0;          // nodes per fiber
   float* d_vec = nullptr;     // b, x, r, 1/diag, p0, p1, q (n each)
-  double* d_part = nullptr;   // 5 x blocks partial sums
+  double* d_part = nullptr;   // per-block sums: two of 4 x blocks (r), one of blocks (p.q)
   Scal* d_s = nullptr;
   Scal* h_s = nullptr;        // pinned copy of the scalars
   dim3 grid;                  // (blocks per layer, layers)
@@ -410,6 +483,8 @@ struct fib_emg {
   float* invd() const { return d_vec + 3 * g.n; }
   float* pb(int i) const { return d_vec + (4 + i) * g.n; }
   float* q() const { return d_vec + 6 * g.n; }
+  double* part_r(int par) const { return d_part + (size_t)par * 4 * nblocks; }
+  double* part_pq() const { return d_part + (size_t)8 * nblocks; }
 };
 
 extern "C" {
@@ -435,6 +510,10 @@ int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
   if (n < 2 || (n - 1) % p->stride != 0)
     return efail(FIB_EINVAL, "fiber length %d: (n - 1) must be a positive multiple of %d", n,
                  p->stride);
+  // the kernels address the fiber state and the mesh vectors with 32-bit
+  // byte offsets
+  if ((int64_t)v.n_fibers * n > (int64_t(1) << 30))
+    return efail(FIB_EUNSUPPORTED, "EMG bundles hold at most 2^30 fiber nodes");
   fib_emg* e = new (std::nothrow) fib_emg();
   if (!e) return efail(FIB_ENOMEM, "host allocation failed");
   e->ctx = ctx;
@@ -451,7 +530,7 @@ int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
   e->nblocks = (int)(e->grid.x * e->grid.y);
   const size_t nv = (size_t)e->g.n * 7;
   if (hipMalloc(&e->d_vec, sizeof(float) * nv) != hipSuccess ||
-      hipMalloc(&e->d_part, sizeof(double) * 5 * e->nblocks) != hipSuccess ||
+      hipMalloc(&e->d_part, sizeof(double) * 9 * e->nblocks) != hipSuccess ||
       hipMalloc(&e->d_s, sizeof(Scal)) != hipSuccess ||
       hipHostMalloc(&e->h_s, sizeof(Scal)) != hipSuccess) {
     fib_emg_destroy(e);
@@ -506,40 +585,57 @@ int fib_emg_solve(fib_emg_t* e, double tol, int32_t max_iter, int32_t* iters, do
               dz = (float)(e->p.sigma_el + e->p.sigma_i);
   const dim3 grid = e->grid, block(kB), one(1);
   const int nb = e->nblocks;
-  // scalars: tolerance and iteration limit
+  // the tolerance; the host bounds the iterations
   e->h_s->tol2 = tol * tol;
-  e->h_s->max_it = max_iter;
   EHIP(hipMemcpyAsync(&e->d_s->tol2, &e->h_s->tol2, sizeof(double), hipMemcpyHostToDevice, st));
-  EHIP(hipMemcpyAsync(&e->d_s->max_it, &e->h_s->max_it, sizeof(int32_t), hipMemcpyHostToDevice,
-                      st));
   hipLaunchKernelGGL(k_emg_rhs, grid, block, 0, st, g, v.d_state, e->n_fib, e->p.stride,
                      (float)e->p.sigma_i, e->b(), e->d_part);
   hipLaunchKernelGGL(k_emg_mean, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
   hipLaunchKernelGGL(k_emg_start, grid, block, 0, st, g, dx, dy, dz, e->b(), e->x(),
-                     e->invd(), e->r(), e->d_part, e->d_s);
-  hipLaunchKernelGGL(k_emg_started, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
+                     e->invd(), e->r(), e->part_r(0), e->part_pq(), e->d_s);
+  hipLaunchKernelGGL(k_emg_started, one, block, 0, st, e->part_r(0), e->part_pq(), nb, g.n,
+                     e->d_s);
   EHIP(hipGetLastError());
-  int par = 0;
-  // batches grow from 8 iterations, so that a converged solve wastes few
-  // no-op launches and a long one few host round trips
+  // Iterations in batches between host checks.  The first batch is 8; then
+  // the residual's mean decay rate over the last batch predicts how many
+  // iterations remain, and the next batch is that (+ 25 %, at most 64), so
+  // a solve wastes few no-op launches past convergence and few round trips.
+  int32_t launched = 0;
   int batch = 8;
-  for (int32_t it = 0;;) {
+  double rr_last = -1.0;
+  int32_t it_last = 0;
+  for (;;) {
     EHIP(hipMemcpyAsync(e->h_s, e->d_s, sizeof(Scal), hipMemcpyDeviceToHost, st));
     EHIP(hipStreamSynchronize(st));
-    if (e->h_s->done || it >= max_iter) break;
-    const int n_it = std::min(batch, max_iter - it);
+    if (e->h_s->done || launched >= max_iter) break;
+    const double rr = e->h_s->rr, goal = e->h_s->tol2 * e->h_s->bb;
+    if (rr_last > 0.0 && rr > 0.0 && rr < rr_last && e->h_s->it > it_last) {
+      const double per_it = std::log(rr / rr_last) / (double)(e->h_s->it - it_last);
+      const double need = std::log(goal / rr) / per_it;  // > 0: rr > goal here
+      batch = (int)std::min(64.0, std::max(2.0, std::ceil(1.25 * need) + 1.0));
+    } else if (rr_last > 0.0) {
+      batch = std::min(2 * batch, 64);
+    }
+    rr_last = rr;
+    it_last = e->h_s->it;
+    const int n_it = std::min(batch, max_iter - launched);
     for (int b = 0; b < n_it; ++b) {
+      const int P = (launched + b) & 1;
       hipLaunchKernelGGL(k_cg_q, grid, block, 0, st, g, dx, dy, dz, e->r(), e->invd(),
-                         e->pb(par), e->pb(par ^ 1), e->q(), e->d_part, e->d_s);
-      hipLaunchKernelGGL(k_cg_alpha, one, block, 0, st, e->d_part, nb, e->d_s);
-      hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, e->pb(par ^ 1), e->q(), e->invd(),
-                         e->x(), e->r(), e->d_part, e->d_s);
-      hipLaunchKernelGGL(k_cg_beta, one, block, 0, st, e->d_part, nb, g.n, e->d_s);
-      par ^= 1;
+                         e->pb(P), e->pb(P ^ 1), e->q(), e->part_r(P), e->part_pq(), nb, P,
+                         e->d_s);
+      hipLaunchKernelGGL(k_cg_x, grid, block, 0, st, g, e->pb(P ^ 1), e->q(), e->invd(),
+                         e->x(), e->r(), e->part_pq(), e->part_r(P ^ 1), nb, P, e->d_s);
     }
     EHIP(hipGetLastError());
-    it += n_it;
-    batch = std::min(2 * batch, 64);
+    launched += n_it;
+  }
+  if (!e->h_s->done && launched > 0) {
+    // stopped by the limit: the residual of the last iterate
+    hipLaunchKernelGGL(k_cg_final, one, block, 0, st, e->part_r(launched & 1), nb, g.n, e->d_s);
+    EHIP(hipGetLastError());
+    EHIP(hipMemcpyAsync(e->h_s, e->d_s, sizeof(Scal), hipMemcpyDeviceToHost, st));
+    EHIP(hipStreamSynchronize(st));
   }
   const int32_t done_it = e->h_s->it;
   if (e->h_s->bb == 0.0) {
