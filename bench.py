@@ -101,6 +101,10 @@ METRIC = "subcellular node-steps/sec at ≤0.5 mV Vm error: plain FP32 vs surrog
 SLOTS_PER_NODE_STEP = 267
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+# EMG conjugate-gradient iteration, per mesh node (FP32 vectors): the
+# stencil launch reads r, 1/diag, p_old and writes p, q (20 B); the update
+# launch reads p, q, 1/diag, x, r and writes x, r (28 B)
+EMG_BYTES_PER_NODE_ITERATION = 48
 
 
 def parse():
@@ -524,12 +528,20 @@ def emg_bench(args):
     s.close()
     n_solves = len(its)
     tot_it = int(sum(its))
+    # CG iteration against HBM: algorithmic bytes per mesh node and iteration
+    # (EMG_BYTES_PER_NODE_ITERATION) over the whole synchronized solve time,
+    # so right-hand side, start, host checks and the final shift count too
+    gbs = EMG_BYTES_PER_NODE_ITERATION * g.n * tot_it / t_emg / 1e9
+    roof = dict(bound="hbm", achieved=gbs, peak=HBM_PEAK / 1e9, unit="GB/s",
+                frac=gbs * 1e9 / HBM_PEAK, traffic=None, kernel="k_cg_q + k_cg_x",
+                bytes_per_node_iteration=EMG_BYTES_PER_NODE_ITERATION,
+                timing="whole EMG solves (host clock around synchronized solves)")
     out = dict(workload=f"hh_emg_{nf}x{nf}x{n}, 3D mesh {nf}x{nf}x{g.nz}, solve every {every} "
                         f"split steps", value=w.node_steps() / secs, seconds=secs, plan=plan,
                emg_solves=n_solves, cg_iterations_mean=tot_it / n_solves,
                cg_iterations_max=int(max(its)), emg_seconds=t_emg,
                emg_share=t_emg / secs, ms_per_cg_iteration=(t_emg / max(tot_it, 1)) * 1e3,
-               last_phi_fp64_relative_residual=res, mesh_nodes=int(g.n))
+               last_phi_fp64_relative_residual=res, mesh_nodes=int(g.n), roofline=roof)
     _log(f"emg: {out['value']:.3e} node-steps/s, {n_solves} solves, {tot_it / n_solves:.1f} "
          f"CG iterations each, EMG share {out['emg_share']:.2f}, residual {res:.1e}")
     return out
