@@ -69,15 +69,14 @@ __device__ __forceinline__ float exp_star_m1(float V, const ExpCoef& c) {
   return d;
 }
 
-// x / (exp(x) - 1) given e = exp(x).  For |x| < 1e-3 the series 1 - x/2
-// (truncation error x^2/12 < 1e-7, below FP32 resolution) replaces the
-// quotient, which is 0/0 at x = 0 and whose cancellation error, about
-// 1.2e-7 / |x| relative, stays below 1.2e-4 outside that interval; the
-// rate is that inexact only within 0.01 mV of the singular voltage.
-__device__ __forceinline__ float x_over_expm1(float x, float e) {
-  const float s = fmaf(x, -0.5f, 1.0f);
-  const float q = x * rcp(e - 1.0f);
-  return fabsf(x) < 1e-3f ? s : q;
+// c x / (exp(x) - 1) from cx = c x and e = exp(x).  The quotient is 0/0 at
+// x = 0, and its cancellation error, about 1.2e-7 / |x| relative, grows as
+// x shrinks; for |x| < 4.9e-4 its limit c replaces it, whose error |x|/2 is
+// below 2.5e-4 there.  Either way the rate is that inexact only within
+// 0.005 mV of the singular voltage.
+__device__ __forceinline__ float cx_over_expm1(float cx, float e, float c) {
+  const float q = cx * rcp(e - 1.0f);
+  return fabsf(cx) < c * 4.9e-4f ? c : q;
 }
 
 // Every state is carried as its offset from the resting state (ref): the
@@ -101,15 +100,15 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
   const float h = y.h + ref.h;
   const float n = y.n + ref.n;
   const float xm = fmaf(V, -0.1f, -5.0f);   // (25 - v)/10 = -(V + 50)/10
-  const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
   float am, an, bm, ah, bh, bn;
   if constexpr (!APX) {
     constexpr float kEm15 = 0.22313016014842982893f;  // e^-1.5
     constexpr float kE05 = 1.6487212707001281468f;    // e^0.5
+    const float xn10 = fmaf(V, -0.01f, -0.65f);       // x_n / 10, x_n = (10 - v)/10
     const float em = ex2(fmaf(V, kXm.k1, kXm.k0));
     const float en = em * kEm15;                      // exp(x_n)
-    am = x_over_expm1(xm, em);
-    an = 0.1f * x_over_expm1(xn, en);
+    am = cx_over_expm1(xm, em, 1.0f);
+    an = cx_over_expm1(xn10, en, 0.1f);
     bm = ex2(fmaf(V, kBm.k1, kBm.k0));
     ah = ex2(fmaf(V, kAh.k1, kAh.k0));
     bh = rcp(fmaf(em, kE05, 1.0f));                   // 1 / (exp((30-v)/10) + 1)
@@ -118,6 +117,7 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
     // x / (exp*(x) - 1) = x / d; near x = 0 its series 1 - (n-1)/(2n) x
     // (truncation below 1e-7 for |x| < 1e-3)
     constexpr float kA = 1023.0f / 2048.0f;
+    const float xn = fmaf(V, -0.1f, -6.5f);   // (10 - v)/10 = -(V + 65)/10
     const float dm = exp_star_m1(V, kXm), dn = exp_star_m1(V, kXn);
     am = fabsf(xm) < 1e-3f ? fmaf(xm, -kA, 1.0f) : xm * rcp(dm);
     an = 0.1f * (fabsf(xn) < 1e-3f ? fmaf(xn, -kA, 1.0f) : xn * rcp(dn));
