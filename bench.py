@@ -86,19 +86,21 @@ METRIC = "subcellular node-steps/sec at ≤0.5 mV Vm error: plain FP32 vs surrog
 # issue at half the FMA rate on gfx950 (measured), so they take two.  Counted
 # from the formulas as the method is carried out in FP32 (states as offsets
 # from rest, removable singularities guarded), not from the compiled code:
-#   right-hand side G: offsets to absolute states 4; quotient arguments x_m,
-#     x_n/10 2; four exponentials (FMA argument + exp) 12 and exp(x_n) as a
-#     constant multiple of exp(x_m) 1; two quotients c x / (e^x - 1) with
-#     their guard (sub, rcp, mul, compare, select of the limit c) 12;
-#     beta_h = 1/(c exp(x_m) + 1) 3; m^3 h and n^4 5; currents 7; dV/dt 2;
-#     three gate rates 6  = 54
-#   Heun step: 2 G + stage 4 + sum 4 + update 4 + tau/2 1 = 121
-#   reaction: two half steps of one Heun substep each = 242
+#   right-hand side G at absolute states, its V component scaled by Cm:
+#     quotient arguments x_m, x_n/10 2; four exponentials (FMA argument +
+#     exp) 12 and exp(x_n) as a constant multiple of exp(x_m) 1; two
+#     quotients c x / (e^x - 1) with their guard (sub, rcp, mul, compare,
+#     select of the limit c) 12; beta_h = 1/(c exp(x_m) + 1) 3; m^3 h and
+#     n^4 5; I_ion as three driving-force FMAs and two FMAs 5; I - I_ion 1;
+#     three gate rates 6  = 47
+#   Heun step: offsets to absolute states 4 + 2 G + stage state 4 + sum 4
+#     + update 4 (tau/2 and tau/Cm are per-launch constants) = 110
+#   reaction: two half steps of one Heun substep each = 220
 #   Crank-Nicolson: right-hand side 5, elimination 3, update 3 = 11
 #   activation-time test: 2
 # The counter-measured issue (rocprofv3 SQ_INSTS_VALU, transcendental
 # instructions counted twice) agrees with this figure to a few percent.
-SLOTS_PER_NODE_STEP = 255
+SLOTS_PER_NODE_STEP = 233
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 VALU_PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # EMG conjugate-gradient iteration, per mesh node (FP32 vectors): the

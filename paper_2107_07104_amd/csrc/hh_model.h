@@ -92,13 +92,12 @@ struct Ref {
 };
 
 // Right-hand side G(y) of the membrane model with stimulus current I
-// (APX: with exp* in the rates).
+// (APX: with exp* in the rates) at the absolute state (V, m, h, n), with
+// the V component scaled by Cm: it returns I - I_ion, the gate components
+// are G's own.
 template <bool APX = false>
-__device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, const Ref& ref) {
-  const float V = y.V + ref.V;
-  const float m = y.m + ref.m;
-  const float h = y.h + ref.h;
-  const float n = y.n + ref.n;
+__device__ __forceinline__ State rhs_abs_cm(const State& a, float I) {
+  const float V = a.V, m = a.m, h = a.h, n = a.n;
   const float xm = fmaf(V, -0.1f, -5.0f);   // (25 - v)/10 = -(V + 50)/10
   float am, an, bm, ah, bh, bn;
   if constexpr (!APX) {
@@ -127,36 +126,55 @@ __device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, cons
     bn = kBn.pre * (exp_star_m1(V, kBn) + 1.0f);
   }
 
+  // I_ion = 120 m^3 h (V - 40) + 36 n^4 (V + 87) + 0.3 (V + 64.387), each
+  // driving force with its conductance folded in (one FMA in V each)
   const float m2 = m * m;
   const float m3h = m2 * (m * h);
   const float n2 = n * n;
   const float n4 = n2 * n2;
-  const float ina = m3h * (V - 40.0f);
-  const float ik = n4 * (V + 87.0f);
-  const float il = fmaf(0.3f, V, 0.3f * 64.387f);
-  const float iion = fmaf(120.0f, ina, fmaf(36.0f, ik, il));
+  const float fna = fmaf(V, 120.0f, -120.0f * 40.0f);
+  const float fk = fmaf(V, 36.0f, 36.0f * 87.0f);
+  const float fl = fmaf(V, 0.3f, 0.3f * 64.387f);
+  const float iion = fmaf(m3h, fna, fmaf(n4, fk, fl));
 
   State d;
-  d.V = (I - iion) * inv_cm;
+  d.V = I - iion;
   d.m = fmaf(-(am + bm), m, am);
   d.h = fmaf(-(ah + bh), h, ah);
   d.n = fmaf(-(an + bn), n, an);
   return d;
 }
 
+__device__ __forceinline__ State absolute(const State& y, const Ref& ref) {
+  return State{y.V + ref.V, y.m + ref.m, y.h + ref.h, y.n + ref.n};
+}
+
+// G(y) itself, y as offsets from ref: dV/dt = (I - I_ion) / Cm.
+template <bool APX = false>
+__device__ __forceinline__ State rhs(const State& y, float I, float inv_cm, const Ref& ref) {
+  State d = rhs_abs_cm<APX>(absolute(y, ref), I);
+  d.V *= inv_cm;
+  return d;
+}
+
 // One Heun step of width tau (eq. heun):
-//   y+ = y + tau/2 (G(y) + G(y + tau G(y))).
+//   y+ = y + tau/2 (G(y) + G(y + tau G(y))),
+// with 1/Cm of the V component folded into its step width.  The stage
+// state is formed in absolute values from the first one; the increment is
+// added to the offsets.
 template <bool APX = false>
 __device__ __forceinline__ void heun(State& y, float I, float tau, float inv_cm, const Ref& ref) {
-  const State k1 = rhs<APX>(y, I, inv_cm, ref);
-  State yt;
-  yt.V = fmaf(tau, k1.V, y.V);
-  yt.m = fmaf(tau, k1.m, y.m);
-  yt.h = fmaf(tau, k1.h, y.h);
-  yt.n = fmaf(tau, k1.n, y.n);
-  const State k2 = rhs<APX>(yt, I, inv_cm, ref);
+  const float tv = tau * inv_cm;
+  const State a1 = absolute(y, ref);
+  const State k1 = rhs_abs_cm<APX>(a1, I);
+  State a2;
+  a2.V = fmaf(tv, k1.V, a1.V);
+  a2.m = fmaf(tau, k1.m, a1.m);
+  a2.h = fmaf(tau, k1.h, a1.h);
+  a2.n = fmaf(tau, k1.n, a1.n);
+  const State k2 = rhs_abs_cm<APX>(a2, I);
   const float ht = 0.5f * tau;
-  y.V = fmaf(ht, k1.V + k2.V, y.V);
+  y.V = fmaf(0.5f * tv, k1.V + k2.V, y.V);
   y.m = fmaf(ht, k1.m + k2.m, y.m);
   y.h = fmaf(ht, k1.h + k2.h, y.h);
   y.n = fmaf(ht, k1.n + k2.n, y.n);
