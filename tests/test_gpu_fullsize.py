@@ -1,0 +1,83 @@
+"""Full-size runs in the launch configuration the benchmark times, checked
+on sampled fibers against the FP64 oracle.  Fibers are independent (the
+per-fiber systems of eq. discretized_fibers_1 form a block-diagonal matrix),
+so the oracle's run of a fiber alone, with its own stimulus and initial
+noise, is that fiber's exact reference.
+
+* batched Hodgkin-Huxley, 1369 fibers of 1000-1500 nodes, 20 ms at
+  dt = 1e-3 ms, fused schedule with the autotuned workgroup shape: the
+  shortest and the longest fiber and two seeded others; V_m samples every
+  0.1 ms, the final state and the activation times within 0.5 mV and one
+  split step;
+* the ST57 bundle, 400 fibers of 1481 nodes, 5 ms (dt_0D = 1e-4 ms,
+  dt_split = 5e-4 ms), split schedule: the first and the last fiber and
+  four seeded others, the same bounds (the oracle runs the sampled fibers in
+  parallel, half a minute on 16 host threads).
+"""
+import numpy as np
+import pytest
+
+from paper_2107_07104_amd import fib as F
+from paper_2107_07104_amd import inputs as I
+
+from gpu_helpers import compare_runs, gpu_solver, oracle_run, say
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    F.lib()
+
+
+def _run_full(w, s):
+    rows = w.n_steps // w.sample_every
+    samples = torch.full((rows, w.n_total), float("nan"), device="cuda")
+    s.run(0, w.n_steps, w.sample_every, samples)
+    s.sync()
+    return s.get_state(), samples.cpu().numpy().astype(np.float64), s.tact().astype(np.float64)
+
+
+def _check_sampled(w, full, fibers):
+    y, smp, ta = full
+    off = w.offsets
+    idx = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
+    sub = w.subset(fibers)
+    ora = oracle_run(sub)
+    res = compare_runs(sub, (y[:, idx], smp[:, idx], ta[idx], None), ora)
+    say(f"   fibers {fibers} ({sub.n_total} nodes): {res}")
+    assert res["vm_err"] <= 0.5
+    assert res["tact_err"] <= w.dt_split
+    assert res["tact_mismatch"] == 0
+    assert res["activated"] > 0
+    return res
+
+
+def test_hh_batched_full_size_on_sampled_fibers():
+    w = I.batched_hh()
+    say(f"[full size] {w.name}: {w.n_total} nodes, {w.n_steps} steps")
+    s = gpu_solver(w)
+    s.autotune(trial_steps=200, max_candidates=8)
+    say(f"   plan {s.plan()}")
+    full = _run_full(w, s)
+    s.close()
+    rng = np.random.Generator(np.random.PCG64(11))
+    fibers = sorted({int(np.argmin(w.n_nodes)), int(np.argmax(w.n_nodes)),
+                     *(int(f) for f in rng.choice(len(w.n_nodes), 2, replace=False))})
+    _check_sampled(w, full, fibers)
+
+
+def test_st57_bundle_full_size_on_sampled_fibers():
+    w = I.st57_bundle()
+    say(f"[full size] {w.name}: {w.n_total} nodes, {w.n_steps} steps")
+    s = gpu_solver(w)
+    full = _run_full(w, s)
+    s.close()
+    rng = np.random.Generator(np.random.PCG64(12))
+    fibers = sorted({0, len(w.n_nodes) - 1,
+                     *(int(f) for f in rng.choice(len(w.n_nodes), 4, replace=False))})
+    _check_sampled(w, full, fibers)
