@@ -123,6 +123,8 @@ def parse():
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--sur-train-steps", type=int, default=20000)
     ap.add_argument("--sur-tol", type=float, default=1e-2)
+    ap.add_argument("--no-sur-relu", action="store_true",
+                    help="skip the Hodgkin-Huxley surrogate with a ReLU network")
     ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--no-exp-approx", action="store_true")
     ap.add_argument("--no-emg", action="store_true")
@@ -315,6 +317,33 @@ def surrogate_hh(args):
     y0[0] += vm[cols]
     parity = _oracle_parity(w, fibers, y0, ss, ts, w.n_steps)
     best_plain = max(res["plain_fused"]["value"], res["plain_split"]["value"])
+    relu = None
+    if not args.no_sur_relu:
+        # the same network with ReLU: one packed integer max per two
+        # activations instead of an exponential and a reciprocal each
+        t0 = time.perf_counter()
+        sr = SU.train_surrogate(I.MODEL_HH, wt, snaps, steps=args.sur_train_steps, act="relu",
+                                log=lambda m: _log("hh relu surrogate:" + m))
+        tr_s = time.perf_counter() - t0
+        s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
+        s.set_stimulus(w.stims)
+        net = sr.network()
+        s.set_surrogate(net, sr.scales, args.sur_tol)
+        _timed_run(s, w.with_steps(40), lambda: s.init_state(vm_noise=vm), w.sample_every)
+        secs, sr_s, sr_t = _timed_run(s, w, lambda: s.init_state(vm_noise=vm), w.sample_every)
+        fb = int(s.last_fallbacks())
+        net.close()
+        s.close()
+        relu = dict(network="5-64-64-64-4 ReLU, BF16 MFMA", value=w.node_steps() / secs,
+                    seconds=secs, fallbacks_last_step=fb,
+                    train=dict(adam_steps=sr.info["steps"], final_loss=sr.info["losses"][-1][1],
+                               seconds=tr_s),
+                    over_best_plain=w.node_steps() / secs / best_plain,
+                    vs_plain_split=_compare(sp, tp, sr_s, sr_t, w.dt_split,
+                                            w.n_steps * w.dt_split),
+                    vs_oracle=_oracle_parity(w, fibers, y0, sr_s, sr_t, w.n_steps))
+        _log(f"hh relu surrogate: {relu['value']:.3e} node-steps/s, "
+             f"{relu['over_best_plain']:.2f}x the best plain path")
     return dict(workload=w.name, fibers=int(len(w.n_nodes)), nodes=int(w.n_total),
                 split_steps=int(w.n_steps), dt_split_ms=w.dt_split, dt_0D_ms=w.dt_0D,
                 network="5-64-64-64-4 SiLU, BF16 MFMA", tol=args.sur_tol,
@@ -323,7 +352,7 @@ def surrogate_hh(args):
                            workload="realization 0 of the same bundle"),
                 **res, surrogate_over_best_plain=res["surrogate"]["value"] / best_plain,
                 surrogate_vs_plain_split=_compare(sp, tp, ss, ts, w.dt_split, w.n_steps * w.dt_split),
-                surrogate_vs_oracle=parity)
+                surrogate_vs_oracle=parity, relu_variant=relu)
 
 
 def surrogate_st57(args):
