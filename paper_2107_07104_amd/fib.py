@@ -508,6 +508,9 @@ class Mlp:
                          X.shape[0], g.data_ptr(), loss.data_ptr())
         return g, loss
 
+    def reset_optimizer(self):
+        fib_mlp_reset_optimizer(self.net)
+
     def adam_step(self, X, T, lr, loss=None):
         fib_mlp_adam_step(self.net, X.data_ptr(), T.data_ptr(), X.shape[0], lr,
                           loss.data_ptr() if loss is not None else 0)
