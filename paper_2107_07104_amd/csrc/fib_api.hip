@@ -517,9 +517,12 @@ int64_t max_bin_load(const fib_ctx* c) {
 int make_plan(fib_ctx* c) {
   const int64_t max_len =
       c->n_fibers ? *std::max_element(c->n_nodes.begin(), c->n_nodes.end()) : 0;
-  if (max_len > 14 * 512)
-    return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the %d nodes one workgroup holds",
-                (long long)max_len, 14 * 512);
+  int64_t max_hold = 0;  // the most nodes one workgroup of any built shape holds
+  for (int K = 2; K <= 14; ++K)
+    max_hold = std::max<int64_t>(max_hold, (int64_t)K * fib::plan_max_threads(K));
+  if (max_len > max_hold)
+    return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the %lld nodes one workgroup holds",
+                (long long)max_len, (long long)max_hold);
   int groups = c->p.groups > 0 ? c->p.groups : c->cu_count;
   groups = (int)std::min<int64_t>(groups, std::max<int32_t>(c->n_fibers, 1));
   for (;;) {

@@ -227,6 +227,29 @@ def test_ragged_and_degenerate_fibers_run():
         gpu[3].close()
 
 
+@pytest.mark.parametrize("schedule", [F.FIB_SCHED_FUSED, F.FIB_SCHED_SPLIT])
+def test_longest_fiber_matches_oracle(schedule):
+    # the longest fiber one workgroup holds (1024 threads x 8 nodes) next to a short one
+    n = np.array([8192, 37], dtype=np.int32)
+    base = I.batched_hh(n_fibers=2, t_end=1.5, onset_max=0.5)
+    w = I.Workload(name="longest", model=I.MODEL_HH, n_nodes=n,
+                   vm_noise=I._normal(17, int(n.sum()), 0.1), rel_noise=None,
+                   stims=[dict(fiber=0, node=4096, half_width=1, step_on=0, n_steps=100,
+                               period=0, amp=I.AMP_SUPRA),
+                          dict(fiber=1, node=0, half_width=1, step_on=200, n_steps=100,
+                               period=0, amp=I.AMP_SUPRA)],
+                   n_steps=base.n_steps, sample_every=100)
+    say(f"[longest fiber] schedule={schedule}")
+    ora = oracle_run(w)
+    gpu = gpu_run(w, schedule=schedule)
+    say(f"   plan {gpu[3].plan()}")
+    assert gpu[3].plan()["threads"] * gpu[3].plan()["nodes_per_thread"] >= 8192
+    res = compare_runs(w, gpu, ora)
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    assert res["activated"] > 40   # both fronts of the long fiber and the short fiber
+    gpu[3].close()
+
+
 def test_chunked_runs_and_reruns_are_bitwise_identical():
     import torch
     w = I.batched_hh(n_fibers=10, t_end=3.0, onset_max=1.0)

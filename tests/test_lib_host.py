@@ -113,6 +113,10 @@ def test_plan_preview_packs_fibers_tightly():
     # one fiber: one bin, all threads of the bin busy
     one = F.fib_plan_preview(F.make_params(), [1000], 256)
     assert one["groups"] == 1 and one["threads"] * one["nodes_per_thread"] >= 1000
-    # a fiber too long for a workgroup
-    with pytest.raises(F.FibError):
-        F.fib_plan_preview(F.make_params(), [9000], 256)
+    # the longest fiber a workgroup holds (1024 threads x 8 nodes), and one more node
+    big = F.fib_plan_preview(F.make_params(), [8192, 100], 256)
+    assert big["threads"] * big["nodes_per_thread"] >= 8192
+    for n in (8193, 9000):
+        with pytest.raises(F.FibError) as e:
+            F.fib_plan_preview(F.make_params(), [n], 256)
+        assert e.value.code == F.FIB_EUNSUPPORTED
