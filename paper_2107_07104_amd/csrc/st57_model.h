@@ -41,25 +41,30 @@ inline __host__ __device__ double fma_(double a, double b, double c) { return a 
 inline __host__ __device__ double fabs_(double x) { return fabs(x); }
 inline __host__ __device__ double fmax_(double a, double b) { return a > b ? a : b; }
 
-// x / (exp(x) - 1) with e = exp(x); Bernoulli series for |x| < 0.1.
+// c x / (exp(x) - 1) from cx = c x and e = exp(x).  The quotient is 0/0 at
+// x = 0, and its cancellation error in FP32, about 1.2e-7 / |x| relative,
+// grows as x shrinks; for |x| < 4.9e-4 its limit c replaces it (error
+// |x|/2 < 2.5e-4 there, far below FP32 resolution in FP64).
 template <typename T>
-__host__ __device__ __forceinline__ T xm1(T x, T e) {
-  const T x2 = x * x;
-  const T s = fma_(x, fma_(x, fma_(x2, T(-1.0 / 720.0), T(1.0 / 12.0)), T(-0.5)), T(1));
-  return fabs_(x) < T(0.1) ? s : x * rcp(e - T(1));
+__host__ __device__ __forceinline__ T cxm1(T cx, T e, T c) {
+  return fabs_(cx) < c * T(4.9e-4) ? c : cx * rcp(e - T(1));
 }
 
-// Hodgkin-Huxley gate derivatives at voltage V for gates (m, h, n).
+// Hodgkin-Huxley gate derivatives at voltage V for gates (m, h, n).  The
+// arguments of alpha_m, alpha_n and beta_h have slope -1/10 in V and differ
+// by constants: x_n = x_m - 3/2 and beta_h's exponent is x_m + 1/2, so one
+// exponential serves the three.
 template <typename T>
 __host__ __device__ __forceinline__ void hh_gates(T V, T m, T h, T n, T& dm, T& dh, T& dn) {
-  const T xm = fma_(V, T(-0.1), T(-5.0));
-  const T xn = fma_(V, T(-0.1), T(-6.5));
-  const T am = xm1(xm, ex2(xm * T(kL2E)));
-  const T an = T(0.1) * xm1(xn, ex2(xn * T(kL2E)));
+  const T xm = fma_(V, T(-0.1), T(-5.0));        // (25 - v)/10
+  const T xn10 = fma_(V, T(-0.01), T(-0.65));    // x_n / 10, x_n = (10 - v)/10
+  const T em = ex2(xm * T(kL2E));
+  const T am = cxm1(xm, em, T(1));
+  const T an = cxm1(xn10, em * T(0.22313016014842982893), T(0.1));  // e^-1.5
   // 4 exp(-(V+75)/18), 0.07 exp(-(V+75)/20), 1/(exp(-(V+45)/10)+1), 0.125 exp(-(V+75)/80)
   const T bm = ex2(fma_(V, T(-kL2E / 18.0), T(-75.0 * kL2E / 18.0 + 2.0)));
   const T ah = ex2(fma_(V, T(-kL2E / 20.0), T(-75.0 * kL2E / 20.0 - 3.8365012677171206)));
-  const T bh = rcp(ex2(fma_(V, T(-kL2E / 10.0), T(-45.0 * kL2E / 10.0))) + T(1));
+  const T bh = rcp(fma_(em, T(1.6487212707001281468), T(1)));  // e^0.5
   const T bn = ex2(fma_(V, T(-kL2E / 80.0), T(-75.0 * kL2E / 80.0 - 3.0)));
   dm = fma_(-(am + bm), m, am);
   dh = fma_(-(ah + bh), h, ah);
@@ -118,14 +123,20 @@ __host__ __device__ __forceinline__ void rhs_abs(const T (&y)[S], T I, T inv_cm,
   d[4] = (F(0.8) * (V - Vt) - (INat + IKt + IClt + F(0.1) * Jp)) * inv_cm;
   hh_gates(Vt, mt, ht, nt, d[5], d[6], d[7]);
 
-  // voltage-sensor chain (states 8-17): rates exp(+-(Vt - V_i)/25), V_i = -70 + 7.5 i
+  // voltage-sensor chain (states 8-17): rates exp(+-(Vt - V_i)/25),
+  // V_i = -70 + 7.5 i, as E exp(-V_i/25) and exp(V_i/25) / E with
+  // E = exp(Vt/25): one exponential and one reciprocal for the eighteen
   {
+    // exp(-V_i/25) and exp(V_i/25)
+    constexpr double kCf[9] = {16.444646771097048, 12.182493960703473, 9.025013499434122, 6.6858944422792685, 4.953032424395115, 3.6692966676192444, 2.718281828459045, 2.0137527074704766, 1.4918246976412703};
+    constexpr double kCb[9] = {0.06081006262521797, 0.0820849986238988, 0.11080315836233387, 0.14956861922263506, 0.20189651799465538, 0.2725317930340126, 0.36787944117144233, 0.4965853037914095, 0.6703200460356393};
     F kf[9], kb[9];
+    const F E = ex2(Vt * F(kL2E / 25.0));
+    const F Einv = rcp(E);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const double Vi = -70.0 + 7.5 * i;
-      kf[i] = ex2(fma_(Vt, F(kL2E / 25.0), F(-Vi * kL2E / 25.0)));
-      kb[i] = ex2(fma_(Vt, F(-kL2E / 25.0), F(Vi * kL2E / 25.0)));
+      kf[i] = E * F(kCf[i]);
+      kb[i] = Einv * F(kCb[i]);
     }
     F flow[9];  // net P_i -> P_{i+1}
 #pragma unroll
