@@ -427,7 +427,7 @@ typedef struct {
 
 /* Sets up the EMG solve for a context (which must outlive it); FIB_EINVAL
  * if the fibers do not form the bundle described above.  phi_e starts at
- * zero.  Hodgkin-Huxley models only (V_m is state row 0). */
+ * zero.  Every model (V_m is state row 0 of each). */
 int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out);
 void fib_emg_destroy(fib_emg_t* emg);
 int fib_emg_dims(const fib_emg_t* emg, int32_t* nx, int32_t* ny, int32_t* nz);

@@ -494,8 +494,6 @@ int fib_emg_create(fib_t* ctx, const fib_emg_params* p, fib_emg_t** out) {
   *out = nullptr;
   if (!ctx || !p) return efail(FIB_EINVAL, "null argument");
   const fib::CtxView v = fib::ctx_view(ctx);
-  if (v.model != FIB_MODEL_HH && v.model != FIB_MODEL_HH_APX_EXP)
-    return efail(FIB_EUNSUPPORTED, "EMG takes the Hodgkin-Huxley models");
   if (p->nx < 2 || p->ny < 2 || p->stride < 1)
     return efail(FIB_EINVAL, "nx, ny must be >= 2 and the stride >= 1");
   auto pos = [](double x) { return std::isfinite(x) && x > 0.0; };

@@ -9,6 +9,7 @@ oracle of oracle/emg.py.
   oracle's direct solve from the same V_m to 1e-4 of its largest value (the
   residual bound times the condition number of the preconditioned system,
   a few hundred on these meshes, plus FP32 rounding);
+* the same on a bundle of the 57-state model during an action potential;
 * V_m linear along the fibers gives phi_e = -sigma_i / (sigma_i + sigma_el)
   V_m up to a constant;
 * CG driven far past the FP32 accuracy of phi_e (relative residual 1e-9)
@@ -96,6 +97,25 @@ def test_deep_solve_converges_and_stays_at_the_solution(nx, ny, n, m):
     say(f"[emg deep] {nx}x{ny}x{n}/{m}: {it} iterations, residual {rel:.2e}, phi err {ep:.2e}")
     assert rel <= 1e-9 and it < 3000
     assert ep < 1e-4
+    emg.close()
+    s.close()
+
+
+def test_st57_bundle_matches_oracle():
+    # V_m is state row 0 of the 57-state model too
+    nx, ny, n, m = 4, 3, 241, 8
+    w = I.st57_bundle(n_fibers=nx * ny, n_nodes=n, t_end=1.0, onset_max=0.1)
+    s = gpu_solver(w)
+    s.run(0, 1200)
+    s.sync()
+    emg = F.Emg(s, nx, ny, m, 0.05, 0.05, **SIG)
+    it, rel = emg.solve(tol=1e-7, max_iter=5000)
+    (phi_o, _), _, V3 = _oracle(s, nx, ny, n, m, 0.05, w.h)
+    ep = np.max(np.abs(emg.phi() - phi_o)) / np.max(np.abs(phi_o))
+    say(f"[emg st57] {it} iterations, residual {rel:.2e}, phi err {ep:.2e}, "
+        f"V range {V3.min():.1f}..{V3.max():.1f}")
+    assert V3.max() - V3.min() > 50.0     # an action potential is in the mesh
+    assert rel <= 1e-7 and ep < 1e-4
     emg.close()
     s.close()
 
