@@ -26,6 +26,9 @@
 // interior values follow by back substitution.  The matrix does not change
 // between steps, so all elimination factors and PCR multipliers are
 // computed once per launch; a step only moves right-hand sides.
+#include <algorithm>
+#include <mutex>
+
 #include "fib_internal.h"
 #include "hh_model.h"
 #include "st57_model.h"
@@ -706,10 +709,11 @@ constexpr int REACT_A = 1, REACT_OBSERVE = 2, REACT_B = 4;
 // Observables at the end of split step `step` for node i with V_m offset
 // v1: activation time from v_prev, the V_m sample of sample steps, then
 // v_prev := v1.
-__device__ __forceinline__ void observe_step(const KArgs& A, int64_t i, int32_t step, float v1) {
-  const float v0 = A.v_prev[i];
+// v0 and ta are the node's v_prev and t_act, read by the caller.
+__device__ __forceinline__ void observe_step_from(const KArgs& A, int64_t i, int32_t step,
+                                                  float v0, float ta, float v1) {
   const float uth = A.v_th - A.rest[0];
-  if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
+  if (isinf(ta) && v0 < uth && v1 >= uth)
     A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
   if (A.sample_every > 0 && ((int64_t)step + 1) % A.sample_every == 0) {
     const int64_t row = ((int64_t)step + 1) / A.sample_every - 1 - A.sample_row0;
@@ -719,15 +723,14 @@ __device__ __forceinline__ void observe_step(const KArgs& A, int64_t i, int32_t 
   if (!isfinite(v1)) atomicOr(A.flag, 1);
 }
 
+__device__ __forceinline__ void observe_step(const KArgs& A, int64_t i, int32_t step, float v1) {
+  observe_step_from(A, i, step, A.v_prev[i], A.t_act[i], v1);
+}
+
+// The reaction phases of one node (flags as above) on its states u.
 template <class M>
-__global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t step_b,
-                                               int flags) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n_total) return;
-  const int64_t nt = A.n_total;
-  float u[M::S];
-#pragma unroll
-  for (int k = 0; k < M::S; ++k) u[k] = A.state[k * nt + i];
+__device__ __forceinline__ void react_node(const KArgs& A, int64_t i, float (&u)[M::S],
+                                           int32_t step_a, int32_t step_b, int flags) {
   const uint32_t sid = (uint32_t)A.node_stim[i];
   if (flags & REACT_A) {
     const float I = stim_current(sid, A.stim, step_a);
@@ -739,8 +742,77 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
     if (stim_eval(sid, A.stim, step_b, I, vp)) u[0] = vp;
     for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
   }
+}
+
+template <class M>
+__global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t step_b,
+                                               int flags) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_total) return;
+  const int64_t nt = A.n_total;
+  float u[M::S];
+#pragma unroll
+  for (int k = 0; k < M::S; ++k) u[k] = A.state[k * nt + i];
+  react_node<M>(A, i, u, step_a, step_b, flags);
 #pragma unroll
   for (int k = 0; k < M::S; ++k) A.state[k * nt + i] = u[k];
+}
+
+// The same phases over a grid that fits on the device at once: a thread
+// takes nodes i, i + stride, ... and loads the next node's states before it
+// solves the current one.  A model whose right-hand side holds a wave at
+// one per SIMD (ST57) has no other wave there to cover the loads; this way
+// they run under the wave's own arithmetic.  Loads return in issue order,
+// so everything the current node reads (stimulus entry, v_prev, t_act) is
+// read before the next node's loads are issued: waiting for it then does
+// not wait for them.
+template <class M>
+__global__ __launch_bounds__(256) void k_react_stream(KArgs A, int32_t step_a, int32_t step_b,
+                                                      int flags) {
+  const int64_t nt = A.n_total;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool obs = flags & REACT_OBSERVE;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nt) return;
+  // the next node's inputs: states, stimulus entry, v_prev and t_act
+  float nx[M::S];
+  uint32_t nsid = (uint32_t)A.node_stim[i];
+  float nv0 = obs ? A.v_prev[i] : 0.0f, nta = obs ? A.t_act[i] : 0.0f;
+#pragma unroll
+  for (int k = 0; k < M::S; ++k) nx[k] = A.state[k * nt + i];
+  for (; i < nt; i += stride) {
+    float u[M::S];
+#pragma unroll
+    for (int k = 0; k < M::S; ++k) u[k] = nx[k];
+    const uint32_t sid = nsid;
+    float v0 = nv0, ta = nta;
+    float Ia = 0.0f, Ib = 0.0f, vb = 0.0f;
+    int set_b = 0;
+    if (flags & REACT_A) Ia = stim_current(sid, A.stim, step_a);
+    if (flags & REACT_B) set_b = stim_eval(sid, A.stim, step_b, Ib, vb);
+    // all of them in registers here, so no later wait for one of them waits
+    // for the next node's loads too
+    asm volatile("" : "+v"(Ia), "+v"(Ib), "+v"(vb), "+v"(set_b), "+v"(v0), "+v"(ta));
+    const int64_t j = i + stride;
+    if (j < nt) {
+      nsid = (uint32_t)A.node_stim[j];
+      if (obs) {
+        nv0 = A.v_prev[j];
+        nta = A.t_act[j];
+      }
+#pragma unroll
+      for (int k = 0; k < M::S; ++k) nx[k] = A.state[k * nt + j];
+    }
+    if (flags & REACT_A)
+      for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, Ia, A.tau, A.inv_cm);
+    if (obs) observe_step_from(A, i, step_a, v0, ta, u[0]);
+    if (flags & REACT_B) {
+      if (set_b) u[0] = vb;
+      for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, Ib, A.tau, A.inv_cm);
+    }
+#pragma unroll
+    for (int k = 0; k < M::S; ++k) A.state[k * nt + i] = u[k];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -945,6 +1017,26 @@ hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KA
   return dispatch_plan<DiffusionLaunch>(K, threads, groups, lds, a, s);
 }
 
+// Workgroups of k_react_stream<ModelST57> resident on the current device at
+// once (queried once per device; without an answer, one thread per node).
+static unsigned st57_stream_blocks() {
+  static std::mutex mu;
+  static unsigned cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return ~0u;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_react_stream<ModelST57>, 256,
+                                                      0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+      return ~0u;
+    cache[dev] = (unsigned)cus * (unsigned)per_cu;
+  }
+  return cache[dev];
+}
+
 hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, const KArgs& a,
                         hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
@@ -954,7 +1046,8 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
   else if (model == 2)
     hipLaunchKernelGGL(k_react<ModelHHApx>, grid, block, 0, s, a, step_a, step_b, flags);
   else if (model == 1)
-    hipLaunchKernelGGL(k_react<ModelST57>, grid, block, 0, s, a, step_a, step_b, flags);
+    hipLaunchKernelGGL(k_react_stream<ModelST57>, dim3(std::min(grid.x, st57_stream_blocks())),
+                       block, 0, s, a, step_a, step_b, flags);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
