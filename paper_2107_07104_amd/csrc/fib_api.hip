@@ -290,6 +290,8 @@ struct fib_ctx {
   uint8_t* d_pt = nullptr;             // [2][n_total] point flags by step parity
   uint8_t* d_fiber_any = nullptr;      // [2][n_fibers] by step parity
   unsigned long long* d_adapt_count = nullptr;  // [kAdaptCounters]
+  int32_t* d_adapt_list = nullptr;     // ST57: [n_total] nodes solved in the step
+  int32_t* d_adapt_lcount = nullptr;   // ST57: [2] list lengths by step parity
   int adapt_par = 0;                   // parity of the buffer with the latest flags
   // tables of the adaptive fused kernel, valid for plan / stimulus versions
   uint8_t* d_slot_fiber = nullptr;     // [groups * cap] bin-local fiber of each slot
@@ -722,10 +724,34 @@ int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * nt, hipMemcpyDeviceToDevice,
                          c->stream));
   const size_t lds = fib::lds_bytes_for(c->threads, c->levels);
+  // ST57: decisions, then the reaction parts over the list of solved nodes
+  const bool listed = c->p.model == FIB_MODEL_ST57;
+  int32_t* list = c->d_adapt_list;
+  int32_t* counts = c->d_adapt_lcount;
+  if (listed && (!list || !counts)) return fail(FIB_EINVAL, "adaptive ST57 list not allocated");
+  if (listed) HIP_TRY(hipMemsetAsync(counts, 0, 2 * sizeof(int32_t), c->stream));
+  auto start = [&](int64_t n, bool godunov_step, bool observe_prev) -> hipError_t {
+    if (!listed)
+      return fib::launch_adapt_start(c->p.model, godunov_step, (int32_t)n, observe_prev, a,
+                                     c->stream);
+    const int slot = (int)(n & 1);
+    hipError_t e = fib::launch_adapt_decide(godunov_step, (int32_t)n, observe_prev, list, counts,
+                                            slot, a, c->stream);
+    if (e != hipSuccess) return e;
+    return fib::launch_adapt_solve(c->p.model, godunov_step ? 2 : 0, (int32_t)n, list,
+                                   counts + slot, a, c->stream);
+  };
+  auto finish = [&](int64_t n) -> hipError_t {
+    if (!listed) return fib::launch_adapt_finish(c->p.model, (int32_t)n, a, c->stream);
+    hipError_t e = fib::launch_adapt_solve(c->p.model, 1, (int32_t)n, list, counts + (n & 1), a,
+                                           c->stream);
+    if (e != hipSuccess) return e;
+    return fib::launch_observe((int32_t)n, a, c->stream);
+  };
   if (godunov) {
     for (int64_t n = step0; n < end; ++n) {
       at(n);
-      HIP_TRY(fib::launch_adapt_start(c->p.model, true, (int32_t)n, n > step0, a, c->stream));
+      HIP_TRY(start(n, true, n > step0));
       HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
     }
     KArgs o = a;
@@ -733,14 +759,14 @@ int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
     HIP_TRY(fib::launch_react(c->p.model, (int32_t)(end - 1), 0, 2, o, c->stream));
   } else {
     at(step0);
-    HIP_TRY(fib::launch_adapt_start(c->p.model, false, (int32_t)step0, false, a, c->stream));
+    HIP_TRY(start(step0, false, false));
     for (int64_t n = step0; n < end; ++n) {
       at(n);
       HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
-      HIP_TRY(fib::launch_adapt_finish(c->p.model, (int32_t)n, a, c->stream));
+      HIP_TRY(finish(n));
       if (n + 1 < end) {
         at(n + 1);
-        HIP_TRY(fib::launch_adapt_start(c->p.model, false, (int32_t)(n + 1), false, a, c->stream));
+        HIP_TRY(start(n + 1, false, false));
       }
     }
   }
@@ -921,6 +947,8 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_pt);
   (void)hipFree(c->d_fiber_any);
   (void)hipFree(c->d_adapt_count);
+  (void)hipFree(c->d_adapt_list);
+  (void)hipFree(c->d_adapt_lcount);
   (void)hipFree(c->d_slot_fiber);
   (void)hipFree(c->d_bin_first_on);
   delete c;
@@ -1486,6 +1514,17 @@ int fib_set_adaptive(fib_t* c, double tol) {
       return fail(FIB_ENOMEM, "device allocation failed");
     }
     HIP_TRY(hipMemcpy(c->d_node_fiber, fib_of.data(), sizeof(int32_t) * nt, hipMemcpyHostToDevice));
+  }
+  if (c->p.model == FIB_MODEL_ST57 && !c->d_adapt_list) {
+    if (c->n_total > INT32_MAX)
+      return fail(FIB_EUNSUPPORTED, "adaptive ST57 lists nodes as 32-bit indices");
+    if (hipMalloc(&c->d_adapt_list, sizeof(int32_t) * nt) != hipSuccess ||
+        hipMalloc(&c->d_adapt_lcount, sizeof(int32_t) * 2) != hipSuccess) {
+      (void)hipFree(c->d_adapt_list);
+      (void)hipFree(c->d_adapt_lcount);
+      c->d_adapt_list = c->d_adapt_lcount = nullptr;
+      return fail(FIB_ENOMEM, "device allocation failed");
+    }
   }
   if (c->n_fibers > 0)
     HIP_TRY(hipMemcpy(c->d_first_on, c->first_on.data(), sizeof(int32_t) * c->n_fibers,

@@ -167,12 +167,23 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
 // observables of step - 1 if observe_prev, the points to solve (from the
 // flags of the previous step and the stimulus), their V_m prescriptions and
 // the reaction part before the diffusion; with Godunov splitting (the
-// step's only reaction part) also their equilibrium check.
+// step's only reaction part) also their equilibrium check.  Hodgkin-Huxley
+// models only (ST57 takes the list form below).
 hipError_t launch_adapt_start(int model, bool godunov, int32_t step, bool observe_prev,
                               const KArgs& a, hipStream_t s);
 // End of Strang split step `step`: the second reaction half and the
-// equilibrium check of the solved points, then the observables.
+// equilibrium check of the solved points, then the observables
+// (Hodgkin-Huxley models).
 hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStream_t s);
+// The adaptive split steps for ST57: decisions and a list of the solved
+// nodes (counts[slot]; counts[slot ^ 1] is cleared), the reaction parts over
+// that list (phase 0: Strang start, 1: Strang end, 2: Godunov step), and the
+// observables of every node.
+hipError_t launch_adapt_decide(bool godunov, int32_t step, bool observe_prev, int* list,
+                              int* counts, int slot, const KArgs& a, hipStream_t s);
+hipError_t launch_adapt_solve(int model, int phase, int32_t step, const int* list,
+                              const int* count, const KArgs& a, hipStream_t s);
+hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);

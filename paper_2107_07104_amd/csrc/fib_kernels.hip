@@ -334,6 +334,22 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
 
 // Equilibrium check: the relative change |y_k+ - y_k| > tol |y_k| of any
 // state over the reaction part (y = offset + rest).
+// The same test against the state before the reaction part, read again from
+// memory (node i's entry `col` of state row 0, rows `stride` apart) rather
+// than held in registers through the substeps.
+template <int S>
+__device__ __forceinline__ bool state_moved(const float (&u)[S], const float* col, int64_t stride,
+                                            const float* rest, float tol) {
+  __asm__("" : "+v"(col));  // a new read, not the registers of the first one
+  bool m = false;
+#pragma unroll
+  for (int k = 0; k < S; ++k) {
+    const float b = col[k * stride];
+    m |= fabsf(u[k] - b) > tol * fabsf(b + rest[k]);
+  }
+  return m;
+}
+
 template <int S>
 __device__ __forceinline__ bool point_moved(const float (&u)[S], const float (&b)[S],
                                             const float* rest, float tol) {
@@ -819,6 +835,30 @@ __global__ __launch_bounds__(256) void k_react_stream(KArgs A, int32_t step_a, i
 // Adaptive computation (split schedule), one node per thread
 // ---------------------------------------------------------------------------
 
+// Whether node i is solved in split step `step` (the rules above); nodes of
+// fibers left out carry their flags.  With observe_prev, first the
+// observables of step - 1.
+__device__ __forceinline__ void adapt_decide(const KArgs& A, int64_t i, int32_t step,
+                                             int observe_prev, bool& solve, bool& on,
+                                             int32_t& f) {
+  const int64_t nt = A.n_total;
+  if (observe_prev) observe_step(A, i, step - 1, A.state[i]);
+  f = A.node_fiber[i];
+  on = step >= A.fiber_first_on[f];
+  solve = false;
+  if (on) {
+    solve = (A.pt_prev[i] & PT_ACTIVE) || stim_any_on((uint32_t)A.node_stim[i], A.stim, step);
+    if (i > 0 && A.node_fiber[i - 1] == f)
+      solve = solve || (A.pt_prev[i - 1] & PT_ACTIVE) ||
+              stim_any_on((uint32_t)A.node_stim[i - 1], A.stim, step);
+    if (i + 1 < nt && A.node_fiber[i + 1] == f)
+      solve = solve || (A.pt_prev[i + 1] & PT_ACTIVE) ||
+              stim_any_on((uint32_t)A.node_stim[i + 1], A.stim, step);
+  } else {
+    A.pt_cur[i] = A.pt_prev[i];
+  }
+}
+
 // Start of split step `step`.  A node of a fiber that takes part (step at or
 // after the fiber's first stimulus) is solved if the last check found it or
 // a neighbour in its fiber active, or a stimulus entry covers it or a
@@ -832,22 +872,7 @@ __global__ __launch_bounds__(256) void k_adapt_start(KArgs A, int32_t step, int 
   const bool real = i < nt;
   bool solve = false, on = false;
   int32_t f = 0;
-  if (real) {
-    if (observe_prev) observe_step(A, i, step - 1, A.state[i]);
-    f = A.node_fiber[i];
-    on = step >= A.fiber_first_on[f];
-    if (on) {
-      solve = (A.pt_prev[i] & PT_ACTIVE) || stim_any_on((uint32_t)A.node_stim[i], A.stim, step);
-      if (i > 0 && A.node_fiber[i - 1] == f)
-        solve = solve || (A.pt_prev[i - 1] & PT_ACTIVE) ||
-                stim_any_on((uint32_t)A.node_stim[i - 1], A.stim, step);
-      if (i + 1 < nt && A.node_fiber[i + 1] == f)
-        solve = solve || (A.pt_prev[i + 1] & PT_ACTIVE) ||
-                stim_any_on((uint32_t)A.node_stim[i + 1], A.stim, step);
-    } else {
-      A.pt_cur[i] = A.pt_prev[i];
-    }
-  }
+  if (real) adapt_decide(A, i, step, observe_prev, solve, on, f);
   const uint64_t mask = __ballot(solve);
   if ((threadIdx.x & 63) == 0 && mask)
     atomicAdd(&A.adapt_count[blockIdx.x % kAdaptCounters], (unsigned long long)__popcll(mask));
@@ -899,6 +924,92 @@ __global__ __launch_bounds__(256) void k_adapt_finish(KArgs A, int32_t step) {
     v1 = A.state[i];
   }
   observe_step(A, i, step, v1);
+}
+
+// The same steps for a model with a heavy right-hand side (ST57), where a
+// kernel that both decides and solves holds its register budget even in the
+// many waves that solve nothing.  k_adapt_decide takes the decisions of
+// k_adapt_start and appends the solved nodes to a list (one atomic per wave);
+// k_adapt_solve runs a reaction part over the list only; k_observe takes
+// the observables of every node.  Per node the arithmetic is that of
+// k_adapt_start / k_adapt_finish.  Each launch of k_adapt_decide also
+// clears the other of the two list counters, the one the next step uses.
+template <bool GODUNOV>
+__global__ __launch_bounds__(256) void k_adapt_decide(KArgs A, int32_t step, int observe_prev,
+                                                      int* __restrict__ list,
+                                                      int* __restrict__ counts, int slot) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool real = i < A.n_total;
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
+  bool solve = false, on = false;
+  int32_t f = 0;
+  if (real) adapt_decide(A, i, step, observe_prev, solve, on, f);
+  const uint64_t mask = __ballot(solve);
+  const int lane = threadIdx.x & 63;
+  if (mask) {
+    const int first = __ffsll((unsigned long long)mask) - 1;
+    int base = 0;
+    if (lane == first) {
+      atomicAdd(&A.adapt_count[blockIdx.x % kAdaptCounters], (unsigned long long)__popcll(mask));
+      base = atomicAdd(counts + slot, __popcll(mask));
+    }
+    base = __shfl(base, first);
+    if (solve) list[base + __popcll(mask & ((1ull << lane) - 1ull))] = (int)i;
+  }
+  if (!real || !on) return;
+  if (!solve) {
+    A.pt_cur[i] = 0;
+    return;
+  }
+  A.fiber_any[f] = 1;
+  if (!GODUNOV) A.pt_cur[i] = PT_SOLVE;
+}
+
+// Reaction part of the nodes list[0 .. *count) in split step `step`.
+// PHASE 0: start of a Strang step (prescriptions, first half);
+// PHASE 1: end of a Strang step (second half, equilibrium check);
+// PHASE 2: a Godunov step (prescriptions, reaction, check).
+template <class M, int PHASE>
+__global__ __launch_bounds__(256) void k_adapt_solve(KArgs A, int32_t step,
+                                                     const int* __restrict__ list,
+                                                     const int* __restrict__ count) {
+  constexpr int S = M::S;
+  const int64_t nt = A.n_total;
+  const int64_t n = *count;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = list[e];
+    float u[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) u[k] = A.state[k * nt + i];
+    const uint32_t sid = (uint32_t)A.node_stim[i];
+    if (PHASE == 1) {
+      const float I = stim_current(sid, A.stim, step);
+      for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+      A.pt_cur[i] = state_moved<S>(u, A.state + i, nt, A.rest, A.adapt_tol) ? PT_ACTIVE : 0;
+    } else {
+      float I, vp;
+      if (stim_eval(sid, A.stim, step, I, vp)) u[0] = vp;
+      if (PHASE == 2) {
+        float b[S];
+#pragma unroll
+        for (int k = 0; k < S; ++k) b[k] = u[k];
+        for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+        A.pt_cur[i] = point_moved<S>(u, b, A.rest, A.adapt_tol) ? PT_ACTIVE : 0;
+      } else {
+        for (int s = 0; s < A.n_sub; ++s) M::heun(u, A.rest, I, A.tau, A.inv_cm);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) A.state[k * nt + i] = u[k];
+  }
+}
+
+// Observables at the end of split step `step` for every node.
+__global__ __launch_bounds__(256) void k_observe(KArgs A, int32_t step) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n_total) return;
+  observe_step(A, i, step, A.state[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,6 +1164,44 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
   return hipGetLastError();
 }
 
+hipError_t launch_adapt_decide(bool godunov, int32_t step, bool observe_prev, int* list,
+                              int* counts, int slot, const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  const dim3 grid(blocks_for(a.n_total, 256)), block(256);
+  if (godunov)
+    hipLaunchKernelGGL(k_adapt_decide<true>, grid, block, 0, s, a, step, observe_prev ? 1 : 0,
+                       list, counts, slot);
+  else
+    hipLaunchKernelGGL(k_adapt_decide<false>, grid, block, 0, s, a, step, observe_prev ? 1 : 0,
+                       list, counts, slot);
+  return hipGetLastError();
+}
+
+template <int PHASE>
+static void adapt_solve_st57(dim3 grid, int32_t step, const int* list, const int* count,
+                             const KArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL((k_adapt_solve<ModelST57, PHASE>), grid, dim3(256), 0, s, a, step, list,
+                     count);
+}
+
+hipError_t launch_adapt_solve(int model, int phase, int32_t step, const int* list,
+                              const int* count, const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  if (model != 1 || phase < 0 || phase > 2) return hipErrorInvalidValue;
+  // grid-stride over the list, whose length only the device knows
+  const dim3 grid(std::min(blocks_for(a.n_total, 256), 1024u));
+  if (phase == 0) adapt_solve_st57<0>(grid, step, list, count, a, s);
+  if (phase == 1) adapt_solve_st57<1>(grid, step, list, count, a, s);
+  if (phase == 2) adapt_solve_st57<2>(grid, step, list, count, a, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_observe, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, step);
+  return hipGetLastError();
+}
+
 template <class M>
 static hipError_t adapt_start_for(bool godunov, int32_t step, bool observe_prev, const KArgs& a,
                                   hipStream_t s) {
@@ -1069,8 +1218,7 @@ hipError_t launch_adapt_start(int model, bool godunov, int32_t step, bool observ
   if (a.n_total == 0) return hipSuccess;
   if (model == 0) return adapt_start_for<ModelHH>(godunov, step, observe_prev, a, s);
   if (model == 2) return adapt_start_for<ModelHHApx>(godunov, step, observe_prev, a, s);
-  if (model == 1) return adapt_start_for<ModelST57>(godunov, step, observe_prev, a, s);
-  return hipErrorInvalidValue;
+  return hipErrorInvalidValue;  // ST57: launch_adapt_decide + launch_adapt_solve
 }
 
 hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStream_t s) {
@@ -1080,10 +1228,8 @@ hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStrea
     hipLaunchKernelGGL(k_adapt_finish<ModelHH>, grid, block, 0, s, a, step);
   else if (model == 2)
     hipLaunchKernelGGL(k_adapt_finish<ModelHHApx>, grid, block, 0, s, a, step);
-  else if (model == 1)
-    hipLaunchKernelGGL(k_adapt_finish<ModelST57>, grid, block, 0, s, a, step);
   else
-    return hipErrorInvalidValue;
+    return hipErrorInvalidValue;  // ST57: launch_adapt_solve + launch_observe
   return hipGetLastError();
 }
 

@@ -14,6 +14,10 @@
   agree with the oracle's to 2 % (the FP32 check may decide points near the
   threshold the other way);
 * chunked runs, starting at odd and even steps, equal one run bit for bit;
+* ST57 runs the list form (decisions, then the reaction parts over the list
+  of solved nodes): at a vanishing tolerance it is the plain split run up
+  to FP32 rounding under both splittings, it matches the oracle under Godunov
+  splitting too, and chunked runs equal one run;
 * the requests the library refuses.
 """
 from dataclasses import replace
@@ -173,6 +177,55 @@ def test_st57_bundle_matches_oracle():
     say(f"[adaptive ST57] steps={w.n_steps}")
     share = _parity(w, 1e-6)
     assert share < 0.8
+
+
+@pytest.mark.parametrize("splitting", [F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV])
+def test_st57_vanishing_tolerance_is_the_plain_schedule(splitting):
+    """ST57 takes the list form (decisions, then the reaction parts over the
+    solved nodes): with every point active it is the plain split run up to
+    FP32 rounding (the two kernels compile the same Heun steps with their
+    multiply-adds contracted differently; a node solved twice or not at all
+    would be millivolts off)."""
+    w = _at_zero(I.st57_bundle(n_fibers=4, n_nodes=180, t_end=0.15, onset_max=0.0))
+    say(f"[adaptive ST57 tol->0] splitting={splitting} nodes={w.n_total} steps={w.n_steps}")
+    plain = gpu_solver(w, splitting=splitting)
+    yp, sp, tp = _run(plain, w, w.n_steps)
+    plain.close()
+    ya, sa, ta, s = _adaptive_gpu(w, 1e-30, splitting=splitting)
+    d = np.abs(ya - yp) / (1.0 + np.abs(yp))
+    say(f"   max relative state difference {d.max():.2e}, "
+        f"{np.count_nonzero(ya != yp)} of {ya.size} entries differ")
+    assert d.max() < 1e-6
+    np.testing.assert_allclose(sa, sp, rtol=0, atol=1e-4)
+    assert np.array_equal(np.isfinite(ta), np.isfinite(tp)) and np.isfinite(tp).any()
+    fin = np.isfinite(tp)
+    assert np.max(np.abs(ta[fin] - tp[fin])) < 1e-6
+    assert s.adaptive_solved() == w.n_total * w.n_steps
+    s.close()
+
+
+def test_st57_godunov_matches_oracle():
+    w = _quiet(I.st57_bundle(n_fibers=4, n_nodes=301, t_end=1.0, onset_max=0.3))
+    say(f"[adaptive ST57 Godunov] steps={w.n_steps}")
+    share = _parity(w, 1e-6, F.FIB_SPLIT_GODUNOV)
+    assert share < 0.8
+
+
+@pytest.mark.parametrize("splitting", [F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV])
+def test_st57_chunked_adaptive_runs_are_bitwise_identical(splitting):
+    w = _quiet(I.st57_bundle(n_fibers=3, n_nodes=150, t_end=0.5, onset_max=0.1))
+    ys, ss, ts, s = _adaptive_gpu(w, 1e-6, splitting=splitting)
+    n1 = s.adaptive_solved()
+    s.close()
+    c = gpu_solver(w, splitting=splitting)
+    c.set_adaptive(1e-6)
+    for a, b in ((0, 171), (171, 500), (500, 733), (733, w.n_steps)):
+        c.run(a, b - a)
+    c.sync()
+    np.testing.assert_array_equal(c.get_state(), ys)
+    np.testing.assert_array_equal(c.tact(), ts)
+    assert c.adaptive_solved() == n1 > 0
+    c.close()
 
 
 @pytest.mark.parametrize("schedule", SCHEDULES)
