@@ -741,12 +741,12 @@ int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
     return fib::launch_adapt_solve(c->p.model, godunov_step ? 2 : 0, (int32_t)n, list,
                                    counts + slot, a, c->stream);
   };
+  // (list form: the observables of step n are taken by the decisions of
+  // step n + 1, those of the last step by k_observe)
   auto finish = [&](int64_t n) -> hipError_t {
     if (!listed) return fib::launch_adapt_finish(c->p.model, (int32_t)n, a, c->stream);
-    hipError_t e = fib::launch_adapt_solve(c->p.model, 1, (int32_t)n, list, counts + (n & 1), a,
-                                           c->stream);
-    if (e != hipSuccess) return e;
-    return fib::launch_observe((int32_t)n, a, c->stream);
+    return fib::launch_adapt_solve(c->p.model, 1, (int32_t)n, list, counts + (n & 1), a,
+                                   c->stream);
   };
   if (godunov) {
     for (int64_t n = step0; n < end; ++n) {
@@ -766,9 +766,10 @@ int run_adaptive(fib_ctx* c, KArgs a, int64_t step0, int64_t n_steps) {
       HIP_TRY(finish(n));
       if (n + 1 < end) {
         at(n + 1);
-        HIP_TRY(start(n + 1, false, false));
+        HIP_TRY(start(n + 1, false, listed));
       }
     }
+    if (listed) HIP_TRY(fib::launch_observe((int32_t)(end - 1), a, c->stream));
   }
   c->adapt_par = (int)((end - 1) & 1);
   return FIB_OK;

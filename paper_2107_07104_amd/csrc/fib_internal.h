@@ -178,7 +178,7 @@ hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStrea
 // The adaptive split steps for ST57: decisions and a list of the solved
 // nodes (counts[slot]; counts[slot ^ 1] is cleared), the reaction parts over
 // that list (phase 0: Strang start, 1: Strang end, 2: Godunov step), and the
-// observables of every node.
+// observables of every node (after a run's last step).
 hipError_t launch_adapt_decide(bool godunov, int32_t step, bool observe_prev, int* list,
                               int* counts, int slot, const KArgs& a, hipStream_t s);
 hipError_t launch_adapt_solve(int model, int phase, int32_t step, const int* list,

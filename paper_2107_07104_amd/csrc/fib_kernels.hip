@@ -930,8 +930,9 @@ __global__ __launch_bounds__(256) void k_adapt_finish(KArgs A, int32_t step) {
 // kernel that both decides and solves holds its register budget even in the
 // many waves that solve nothing.  k_adapt_decide takes the decisions of
 // k_adapt_start and appends the solved nodes to a list (one atomic per wave);
-// k_adapt_solve runs a reaction part over the list only; k_observe takes
-// the observables of every node.  Per node the arithmetic is that of
+// k_adapt_solve runs a reaction part over the list only.  The observables
+// of a Strang step are taken by the next step's decisions (observe_prev),
+// those of a run's last step by k_observe.  Per node the arithmetic is that of
 // k_adapt_start / k_adapt_finish.  Each launch of k_adapt_decide also
 // clears the other of the two list counters, the one the next step uses.
 template <bool GODUNOV>
