@@ -843,20 +843,24 @@ __device__ __forceinline__ void adapt_decide(const KArgs& A, int64_t i, int32_t 
                                              int32_t& f) {
   const int64_t nt = A.n_total;
   if (observe_prev) observe_step(A, i, step - 1, A.state[i]);
+  // every flag of the node and its neighbours read at once (no short
+  // circuit, whose branches would serialise the loads); a neighbour counts
+  // if it exists and lies on the same fiber
+  const int64_t il = i > 0 ? i - 1 : i, ir = i + 1 < nt ? i + 1 : i;
   f = A.node_fiber[i];
+  const int32_t fl = A.node_fiber[il], fr = A.node_fiber[ir];
+  const uint8_t p = A.pt_prev[i], pl = A.pt_prev[il], pr = A.pt_prev[ir];
+  const uint32_t sc = (uint32_t)A.node_stim[i], sl = (uint32_t)A.node_stim[il],
+                 sr = (uint32_t)A.node_stim[ir];
   on = step >= A.fiber_first_on[f];
-  solve = false;
-  if (on) {
-    solve = (A.pt_prev[i] & PT_ACTIVE) || stim_any_on((uint32_t)A.node_stim[i], A.stim, step);
-    if (i > 0 && A.node_fiber[i - 1] == f)
-      solve = solve || (A.pt_prev[i - 1] & PT_ACTIVE) ||
-              stim_any_on((uint32_t)A.node_stim[i - 1], A.stim, step);
-    if (i + 1 < nt && A.node_fiber[i + 1] == f)
-      solve = solve || (A.pt_prev[i + 1] & PT_ACTIVE) ||
-              stim_any_on((uint32_t)A.node_stim[i + 1], A.stim, step);
-  } else {
-    A.pt_cur[i] = A.pt_prev[i];
-  }
+  const bool use_l = il != i && fl == f, use_r = ir != i && fr == f;
+  const bool act = ((p & PT_ACTIVE) != 0) | (use_l & ((pl & PT_ACTIVE) != 0)) |
+                   (use_r & ((pr & PT_ACTIVE) != 0));
+  const int stim = (int)stim_any_on(sc, A.stim, step) |
+                   ((int)use_l & (int)stim_any_on(sl, A.stim, step)) |
+                   ((int)use_r & (int)stim_any_on(sr, A.stim, step));
+  solve = on && (act || stim);
+  if (!on) A.pt_cur[i] = p;
 }
 
 // Start of split step `step`.  A node of a fiber that takes part (step at or
