@@ -252,9 +252,13 @@ int fib_run(fib_t* ctx, int64_t step0, int64_t n_steps, int64_t sample_every, fl
  * fused kernel that keeps each bin's states in LDS and compacts the solved
  * nodes of every step; it takes plans with at most 64 fibers per bin whose
  * states fit the LDS (fib_run returns FIB_EUNSUPPORTED otherwise).  SPLIT
- * runs one start kernel, the diffusion and (Strang) one finish kernel per
- * step, for both models.  AUTO takes the fused variant where it can, else
- * the split schedule.  FIB_EUNSUPPORTED with an attached surrogate.
+ * runs, for Hodgkin-Huxley, one start kernel, the diffusion and (Strang) one
+ * finish kernel per step; for ST57 a decision kernel that lists the solved
+ * nodes, the reaction parts over that list, and the diffusion (the library
+ * then holds a list of n_total 32-bit indices on the device, allocated here;
+ * FIB_EUNSUPPORTED for more than 2^31 - 1 nodes, FIB_ENOMEM if it does not
+ * fit).  AUTO takes the fused variant where it can, else the split
+ * schedule.  FIB_EUNSUPPORTED with an attached surrogate.
  * fib_autotune times the plain schedule and leaves the points alone.
  * Blocking. */
 int fib_set_adaptive(fib_t* ctx, double tol);
