@@ -8,6 +8,11 @@
 * backpropagation of the full network against central finite differences;
 * the first Adam step moves every parameter by lr * sign(g) (bias-corrected
   moments give m/sqrt(v) = g/|g| at t = 1);
+* Adam beyond the first step: with a constant gradient the bias-corrected
+  moments are exactly g and g^2 at every step, so every step moves by
+  lr * sign(g) (a wrong step count or bias correction breaks this from t = 2
+  on); hand-computed three-step examples with alternating signs and with a
+  changing magnitude (these separate beta1 from beta2);
 * ReLU: closed forms, a ReLU network whose pre-activations are all positive
   is the product of its affine maps, one whose hidden pre-activations are
   all negative outputs its last bias, and its backpropagation matches
@@ -82,6 +87,41 @@ def test_first_adam_step_moves_by_lr_times_sign():
     new = M.adam_step(params, grads, {}, lr=0.01)
     np.testing.assert_allclose(new[0][0], [[1.0 - 0.01, -2.0 + 0.01]], rtol=1e-6)
     assert new[0][1][0] == 0.5
+
+
+def test_adam_with_a_constant_gradient_moves_by_lr_every_step():
+    W0, b0 = np.array([[1.0, -2.0, 0.25]]), np.array([0.5])
+    gW, gb = np.array([[0.3, -4.0, 1e-3]]), np.array([2.0])
+    state, p = {}, [(W0, b0)]
+    for t in range(1, 8):
+        p = M.adam_step(p, [(gW, gb)], state, lr=0.01)
+        np.testing.assert_allclose(p[0][0], W0 - t * 0.01 * gW / (np.abs(gW) + 1e-8),
+                                   rtol=1e-12, atol=1e-15)
+        np.testing.assert_allclose(p[0][1], b0 - t * 0.01 * 2.0 / (2.0 + 1e-8), rtol=1e-12)
+    assert state["t"] == 7
+
+
+def test_adam_hand_computed_three_steps():
+    """Kingma & Ba's update by hand (eps = 0).  Gradients +g, -g, +g (|g| fixed, so the
+    bias-corrected second moment is g^2 at every step):
+      t=1: m = 0.1 g,               m/(1-0.9)   = g,          step -lr
+      t=2: m = 0.09 g - 0.1 g,      m/(1-0.81)  = -g/19,      step +lr/19
+      t=3: m = -0.009 g + 0.1 g,    m/(1-0.729) = 91 g/271,   step -91 lr/271
+    Gradients 1 then 3 on one parameter:
+      t=2: m = 0.09 + 0.3 = 0.39,   v = 0.000999 + 0.009 = 0.009999,
+           m_hat = 39/19,           v_hat = 0.009999/0.001999 = 9999/1999."""
+    lr, g = 0.01, 0.7
+    state, p = {}, [(np.array([[0.0]]), np.array([0.0]))]
+    want = [-lr, -lr + lr / 19.0, -lr + lr / 19.0 - 91.0 * lr / 271.0]
+    for t, sgn in enumerate((1.0, -1.0, 1.0)):
+        p = M.adam_step(p, [(np.array([[sgn * g]]), np.array([-sgn * g]))], state, lr=lr, eps=0.0)
+        assert p[0][0][0, 0] == pytest.approx(want[t], rel=1e-9)
+        assert p[0][1][0] == pytest.approx(-want[t], rel=1e-9)
+    state, p = {}, [(np.array([[0.0]]), np.array([0.0]))]
+    p = M.adam_step(p, [(np.array([[1.0]]), np.array([1.0]))], state, lr=lr, eps=0.0)
+    p = M.adam_step(p, [(np.array([[3.0]]), np.array([3.0]))], state, lr=lr, eps=0.0)
+    step2 = (39.0 / 19.0) / np.sqrt(9999.0 / 1999.0)
+    assert p[0][0][0, 0] == pytest.approx(-lr - lr * step2, rel=1e-9)
 
 
 def test_param_count_of_the_surrogate_shapes():
