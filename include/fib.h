@@ -405,6 +405,54 @@ int fib_clear_surrogate(fib_t* ctx);
  * (blocking). */
 int fib_surrogate_last_fallbacks(fib_t* ctx, int64_t* n);
 
+/* Nodes that took the plain path, summed over every surrogate step since
+ * the step was attached (fib_set_surrogate or fib_set_predictor), and the
+ * number of those steps: the rejected share is total / (steps n_total).
+ * Blocking. */
+int fib_surrogate_fallbacks(fib_t* ctx, int64_t* total, int64_t* steps);
+
+/* Kernel timing for measurement.  With timing on, fib_run and
+ * fib_step_surrogate record a HIP event on the context's stream before and
+ * after each kernel launch of these classes:
+ *   FUSED:      the persistent split-step kernel (one launch per fib_run);
+ *   REACTION:   reaction launches of the split schedule;
+ *   DIFFUSION:  diffusion launches of the split schedule;
+ *   SURROGATE:  the surrogate step kernel (network or closed-form predictor);
+ *   FALLBACK:   the plain Heun pair on the rejected nodes.
+ * (Adaptive runs are not timed.)  Completed pairs are read back without
+ * blocking once more than a few thousand are outstanding. */
+enum { FIB_KT_FUSED = 0, FIB_KT_REACTION = 1, FIB_KT_DIFFUSION = 2, FIB_KT_SURROGATE = 3,
+       FIB_KT_FALLBACK = 4, FIB_KT_COUNT = 5 };
+
+/* Turns kernel timing on (enable != 0) or off and clears the sums.
+ * Blocking. */
+int fib_set_kernel_timing(fib_t* ctx, int32_t enable);
+
+/* Summed device time (ms, host) and number of timed launches of kernel
+ * class `cls` since timing was last turned on.  Blocking. */
+int fib_kernel_time(fib_t* ctx, int32_t cls, double* ms, int64_t* launches);
+
+/* Predictors of the surrogate step.  NETWORK is the trained network
+ * (fib_set_surrogate); ZERO and EULER are closed-form guesses that go
+ * through the same corrector, acceptance test and fallback:
+ *   ZERO:  du = 0, so the first iterate is dt G(y, I) and a node is
+ *          accepted only if its whole increment is within the tolerance;
+ *   EULER: du = dt G(y, I) (one more right-hand side), so the first iterate
+ *          is the explicit-midpoint (second-order Runge-Kutta) increment
+ *          and the test bounds its difference to the Euler increment.
+ * They are the method without the network: the baseline that shows what the
+ * network gains. */
+enum { FIB_PRED_NETWORK = 0, FIB_PRED_ZERO = 1, FIB_PRED_EULER = 2 };
+
+/* Attaches the surrogate step of fib_set_surrogate with a closed-form
+ * predictor (FIB_PRED_ZERO or FIB_PRED_EULER) in place of a network:
+ * acceptance |du1 - du|_k <= tol * res_scale[k] for every state (host
+ * array of n_states values), the same corrector iterations, the same
+ * refusals of stimulus changes and prescriptions, and the same fallback.
+ * Replaces an attached network; fib_clear_surrogate detaches it.  Models
+ * Hodgkin-Huxley and ST57, Strang splitting.  Blocking. */
+int fib_set_predictor(fib_t* ctx, int32_t predictor, const float* res_scale, double tol);
+
 /* ------------------------------------------------------------------------
  * EMG: the static bidomain step on the 3D mesh (eq. discretized_fibers_2 and
  * eq. discretized_fibers_3, the first bidomain equation eq. bidomain1 with
@@ -455,6 +503,29 @@ int fib_emg_get_phi(fib_emg_t* emg, double* phi, int64_t n);
 /* The right-hand side -K_{sigma_i} P V_m of the last solve, before its
  * zero-mean projection, into a host array of nx ny nz values. */
 int fib_emg_get_rhs(fib_emg_t* emg, double* rhs, int64_t n);
+
+/* ------------------------------------------------------------------------
+ * Measured ceilings of the current device, the empirical side of the
+ * roofline (the thesis measures its CPU's peak performance with a
+ * microbenchmark rather than taking the data sheet's, section "Roofline
+ * Model").  One probe kernel per call, filling every compute unit, timed
+ * with HIP events on the null stream after a warm-up launch:
+ *   FMA:  FP32 fused multiply-adds in the two-operand (VOP2) encoding
+ *         (lane operations per second);
+ *   FMA_VOP3: the same in the three-operand (VOP3) encoding, which issues
+ *         at half the VOP2 rate on gfx950;
+ *   EXP:  v_exp_f32 (lane operations per second);
+ *   RCP:  v_rcp_f32 (lane operations per second);
+ *   LOG:  v_exp_f32 and v_log_f32 alternating in one chain, both counted
+ *         (with the EXP rate the two separate);
+ *   COPY: device-to-device copy of `bytes` (1 MiB .. 64 GiB), bytes read
+ *         plus bytes written per second;
+ *   MFMA_BF16: FLOP/s of v_mfma_f32_16x16x32_bf16.
+ * `bytes` is ignored except for COPY.  Allocates and frees its own device
+ * buffers; synchronizes the device.  rate (host) receives the result. */
+enum { FIB_PROBE_FMA = 0, FIB_PROBE_EXP = 1, FIB_PROBE_RCP = 2, FIB_PROBE_LOG = 3,
+       FIB_PROBE_COPY = 4, FIB_PROBE_MFMA_BF16 = 5, FIB_PROBE_FMA_VOP3 = 6 };
+int fib_probe(int32_t kind, int64_t bytes, double* rate);
 
 #ifdef __cplusplus
 }

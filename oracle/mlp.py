@@ -12,7 +12,12 @@ with Adam (Kingma & Ba 2015):
     theta -= lr * (m / (1 - b1^t)) / (sqrt(v / (1 - b2^t)) + eps).
 
 This module is the oracle for the GPU network kernels: plain NumPy in
-float64, backpropagation written out layer by layer.  Only the test suite
+float64, backpropagation written out layer by layer.  With bf16=True every
+operand of a matrix product (inputs, activations, weights, output errors) is
+first rounded to bfloat16, as the matrix cores take them, while the
+products and sums stay in float64: the ReLU derivative, a 0/1 decision on
+the sign of a pre-activation, is then taken from the same operands as on
+the device.  Only the test suite
 and the benchmark's baseline leg may import it; it imports nothing from the
 GPU library.
 
@@ -30,6 +35,18 @@ def silu(z):
 def silu_grad(z):
     s = 1.0 / (1.0 + np.exp(-z))
     return s * (1.0 + z * (1.0 - s))
+
+
+def round_bf16(a):
+    """Nearest bfloat16 value (ties to even) of float32(a), as float64: the
+    float32 bit pattern rounded to its upper 16 bits (finite values)."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _mm(a, b, bf16):
+    return round_bf16(a) @ round_bf16(b) if bf16 else a @ b
 
 
 def relu(z):
@@ -57,13 +74,13 @@ def init_params(sizes, seed: int):
     return params
 
 
-def forward(params, X, act: str = "silu"):
+def forward(params, X, act: str = "silu", bf16: bool = False):
     """X: (B, in) -> (outputs (B, out), cache of pre-activations)."""
     f = ACTS[act][0]
     a = np.asarray(X, dtype=np.float64)
     zs, acts = [], [a]
     for i, (W, b) in enumerate(params):
-        z = a @ W.T + b
+        z = _mm(a, W.T, bf16) + b
         zs.append(z)
         a = f(z) if i < len(params) - 1 else z
         acts.append(a)
@@ -76,20 +93,20 @@ def loss(params, X, T, act: str = "silu"):
     return 0.5 * np.sum((O - T) ** 2) / (B * n)
 
 
-def backward(params, X, T, act: str = "silu"):
+def backward(params, X, T, act: str = "silu", bf16: bool = False):
     """Gradients of `loss` with respect to every W and b."""
     fg = ACTS[act][1]
-    O, (zs, acts) = forward(params, X, act)
+    O, (zs, acts) = forward(params, X, act, bf16)
     B, n = O.shape
     dz = (O - T) / (B * n)
     grads = [None] * len(params)
     for i in range(len(params) - 1, -1, -1):
         W, _ = params[i]
-        gW = dz.T @ acts[i]
+        gW = _mm(dz.T, acts[i], bf16)
         gb = dz.sum(axis=0)
         grads[i] = (gW, gb)
         if i > 0:
-            da = dz @ W
+            da = _mm(dz, W, bf16)
             dz = da * fg(zs[i - 1])
     return grads
 

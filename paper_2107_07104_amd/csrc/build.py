@@ -17,7 +17,7 @@ PKG = os.path.dirname(HERE)
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libfib.so")
 SOURCES = ["fib_api.hip", "fib_kernels.hip", "mlp_api.hip", "mlp_kernels.hip",
-           "surrogate_kernels.hip", "emg.hip"]
+           "surrogate_kernels.hip", "emg.hip", "probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

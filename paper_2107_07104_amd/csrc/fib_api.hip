@@ -14,6 +14,7 @@
 #include <queue>
 #include <string>
 #include <utility>
+#include <deque>
 #include <vector>
 
 #include "../../include/fib.h"
@@ -281,6 +282,9 @@ struct fib_ctx {
   int sur_slot = 0;             // counter of the next surrogate step
   int sur_last_slot = -1;       // counter of the last one (-1: none yet)
   int sur_grid = 0;
+  int sur_pred = FIB_PRED_NETWORK;            // predictor of the attached step
+  unsigned long long* d_sur_total = nullptr;  // rejections since the step was attached
+  int64_t sur_steps = 0;                      // surrogate steps since then
 
   // adaptive computation (split schedule)
   double adapt_tol = 0.0;              // > 0: on
@@ -300,6 +304,19 @@ struct fib_ctx {
   uint64_t plan_version = 0, stim_version = 0;
   uint64_t adapt_tables_plan = ~0ull, adapt_tables_stim = ~0ull;
   bool adapt_fused_ok = false;
+
+  // kernel timing (fib_set_kernel_timing): HIP event pairs around launches,
+  // harvested in order once they have completed
+  struct KtRec {
+    int cls;
+    hipEvent_t a, b;
+    bool own_a, own_b;  // the events go back to the pool with this record
+  };
+  bool kt_on = false;
+  std::deque<KtRec> kt_pending;
+  std::vector<hipEvent_t> kt_pool;
+  double kt_ms[FIB_KT_COUNT] = {};
+  int64_t kt_n[FIB_KT_COUNT] = {};
 };
 
 namespace fib {
@@ -789,6 +806,124 @@ int check_levels_fit(const fib_ctx* c, int levels) {
 // C ABI
 // ---------------------------------------------------------------------------
 
+// Kernel timing.  kt_mark() records an event on the context's stream (null
+// when timing is off or no event is available); kt_close() files the pair
+// (a, b) under a kernel class.  Pairs are read back in order as they
+// complete, without blocking, once more than kKtPending are outstanding,
+// and all of them by fib_kernel_time.
+constexpr size_t kKtPending = 4096;
+
+hipEvent_t kt_mark(fib_ctx* c) {
+  if (!c->kt_on) return nullptr;
+  hipEvent_t e = nullptr;
+  if (!c->kt_pool.empty()) {
+    e = c->kt_pool.back();
+    c->kt_pool.pop_back();
+  } else if (hipEventCreate(&e) != hipSuccess) {
+    return nullptr;
+  }
+  if (hipEventRecord(e, c->stream) != hipSuccess) {
+    c->kt_pool.push_back(e);
+    return nullptr;
+  }
+  return e;
+}
+
+void kt_harvest(fib_ctx* c, bool wait) {
+  while (!c->kt_pending.empty()) {
+    const fib_ctx::KtRec r = c->kt_pending.front();
+    if (wait) (void)hipEventSynchronize(r.b);
+    float ms = 0.0f;
+    const hipError_t e = hipEventElapsedTime(&ms, r.a, r.b);
+    if (e == hipErrorNotReady) break;
+    if (e == hipSuccess) {
+      c->kt_ms[r.cls] += ms;
+      c->kt_n[r.cls] += 1;
+    }
+    if (r.own_a) c->kt_pool.push_back(r.a);
+    if (r.own_b) c->kt_pool.push_back(r.b);
+    c->kt_pending.pop_front();
+  }
+}
+
+void kt_close(fib_ctx* c, int cls, hipEvent_t a, hipEvent_t b, bool own_a = true,
+              bool own_b = true) {
+  if (!a || !b) {
+    if (a && own_a) c->kt_pool.push_back(a);
+    if (b && own_b) c->kt_pool.push_back(b);
+    return;
+  }
+  c->kt_pending.push_back({cls, a, b, own_a, own_b});
+  if (c->kt_pending.size() > kKtPending) kt_harvest(c, false);
+}
+
+// A launch between two timing events filed under `cls`.
+#define KT_LAUNCH(c, cls, expr)                 \
+  do {                                          \
+    hipEvent_t kt_a_ = kt_mark(c);              \
+    HIP_TRY(expr);                              \
+    kt_close((c), (cls), kt_a_, kt_mark(c));    \
+  } while (0)
+
+// One surrogate pair (network or closed-form predictor) finishing step n
+// and starting step n + 1, with the fallback kernel.
+int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n) {
+  // the launchers record `mid` between their two kernels (they launch
+  // nothing for an empty context)
+  const bool timed = c->kt_on && c->n_total > 0;
+  hipEvent_t e0 = timed ? kt_mark(c) : nullptr;
+  hipEvent_t mid = nullptr;
+  if (timed && !c->kt_pool.empty()) {
+    mid = c->kt_pool.back();
+    c->kt_pool.pop_back();
+  } else if (timed && hipEventCreate(&mid) != hipSuccess) {
+    mid = nullptr;
+  }
+  if (c->sur_pred == FIB_PRED_NETWORK)
+    HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
+                                       c->d_sur_tab, c->sur_sc, (int32_t)n, c->d_sur_list,
+                                       c->d_sur_count, c->sur_slot, c->d_sur_total, c->sur_grid,
+                                       mid, c->stream));
+  else
+    HIP_TRY(fib::launch_predictor_step(c->p.model, c->sur_pred, a, c->d_sur_tab, (int32_t)n,
+                                       c->d_sur_list, c->d_sur_count, c->sur_slot,
+                                       c->d_sur_total, c->sur_grid, mid, c->stream));
+  hipEvent_t e1 = timed ? kt_mark(c) : nullptr;
+  if (mid && e0 && e1) {
+    // the first pair leaves `mid` to the second, which is read back later
+    kt_close(c, FIB_KT_SURROGATE, e0, mid, true, false);
+    kt_close(c, FIB_KT_FALLBACK, mid, e1, true, true);
+  } else {
+    kt_close(c, FIB_KT_SURROGATE, e0, nullptr);
+    kt_close(c, FIB_KT_SURROGATE, e1, nullptr);
+    if (mid) c->kt_pool.push_back(mid);
+  }
+  c->sur_last_slot = c->sur_slot;
+  c->sur_slot ^= 1;
+  c->sur_steps += 1;
+  return FIB_OK;
+}
+
+// Device buffers of the surrogate step that do not depend on the predictor:
+// the rejection list, the two alternating counters (both zero) and the
+// running rejection total (zero).
+int surrogate_buffers(fib_ctx* c) {
+  if (!c->d_sur_tab && hipMalloc(&c->d_sur_tab, sizeof(float) * fib::kSurTabFloats) != hipSuccess)
+    return fail(FIB_ENOMEM, "device allocation failed");
+  if (!c->d_sur_list) {
+    if (hipMalloc(&c->d_sur_list, sizeof(int) * (size_t)std::max<int64_t>(c->n_total, 1)) != hipSuccess ||
+        hipMalloc(&c->d_sur_count, 2 * sizeof(int)) != hipSuccess ||
+        hipMalloc(&c->d_sur_total, sizeof(unsigned long long)) != hipSuccess)
+      return fail(FIB_ENOMEM, "device allocation failed");
+  }
+  HIP_TRY(hipMemset(c->d_sur_count, 0, 2 * sizeof(int)));
+  HIP_TRY(hipMemset(c->d_sur_total, 0, sizeof(unsigned long long)));
+  c->sur_slot = 0;
+  c->sur_last_slot = -1;
+  c->sur_steps = 0;
+  return FIB_OK;
+}
+
 extern "C" {
 
 const char* fib_last_error(void) { return g_err.c_str(); }
@@ -943,6 +1078,7 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_sur_tab);
   (void)hipFree(c->d_sur_list);
   (void)hipFree(c->d_sur_count);
+  (void)hipFree(c->d_sur_total);
   (void)hipFree(c->d_node_fiber);
   (void)hipFree(c->d_first_on);
   (void)hipFree(c->d_pt);
@@ -952,6 +1088,11 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_adapt_lcount);
   (void)hipFree(c->d_slot_fiber);
   (void)hipFree(c->d_bin_first_on);
+  for (const auto& r : c->kt_pending) {
+    if (r.own_a) (void)hipEventDestroy(r.a);
+    if (r.own_b) (void)hipEventDestroy(r.b);
+  }
+  for (hipEvent_t e : c->kt_pool) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -1179,8 +1320,9 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   if (fused) {
     if (!hh_like)
       return fail(FIB_EUNSUPPORTED, "the fused schedule holds Hodgkin-Huxley states only");
-    HIP_TRY(fib::launch_run_fused(c->p.model, c->K, c->groups, c->threads,
-                                  fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
+    KT_LAUNCH(c, FIB_KT_FUSED,
+              fib::launch_run_fused(c->p.model, c->K, c->groups, c->threads,
+                                    fib::lds_bytes_for(c->threads, c->levels), a, c->stream));
     return FIB_OK;
   }
   HIP_TRY(hipMemcpyAsync(c->d_vprev, c->d_state, sizeof(float) * c->n_total,
@@ -1193,30 +1335,30 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
     // diffusion launch; the observables of the last step follow the loop
     for (int64_t n = step0; n < end; ++n) {
       const int flags = (n > step0 ? 2 : 0) | 4;
-      HIP_TRY(fib::launch_react(c->p.model, (int32_t)(n - 1), (int32_t)n, flags, a, c->stream));
-      HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+      KT_LAUNCH(c, FIB_KT_REACTION,
+                fib::launch_react(c->p.model, (int32_t)(n - 1), (int32_t)n, flags, a, c->stream));
+      KT_LAUNCH(c, FIB_KT_DIFFUSION,
+                fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
     }
-    HIP_TRY(fib::launch_react(c->p.model, (int32_t)(end - 1), 0, 2, a, c->stream));
+    KT_LAUNCH(c, FIB_KT_REACTION,
+              fib::launch_react(c->p.model, (int32_t)(end - 1), 0, 2, a, c->stream));
     return FIB_OK;
   }
   // SPLIT, Strang: per split step one diffusion launch and one reaction
   // launch that finishes step n (second half, observables) and starts step
   // n+1 (prescriptions, first half)
-  HIP_TRY(fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
+  KT_LAUNCH(c, FIB_KT_REACTION, fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
   for (int64_t n = step0; n < end; ++n) {
-    HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
+    KT_LAUNCH(c, FIB_KT_DIFFUSION,
+              fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
     const bool last = n + 1 >= end;
     const bool sample = a.samples && a.sample_every > 0 && (n + 1) % a.sample_every == 0;
     if (c->sur_on && !last && !sample) {
-      HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags,
-                                         c->d_sur_bias, c->d_sur_tab, c->sur_sc, (int32_t)n,
-                                         c->d_sur_list, c->d_sur_count, c->sur_slot, c->sur_grid,
-                                         c->stream));
-      c->sur_last_slot = c->sur_slot;
-      c->sur_slot ^= 1;
+      if (int rc = surrogate_step(c, a, n)) return rc;
     } else {
       const int flags = 1 | 2 | (last ? 0 : 4);
-      HIP_TRY(fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
+      KT_LAUNCH(c, FIB_KT_REACTION,
+                fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
     }
   }
   return FIB_OK;
@@ -1414,25 +1556,47 @@ int fib_set_surrogate(fib_t* c, const fib_mlp_t* net, const float* in_shift, con
   if (hipMalloc(&c->d_sur_frags, (size_t)sn.frag_elems * 2) != hipSuccess ||
       hipMalloc(&c->d_sur_bias, (size_t)sn.bias_elems * 4) != hipSuccess)
     return fail(FIB_ENOMEM, "device allocation failed");
-  if (!c->d_sur_tab && hipMalloc(&c->d_sur_tab, sizeof(float) * tab.size()) != hipSuccess)
-    return fail(FIB_ENOMEM, "device allocation failed");
-  HIP_TRY(hipMemcpy(c->d_sur_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
-  if (!c->d_sur_list) {
-    if (hipMalloc(&c->d_sur_list, sizeof(int) * (size_t)std::max<int64_t>(c->n_total, 1)) != hipSuccess ||
-        hipMalloc(&c->d_sur_count, 2 * sizeof(int)) != hipSuccess)
-      return fail(FIB_ENOMEM, "device allocation failed");
-  }
   // both rejection counters start at zero; each surrogate step clears the
   // one the next step uses
-  HIP_TRY(hipMemset(c->d_sur_count, 0, 2 * sizeof(int)));
-  c->sur_slot = 0;
-  c->sur_last_slot = -1;
+  if (int rc = surrogate_buffers(c)) return rc;
+  HIP_TRY(hipMemcpy(c->d_sur_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
   HIP_TRY(fib::launch_pack(sn, fib::mlp_device_params(net), c->d_sur_frags, c->d_sur_bias, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const int per_cu = (int)std::max<size_t>(1, std::min<size_t>(4, c->max_lds / lds));
   c->sur_grid = c->cu_count * per_cu;
   c->sur_net = sn;
   c->sur_sc = sc;
+  c->sur_pred = FIB_PRED_NETWORK;
+  c->sur_on = true;
+  return FIB_OK;
+}
+
+int fib_set_predictor(fib_t* c, int32_t predictor, const float* res_scale, double tol) {
+  if (int rc = check_ctx(c)) return rc;
+  if (predictor != FIB_PRED_ZERO && predictor != FIB_PRED_EULER)
+    return fail(FIB_EINVAL, "unknown predictor %d", predictor);
+  if (!res_scale) return fail(FIB_EINVAL, "null argument");
+  if (!(tol > 0.0)) return fail(FIB_EINVAL, "bad tolerance");
+  if (c->p.splitting != FIB_SPLIT_STRANG)
+    return fail(FIB_EUNSUPPORTED, "the surrogate step replaces Strang reaction halves");
+  if (c->adapt_tol > 0.0)
+    return fail(FIB_EUNSUPPORTED, "adaptive computation and the surrogate step do not combine");
+  if (c->p.model != FIB_MODEL_HH && c->p.model != FIB_MODEL_ST57)
+    return fail(FIB_EUNSUPPORTED, "the surrogate step holds Hodgkin-Huxley and ST57");
+  const KArgs a0 = base_args(c);
+  std::vector<float> tab((size_t)fib::kSurTabFloats, 0.0f);
+  for (int k = 0; k < c->S; ++k) {
+    if (!(res_scale[k] > 0.0f) || !std::isfinite(res_scale[k]))
+      return fail(FIB_EINVAL, "state %d: res_scale must be finite and > 0", k);
+    tab[fib::kTabChk + 4 * k + 2] = (float)(tol * (double)res_scale[k]);
+    tab[fib::kTabChk + 4 * k + 3] = a0.rest[k];
+  }
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  c->sur_on = false;
+  if (int rc = surrogate_buffers(c)) return rc;
+  HIP_TRY(hipMemcpy(c->d_sur_tab, tab.data(), sizeof(float) * tab.size(), hipMemcpyHostToDevice));
+  c->sur_grid = c->cu_count * 8;
+  c->sur_pred = predictor;
   c->sur_on = true;
   return FIB_OK;
 }
@@ -1446,17 +1610,14 @@ int fib_step_surrogate(fib_t* c, int64_t step) {
   const int64_t ns = ceil_steps(0.5 * c->p.dt_split, c->p.dt_0D);
   a.n_sub = (int32_t)ns;
   a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
-  HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
-                                     c->d_sur_tab, c->sur_sc, (int32_t)step, c->d_sur_list,
-                                     c->d_sur_count, c->sur_slot, c->sur_grid, c->stream));
-  c->sur_last_slot = c->sur_slot;
-  c->sur_slot ^= 1;
-  return FIB_OK;
+  return surrogate_step(c, a, step);
 }
 
 int fib_surrogate_predict(fib_t* c, int64_t step, float* du) {
   if (int rc = check_ctx(c)) return rc;
   if (!c->sur_on) return fail(FIB_ESTATE, "no surrogate attached");
+  if (c->sur_pred != FIB_PRED_NETWORK)
+    return fail(FIB_ESTATE, "the attached step has a closed-form predictor, not a network");
   if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
   if (!du && c->n_total > 0) return fail(FIB_EINVAL, "du is null");
   if (step < 0 || step + 1 >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
@@ -1482,6 +1643,43 @@ int fib_surrogate_last_fallbacks(fib_t* c, int64_t* n) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(&v, c->d_sur_count + c->sur_last_slot, sizeof(int), hipMemcpyDeviceToHost));
   *n = v;
+  return FIB_OK;
+}
+
+int fib_set_kernel_timing(fib_t* c, int32_t enable) {
+  if (int rc = check_ctx(c)) return rc;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  kt_harvest(c, true);
+  for (int k = 0; k < FIB_KT_COUNT; ++k) {
+    c->kt_ms[k] = 0.0;
+    c->kt_n[k] = 0;
+  }
+  c->kt_on = enable != 0;
+  return FIB_OK;
+}
+
+int fib_kernel_time(fib_t* c, int32_t cls, double* ms, int64_t* launches) {
+  if (int rc = check_ctx(c)) return rc;
+  if (cls < 0 || cls >= FIB_KT_COUNT) return fail(FIB_EINVAL, "unknown kernel class %d", cls);
+  if (!ms || !launches) return fail(FIB_EINVAL, "null output");
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  kt_harvest(c, true);
+  *ms = c->kt_ms[cls];
+  *launches = c->kt_n[cls];
+  return FIB_OK;
+}
+
+int fib_surrogate_fallbacks(fib_t* c, int64_t* total, int64_t* steps) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!total || !steps) return fail(FIB_EINVAL, "null output");
+  *total = 0;
+  *steps = 0;
+  if (!c->d_sur_total) return FIB_OK;
+  unsigned long long v = 0;
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  HIP_TRY(hipMemcpy(&v, c->d_sur_total, sizeof v, hipMemcpyDeviceToHost));
+  *total = (int64_t)v;
+  *steps = c->sur_steps;
   return FIB_OK;
 }
 

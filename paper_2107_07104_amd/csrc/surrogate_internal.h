@@ -60,10 +60,20 @@ size_t surrogate_lds_bytes(int model, const SurrogateNet& net);
 // One surrogate step: appends rejected nodes to list through counts[slot]
 // and clears counts[slot ^ 1] for the next step (the caller alternates the
 // slot between launches; both counters start at zero).
+// The fallback kernel adds each step's rejection count to *total (nullable);
+// `mid` (nullable) is recorded between the step kernel and the fallback.
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
                                  const __bf16* frags, const float* biases, const float* tab,
                                  const SurrogateScales& sc, int32_t step_a, int* list, int* counts,
-                                 int slot, int grid, hipStream_t s);
+                                 int slot, unsigned long long* total, int grid, hipEvent_t mid,
+                                 hipStream_t s);
+// The same step with a closed-form predictor (FIB_PRED_ZERO or
+// FIB_PRED_EULER) instead of the network; tab as for the network step (only
+// its kTabChk thresholds and resting state are read).
+hipError_t launch_predictor_step(int model, int pred, const KArgs& a, const float* tab,
+                                 int32_t step_a, int* list, int* counts, int slot,
+                                 unsigned long long* total, int grid, hipEvent_t mid,
+                                 hipStream_t s);
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
                                     const __bf16* frags, const float* biases, const float* tab,
                                     const SurrogateScales& sc, int32_t step_a, float* pred,

@@ -38,6 +38,8 @@
 // elements) spread 16-byte row accesses of consecutive lanes over all
 // banks; the outputs overwrite the inputs, which are all in registers by
 // then.  Biases initialise the accumulators.
+#include <mutex>
+
 #include "../../include/fib.h"
 #include "fib_internal.h"
 #include "hh_model.h"
@@ -456,15 +458,130 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
   }
 }
 
+// The same step with a closed-form predictor instead of the network, as the
+// baseline the network is measured against: du = 0 (PRED_ZERO), or the
+// explicit Euler increment du = dt G(y, I) (PRED_EULER, one more right-hand
+// side), then the corrector iterations, the acceptance test and the
+// compaction of the rejected nodes exactly as in k_surrogate.  With the
+// zero guess the first iterate is dt G(y) and the test accepts a node only
+// if its whole increment is within the tolerance; with the Euler guess the
+// first iterate is the explicit midpoint (second-order Runge-Kutta)
+// increment and the test bounds its difference to Euler.  The stimulus
+// enters G, so stimulated nodes need no flag input.
+//
+// Streamed like the plain reaction kernel: a grid resident at once, each
+// wave takes 64 consecutive nodes per round and issues the loads of its
+// next round (states, stimulus entry, v_prev, t_act) before it solves the
+// current one.  Every lane of a wave runs the same rounds (lanes past the
+// end read the last node and drop their results), so the ballot below sees
+// whole waves.  Launch: 256 threads.
+template <class M, int PRED, int NCORR>
+__global__ __launch_bounds__(256, 2) void k_midpoint(KArgs A, const float* __restrict__ tab_g,
+                                                  int32_t step_a, int* __restrict__ list,
+                                                  int* __restrict__ counts, int slot) {
+  constexpr int S = M::S;
+  __shared__ float2 tchk[S];  // (tol res_k, rest_k)
+  for (int k = threadIdx.x; k < S; k += 256) {
+    const float4 t = reinterpret_cast<const float4*>(tab_g + kTabChk)[k];
+    tchk[k] = make_float2(t.z, t.w);
+  }
+  __syncthreads();
+  int* count = counts + slot;
+  if (blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
+  const int64_t nt = A.n_total;
+  const int32_t step_b = step_a + 1;
+  const float span = 2.0f * A.tau * (float)A.n_sub;
+  const float uth = A.v_th - A.rest[0];
+  const int lane = threadIdx.x & 63;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i - lane >= nt) return;  // whole wave past the end
+  // the next round's inputs
+  float nx[S];
+  int64_t ic = i < nt ? i : nt - 1;
+  uint32_t nsid = (uint32_t)A.node_stim[ic];
+  float nv0 = A.v_prev[ic], nta = A.t_act[ic];
+#pragma unroll
+  for (int k = 0; k < S; ++k) nx[k] = A.state[k * nt + ic];
+  for (; i - lane < nt; i += stride) {
+    const bool real = i < nt;
+    float u[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) u[k] = nx[k];
+    const uint32_t sid = nsid;
+    float v0 = nv0, ta = nta;
+    float Ia = stim_current(sid, A.stim, step_a), Ib, vp;
+    int pres_b = stim_eval(sid, A.stim, step_b, Ib, vp);
+    // in registers before the next round's loads are issued, so no later
+    // wait for one of them waits for those too
+    asm volatile("" : "+v"(Ia), "+v"(Ib), "+v"(pres_b), "+v"(v0), "+v"(ta));
+    const int64_t j = i + stride;
+    if (j - lane < nt) {
+      const int64_t jc = j < nt ? j : nt - 1;
+      nsid = (uint32_t)A.node_stim[jc];
+      nv0 = A.v_prev[jc];
+      nta = A.t_act[jc];
+#pragma unroll
+      for (int k = 0; k < S; ++k) nx[k] = A.state[k * nt + jc];
+    }
+    float y[S], G[S], du[S];
+    if constexpr (PRED == FIB_PRED_EULER) {
+#pragma unroll
+      for (int k = 0; k < S; ++k) y[k] = u[k] + tchk[k].y;
+      M::rhs_abs(y, Ia, A.inv_cm, G);
+#pragma unroll
+      for (int k = 0; k < S; ++k) du[k] = span * G[k];
+    } else {
+#pragma unroll
+      for (int k = 0; k < S; ++k) du[k] = 0.0f;
+    }
+#pragma unroll
+    for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f, du[k], u[k]) + tchk[k].y;
+    M::rhs_abs(y, Ia, A.inv_cm, G);
+    bool within = true;
+#pragma unroll
+    for (int k = 0; k < S; ++k) within &= fabsf(fmaf(span, G[k], -du[k])) <= tchk[k].x;
+    const bool ok = real && within && Ia == Ib && !pres_b;
+    if (ok) {
+#pragma unroll
+      for (int c = 1; c < NCORR; ++c) {
+#pragma unroll
+        for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tchk[k].y;
+        M::rhs_abs(y, Ia, A.inv_cm, G);
+      }
+      // observables at the end of step_a from the midpoint
+      const float v1 = fmaf(0.5f * span, G[0], u[0]);
+      if (isinf(ta) && v0 < uth && v1 >= uth)
+        A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step_a * A.dt);
+      A.v_prev[i] = v1;
+      if (!isfinite(v1)) atomicOr(A.flag, 1);
+#pragma unroll
+      for (int k = 0; k < S; ++k) A.state[k * nt + i] = fmaf(span, G[k], u[k]);
+    }
+    const bool reject = real && !ok;
+    const uint64_t mask = __ballot(reject);
+    if (mask) {
+      const int first = __ffsll((unsigned long long)mask) - 1;
+      int b = 0;
+      if (lane == first) b = atomicAdd(count, __popcll(mask));
+      b = __shfl(b, first);
+      if (reject) list[b + __popcll(mask & ((1ull << lane) - 1ull))] = (int)i;
+    }
+  }
+}
+
 // Plain reaction pair (second half of step_a, observables, then the start of
 // step_a + 1: its V_m prescription and first half) for the nodes in
-// list[0..count).  Grid-stride loop, so the
-// grid does not depend on the count.
+// list[0..count).  Grid-stride loop, so the grid does not depend on the
+// count.  The count is added to *total (nullable), the running number of
+// rejections.
 template <class M>
 __global__ __launch_bounds__(256) void k_fallback(KArgs A, const int* __restrict__ list,
-                                                  const int* __restrict__ count, int32_t step_a) {
+                                                  const int* __restrict__ count, int32_t step_a,
+                                                  unsigned long long* __restrict__ total) {
   constexpr int S = M::S;
   const int n = *count;
+  if (total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(total, (unsigned long long)n);
   const int64_t nt = A.n_total;
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int64_t i = list[e];
@@ -534,7 +651,7 @@ template <class M, int ACT>
 static hipError_t sur_launch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
                              const float* biases, const float* tab, const SurrogateScales& sc,
                              int32_t step_a, int* list, int* counts, int slot, float* pred,
-                             int grid, hipStream_t s) {
+                             unsigned long long* total, hipEvent_t mid, int grid, hipStream_t s) {
   using C = SurCfg<M>;
   const size_t lds = sur_lds<M>(net);
   const int64_t tiles = (a.n_total + 63) / 64;
@@ -546,8 +663,9 @@ static hipError_t sur_launch(const KArgs& a, const SurrogateNet& net, const __bf
                      step_a, list, counts, slot, pred);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pred) return e;
+  if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, counts + slot,
-                     step_a);
+                     step_a, total);
   return hipGetLastError();
 }
 
@@ -555,12 +673,66 @@ template <class M>
 static hipError_t sur_dispatch(const KArgs& a, const SurrogateNet& net, const __bf16* frags,
                                const float* biases, const float* tab, const SurrogateScales& sc,
                                int32_t step_a, int* list, int* counts, int slot, float* pred,
-                               int grid, hipStream_t s) {
+                               unsigned long long* total, hipEvent_t mid, int grid,
+                               hipStream_t s) {
   if (net.act == FIB_ACT_RELU)
     return sur_launch<M, FIB_ACT_RELU>(a, net, frags, biases, tab, sc, step_a, list, counts, slot,
-                                       pred, grid, s);
+                                       pred, total, mid, grid, s);
   return sur_launch<M, FIB_ACT_SILU>(a, net, frags, biases, tab, sc, step_a, list, counts, slot,
-                                     pred, grid, s);
+                                     pred, total, mid, grid, s);
+}
+
+// Workgroups of k_midpoint<M, PRED, NCORR> resident at once on the current
+// device (queried once per device and kernel; 0 if the query fails).
+template <class M, int PRED>
+static unsigned midpoint_resident_blocks() {
+  static std::mutex mu;
+  static unsigned cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (cache[dev] == 0) {
+    int cus = 0, per_cu = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, k_midpoint<M, PRED, SurCfg<M>::NCORR>, 256, 0) != hipSuccess ||
+        cus <= 0 || per_cu <= 0)
+      return 0;
+    cache[dev] = (unsigned)cus * (unsigned)per_cu;
+  }
+  return cache[dev];
+}
+
+template <class M, int PRED>
+static hipError_t pred_launch(const KArgs& a, const float* tab, int32_t step_a, int* list,
+                              int* counts, int slot, unsigned long long* total, hipEvent_t mid,
+                              int grid, hipStream_t s) {
+  const int64_t need = (a.n_total + 255) / 256;
+  const unsigned resident = midpoint_resident_blocks<M, PRED>();
+  const int64_t cap = resident > 0 ? (int64_t)resident : need;
+  const unsigned blocks = (unsigned)(need < cap ? need : cap);
+  hipLaunchKernelGGL((k_midpoint<M, PRED, SurCfg<M>::NCORR>), dim3(blocks), dim3(256), 0, s, a,
+                     tab, step_a, list, counts, slot);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, counts + slot,
+                     step_a, total);
+  return hipGetLastError();
+}
+
+hipError_t launch_predictor_step(int model, int pred, const KArgs& a, const float* tab,
+                                 int32_t step_a, int* list, int* counts, int slot,
+                                 unsigned long long* total, int grid, hipEvent_t mid,
+                                 hipStream_t s) {
+  if (a.n_total == 0) return hipSuccess;
+  if (model == 0)
+    return pred == FIB_PRED_EULER
+               ? pred_launch<SurHH, FIB_PRED_EULER>(a, tab, step_a, list, counts, slot, total, mid, grid, s)
+               : pred_launch<SurHH, FIB_PRED_ZERO>(a, tab, step_a, list, counts, slot, total, mid, grid, s);
+  return pred == FIB_PRED_EULER
+             ? pred_launch<SurST57, FIB_PRED_EULER>(a, tab, step_a, list, counts, slot, total, mid, grid, s)
+             : pred_launch<SurST57, FIB_PRED_ZERO>(a, tab, step_a, list, counts, slot, total, mid, grid, s);
 }
 
 size_t surrogate_lds_bytes(int model, const SurrogateNet& net) {
@@ -570,13 +742,14 @@ size_t surrogate_lds_bytes(int model, const SurrogateNet& net) {
 hipError_t launch_surrogate_step(int model, const KArgs& a, const SurrogateNet& net,
                                  const __bf16* frags, const float* biases, const float* tab,
                                  const SurrogateScales& sc, int32_t step_a, int* list, int* counts,
-                                 int slot, int grid, hipStream_t s) {
+                                 int slot, unsigned long long* total, int grid, hipEvent_t mid,
+                                 hipStream_t s) {
   if (a.n_total == 0) return hipSuccess;
   if (model == 0)
     return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, list, counts, slot, nullptr,
-                               grid, s);
+                               total, mid, grid, s);
   return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, list, counts, slot, nullptr,
-                               grid, s);
+                               total, mid, grid, s);
 }
 
 hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNet& net,
@@ -586,9 +759,9 @@ hipError_t launch_surrogate_predict(int model, const KArgs& a, const SurrogateNe
   if (a.n_total == 0) return hipSuccess;
   if (model == 0)
     return sur_dispatch<SurHH>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, 0, pred,
-                               grid, s);
+                               nullptr, nullptr, grid, s);
   return sur_dispatch<SurST57>(a, net, frags, biases, tab, sc, step_a, nullptr, nullptr, 0, pred,
-                               grid, s);
+                               nullptr, nullptr, grid, s);
 }
 
 }  // namespace fib

@@ -41,6 +41,21 @@ FIB_1D_CRANK_NICOLSON = 0
 FIB_1D_IMPLICIT_EULER = 1
 FIB_STIM_CURRENT = 0
 FIB_STIM_VOLTAGE = 1
+FIB_PRED_NETWORK = 0
+FIB_PRED_ZERO = 1
+FIB_PRED_EULER = 2
+FIB_KT_FUSED = 0
+FIB_KT_REACTION = 1
+FIB_KT_DIFFUSION = 2
+FIB_KT_SURROGATE = 3
+FIB_KT_FALLBACK = 4
+FIB_PROBE_FMA = 0
+FIB_PROBE_EXP = 1
+FIB_PROBE_RCP = 2
+FIB_PROBE_LOG = 3
+FIB_PROBE_COPY = 4
+FIB_PROBE_MFMA_BF16 = 5
+FIB_PROBE_FMA_VOP3 = 6
 
 # Every function the header declares, for the export check.
 EXPORTS = (
@@ -51,7 +66,8 @@ EXPORTS = (
     "fib_plan_preview", "fib_mlp_create", "fib_mlp_destroy", "fib_mlp_n_params",
     "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
     "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
-    "fib_surrogate_last_fallbacks", "fib_step_surrogate",
+    "fib_surrogate_last_fallbacks", "fib_step_surrogate", "fib_surrogate_fallbacks",
+    "fib_set_predictor", "fib_set_kernel_timing", "fib_kernel_time", "fib_probe",
     "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
     "fib_adaptive_points", "fib_emg_create", "fib_emg_destroy", "fib_emg_dims",
     "fib_emg_solve", "fib_emg_get_phi", "fib_emg_get_rhs",
@@ -140,6 +156,13 @@ def lib():
             "fib_step_surrogate": ([_vp, C.c_int64], C.c_int),
             "fib_surrogate_predict": ([_vp, C.c_int64, _vp], C.c_int),
             "fib_surrogate_last_fallbacks": ([_vp, C.POINTER(C.c_int64)], C.c_int),
+            "fib_surrogate_fallbacks": ([_vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64)],
+                                        C.c_int),
+            "fib_set_predictor": ([_vp, C.c_int32, _fp, C.c_double], C.c_int),
+            "fib_set_kernel_timing": ([_vp, C.c_int32], C.c_int),
+            "fib_kernel_time": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
+                                C.c_int),
+            "fib_probe": ([C.c_int32, C.c_int64, C.POINTER(C.c_double)], C.c_int),
             "fib_set_adaptive": ([_vp, C.c_double], C.c_int),
             "fib_adaptive_solved": ([_vp, C.POINTER(C.c_int64)], C.c_int),
             "fib_adaptive_points": ([_vp, _vp, C.c_int64], C.c_int),
@@ -460,6 +483,36 @@ def fib_surrogate_last_fallbacks(ctx) -> int:
     return n.value
 
 
+def fib_surrogate_fallbacks(ctx):
+    """(rejected node-steps, surrogate steps) since the step was attached."""
+    t, n = C.c_int64(), C.c_int64()
+    _check(lib().fib_surrogate_fallbacks(_vp(ctx), C.byref(t), C.byref(n)))
+    return t.value, n.value
+
+
+def fib_set_kernel_timing(ctx, enable: bool) -> None:
+    _check(lib().fib_set_kernel_timing(_vp(ctx), 1 if enable else 0))
+
+
+def fib_kernel_time(ctx, cls: int):
+    """(summed device ms, launches) of a kernel class since timing was turned on."""
+    ms, n = C.c_double(), C.c_int64()
+    _check(lib().fib_kernel_time(_vp(ctx), int(cls), C.byref(ms), C.byref(n)))
+    return ms.value, n.value
+
+
+def fib_probe(kind: int, nbytes: int = 0) -> float:
+    """Measured ceiling of the current device (see fib.h)."""
+    r = C.c_double()
+    _check(lib().fib_probe(int(kind), int(nbytes), C.byref(r)))
+    return r.value
+
+
+def fib_set_predictor(ctx, predictor: int, res_scale, tol: float) -> None:
+    r = np.ascontiguousarray(res_scale, dtype=np.float32)
+    _check(lib().fib_set_predictor(_vp(ctx), int(predictor), r.ctypes.data_as(_fp), float(tol)))
+
+
 class Mlp:
     """Owns one surrogate network; data arrays are torch CUDA tensors."""
 
@@ -634,6 +687,22 @@ class Solver:
 
     def last_fallbacks(self):
         return fib_surrogate_last_fallbacks(self.ctx)
+
+    def fallbacks(self):
+        """(rejected node-steps, surrogate steps) since the step was attached."""
+        return fib_surrogate_fallbacks(self.ctx)
+
+    def set_kernel_timing(self, enable=True):
+        fib_set_kernel_timing(self.ctx, enable)
+
+    def kernel_time(self, cls):
+        """(summed device ms, launches) of a kernel class (FIB_KT_*)."""
+        return fib_kernel_time(self.ctx, cls)
+
+    def set_predictor(self, predictor, res_scale, tol: float):
+        """The surrogate step with a closed-form predictor (FIB_PRED_ZERO or
+        FIB_PRED_EULER) in place of a network."""
+        fib_set_predictor(self.ctx, predictor, res_scale, tol)
 
     def set_adaptive(self, tol):
         """Adaptive computation with relative tolerance tol (0: off)."""

@@ -3,8 +3,13 @@
 BF16 operands carry 8 significant bits (relative rounding 2^-9), so a dot
 product of K terms is accurate to about 2^-9 relative to the sum of the
 absolute terms; the tests bound errors by 3e-2 relative to the typical
-output magnitude (forward) and to the gradient's norm (backward).  The FP64
-reference itself is pinned by central differences on the CPU.
+output magnitude (forward) and, element by element, to the largest
+gradient entry of the same weight matrix or bias vector (backward; for
+ReLU against the reference with bfloat16 operands, whose 0/1 derivative
+decisions are those of the device).  Adam
+runs on the FP32 masters: over ten steps fed with the GPU's own gradients
+it matches the FP64 update of oracle/mlp.py to FP32 rounding.  The FP64
+reference itself is pinned on the CPU (central differences, closed forms).
 """
 import numpy as np
 import pytest
@@ -64,11 +69,28 @@ def test_gradient_matches_reference(sizes, act):
     g, loss = net.gradient(torch.as_tensor(X, dtype=torch.float32, device="cuda"),
                            torch.as_tensor(T, dtype=torch.float32, device="cuda"))
     g = g.cpu().numpy()
-    ref = M.flatten(M.backward(params, X, T, act))
+    ref_layers = M.backward(params, X, T, act)
+    ref = M.flatten(ref_layers)
     err = np.linalg.norm(g - ref) / np.linalg.norm(ref)
     ref_loss = M.loss(params, X, T, act)
     say("   rel err", err, "loss", float(loss.item()), ref_loss)
     assert err < 3e-2
+    # element by element, per layer: every weight and bias gradient against
+    # the largest entry of its own array.  ReLU's derivative is a 0/1
+    # decision on the sign of each pre-activation, so that reference takes
+    # it from bfloat16-rounded operands as the matrix cores do (a
+    # pre-activation within BF16 rounding of zero would otherwise switch a
+    # sample's whole contribution through that unit)
+    if act == "relu":
+        ref_layers = M.backward(params, X, T, act, bf16=True)
+    gl = M.unflatten(g.astype(np.float64), sizes)
+    for li, ((gW, gb), (rW, rb)) in enumerate(zip(gl, ref_layers)):
+        for name, a, r in (("W", gW, rW), ("b", gb, rb)):
+            scale = np.max(np.abs(r))
+            worst = np.max(np.abs(a - r)) / scale
+            say(f"   layer {li + 1} {name}{list(r.shape)}: max |g - g_ref| / max |g_ref| = "
+                f"{worst:.2e}")
+            assert worst < 3e-2, (li, name)
     assert abs(float(loss.item()) - ref_loss) < 3e-2 * ref_loss
     # deterministic: the same call gives the same bits
     g2, _ = net.gradient(torch.as_tensor(X, dtype=torch.float32, device="cuda"),
@@ -106,4 +128,37 @@ def test_adam_step_and_training_reduce_the_loss():
             losses.append(float(loss.item()))
     say("   losses", losses)
     assert losses[-1] < 0.2 * losses[0]
+    net.close()
+
+
+@pytest.mark.parametrize("sizes,act", [([5, 64, 64, 64, 4], "silu"), ([57, 128, 128, 57], "relu")])
+def test_adam_matches_the_reference_over_ten_steps(sizes, act):
+    """Ten GPU Adam steps, each on the gradient the GPU computes at the
+    current parameters (deterministic: the same bits the step uses), against
+    the FP64 Adam of oracle/mlp.py fed with those gradients."""
+    say(f"[mlp adam x10] {sizes} {act}")
+    net, params = _net(sizes, 12, act)
+    rng = np.random.default_rng(13)
+    B = 1500
+    Xt = torch.as_tensor(rng.standard_normal((B, sizes[0])), dtype=torch.float32, device="cuda")
+    Tt = torch.as_tensor(rng.standard_normal((B, sizes[-1])), dtype=torch.float32, device="cuda")
+    state = {}
+    lr = 3e-3
+    for t in range(1, 11):
+        # the reference steps from the GPU's FP32 parameters of this step, so
+        # parameter rounding does not accumulate; its moments are its own
+        p_prev = M.unflatten(net.get_params().astype(np.float64), sizes)
+        g, _ = net.gradient(Xt, Tt)
+        g = M.unflatten(g.cpu().numpy().astype(np.float64), sizes)
+        net.adam_step(Xt, Tt, lr)
+        flat_ref = M.flatten(M.adam_step(p_prev, g, state, lr=lr))
+        p_gpu = net.get_params().astype(np.float64)
+        # FP32 parameters, moments and update: two ulp of each parameter plus
+        # a small fraction of the step size
+        tol = 3e-7 * np.abs(flat_ref) + 1e-5 * lr
+        bad = np.abs(p_gpu - flat_ref) > tol
+        say(f"   step {t}: max |p - p_ref| {np.max(np.abs(p_gpu - flat_ref)):.2e}, "
+            f"beyond tolerance {int(bad.sum())}")
+        assert not bad.any()
+        assert state["t"] == t
     net.close()

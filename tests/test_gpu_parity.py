@@ -133,6 +133,10 @@ def _assert_parity(w, res, end_time):
     say("  ", res)
     assert res["vm_err"] <= 0.5
     assert res["tact_err"] <= 1.0 * w.dt_split
+    # the stated budget is one split step; the FP32 path agrees far more
+    # closely, so one percent of a step guards against regressions
+    # such as a crossing attributed to the neighbouring step
+    assert res["tact_err"] <= 0.01 * w.dt_split
     assert res["tact_mismatch"] == 0
 
 

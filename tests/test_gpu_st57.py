@@ -75,6 +75,10 @@ def test_st57_run_matches_oracle_and_keeps_invariants():
     say("  ", res)
     assert res["vm_err"] <= 0.5
     assert res["tact_err"] <= w.dt_split
+    # the stated budget is one split step; the FP32 path agrees far more
+    # closely, so one percent of a step guards against regressions
+    # such as a crossing attributed to the neighbouring step
+    assert res["tact_err"] <= 0.01 * w.dt_split
     assert res["tact_mismatch"] == 0 and res["activated"] > 300
     inv0 = np.array([O.st57_invariants(c) for c in oracle_init(w).T])
     inv1 = np.array([O.st57_invariants(c) for c in gpu[0].T])

@@ -217,3 +217,55 @@ def test_rejection_counts_of_consecutive_steps():
         assert s.last_fallbacks() == 0
     s.close()
     net.close()
+
+
+@pytest.mark.parametrize("model", [I.MODEL_HH, I.MODEL_ST57])
+@pytest.mark.parametrize("pred", [F.FIB_PRED_ZERO, F.FIB_PRED_EULER])
+def test_closed_form_predictor_step(model, pred):
+    """The step with a closed-form predictor and every node accepted is the
+    fixed-point iteration of the implicit midpoint rule started from du = 0
+    or from the explicit Euler increment du = dt G(y), with the oracle's
+    right-hand sides; with every node rejected it is the plain split run
+    bit for bit, and the running rejection count is the sum over steps."""
+    say(f"[predictor step] model {model} predictor {pred}")
+    w, s, y, steps = _active_state(model)
+    S = y.shape[0]
+    s.set_predictor(pred, np.ones(S, dtype=np.float32), 1e30)
+    step = steps
+    I_stim = O.stimulus_current(w.n_nodes, w.stims, step)
+    assert not I_stim.any() and not O.stimulus_current(w.n_nodes, w.stims, step + 1).any()
+    s.step_surrogate(step)
+    s.sync()
+    assert s.last_fallbacks() == 0 and s.fallbacks() == (0, 1)
+    y_dev = s.get_state()
+    dt = w.dt_split
+    du = dt * _rhs(model, y, I_stim, w.Cm) if pred == F.FIB_PRED_EULER else np.zeros_like(y)
+    for _ in range(ITERATIONS[model]):
+        du = dt * _rhs(model, y + 0.5 * du, I_stim, w.Cm)
+    # FP32 rounding of the states and of the right-hand sides
+    tol = (1e-5 * np.abs(y).max(axis=1, keepdims=True) + 2e-3 * np.abs(du).max(axis=1, keepdims=True)
+           + 1e-30)
+    err = np.abs(y_dev - (y + du))
+    say(f"   V err {err[0].max():.3e} (|du_V| up to {np.abs(du[0]).max():.3e}); worst ratio "
+        f"{(err / tol).max():.2f}")
+    assert np.all(err <= tol)
+    with pytest.raises(F.FibError):
+        s.surrogate_predict(step)      # no network attached
+    s.close()
+
+    n = min(steps, 200)
+    a = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    a.run(0, n)
+    a.sync()
+    ya, ta = a.get_state(), a.tact()
+    a.close()
+    b = gpu_solver(w, schedule=F.FIB_SCHED_SPLIT)
+    b.set_predictor(pred, np.ones(S, dtype=np.float32), 1e-30)
+    b.run(0, n)
+    b.sync()
+    np.testing.assert_array_equal(b.get_state(), ya)
+    np.testing.assert_array_equal(b.tact(), ta)
+    total, k = b.fallbacks()
+    # every step but the last of the call takes the surrogate path
+    assert k == n - 1 and total == k * w.n_total
+    b.close()

@@ -1,17 +1,28 @@
-"""What a surrogate trained on the GPU gains over the plain method.
+"""What a surrogate trained on the GPU gains over the method without it.
 
 Each test trains the model's network with the library's own kernels from
 plain runs of one seeded realization (fewer Adam steps than the benchmark,
-to keep the test short), then runs an independent realization with the
-plain split schedule and with the surrogate attached, and checks
+to keep the test short), then runs an independent realization at the
+configured acceptance tolerance 1e-3 four ways from the same state:
 
-* the surrogate run against the FP64 oracle on sampled fibers: V_m within
-  0.5 mV and activation times within one split step, with every node that
-  activates in one run activating in the other;
-* the share of node-steps that fell back to the plain Heun substeps;
-* node-steps/s of both runs on the same GPU: for ST57 the surrogate must be
-  faster; for Hodgkin-Huxley, whose right-hand side is cheaper than the
-  network's activations, the ratio is printed and not asserted.
+* plain: the plain split schedule;
+* network: the surrogate step with the trained network as predictor;
+* Euler: the same step with the explicit Euler increment as predictor;
+* zero: the same step with no prediction (du = 0), i.e. the acceptance
+  test and the corrector alone.
+
+Checked (speed is measured by the benchmark, not asserted here):
+
+* the network run against the FP64 oracle on sampled fibers that fire
+  inside the window: V_m within 0.5 mV and activation times within one
+  split step, every node that activates in one run activating in the other;
+* its states other than V_m stay close to the plain run's (a bound on the
+  drift of the slow states that the per-step acceptance test does not
+  control), and its rejected share stays small;
+* against the method without the network: the zero guess, which accepts
+  only nodes whose whole increment is within the tolerance, leaves more
+  rejections than the network; the rejected shares, speeds and errors of
+  all four runs are printed.
 """
 import time
 from dataclasses import replace
@@ -29,6 +40,8 @@ from gpu_helpers import say
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
+TOL = 1e-3
+
 
 @pytest.fixture(scope="module", autouse=True)
 def _need_gpu():
@@ -37,34 +50,32 @@ def _need_gpu():
     F.lib()
 
 
-def _run(w, init, sur=None, tol=1e-2):
+def _run(w, init, attach=None):
     s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
     s.set_stimulus(w.stims)
-    net = None
-    if sur is not None:
-        net = sur.network()
-        s.set_surrogate(net, sur.scales, tol)
     rows = w.n_steps // w.sample_every
     samples = torch.empty((rows, w.n_total), device="cuda")
     init(s)
+    if attach:
+        attach(s)
     s.run(0, 20)          # warm-up (kernel loading)
     s.sync()
     init(s)
-    fb = []
+    if attach:
+        attach(s)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     chunk = w.n_steps // 4
     for c in range(4):
         s.run(c * chunk, chunk, w.sample_every,
               samples[c * chunk // w.sample_every:(c + 1) * chunk // w.sample_every])
-        if net is not None:
-            fb.append(s.last_fallbacks())
     s.sync()
     secs = time.perf_counter() - t0
-    out = (w.node_steps() / secs, samples.cpu().numpy().astype(np.float64), s.tact(), fb)
+    tot, nst = s.fallbacks() if attach else (0, 0)
+    out = dict(rate=w.node_steps() / secs, samples=samples.cpu().numpy().astype(np.float64),
+               tact=s.tact(), state=s.get_state(),
+               rejected=tot / max(1, nst * w.n_total) if attach else None)
     s.close()
-    if net is not None:
-        net.close()
     return out
 
 
@@ -75,48 +86,78 @@ def _oracle(w, fibers, y0):
     return O.run(cfg, sub.n_nodes, y0, sub.stims, sub.n_steps, sample_every=sub.sample_every)
 
 
-def _parity(w, fibers, samples, tact, oracle):
+def _parity(w, fibers, r, oracle):
     _, so, to = oracle
     off = w.offsets
     cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
-    vm = float(np.max(np.abs(samples[:, cols] - so)))
-    tg = tact[cols].astype(np.float64)
+    vm = float(np.max(np.abs(r["samples"][:, cols] - so)))
+    tg = r["tact"][cols].astype(np.float64)
     both = np.isfinite(tg) & np.isfinite(to)
     dta = float(np.max(np.abs(tg[both] - to[both]))) if both.any() else 0.0
     return vm, dta, int(np.sum(np.isfinite(tg) != np.isfinite(to))), int(both.sum())
 
 
-def test_st57_surrogate_is_faster_within_the_tolerances():
+def _four_runs(w, sur, init):
+    net = sur.network()
+    runs = {
+        "plain": _run(w, init),
+        "network": _run(w, init, lambda s: s.set_surrogate(net, sur.scales, TOL)),
+        "Euler": _run(w, init, lambda s: s.set_predictor(F.FIB_PRED_EULER,
+                                                         sur.scales["res_scale"], TOL)),
+        "zero": _run(w, init, lambda s: s.set_predictor(F.FIB_PRED_ZERO,
+                                                        sur.scales["res_scale"], TOL)),
+    }
+    net.close()
+    return runs
+
+
+def _report(w, fibers, runs, ora):
+    out = {}
+    for k, r in runs.items():
+        vm, dta, mism, act = _parity(w, fibers, r, ora)
+        out[k] = (vm, dta, mism, act)
+        rej = "-" if r["rejected"] is None else f"{r['rejected']:.2e}"
+        say(f"   {k:8s} {r['rate']:.3e} node-steps/s, rejected share {rej}; vs oracle: "
+            f"V_m {vm:.3e} mV, t_act {dta:.2e} ms, mismatch {mism}, activated {act}")
+    return out
+
+
+def test_st57_surrogate_over_5_ms_against_the_method_without_it():
     say("[gain st57] training")
     wt = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=2.0)
     snaps = [int(round(t / wt.dt_split)) for t in (0.5, 1.0, 1.5, 2.0)]
     sur = SU.train_surrogate(I.MODEL_ST57, wt, snaps, steps=6000, log=say)
-    w = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=1.0, onset_max=0.5, realization=1)
+    w = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0, onset_max=1.0, realization=1)
     rel = w.rel_noise.astype(np.float32)
-    say("[gain st57] plain and surrogate runs")
-    plain = _run(w, lambda s: s.init_state(rel_noise=rel))
-    surr = _run(w, lambda s: s.init_state(rel_noise=rel), sur)
-    gain = surr[0] / plain[0]
-    fb_share = sum(surr[3]) / (len(surr[3]) * w.n_total)
-    say(f"   plain {plain[0]:.3e}, surrogate {surr[0]:.3e} node-steps/s: gain {gain:.2f}; "
-        f"fallbacks per step {surr[3]} of {w.n_total}")
+    say("[gain st57] plain, network, Euler and zero-guess runs over 5 ms")
+    runs = _four_runs(w, sur, lambda s: s.init_state(rel_noise=rel))
     onsets = np.array([st["step_on"] for st in w.stims])
-    fibers = sorted(int(f) for f in np.argsort(onsets, kind="stable")[:4])
+    fibers = sorted(int(f) for f in np.argsort(onsets, kind="stable")[:2])
     off = w.offsets
     cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
     y0 = O.rest_state(I.MODEL_ST57)[:, None] * (1.0 + rel[:, cols].astype(np.float64))
-    say(f"[gain st57] oracle on fibers {fibers}")
+    say(f"[gain st57] oracle on fibers {fibers} (onsets {onsets[fibers] * w.dt_split} ms)")
     ora = _oracle(w, fibers, y0)
-    vm, dta, mism, act = _parity(w, fibers, surr[1], surr[2], ora)
-    say(f"   surrogate vs oracle: V_m {vm:.3e} mV, t_act {dta:.2e} ms, mismatch {mism}, "
-        f"activated {act}")
-    assert act > 0
+    par = _report(w, fibers, runs, ora)
+    vm, dta, mism, act = par["network"]
+    assert act > 300  # the fronts cross hundreds of the sampled nodes
     assert vm <= 0.5 and dta <= w.dt_split and mism == 0
-    assert fb_share < 0.05
-    assert gain > 1.1
+    net = runs["network"]
+    assert net["rejected"] < 0.05
+    # states other than V_m against the plain run, relative to each state's
+    # range in the run (the per-step test bounds each step, not the drift)
+    yp, yn = runs["plain"]["state"], net["state"]
+    rng = np.maximum(yp.max(axis=1) - yp.min(axis=1), 1e-6 * np.abs(yp).max(axis=1) + 1e-12)
+    drift = np.max(np.abs(yn - yp), axis=1) / rng
+    k = int(np.argmax(drift[1:])) + 1
+    say(f"   non-V states vs plain: worst relative drift {drift[k]:.3e} (state {k}), "
+        f"median {np.median(drift[1:]):.1e}")
+    assert drift[1:].max() < 0.1
+    # without a prediction the acceptance test alone rejects more nodes
+    assert runs["zero"]["rejected"] > net["rejected"]
 
 
-def test_hh_surrogate_within_the_tolerances_and_its_gain():
+def test_hh_surrogate_against_the_method_without_it():
     say("[gain hh] training")
     wt = SU.hh_training_workload().subset(range(256))
     snaps = [int(round(t / wt.dt_split)) for t in (1.0, 3.0, 5.0, 7.0, 10.0)]
@@ -124,21 +165,17 @@ def test_hh_surrogate_within_the_tolerances_and_its_gain():
     w = replace(I.batched_hh(n_fibers=256, n_min=1481, n_max=1481, dt=5e-3, realization=1),
                 dt_0D=1e-3)
     vm_noise = w.vm_noise.astype(np.float32)
-    say("[gain hh] plain and surrogate runs")
-    plain = _run(w, lambda s: s.init_state(vm_noise=vm_noise))
-    surr = _run(w, lambda s: s.init_state(vm_noise=vm_noise), sur)
-    fb_share = sum(surr[3]) / (len(surr[3]) * w.n_total)
-    say(f"   plain split {plain[0]:.3e}, surrogate {surr[0]:.3e} node-steps/s: ratio "
-        f"{surr[0] / plain[0]:.2f} (not asserted); fallbacks per step {surr[3]}")
+    say("[gain hh] plain, network, Euler and zero-guess runs")
+    runs = _four_runs(w, sur, lambda s: s.init_state(vm_noise=vm_noise))
     fibers = [0, 1, 2, 3]
     off = w.offsets
     cols = np.concatenate([np.arange(off[f], off[f + 1]) for f in fibers])
     y0 = np.tile(O.rest_state(I.MODEL_HH)[:, None], (1, len(cols)))
     y0[0] += vm_noise[cols]
     ora = _oracle(w, fibers, y0)
-    vm, dta, mism, act = _parity(w, fibers, surr[1], surr[2], ora)
-    say(f"   surrogate vs oracle: V_m {vm:.3e} mV, t_act {dta:.2e} ms, mismatch {mism}, "
-        f"activated {act}")
+    par = _report(w, fibers, runs, ora)
+    vm, dta, mism, act = par["network"]
     assert act > 0
     assert vm <= 0.5 and dta <= w.dt_split and mism == 0
-    assert fb_share < 0.05
+    assert runs["network"]["rejected"] < 0.05
+    assert runs["zero"]["rejected"] > runs["network"]["rejected"]

@@ -13,6 +13,10 @@
   lr * sign(g) (a wrong step count or bias correction breaks this from t = 2
   on); hand-computed three-step examples with alternating signs and with a
   changing magnitude (these separate beta1 from beta2);
+* bfloat16 operand rounding: exact ties-to-even cases, agreement with
+  torch's float32 -> bfloat16 conversion, and a network whose weights and
+  inputs are bfloat16 values computes its first layer exactly as without
+  rounding;
 * ReLU: closed forms, a ReLU network whose pre-activations are all positive
   is the product of its affine maps, one whose hidden pre-activations are
   all negative outputs its last bias, and its backpropagation matches
@@ -175,3 +179,27 @@ def test_relu_backprop_matches_central_differences():
         num[i] = (M.loss(M.unflatten(tp, sizes), X, T, "relu") -
                   M.loss(M.unflatten(tm, sizes), X, T, "relu")) / (2 * h)
     np.testing.assert_allclose(g, num, rtol=1e-5, atol=1e-9)
+
+
+def test_bf16_rounding():
+    one = 1.0
+    # spacing of bfloat16 at 1 is 2^-7: halfway cases go to the even neighbour
+    assert M.round_bf16(one + 2.0 ** -8) == 1.0
+    assert M.round_bf16(one + 3 * 2.0 ** -8) == 1.0 + 2 * 2.0 ** -7
+    assert M.round_bf16(one + 2.0 ** -8 + 2.0 ** -20) == 1.0 + 2.0 ** -7
+    assert M.round_bf16(-(one + 3 * 2.0 ** -8)) == -(1.0 + 2 * 2.0 ** -7)
+    assert M.round_bf16(0.0) == 0.0
+    torch = pytest.importorskip("torch")
+    x = np.random.default_rng(3).standard_normal(10000) * 10.0 ** np.random.default_rng(4).integers(-6, 6, 10000)
+    ref = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(M.round_bf16(x), ref)
+
+
+def test_bf16_operands_change_nothing_for_bf16_values():
+    rng = np.random.default_rng(5)
+    sizes = [6, 8, 3]
+    params = [(M.round_bf16(W), b) for W, b in M.init_params(sizes, seed=6)]
+    X = M.round_bf16(rng.standard_normal((4, 6)))
+    _, (z_plain, _) = M.forward(params, X, "relu")
+    _, (z_bf, _) = M.forward(params, X, "relu", bf16=True)
+    np.testing.assert_array_equal(z_plain[0], z_bf[0])
