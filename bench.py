@@ -1029,7 +1029,49 @@ def exp_approx_bench(args):
     return out
 
 
+def trace_gaps(path, max_gap_us=500.0):
+    """Idle time between consecutive kernels in a rocprofv3 kernel trace
+    (csv): per kernel and grid size, launches, mean duration and the mean
+    idle gap before it; overall, kernel time and the idle gaps below
+    max_gap_us (gaps above it are host-side pauses between runs, not launch
+    overhead)."""
+    import csv
+    rows = []
+    with open(path, newline="") as f:
+        for r in csv.DictReader(f):
+            name = r["Kernel_Name"]
+            short = name.split("(")[0]
+            short = short.split("void ")[-1]
+            if r.get("Grid_Size_X"):
+                # the same kernel on workloads of different sizes apart
+                short += f" [grid {r['Grid_Size_X']}]"
+            rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short))
+    rows.sort()
+    per = {}
+    busy = idle = 0.0
+    for i, (t0, t1, k) in enumerate(rows):
+        d = per.setdefault(k, dict(launches=0, kernel_us=0.0, gap_us=0.0, gaps=0))
+        d["launches"] += 1
+        d["kernel_us"] += (t1 - t0) / 1e3
+        busy += (t1 - t0) / 1e3
+        if i:
+            g = (t0 - rows[i - 1][1]) / 1e3
+            if 0.0 < g <= max_gap_us:
+                d["gap_us"] += g
+                d["gaps"] += 1
+                idle += g
+    table = {k: dict(launches=v["launches"], mean_us=v["kernel_us"] / v["launches"],
+                     mean_gap_before_us=v["gap_us"] / max(1, v["gaps"]),
+                     gap_share_of_own_time=v["gap_us"] / max(v["kernel_us"], 1e-9))
+             for k, v in sorted(per.items(), key=lambda kv: -kv[1]["kernel_us"])}
+    return dict(kernels=table, kernel_us=busy, idle_gap_us=idle,
+                idle_share=idle / max(busy + idle, 1e-9), max_gap_us=max_gap_us)
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--trace-gaps":
+        print(json.dumps(trace_gaps(sys.argv[2]), indent=1))
+        return
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the fibers are "

@@ -74,3 +74,22 @@ def test_source_hash_covers_the_bytes(bench, tmp_path, monkeypatch):
     data[-1] ^= 1
     last.write_bytes(bytes(data))
     assert bench.kernel_source_hash(bench.KERNEL_SOURCES) != h0
+
+
+def test_trace_gap_analysis(bench, tmp_path):
+    """Idle gaps between consecutive kernels of a kernel trace: gaps up to
+    the threshold count as launch gaps, longer ones as host pauses."""
+    rows = [("k_a(int)", 0, 1000), ("k_b(float)", 1200, 3200), ("k_a(int)", 3300, 4300),
+            ("k_b(float)", 900000, 902000)]       # after a 895.7 us pause
+    p = tmp_path / "kernel_trace.csv"
+    with open(p, "w") as f:
+        f.write("Kernel_Name,Start_Timestamp,End_Timestamp\n")
+        for name, a, b in rows:
+            f.write(f'"{name}",{a},{b}\n')
+    r = bench.trace_gaps(str(p), max_gap_us=500.0)
+    assert r["kernel_us"] == pytest.approx(1.0 + 2.0 + 1.0 + 2.0)
+    assert r["idle_gap_us"] == pytest.approx(0.2 + 0.1)
+    assert r["idle_share"] == pytest.approx(0.3 / 6.3)
+    assert r["kernels"]["k_a"]["launches"] == 2
+    assert r["kernels"]["k_b"]["mean_gap_before_us"] == pytest.approx(0.2)
+    assert r["kernels"]["k_a"]["mean_gap_before_us"] == pytest.approx(0.1)
