@@ -94,13 +94,48 @@ double or_exp_star(double x) {
   return u;
 }
 
+/* The approximate logarithm of section "Evaluation of Code Generator
+ * Optimizations" (figure apxlog): the sixth-order Taylor polynomial of log
+ * around a = 1 for x < 2, around a = 3 for 2 <= x < 6 and around a = 9 for
+ * x >= 6,
+ *   log a + sum_{k=1..6} (-1)^(k+1) u^k / k,   u = (x - a) / a,
+ * stated for 0.2 <= x <= 20. */
+double or_log_star_taylor(double x) {
+  const double a = x < 2.0 ? 1.0 : (x < 6.0 ? 3.0 : 9.0);
+  const double u = (x - a) / a;
+  double s = 0.0, p = 1.0;
+  for (int k = 1; k <= 6; ++k) {
+    p *= u;
+    s += (k % 2 ? p : -p) / (double)k;
+  }
+  return log(a) + s;
+}
+
+/* log*(x): the Taylor value y followed by one Newton step on exp*(y) = x
+ * with the derivative taken as exp*(y), i.e. y - (1 - x / exp*(y)), which
+ * makes log* the inverse of exp* (eq. apx-e-function) up to the step's
+ * quadratic remainder.  Reading: arguments outside [0.2, 20], where the
+ * polynomials are not meant to be used, are first brought into it by an
+ * exact power-of-two scaling, log x = log(x 2^-k) + k log 2.  NaN for
+ * x <= 0. */
+double or_log_star(double x) {
+  if (!(x > 0.0) || isinf(x)) return NAN;
+  int k = 0;
+  double m = x;
+  while (m >= 20.0) { m *= 0.5; ++k; }
+  while (m < 0.2) { m *= 2.0; --k; }
+  double y = or_log_star_taylor(m);
+  y -= 1.0 - m / or_exp_star(y);
+  return y + (double)k * log(2.0);
+}
+
 /* x / (exp(x) - 1), the shape of alpha_m and alpha_n; removable singularity
  * at x = 0 where the value is 1.  Near 0 the Taylor series 1 - x/2 + x^2/12
  * is used (its truncation error x^4/720 is below 1e-18 for |x| < 1e-4).
  * With apx, exp is exp*: (1 + x/n)^n - 1 = x + a' x^2 + b' x^3 + ... with
  * a' = (n-1)/(2n), b' = (n-1)(n-2)/(6 n^2), so the quotient is
  * 1 - a' x + (a'^2 - b') x^2 + O(x^3) near 0. */
-static double x_over_expm1(int apx, double x) {
+double or_x_over_expm1(int apx, double x) {
   if (!apx) {
     if (fabs(x) < 1e-4) return 1.0 - 0.5 * x + x * x / 12.0;
     return x / expm1(x);
@@ -120,11 +155,11 @@ static double hh_exp(int apx, double x) { return apx ? or_exp_star(x) : exp(x); 
  * with apx every exp is the exp* of eq. apx-e-function. */
 static void hh_rates(int apx, double V, double ab[6]) {
   double v = V - HH_ER;
-  ab[0] = x_over_expm1(apx, (25.0 - v) / 10.0);
+  ab[0] = or_x_over_expm1(apx, (25.0 - v) / 10.0);
   ab[1] = 4.0 * hh_exp(apx, -v / 18.0);
   ab[2] = 0.07 * hh_exp(apx, -v / 20.0);
   ab[3] = 1.0 / (hh_exp(apx, (30.0 - v) / 10.0) + 1.0);
-  ab[4] = 0.1 * x_over_expm1(apx, (10.0 - v) / 10.0);
+  ab[4] = 0.1 * or_x_over_expm1(apx, (10.0 - v) / 10.0);
   ab[5] = 0.125 * hh_exp(apx, -v / 80.0);
 }
 
@@ -202,21 +237,26 @@ int or_hh_apx_rest(double y[4]) { return hh_rest(1, y); }
 /* Model dispatch                                                            */
 /* ------------------------------------------------------------------------ */
 
-/* ST57, the 57-state Shorten-type stand-in (st57_oracle.c) */
+/* ST57, the 57-state Shorten-type stand-in (st57_oracle.c), exact and with
+ * exp* / log* */
 int or_st57_n_states(void);
 void or_st57_rhs(double Cm, const double* y, double I, double* dydt);
+void or_st57_apx_rhs(double Cm, const double* y, double I, double* dydt);
 
 /* Models: 0 Hodgkin-Huxley, 1 ST57, 2 Hodgkin-Huxley with exp* in its
- * rates (eq. apx-e-function). */
+ * rates (eq. apx-e-function), 3 ST57 with every exp replaced by exp* and
+ * every log by log*. */
 int or_n_states(int model) {
   if (model == 0 || model == 2) return 4;
-  if (model == 1) return or_st57_n_states();
+  if (model == 1 || model == 3) return or_st57_n_states();
   return -1;
 }
 
 static void model_rhs(int model, double Cm, const double* y, double I, double* dydt) {
   if (model == 1)
     or_st57_rhs(Cm, y, I, dydt);
+  else if (model == 3)
+    or_st57_apx_rhs(Cm, y, I, dydt);
   else
     hh_rhs(model == 2, Cm, y, I, dydt);
 }

@@ -25,6 +25,7 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 MODEL_HH = 0
 MODEL_ST57 = 1
 MODEL_HH_APX_EXP = 2   # Hodgkin-Huxley with exp* (eq. apx-e-function) in its rates
+MODEL_ST57_APX = 3     # ST57 with exp* and log* (figure apxlog)
 SCHEME_STRANG = 0
 SCHEME_GODUNOV = 1
 
@@ -74,6 +75,12 @@ def lib():
         L.or_hh_apx_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
         L.or_exp_star.argtypes = [C.c_double]
         L.or_exp_star.restype = C.c_double
+        L.or_log_star.argtypes = [C.c_double]
+        L.or_log_star.restype = C.c_double
+        L.or_log_star_taylor.argtypes = [C.c_double]
+        L.or_log_star_taylor.restype = C.c_double
+        L.or_st57_apx_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
+        L.or_st57_apx_rest.argtypes = [_dp, C.POINTER(C.c_int)]
         L.or_n_states.argtypes = [C.c_int]
         L.or_st57_rhs.argtypes = [C.c_double, _dp, C.c_double, _dp]
         L.or_st57_invariants.argtypes = [_dp, _dp]
@@ -154,6 +161,9 @@ def rest_state(model: int = MODEL_HH) -> np.ndarray:
     elif model == MODEL_ST57:
         it = C.c_int(0)
         rc = lib().or_st57_rest(_d(y), C.byref(it))
+    elif model == MODEL_ST57_APX:
+        it = C.c_int(0)
+        rc = lib().or_st57_apx_rest(_d(y), C.byref(it))
     else:
         raise ValueError("unknown model")
     if rc != 0:
@@ -164,6 +174,18 @@ def rest_state(model: int = MODEL_HH) -> np.ndarray:
 def exp_star(x: float) -> float:
     """exp*(x) = (1 + x/1024)^1024 (eq. apx-e-function)."""
     return lib().or_exp_star(float(x))
+
+
+def log_star(x: float) -> float:
+    """log*(x): piecewise sixth-order Taylor value refined by one Newton step
+    on exp* (figure apxlog), with an exact power-of-two range reduction
+    outside [0.2, 20]."""
+    return lib().or_log_star(float(x))
+
+
+def log_star_taylor(x: float) -> float:
+    """The piecewise sixth-order Taylor polynomial of log alone."""
+    return lib().or_log_star_taylor(float(x))
 
 
 def hh_apx_rates(V: float) -> np.ndarray:
@@ -183,6 +205,13 @@ def st57_rhs(y, I_stim: float = 0.0, Cm: float = 1.0) -> np.ndarray:
     y = _f64(y)
     out = np.zeros(57)
     lib().or_st57_rhs(float(Cm), _d(y), float(I_stim), _d(out))
+    return out
+
+
+def st57_apx_rhs(y, I_stim: float = 0.0, Cm: float = 1.0) -> np.ndarray:
+    y = _f64(y)
+    out = np.zeros(57)
+    lib().or_st57_apx_rhs(float(Cm), _d(y), float(I_stim), _d(out))
     return out
 
 

@@ -21,21 +21,26 @@
 #define ST_N 57
 #define KT 26.71
 
-/* HH rate constants at voltage V (same forms as the membrane model) */
-static double lin(double x) {
-  if (fabs(x) < 1e-4) return 1.0 - 0.5 * x + x * x / 12.0;
-  return x / expm1(x);
-}
+/* exp*, log* and x / (exp(x) - 1) of fib_oracle.c (the approximations of
+ * section "Evaluation of Code Generator Optimizations") */
+double or_exp_star(double x);
+double or_log_star(double x);
+double or_x_over_expm1(int apx, double x);
 
-static void hh_rates(double V, double* am, double* bm, double* ah, double* bh, double* an,
-                     double* bn) {
+/* The model's exponential and logarithm: exact, or exp* and log* (apx). */
+static double EXP(int apx, double x) { return apx ? or_exp_star(x) : exp(x); }
+static double LOG(int apx, double x) { return apx ? or_log_star(x) : log(x); }
+
+/* HH rate constants at voltage V (same forms as the membrane model) */
+static void hh_rates(int apx, double V, double* am, double* bm, double* ah, double* bh,
+                     double* an, double* bn) {
   double v = V + 75.0;
-  *am = lin((25.0 - v) / 10.0);
-  *bm = 4.0 * exp(-v / 18.0);
-  *ah = 0.07 * exp(-v / 20.0);
-  *bh = 1.0 / (exp((30.0 - v) / 10.0) + 1.0);
-  *an = 0.1 * lin((10.0 - v) / 10.0);
-  *bn = 0.125 * exp(-v / 80.0);
+  *am = or_x_over_expm1(apx, (25.0 - v) / 10.0);
+  *bm = 4.0 * EXP(apx, -v / 18.0);
+  *ah = 0.07 * EXP(apx, -v / 20.0);
+  *bh = 1.0 / (EXP(apx, (30.0 - v) / 10.0) + 1.0);
+  *an = 0.1 * or_x_over_expm1(apx, (10.0 - v) / 10.0);
+  *bn = 0.125 * EXP(apx, -v / 80.0);
 }
 
 int or_st57_n_states(void) { return ST_N; }
@@ -58,8 +63,9 @@ void or_st57_invariants(const double* y, double out[6]) {
   out[5] = y[26] + y[23] + y[25];
 }
 
-/* Right-hand side of ST57 with stimulus current I (uA/cm^2). */
-void or_st57_rhs(double Cm, const double* y, double I, double* d) {
+/* Right-hand side of ST57 with stimulus current I (uA/cm^2); with apx every
+ * exp is exp* and every log is log*. */
+static void st57_rhs(int apx, double Cm, const double* y, double I, double* d) {
   /* states */
   const double V = y[0], m = y[1], h = y[2], n = y[3];
   const double Vt = y[4], mt = y[5], ht = y[6], nt = y[7];
@@ -74,7 +80,7 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
 
   /* F: Na/K pump cycle */
   const double k1 = Nai * Nai * Nai / (1000.0 + Nai * Nai * Nai), b1 = 0.05;
-  const double k2 = 0.8 * exp(0.3 * V / KT), b2 = 0.05;
+  const double k2 = 0.8 * EXP(apx, 0.3 * V / KT), b2 = 0.05;
   const double k3 = 1.2 * Kt * Kt / (2.25 + Kt * Kt), b3 = 0.02;
   const double k4 = 0.6, b4 = 0.01;
   const double J01 = k1 * Q[0] - b1 * Q[1];
@@ -89,11 +95,11 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
 
   /* A: surface membrane */
   double am, bm, ah, bh, an, bn;
-  hh_rates(V, &am, &bm, &ah, &bh, &an, &bn);
+  hh_rates(apx, V, &am, &bm, &ah, &bh, &an, &bn);
   const double INas = 120.0 * m * m * m * h * (V - 40.0);
   const double IKs = 36.0 * n * n * n * n * (V + 87.0);
   const double ILs = 0.3 * (V + 64.387);
-  const double ECl = -KT * log(128.0 / Cli);
+  const double ECl = -KT * LOG(apx, 128.0 / Cli);
   const double IClS = 0.05 * (V - ECl);
   const double Ic = 0.2 * (V - Vt);
   const double Ips = 0.2 * Jp;
@@ -104,10 +110,10 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
 
   /* B: tubular membrane */
   double amt, bmt, aht, bht, ant, bnt;
-  hh_rates(Vt, &amt, &bmt, &aht, &bht, &ant, &bnt);
-  const double ENa = KT * log(Nat / Nai);
-  const double EK = KT * log(Kt / Ki);
-  const double EClt = -KT * log(Clt / Cli);
+  hh_rates(apx, Vt, &amt, &bmt, &aht, &bht, &ant, &bnt);
+  const double ENa = KT * LOG(apx, Nat / Nai);
+  const double EK = KT * LOG(apx, Kt / Ki);
+  const double EClt = -KT * LOG(apx, Clt / Cli);
   const double INat = 12.0 * mt * mt * mt * ht * (Vt - ENa);
   const double IKt = 3.6 * nt * nt * nt * nt * (Vt - EK);
   const double IClt = 0.05 * (Vt - EClt);
@@ -121,8 +127,8 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
   double kf[9], kb[9];
   for (int i = 0; i < 9; ++i) {
     const double Vi = -70.0 + 7.5 * i;
-    kf[i] = exp((Vt - Vi) / 25.0);
-    kb[i] = exp(-(Vt - Vi) / 25.0);
+    kf[i] = EXP(apx, (Vt - Vi) / 25.0);
+    kb[i] = EXP(apx, -(Vt - Vi) / 25.0);
   }
   for (int i = 0; i < 10; ++i) {
     double r = 0.0;
@@ -179,7 +185,7 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
 
   /* H: cross-bridge cycle */
   const double a = gA / 8000.0;
-  const double dtc = 0.8 * a / (0.1 + a) * exp(0.5 * (Ls - 1.1));
+  const double dtc = 0.8 * a / (0.1 + a) * EXP(apx, 0.5 * (Ls - 1.1));
   double flux[8]; /* flux[j]: net X_j -> X_{j+1 mod 8} */
   flux[0] = 1.5 * R[7] * X[0] - 0.1 * X[1];
   for (int j = 1; j <= 6; ++j) flux[j] = 1.0 * X[j] - 0.2 * X[j + 1];
@@ -192,13 +198,21 @@ void or_st57_rhs(double Cm, const double* y, double I, double* d) {
   d[56] = (Fn - gam) / 5.0;
 }
 
+void or_st57_rhs(double Cm, const double* y, double I, double* d) { st57_rhs(0, Cm, y, I, d); }
+
+/* ST57 with every exp replaced by exp* (eq. apx-e-function) and every log by
+ * log* (figure apxlog), as the thesis does for its Shorten model. */
+void or_st57_apx_rhs(double Cm, const double* y, double I, double* d) {
+  st57_rhs(1, Cm, y, I, d);
+}
+
 /* ---------------------------------------------------------------------- */
 /* Resting state: damped Newton on G(y) = 0 with the seven conserved sums  */
 /* fixed (one equation of each conserving block replaced by its sum).      */
 /* ---------------------------------------------------------------------- */
 
-static void rest_residual(const double* y, double* F) {
-  or_st57_rhs(1.0, y, 0.0, F);
+static void rest_residual(int apx, const double* y, double* F) {
+  st57_rhs(apx, 1.0, y, 0.0, F);
   double inv[6];
   or_st57_invariants(y, inv);
   F[17] = inv[0] - 1.0;     /* sum P */
@@ -259,11 +273,11 @@ static void rest_guess(double* y) {
 
 /* Returns 0 on convergence (max |residual| < 1e-11 after scaling), -1 else;
  * `iters` (nullable) receives the iteration count. */
-int or_st57_rest(double* y, int* iters) {
+static int st57_rest(int apx, double* y, int* iters) {
   double F[ST_N], Fp[ST_N], J[ST_N * ST_N], yp[ST_N], dx[ST_N];
   rest_guess(y);
   for (int it = 0; it < 200; ++it) {
-    rest_residual(y, F);
+    rest_residual(apx, y, F);
     double norm = 0.0;
     for (int i = 0; i < ST_N; ++i) norm = fmax(norm, fabs(F[i]));
     if (iters) *iters = it;
@@ -272,7 +286,7 @@ int or_st57_rest(double* y, int* iters) {
       memcpy(yp, y, sizeof yp);
       double e = 1e-7 * fmax(1.0, fabs(y[j]));
       yp[j] += e;
-      rest_residual(yp, Fp);
+      rest_residual(apx, yp, Fp);
       for (int i = 0; i < ST_N; ++i) J[i * ST_N + j] = (Fp[i] - F[i]) / e;
     }
     for (int i = 0; i < ST_N; ++i) dx[i] = -F[i];
@@ -287,7 +301,7 @@ int or_st57_rest(double* y, int* iters) {
         if (i >= 8 && i != 55 && i != 56 && yp[i] < 0.0) ok = 0;
       }
       if (ok) {
-        rest_residual(yp, Fp);
+        rest_residual(apx, yp, Fp);
         double np = 0.0;
         for (int i = 0; i < ST_N; ++i) np = fmax(np, fabs(Fp[i]));
         if (np < norm || np < 1e-11) break;
@@ -298,3 +312,6 @@ int or_st57_rest(double* y, int* iters) {
   }
   return -1;
 }
+
+int or_st57_rest(double* y, int* iters) { return st57_rest(0, y, iters); }
+int or_st57_apx_rest(double* y, int* iters) { return st57_rest(1, y, iters); }
