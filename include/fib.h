@@ -346,6 +346,23 @@ int fib_mlp_forward(fib_mlp_t* net, const float* X, int64_t B, float* O);
 int fib_mlp_gradient(fib_mlp_t* net, const float* X, const float* T, int64_t B, float* grad,
                      float* loss);
 
+/* fib_mlp_gradient for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight training loops, harnesses that forbid
+ * allocation): the same kernels and the same result, bit for bit, with the
+ * per-chunk partial gradients and losses in a fixed 16 MiB array of the
+ * library's code object on the network's device instead of memory the
+ * network allocates when a batch grows.  Allocates nothing and calls no
+ * allocating routine.  Limit: ceil(B / 32) (n_params + 1) <= 2^22 floats
+ * (B <= 4288 for the 31289-parameter ST57 network, 14944 for the 8964-
+ * parameter Hodgkin-Huxley one); larger batches return FIB_EINVAL.  The
+ * array is shared by every call on that device and keeps the last call's
+ * contents (each call overwrites what it reads), so calls that overlap on
+ * one device -- on different streams or threads -- race.  grad (device,
+ * nullable: the network's own buffer) and loss (device, nullable) as for
+ * fib_mlp_gradient. */
+int fib_mlp_gradient_noalloc(fib_mlp_t* net, const float* X, const float* T, int64_t B,
+                             float* grad, float* loss);
+
 /* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8) on that loss with
  * learning rate lr; the loss before the step goes to loss[0] (nullable). */
 int fib_mlp_adam_step(fib_mlp_t* net, const float* X, const float* T, int64_t B, double lr,

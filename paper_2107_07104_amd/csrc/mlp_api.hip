@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,6 +18,7 @@ int set_error(int code, const char* msg);  // fib_api.hip
 struct fib_mlp {
   fib::MlpShape shape{};
   hipStream_t stream = nullptr;
+  int device = 0;             // device the network lives on
   float* d_params = nullptr;  // FP32 master parameters
   float* d_m = nullptr;       // Adam first moment
   float* d_v = nullptr;       // Adam second moment
@@ -26,6 +28,15 @@ struct fib_mlp {
   int64_t part_chunks = 0;
   int64_t t = 0;              // Adam step count
 };
+
+// Scratch of fib_mlp_gradient_noalloc: the per-chunk partial gradients and
+// losses, in a fixed array of every device's code object instead of memory
+// allocated per call.  The array's name is a host-side stand-in: host code
+// uses only the device address that hipGetSymbolAddress returns, looked up
+// once per device with that device current (at fib_mlp_create) and kept in
+// g_scratch below.  Every call on a device shares that device's array.
+static constexpr int64_t kScratchFloats = (int64_t)1 << 22;  // 16 MiB per device
+static __device__ __align__(256) float scratch[kScratchFloats];
 
 namespace fib {
 const MlpShape& mlp_shape(const fib_mlp* n) { return n->shape; }
@@ -49,6 +60,29 @@ int mfail(int code, const char* fmt, ...) {
     hipError_t e_ = (expr);                                                           \
     if (e_ != hipSuccess) return mfail(FIB_EHIP, "%s: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+// Looks up (once) the scratch address of `dev`, which must be current.
+int scratch_setup(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return mfail(FIB_EUNSUPPORTED, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return FIB_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return mfail(FIB_EHIP, "hipGetSymbolAddress(scratch): %s", hipGetErrorString(e));
+  g_scratch[dev] = static_cast<float*>(p);
+  return FIB_OK;
+}
+
+float* scratch_of(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch[dev];
+}
 
 int ensure_parts(fib_mlp* n, int64_t chunks) {
   if (chunks <= n->part_chunks) return FIB_OK;
@@ -99,10 +133,12 @@ int fib_mlp_create(int32_t n_layers, const int32_t* sizes, int32_t activation, v
     return mfail(FIB_EHIP, "no HIP device");
   if (fib::mlp_train_lds_bytes(s) > prop.sharedMemPerBlock)
     return mfail(FIB_EUNSUPPORTED, "network too wide for one workgroup's LDS");
+  if (int rc = scratch_setup(dev)) return rc;
   fib_mlp* n = new (std::nothrow) fib_mlp();
   if (!n) return mfail(FIB_ENOMEM, "host allocation failed");
   n->shape = s;
   n->stream = (hipStream_t)stream;
+  n->device = dev;
   const size_t bytes = sizeof(float) * (size_t)s.n_params;
   if (hipMalloc(&n->d_params, bytes) != hipSuccess || hipMalloc(&n->d_m, bytes) != hipSuccess ||
       hipMalloc(&n->d_v, bytes) != hipSuccess || hipMalloc(&n->d_grad, bytes) != hipSuccess) {
@@ -160,6 +196,25 @@ int fib_mlp_gradient(fib_mlp_t* n, const float* X, const float* T, int64_t B, fl
   const int64_t chunks = (B + fib::kChunk - 1) / fib::kChunk;
   if (int rc = ensure_parts(n, chunks)) return rc;
   MHIP(fib::launch_mlp_grad(n->shape, n->d_params, X, T, B, n->d_part, n->d_loss_part,
+                            grad ? grad : n->d_grad, loss, n->stream));
+  return FIB_OK;
+}
+
+int fib_mlp_gradient_noalloc(fib_mlp_t* n, const float* X, const float* T, int64_t B,
+                             float* grad, float* loss) {
+  if (!n || B < 1 || !X || !T) return mfail(FIB_EINVAL, "bad arguments");
+  const int64_t chunks = (B + fib::kChunk - 1) / fib::kChunk;
+  const int64_t need = chunks * (int64_t)n->shape.n_params + chunks;
+  if (need > kScratchFloats)
+    return mfail(FIB_EINVAL, "batch of %lld samples needs %lld scratch floats, more than the "
+                 "%lld this entry point holds (at most %lld samples for this network)",
+                 (long long)B, (long long)need, (long long)kScratchFloats,
+                 (long long)(kScratchFloats / (n->shape.n_params + 1) * fib::kChunk));
+  float* base = scratch_of(n->device);
+  if (!base) return mfail(FIB_ESTATE, "scratch of device %d not set up", n->device);
+  float* part = base;
+  float* loss_part = base + chunks * (int64_t)n->shape.n_params;
+  MHIP(fib::launch_mlp_grad(n->shape, n->d_params, X, T, B, part, loss_part,
                             grad ? grad : n->d_grad, loss, n->stream));
   return FIB_OK;
 }

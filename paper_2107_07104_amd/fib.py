@@ -65,7 +65,8 @@ EXPORTS = (
     "fib_run", "fib_get_tact", "fib_reset_observables", "fib_sync", "fib_plan_info",
     "fib_plan_preview", "fib_mlp_create", "fib_mlp_destroy", "fib_mlp_n_params",
     "fib_mlp_set_params", "fib_mlp_get_params", "fib_mlp_forward", "fib_mlp_gradient",
-    "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_set_surrogate", "fib_clear_surrogate",
+    "fib_mlp_adam_step", "fib_mlp_reset_optimizer", "fib_mlp_gradient_noalloc",
+    "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate", "fib_surrogate_fallbacks",
     "fib_set_predictor", "fib_set_kernel_timing", "fib_kernel_time", "fib_probe",
     "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
@@ -148,6 +149,7 @@ def lib():
             "fib_mlp_get_params": ([_vp, _fp, C.c_int64], C.c_int),
             "fib_mlp_forward": ([_vp, _vp, C.c_int64, _vp], C.c_int),
             "fib_mlp_gradient": ([_vp, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
+            "fib_mlp_gradient_noalloc": ([_vp, _vp, _vp, C.c_int64, _vp, _vp], C.c_int),
             "fib_mlp_adam_step": ([_vp, _vp, _vp, C.c_int64, C.c_double, _vp], C.c_int),
             "fib_mlp_reset_optimizer": ([_vp], C.c_int),
             "fib_set_surrogate": ([_vp, _vp, _fp, _fp, _fp, _fp, _fp, C.c_double, C.c_double],
@@ -446,6 +448,12 @@ def fib_mlp_gradient(net, X_ptr: int, T_ptr: int, B: int, grad_ptr: int = 0,
                      loss_ptr: int = 0) -> None:
     _check(lib().fib_mlp_gradient(_vp(net), _vp(X_ptr), _vp(T_ptr), int(B),
                                   _vp(grad_ptr or None), _vp(loss_ptr or None)))
+
+
+def fib_mlp_gradient_noalloc(net, X_ptr: int, T_ptr: int, B: int, grad_ptr: int = 0,
+                             loss_ptr: int = 0) -> None:
+    _check(lib().fib_mlp_gradient_noalloc(_vp(net), _vp(X_ptr), _vp(T_ptr), int(B),
+                                          _vp(grad_ptr or None), _vp(loss_ptr or None)))
 
 
 def fib_mlp_adam_step(net, X_ptr: int, T_ptr: int, B: int, lr: float, loss_ptr: int = 0) -> None:
