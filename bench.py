@@ -709,7 +709,11 @@ def hh_batched(args):
 def st57_bundle(args, bg):
     """400 x 1481 ST57 nodes with the 1 % perturbation, 5 ms, plain split
     schedule: throughput, the reaction kernel's VALU roofline, and the FP64
-    oracle on two fibers (background)."""
+    oracle on two fibers (background); then the same bundle with the
+    thesis's exp* and log* in the model (its speed, its oracle parity, and
+    how far it lies from the exact model)."""
+    from dataclasses import replace
+
     import torch
 
     from oracle import oracle as O
@@ -717,49 +721,64 @@ def st57_bundle(args, bg):
     from paper_2107_07104_amd import inputs as I
     from paper_2107_07104_amd import surrogate as SU
 
-    w = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0)
+    w0 = I.st57_bundle(n_fibers=400, n_nodes=1481, t_end=5.0)
     fibers = [0, 1]
-    cols = _cols(w, fibers)
-    rel = w.rel_noise.astype(np.float32)
-    if not args.no_cpu_baseline:
-        sub = w.subset(fibers)
-        y0 = O.rest_state(I.MODEL_ST57)[:, None] * (1.0 + rel[:, cols].astype(np.float64))
-        bg.submit("st57_bundle", dict(
-            threads=2, cfg=dict(model=I.MODEL_ST57, Cm=w.Cm, Am=w.Am, sigma=w.sigma, h=w.h,
-                                dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split, v_th=w.v_th),
-            n_nodes=sub.n_nodes, y0=y0, stims=sub.stims, n_steps=w.n_steps,
-            sample_every=w.sample_every))
-    s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
-    s.set_stimulus(w.stims)
+    cols = _cols(w0, fibers)
+    ci = torch.as_tensor(cols, device="cuda")
+    rel = w0.rel_noise.astype(np.float32)
     relt = torch.as_tensor(rel, device="cuda")
-    rows = w.n_steps // w.sample_every
-    smp = torch.empty((rows, w.n_total), device="cuda")
-    secs, _ = _run_timed(s, w, smp, 1, 1, lambda: s.init_state(rel_noise=relt), lambda: None,
-                         "st57 bundle", step_split=w.n_steps)
-    kt = _ktimes(s)
-    kr = kt["reaction"]
-    slots = ST57_REACT_OPS * w.n_total * w.n_steps / (kr["ms_total"] * 1e-3)
-    value = w.node_steps() / secs
-    out = dict(workload="st57_400x1481_5ms, 1 % perturbation", fibers=400,
-               nodes=int(w.n_total), split_steps=int(w.n_steps), dt_split_ms=w.dt_split,
-               value=value, seconds=secs, kernels=kt,
-               roofline={"bound": "alu", "achieved": slots / 1e12,
-                         "peak": VALU_PEAK_OPS / 1e12, "unit": "T FP32 lane-ops/s (transcendental = 4)",
-                         "frac": slots / VALU_PEAK_OPS, "kernel": "k_react_stream<ST57>",
-                         "ops_per_node_step": ST57_REACT_OPS,
-                         "whole_step_frac": ST57_OPS_PER_NODE_STEP * value / VALU_PEAK_OPS})
-    gs = smp.index_select(1, torch.as_tensor(cols, device="cuda")).cpu().numpy()
-    tg = s.tact()[cols]
-    s.close()
-    del smp
-    torch.cuda.empty_cache()
-    _log(f"st57 bundle: {value:.3e} node-steps/s, reaction frac {out['roofline']['frac']:.3f}")
+    rows = w0.n_steps // w0.sample_every
+    out, keep = {}, {}
+    for key, model in (("exact", I.MODEL_ST57), ("exp_log_star", O.MODEL_ST57_APX)):
+        w = replace(w0, model=model)
+        if not args.no_cpu_baseline:
+            sub = w.subset(fibers)
+            y0 = O.rest_state(model)[:, None] * (1.0 + rel[:, cols].astype(np.float64))
+            bg.submit(f"st57_bundle_{key}", dict(
+                threads=2, cfg=dict(model=model, Cm=w.Cm, Am=w.Am, sigma=w.sigma, h=w.h,
+                                    dt_0D=w.dt_0D, dt_1D=w.dt_1D, dt_split=w.dt_split,
+                                    v_th=w.v_th),
+                n_nodes=sub.n_nodes, y0=y0, stims=sub.stims, n_steps=w.n_steps,
+                sample_every=w.sample_every))
+        s = SU._solver(w, schedule=F.FIB_SCHED_SPLIT)
+        s.set_stimulus(w.stims)
+        smp = torch.empty((rows, w.n_total), device="cuda")
+        secs, _ = _run_timed(s, w, smp, 1, 1, lambda s=s: s.init_state(rel_noise=relt),
+                             lambda: None, f"st57 bundle {key}", step_split=w.n_steps)
+        kt = _ktimes(s)
+        r = dict(value=w.node_steps() / secs, seconds=secs, kernels=kt)
+        if key == "exact":
+            kr = kt["reaction"]
+            ops = ST57_REACT_OPS * w.n_total * w.n_steps / (kr["ms_total"] * 1e-3)
+            r["roofline"] = {"bound": "alu", "achieved": ops / 1e12,
+                             "peak": VALU_PEAK_OPS / 1e12,
+                             "unit": "T FP32 lane-ops/s (transcendental = 4)",
+                             "frac": ops / VALU_PEAK_OPS, "kernel": "k_react_stream<ST57>",
+                             "ops_per_node_step": ST57_REACT_OPS,
+                             "whole_step_frac": ST57_OPS_PER_NODE_STEP * r["value"] /
+                             VALU_PEAK_OPS}
+        keep[key] = (smp, s.tact(), smp.index_select(1, ci).cpu().numpy())
+        s.close()
+        out[key] = r
+        _log(f"st57 bundle {key}: {r['value']:.3e} node-steps/s")
+    (sa, ta, _), (sb, tb, _) = keep["exact"], keep["exp_log_star"]
+    out["exp_log_star"]["vs_exact"] = _compare(sa, ta, sb, tb, w0.dt_split,
+                                               w0.n_steps * w0.dt_split)
+    out["exp_log_star"]["over_exact"] = out["exp_log_star"]["value"] / out["exact"]["value"]
     if not args.no_cpu_baseline:
-        o = bg.get("st57_bundle")
-        out["vs_oracle"] = _parity_cols(gs, tg, o["samples"], o["tact"], w.n_steps * w.dt_split)
-        out["vs_oracle"]["fibers"] = fibers
-        out["vs_oracle"]["oracle_seconds"] = o["seconds"]
-    return out
+        for key in keep:
+            o = bg.get(f"st57_bundle_{key}")
+            out[key]["vs_oracle"] = _parity_cols(keep[key][2], keep[key][1][cols], o["samples"],
+                                                 o["tact"], w0.n_steps * w0.dt_split)
+            out[key]["vs_oracle"].update(fibers=fibers, oracle_seconds=o["seconds"])
+    del keep, sa, sb
+    torch.cuda.empty_cache()
+    ex = out["exact"]
+    return dict(workload="st57_400x1481_5ms, 1 % perturbation", fibers=400,
+                nodes=int(w0.n_total), split_steps=int(w0.n_steps), dt_split_ms=w0.dt_split,
+                value=ex["value"], seconds=ex["seconds"], kernels=ex["kernels"],
+                roofline=ex["roofline"], vs_oracle=ex.get("vs_oracle"),
+                exp_log_star=out["exp_log_star"])
 
 
 def surrogate_hh(args):

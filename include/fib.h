@@ -63,12 +63,19 @@ typedef enum {
 } fib_status;
 
 /* Subcellular models: Hodgkin-Huxley (4 states), the 57-state ST57 stand-in
- * for the Shorten model, and Hodgkin-Huxley with every exponential of its
- * rates replaced by the approximation exp*(x) = (1 + x/1024)^1024 of
- * eq. apx-e-function (4 states; its own resting state).  The fused schedule,
- * the adaptive fused kernel and the surrogate step take Hodgkin-Huxley only
- * (HH_APX_EXP: the fused schedule and the split schedule). */
-enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1, FIB_MODEL_HH_APX_EXP = 2 };
+ * for the Shorten model, Hodgkin-Huxley with every exponential of its rates
+ * replaced by the approximation exp*(x) = (1 + x/1024)^1024 of
+ * eq. apx-e-function (4 states; its own resting state), and ST57 with every
+ * exponential replaced by exp* and every logarithm by log* (the thesis's
+ * sixth-order Taylor pieces of log around 1, 3 and 9, split at 2 and 6, then
+ * one Newton step y - (1 - x / exp*(y)); figure apxlog), applied to the
+ * arguments as the model writes them, with arguments outside [0.2, 20]
+ * scaled into it by powers of two first (57 states; its own resting state).
+ * The fused schedule, the adaptive fused kernel and the surrogate step take
+ * Hodgkin-Huxley (and ST57 for the surrogate step) only; HH_APX_EXP runs the
+ * fused and the split schedule, ST57_APX the split schedule without
+ * adaptive computation or surrogate. */
+enum { FIB_MODEL_HH = 0, FIB_MODEL_ST57 = 1, FIB_MODEL_HH_APX_EXP = 2, FIB_MODEL_ST57_APX = 3 };
 
 /* Execution schedule of fib_run.
  *   FUSED: one persistent kernel keeps every node's states in registers and

@@ -57,7 +57,7 @@ int fail(int code, const char* fmt, ...) {
 
 int n_states_of(int model) {
   if (model == FIB_MODEL_HH || model == FIB_MODEL_HH_APX_EXP) return 4;
-  if (model == FIB_MODEL_ST57) return fib::st57::S;
+  if (model == FIB_MODEL_ST57 || model == FIB_MODEL_ST57_APX) return fib::st57::S;
   return -1;
 }
 
@@ -118,13 +118,16 @@ int hh_rest(double* y, bool apx = false) {
 
 constexpr int kS57 = fib::st57::S;
 
-void st57_residual(const std::vector<double>& y, std::vector<double>& F) {
+void st57_residual(bool apx, const std::vector<double>& y, std::vector<double>& F) {
   double u[kS57], d[kS57], zero[kS57];
   for (int k = 0; k < kS57; ++k) {
     u[k] = y[k];
     zero[k] = 0.0;
   }
-  fib::st57::rhs<double>(u, zero, 0.0, 1.0, d);
+  if (apx)
+    fib::st57::rhs<double, true>(u, zero, 0.0, 1.0, d);
+  else
+    fib::st57::rhs<double, false>(u, zero, 0.0, 1.0, d);
   for (int k = 0; k < kS57; ++k) F[k] = d[k];
   auto sum = [&](int a, int b) {
     double s = 0.0;
@@ -164,7 +167,7 @@ int lu_solve(std::vector<double>& A, std::vector<double>& b, int n) {
   return 0;
 }
 
-int st57_rest(double* out) {
+int st57_rest(double* out, bool apx = false) {
   std::vector<double> y(kS57, 0.0), F(kS57), Fp(kS57), yp(kS57), J((size_t)kS57 * kS57),
       dx(kS57);
   // start: membranes at -75 mV with Hodgkin-Huxley resting gates, every
@@ -192,7 +195,7 @@ int st57_rest(double* out) {
   for (int i = 39; i <= 54; ++i) y[i] = 0.125;
   y[55] = 1.1;
   for (int it = 0; it < 300; ++it) {
-    st57_residual(y, F);
+    st57_residual(apx, y, F);
     double nrm = 0.0;
     for (double f : F) nrm = std::max(nrm, std::fabs(f));
     if (nrm < 1e-11) {
@@ -203,7 +206,7 @@ int st57_rest(double* out) {
       yp = y;
       const double e = 1e-7 * std::max(1.0, std::fabs(y[j]));
       yp[j] += e;
-      st57_residual(yp, Fp);
+      st57_residual(apx, yp, Fp);
       for (int i = 0; i < kS57; ++i) J[(size_t)i * kS57 + j] = (Fp[i] - F[i]) / e;
     }
     for (int i = 0; i < kS57; ++i) dx[i] = -F[i];
@@ -216,7 +219,7 @@ int st57_rest(double* out) {
         if (i >= 8 && i <= 54 && yp[i] < 0.0) ok = false;
       }
       if (!ok) continue;
-      st57_residual(yp, Fp);
+      st57_residual(apx, yp, Fp);
       double np = 0.0;
       for (double f : Fp) np = std::max(np, std::fabs(f));
       if (np < nrm) break;
@@ -1002,6 +1005,7 @@ int fib_rest_state(const fib_params* p, double* y_out) {
   if (p->model == FIB_MODEL_HH) return hh_rest(y_out);
   if (p->model == FIB_MODEL_HH_APX_EXP) return hh_rest(y_out, true);
   if (p->model == FIB_MODEL_ST57) return st57_rest(y_out);
+  if (p->model == FIB_MODEL_ST57_APX) return st57_rest(y_out, true);
   return fail(FIB_EINVAL, "unknown model %d", p->model);
 }
 
@@ -1692,6 +1696,8 @@ int fib_set_adaptive(fib_t* c, double tol) {
   }
   if (c->sur_on)
     return fail(FIB_EUNSUPPORTED, "adaptive computation and the surrogate step do not combine");
+  if (c->p.model == FIB_MODEL_ST57_APX)
+    return fail(FIB_EUNSUPPORTED, "adaptive computation holds the exact models only");
   HIP_TRY(hipStreamSynchronize(c->stream));
   const size_t nt = (size_t)std::max<int64_t>(c->n_total, 1), nf = (size_t)std::max(c->n_fibers, 1);
   if (!c->d_pt) {

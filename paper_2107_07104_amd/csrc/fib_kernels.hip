@@ -704,12 +704,16 @@ struct ModelHHT {
 using ModelHH = ModelHHT<false>;
 using ModelHHApx = ModelHHT<true>;
 
-struct ModelST57 {
+template <bool APX>
+struct ModelST57T {
   static constexpr int S = st57::S;
   __device__ static void heun(float (&u)[S], const float* ref, float I, float tau, float inv_cm) {
-    st57::heun(u, ref, I, tau, inv_cm);
+    st57::heun<APX>(u, ref, I, tau, inv_cm);
   }
 };
+using ModelST57 = ModelST57T<false>;
+// ST57 with exp* and log* (eq. apx-e-function, figure apxlog)
+using ModelST57Apx = ModelST57T<true>;
 
 // flags bit 0: reaction with the stimulus of split step `step_a`;
 // bit 1: then the observables at the end of split step `step_a`
@@ -1133,8 +1137,10 @@ hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KA
   return dispatch_plan<DiffusionLaunch>(K, threads, groups, lds, a, s);
 }
 
-// Workgroups of k_react_stream<ModelST57> resident on the current device at
-// once (queried once per device; without an answer, one thread per node).
+// Workgroups of k_react_stream<M> resident on the current device at once
+// (queried once per device and model; without an answer, one thread per
+// node).
+template <class M>
 static unsigned st57_stream_blocks() {
   static std::mutex mu;
   static unsigned cache[64] = {};
@@ -1144,7 +1150,7 @@ static unsigned st57_stream_blocks() {
   if (cache[dev] == 0) {
     int cus = 0, per_cu = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_react_stream<ModelST57>, 256,
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_react_stream<M>, 256,
                                                       0) != hipSuccess ||
         cus <= 0 || per_cu <= 0)
       return ~0u;
@@ -1162,8 +1168,13 @@ hipError_t launch_react(int model, int32_t step_a, int32_t step_b, int flags, co
   else if (model == 2)
     hipLaunchKernelGGL(k_react<ModelHHApx>, grid, block, 0, s, a, step_a, step_b, flags);
   else if (model == 1)
-    hipLaunchKernelGGL(k_react_stream<ModelST57>, dim3(std::min(grid.x, st57_stream_blocks())),
-                       block, 0, s, a, step_a, step_b, flags);
+    hipLaunchKernelGGL(k_react_stream<ModelST57>,
+                       dim3(std::min(grid.x, st57_stream_blocks<ModelST57>())), block, 0, s, a,
+                       step_a, step_b, flags);
+  else if (model == 3)
+    hipLaunchKernelGGL(k_react_stream<ModelST57Apx>,
+                       dim3(std::min(grid.x, st57_stream_blocks<ModelST57Apx>())), block, 0, s, a,
+                       step_a, step_b, flags);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -1240,7 +1251,8 @@ hipError_t launch_adapt_finish(int model, int32_t step, const KArgs& a, hipStrea
 
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s) {
-  const int S = (model == 0 || model == 2) ? ModelHH::S : (model == 1) ? ModelST57::S : 0;
+  const int S = (model == 0 || model == 2) ? ModelHH::S
+                : (model == 1 || model == 3) ? ModelST57::S : 0;
   if (S == 0) return hipErrorInvalidValue;
   if (a.n_total == 0) return hipSuccess;
   hipLaunchKernelGGL(k_init, dim3(blocks_for(a.n_total, 256)), dim3(256), 0, s, a, S, vm_noise,

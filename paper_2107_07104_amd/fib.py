@@ -29,6 +29,7 @@ FIB_EUNSUPPORTED = -6
 FIB_MODEL_HH = 0
 FIB_MODEL_ST57 = 1
 FIB_MODEL_HH_APX_EXP = 2
+FIB_MODEL_ST57_APX = 3
 FIB_ACT_SILU = 0
 FIB_ACT_RELU = 1
 ACTS = {"silu": FIB_ACT_SILU, "relu": FIB_ACT_RELU}

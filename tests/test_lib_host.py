@@ -90,6 +90,11 @@ def test_rest_state_agrees_with_oracle():
     y_apx = F.fib_rest_state(F.make_params(model=F.FIB_MODEL_HH_APX_EXP))
     np.testing.assert_allclose(y_apx, O.rest_state(O.MODEL_HH_APX_EXP), rtol=0, atol=1e-10)
     assert abs(y_apx[0] - y_lib[0]) > 1e-5
+    # ST57 with exp* and log*: the library's Newton against the oracle's
+    y57 = F.fib_rest_state(F.make_params(model=F.FIB_MODEL_ST57_APX))
+    r57 = O.rest_state(O.MODEL_ST57_APX)
+    np.testing.assert_allclose(y57, r57, rtol=1e-9, atol=1e-9)
+    assert abs(y57[0] - O.rest_state(O.MODEL_ST57)[0]) > 1e-4
 
 
 def test_create_rejects_bad_fibers_without_touching_the_gpu():
