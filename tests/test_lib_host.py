@@ -40,7 +40,7 @@ def test_n_states():
     ("Cm", 0.0), ("Am", -1.0), ("h", float("nan")), ("sigma", -0.1), ("dt_0D", 0.0),
     ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
     ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
-    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("model", 3), ("schedule", 3),
+    ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("model", 4), ("schedule", 3),
     ("splitting", 2), ("time_1d", 2), ("time_1d", -1)])
 def test_check_params_rejects(field, value):
     p = F.make_params()
