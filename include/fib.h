@@ -435,6 +435,24 @@ int fib_surrogate_last_fallbacks(fib_t* ctx, int64_t* n);
  * Blocking. */
 int fib_surrogate_fallbacks(fib_t* ctx, int64_t* total, int64_t* steps);
 
+/* HIP graph replay of the split schedule (on by default).  With the Strang
+ * splitting, fib_run captures one block of P consecutive split steps --
+ * diffusion, then the reaction pair (or surrogate pair) that ends each step
+ * and starts the next -- once per call, with its step arguments relative to
+ * a device step base, and launches the captured graph once per block: P is
+ * twice the sample interval (an odd interval: the interval itself; no
+ * samples: 64 steps), blocks start at multiples of P, and the first and
+ * last steps of the call and the steps before the first block are launched
+ * as before.  Results are bitwise those of the step-by-step launches.  The
+ * graph of a call is released at the next call that captures one (after
+ * waiting for its replays) or at fib_destroy.  Not used while kernel timing
+ * is on, for adaptive runs, Godunov splitting or the fused schedule.
+ * enable = 0 turns it off. */
+int fib_set_graphs(fib_t* ctx, int32_t enable);
+
+/* Number of graph launches fib_run has made on this context. */
+int fib_graph_replays(fib_t* ctx, int64_t* n);
+
 /* Kernel timing for measurement.  With timing on, fib_run and
  * fib_step_surrogate record a HIP event on the context's stream before and
  * after each kernel launch of these classes:

@@ -317,6 +317,14 @@ struct fib_ctx {
   };
   bool kt_on = false;
   std::deque<KtRec> kt_pending;
+  // graph replay of the split schedule (fib_set_graphs)
+  bool graphs = true;
+  hipStream_t cap_stream = nullptr;      // non-blocking stream the blocks are captured on
+  int32_t* d_step_base = nullptr;        // device step base of the replays
+  hipGraph_t graph = nullptr;            // the last captured block and its executable,
+  hipGraphExec_t graph_exec = nullptr;   // kept until its replays have completed
+  hipEvent_t graph_done = nullptr;       // recorded after the last replay of graph_exec
+  int64_t graph_replays = 0;
   std::vector<hipEvent_t> kt_pool;
   double kt_ms[FIB_KT_COUNT] = {};
   int64_t kt_n[FIB_KT_COUNT] = {};
@@ -870,10 +878,10 @@ void kt_close(fib_ctx* c, int cls, hipEvent_t a, hipEvent_t b, bool own_a = true
 
 // One surrogate pair (network or closed-form predictor) finishing step n
 // and starting step n + 1, with the fallback kernel.
-int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n) {
+int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n, hipStream_t stream) {
   // the launchers record `mid` between their two kernels (they launch
-  // nothing for an empty context)
-  const bool timed = c->kt_on && c->n_total > 0;
+  // nothing for an empty context); no timing while a graph is captured
+  const bool timed = c->kt_on && c->n_total > 0 && stream == c->stream;
   hipEvent_t e0 = timed ? kt_mark(c) : nullptr;
   hipEvent_t mid = nullptr;
   if (timed && !c->kt_pool.empty()) {
@@ -886,11 +894,11 @@ int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n) {
     HIP_TRY(fib::launch_surrogate_step(c->p.model, a, c->sur_net, c->d_sur_frags, c->d_sur_bias,
                                        c->d_sur_tab, c->sur_sc, (int32_t)n, c->d_sur_list,
                                        c->d_sur_count, c->sur_slot, c->d_sur_total, c->sur_grid,
-                                       mid, c->stream));
+                                       mid, stream));
   else
     HIP_TRY(fib::launch_predictor_step(c->p.model, c->sur_pred, a, c->d_sur_tab, (int32_t)n,
                                        c->d_sur_list, c->d_sur_count, c->sur_slot,
-                                       c->d_sur_total, c->sur_grid, mid, c->stream));
+                                       c->d_sur_total, c->sur_grid, mid, stream));
   hipEvent_t e1 = timed ? kt_mark(c) : nullptr;
   if (mid && e0 && e1) {
     // the first pair leaves `mid` to the second, which is read back later
@@ -904,6 +912,102 @@ int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n) {
   c->sur_last_slot = c->sur_slot;
   c->sur_slot ^= 1;
   c->sur_steps += 1;
+  return FIB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Graph replay of the split schedule.  A block of P consecutive Strang split
+// steps -- diffusion, then the reaction pair (or surrogate pair) that ends
+// each step and starts the next -- is captured once per fib_run call on a
+// non-blocking stream, with the step arguments relative to a device step
+// base and a final node that advances the base by P; fib_run then launches
+// the executable graph once per block on the context's stream.  Blocks
+// start at multiples of P, and P is a multiple of the sample interval, so
+// every block writes V_m samples at the same offsets; with a surrogate
+// attached it holds an even number of surrogate steps, so the two
+// alternating rejection counters end each block where they began.  The
+// first and last steps of a call, and steps before the first block, run as
+// before.
+// ---------------------------------------------------------------------------
+
+// Split steps per graph block for these arguments, or 0 (no replay).
+int64_t graph_period(const fib_ctx* c, const KArgs& a) {
+  if (!c->graphs || c->kt_on || c->n_total == 0) return 0;
+  const int64_t se = a.samples && a.sample_every > 0 ? a.sample_every : 0;
+  const int64_t P = se == 0 ? 64 : (se % 2 == 0 ? 2 * se : se);
+  return P <= 4096 ? P : 0;
+}
+
+// Releases the executable graph of an earlier call once its replays are done.
+void graph_release(fib_ctx* c) {
+  if (c->graph_done) (void)hipEventSynchronize(c->graph_done);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
+}
+
+int surrogate_step(fib_ctx* c, const KArgs& a, int64_t n, hipStream_t stream);
+
+// Captures one block of P steps (relative steps 0 .. P-1) and replays it
+// `blocks` times from absolute step n0.
+int run_graph_blocks(fib_ctx* c, const KArgs& a, int64_t n0, int64_t P, int64_t blocks) {
+  graph_release(c);
+  if (!c->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  if (!c->graph_done) HIP_TRY(hipEventCreateWithFlags(&c->graph_done, hipEventDisableTiming));
+  if (!c->d_step_base && hipMalloc(&c->d_step_base, sizeof(int32_t)) != hipSuccess)
+    return fail(FIB_ENOMEM, "device allocation failed");
+  KArgs g = a;
+  g.step_base = c->d_step_base;
+  const size_t lds = fib::lds_bytes_for(c->threads, c->levels);
+  const int slot0 = c->sur_slot, last0 = c->sur_last_slot;
+  const int64_t steps0 = c->sur_steps;
+  HIP_TRY(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  int rc = FIB_OK;
+  for (int64_t j = 0; j < P && le == hipSuccess && rc == FIB_OK; ++j) {
+    le = fib::launch_diffusion(c->K, c->groups, c->threads, lds, g, c->cap_stream);
+    if (le != hipSuccess) break;
+    const bool sample = g.samples && g.sample_every > 0 && (j + 1) % g.sample_every == 0;
+    if (c->sur_on && !sample)
+      rc = surrogate_step(c, g, j, c->cap_stream);
+    else
+      le = fib::launch_react(c->p.model, (int32_t)j, (int32_t)(j + 1), 1 | 2 | 4, g,
+                             c->cap_stream);
+  }
+  if (le == hipSuccess && rc == FIB_OK)
+    le = fib::launch_step_base(c->d_step_base, (int32_t)P, false, c->cap_stream);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->cap_stream, &graph);
+  const int64_t per_block = c->sur_steps - steps0;
+  c->sur_steps = steps0;
+  if (rc != FIB_OK || le != hipSuccess || ec != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    c->sur_slot = slot0;
+    c->sur_last_slot = last0;
+    if (rc != FIB_OK) return rc;
+    return fail(FIB_EHIP, "graph capture: %s",
+                hipGetErrorString(le != hipSuccess ? le : ec));
+  }
+  hipGraphExec_t exec = nullptr;
+  const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    c->sur_slot = slot0;
+    c->sur_last_slot = last0;
+    return fail(FIB_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+  }
+  c->graph = graph;
+  c->graph_exec = exec;
+  // the capture stepped the counter bookkeeping through one block; an even
+  // number of surrogate steps leaves the slot where it was
+  HIP_TRY(fib::launch_step_base(c->d_step_base, (int32_t)n0, true, c->stream));
+  for (int64_t b = 0; b < blocks; ++b) {
+    HIP_TRY(hipGraphLaunch(exec, c->stream));
+    c->sur_steps += per_block;
+    ++c->graph_replays;
+  }
+  HIP_TRY(hipEventRecord(c->graph_done, c->stream));
   return FIB_OK;
 }
 
@@ -1097,6 +1201,10 @@ void fib_destroy(fib_t* c) {
     if (r.own_b) (void)hipEventDestroy(r.b);
   }
   for (hipEvent_t e : c->kt_pool) (void)hipEventDestroy(e);
+  graph_release(c);
+  if (c->graph_done) (void)hipEventDestroy(c->graph_done);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  (void)hipFree(c->d_step_base);
   delete c;
 }
 
@@ -1350,21 +1458,36 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   }
   // SPLIT, Strang: per split step one diffusion launch and one reaction
   // launch that finishes step n (second half, observables) and starts step
-  // n+1 (prescriptions, first half)
+  // n+1 (prescriptions, first half); whole blocks of steps as graph replays
   KT_LAUNCH(c, FIB_KT_REACTION, fib::launch_react(c->p.model, 0, (int32_t)step0, 4, a, c->stream));
-  for (int64_t n = step0; n < end; ++n) {
+  auto eager = [&](int64_t n) -> int {
     KT_LAUNCH(c, FIB_KT_DIFFUSION,
               fib::launch_diffusion(c->K, c->groups, c->threads, lds, a, c->stream));
     const bool last = n + 1 >= end;
     const bool sample = a.samples && a.sample_every > 0 && (n + 1) % a.sample_every == 0;
     if (c->sur_on && !last && !sample) {
-      if (int rc = surrogate_step(c, a, n)) return rc;
+      if (int rc = surrogate_step(c, a, n, c->stream)) return rc;
     } else {
       const int flags = 1 | 2 | (last ? 0 : 4);
       KT_LAUNCH(c, FIB_KT_REACTION,
                 fib::launch_react(c->p.model, (int32_t)n, (int32_t)(n + 1), flags, a, c->stream));
     }
+    return FIB_OK;
+  };
+  int64_t n = step0;
+  const int64_t P = graph_period(c, a);
+  if (P > 0) {
+    for (; n < end && n % P != 0; ++n)
+      if (int rc = eager(n)) return rc;
+    // whole blocks, none of which holds the last step of the call
+    const int64_t blocks = n < end ? (end - 1 - n) / P : 0;
+    if (blocks > 0) {
+      if (int rc = run_graph_blocks(c, a, n, P, blocks)) return rc;
+      n += blocks * P;
+    }
   }
+  for (; n < end; ++n)
+    if (int rc = eager(n)) return rc;
   return FIB_OK;
 }
 
@@ -1614,7 +1737,7 @@ int fib_step_surrogate(fib_t* c, int64_t step) {
   const int64_t ns = ceil_steps(0.5 * c->p.dt_split, c->p.dt_0D);
   a.n_sub = (int32_t)ns;
   a.tau = (float)(0.5 * c->p.dt_split / (double)ns);
-  return surrogate_step(c, a, step);
+  return surrogate_step(c, a, step, c->stream);
 }
 
 int fib_surrogate_predict(fib_t* c, int64_t step, float* du) {
@@ -1647,6 +1770,19 @@ int fib_surrogate_last_fallbacks(fib_t* c, int64_t* n) {
   HIP_TRY(hipStreamSynchronize(c->stream));
   HIP_TRY(hipMemcpy(&v, c->d_sur_count + c->sur_last_slot, sizeof(int), hipMemcpyDeviceToHost));
   *n = v;
+  return FIB_OK;
+}
+
+int fib_set_graphs(fib_t* c, int32_t enable) {
+  if (int rc = check_ctx(c)) return rc;
+  c->graphs = enable != 0;
+  return FIB_OK;
+}
+
+int fib_graph_replays(fib_t* c, int64_t* n) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!n) return fail(FIB_EINVAL, "null output");
+  *n = c->graph_replays;
   return FIB_OK;
 }
 

@@ -83,6 +83,9 @@ struct KArgs {
   float adapt_tol;                // relative change of an active point
   const uint8_t* slot_fiber;      // fused: [groups * cap] bin-local fiber of each slot
   const int32_t* bin_first_on;    // fused: [groups * kBinFibers] first stimulus step
+  // graph replays of the split schedule: a device value added to the step
+  // arguments of the reaction, surrogate and fallback kernels (null: none)
+  const int32_t* step_base;
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
@@ -187,6 +190,13 @@ hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// *p = v (set) or *p += v, by one thread: the step base of graph replays.
+hipError_t launch_step_base(int32_t* p, int32_t v, bool set, hipStream_t s);
+
+// The device step base as a kernel sees it: 0 without graph replay.
+__device__ __forceinline__ int32_t step_base_of(const KArgs& a) {
+  return a.step_base ? *a.step_base : 0;
+}
 hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t s);
 
 // LDS bytes the fused / diffusion kernels need for `threads` threads and

@@ -769,6 +769,9 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
                                                int flags) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n_total) return;
+  const int32_t base = step_base_of(A);
+  step_a += base;
+  step_b += base;
   const int64_t nt = A.n_total;
   float u[M::S];
 #pragma unroll
@@ -794,6 +797,9 @@ __global__ __launch_bounds__(256) void k_react_stream(KArgs A, int32_t step_a, i
   const bool obs = flags & REACT_OBSERVE;
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nt) return;
+  const int32_t base = step_base_of(A);
+  step_a += base;
+  step_b += base;
   // the next node's inputs: states, stimulus entry, v_prev and t_act
   float nx[M::S];
   uint32_t nsid = (uint32_t)A.node_stim[i];
@@ -1040,6 +1046,10 @@ __global__ __launch_bounds__(256) void k_init(KArgs A, int S, const float* __res
   A.v_prev[i] = A.state[i];
 }
 
+__global__ __launch_bounds__(64) void k_step_base(int32_t* p, int32_t v, int set) {
+  if (threadIdx.x == 0) *p = set ? v : *p + v;
+}
+
 __global__ __launch_bounds__(256) void k_fill(float* p, int64_t n, float v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1263,6 +1273,11 @@ hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise,
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_base(int32_t* p, int32_t v, bool set, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_base, dim3(1), dim3(64), 0, s, p, v, set ? 1 : 0);
   return hipGetLastError();
 }
 

@@ -336,6 +336,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
 
   const int64_t nt = A.n_total;
   const int64_t tiles = (nt + 63) / 64;
+  step_a += step_base_of(A);
   const int32_t step_b = step_a + 1;
   const float span = 2.0f * A.tau * (float)A.n_sub;
   for (int64_t tile = (int64_t)blockIdx.x * WAVES + wave; tile < tiles;
@@ -489,6 +490,7 @@ __global__ __launch_bounds__(256, 2) void k_midpoint(KArgs A, const float* __res
   int* count = counts + slot;
   if (blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
   const int64_t nt = A.n_total;
+  step_a += step_base_of(A);
   const int32_t step_b = step_a + 1;
   const float span = 2.0f * A.tau * (float)A.n_sub;
   const float uth = A.v_th - A.rest[0];
@@ -583,6 +585,7 @@ __global__ __launch_bounds__(256) void k_fallback(KArgs A, const int* __restrict
   const int n = *count;
   if (total && blockIdx.x == 0 && threadIdx.x == 0) atomicAdd(total, (unsigned long long)n);
   const int64_t nt = A.n_total;
+  step_a += step_base_of(A);
   for (int e = blockIdx.x * 256 + threadIdx.x; e < n; e += gridDim.x * 256) {
     const int64_t i = list[e];
     float u[S];

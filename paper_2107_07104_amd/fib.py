@@ -70,6 +70,7 @@ EXPORTS = (
     "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate", "fib_surrogate_fallbacks",
     "fib_set_predictor", "fib_set_kernel_timing", "fib_kernel_time", "fib_probe",
+    "fib_set_graphs", "fib_graph_replays",
     "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
     "fib_adaptive_points", "fib_emg_create", "fib_emg_destroy", "fib_emg_dims",
     "fib_emg_solve", "fib_emg_get_phi", "fib_emg_get_rhs",
@@ -163,6 +164,8 @@ def lib():
                                         C.c_int),
             "fib_set_predictor": ([_vp, C.c_int32, _fp, C.c_double], C.c_int),
             "fib_set_kernel_timing": ([_vp, C.c_int32], C.c_int),
+            "fib_set_graphs": ([_vp, C.c_int32], C.c_int),
+            "fib_graph_replays": ([_vp, C.POINTER(C.c_int64)], C.c_int),
             "fib_kernel_time": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
                                 C.c_int),
             "fib_probe": ([C.c_int32, C.c_int64, C.POINTER(C.c_double)], C.c_int),
@@ -499,6 +502,16 @@ def fib_surrogate_fallbacks(ctx):
     return t.value, n.value
 
 
+def fib_set_graphs(ctx, enable: bool) -> None:
+    _check(lib().fib_set_graphs(_vp(ctx), 1 if enable else 0))
+
+
+def fib_graph_replays(ctx) -> int:
+    n = C.c_int64()
+    _check(lib().fib_graph_replays(_vp(ctx), C.byref(n)))
+    return n.value
+
+
 def fib_set_kernel_timing(ctx, enable: bool) -> None:
     _check(lib().fib_set_kernel_timing(_vp(ctx), 1 if enable else 0))
 
@@ -700,6 +713,12 @@ class Solver:
     def fallbacks(self):
         """(rejected node-steps, surrogate steps) since the step was attached."""
         return fib_surrogate_fallbacks(self.ctx)
+
+    def set_graphs(self, enable=True):
+        fib_set_graphs(self.ctx, enable)
+
+    def graph_replays(self):
+        return fib_graph_replays(self.ctx)
 
     def set_kernel_timing(self, enable=True):
         fib_set_kernel_timing(self.ctx, enable)
