@@ -378,6 +378,36 @@ int fib_mlp_adam_step(fib_mlp_t* net, const float* X, const float* T, int64_t B,
 /* Clears the Adam moments and step count. */
 int fib_mlp_reset_optimizer(fib_mlp_t* net);
 
+/* Training data of the surrogate.  Statistics of the columns of A (device,
+ * rows x cols FP32, row-major, 1 <= cols <= 64) on `stream`: the mean and
+ * the sample standard deviation (two passes, FP64 sums in a fixed order, so
+ * the result is deterministic) and the minimum and maximum, into host
+ * arrays of cols values.  Allocates and frees a small device buffer;
+ * blocking. */
+int fib_column_stats(const float* A, int64_t rows, int32_t cols, void* stream, double* mean,
+                     double* std, float* cmin, float* cmax);
+
+/* Y[r][k] = (A[r][k] - shift[k]) * scale[k] for k < cols (A device, rows x
+ * cols; shift, scale host arrays of cols values) into Y (device, row
+ * stride ldy >= cols); if ldy > cols, also Y[r][cols] = extra (the
+ * stimulus-flag input).  Columns beyond are left as they are.  Blocking. */
+int fib_normalize_rows(const float* A, int64_t rows, int32_t cols, const float* shift,
+                       const float* scale, double extra, float* Y, int32_t ldy, void* stream);
+
+/* The context's device state, node-major, into U (device, n_total x
+ * n_states floats): U[i][k] = y_k - ref_k of node i.  Asynchronous. */
+int fib_state_rows(fib_t* ctx, float* U);
+
+/* Targets of the surrogate: for every row of U (device, rows x n_states,
+ * node-major offsets from the reference as fib_state_rows writes them), the
+ * increment of the plain method's two reaction halves R(dt/2) R(dt/2)
+ * (eq. heun, ceil((dt/2)/dt_0D) substeps each) with the stimulus current of
+ * split step `step` at the node the row is loaded into (rows are loaded n_total at
+ * a time into the context's state, row j of a chunk into node j), written
+ * to dU (device, rows x n_states).  Overwrites the context's state (it is
+ * left initialized).  Asynchronous. */
+int fib_reaction_increments(fib_t* ctx, const float* U, int64_t rows, int64_t step, float* dU);
+
 /* ------------------------------------------------------------------------
  * Surrogate split step.  With a network attached, fib_run (split schedule)
  * replaces the two reaction halves that meet between consecutive diffusion

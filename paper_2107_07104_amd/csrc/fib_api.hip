@@ -1351,6 +1351,38 @@ int fib_step_reaction(fib_t* c, int64_t step, double span) {
   return FIB_OK;
 }
 
+int fib_state_rows(fib_t* c, float* U) {
+  if (int rc = check_ctx(c)) return rc;
+  if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
+  if (!U && c->n_total > 0) return fail(FIB_EINVAL, "U is null");
+  HIP_TRY(fib::launch_state_rows(c->d_state, c->n_total, c->S, U, c->stream));
+  return FIB_OK;
+}
+
+int fib_reaction_increments(fib_t* c, const float* U, int64_t rows, int64_t step, float* dU) {
+  if (int rc = check_ctx(c)) return rc;
+  if (rows < 0 || (rows > 0 && (!U || !dU))) return fail(FIB_EINVAL, "bad arguments");
+  if (step < 0 || step >= ((int64_t)1 << 31)) return fail(FIB_EINVAL, "step out of range");
+  if (rows == 0) return FIB_OK;
+  if (c->n_total == 0) return fail(FIB_EINVAL, "the context has no nodes");
+  KArgs a = base_args(c);
+  const double span = 0.5 * c->p.dt_split;
+  const int64_t ns = ceil_steps(span, c->p.dt_0D);
+  if (ns > (1 << 20)) return fail(FIB_EINVAL, "more than 2^20 substeps");
+  a.n_sub = (int32_t)ns;
+  a.tau = (float)(span / (double)ns);
+  const int64_t nt = c->n_total;
+  for (int64_t r0 = 0; r0 < rows; r0 += nt) {
+    const int64_t n = std::min<int64_t>(nt, rows - r0);
+    HIP_TRY(fib::launch_rows_to_state(U, r0, n, c->S, c->d_state, nt, c->stream));
+    HIP_TRY(fib::launch_react(c->p.model, (int32_t)step, 0, 1, a, c->stream));
+    HIP_TRY(fib::launch_react(c->p.model, (int32_t)step, 0, 1, a, c->stream));
+    HIP_TRY(fib::launch_state_minus_rows(c->d_state, U, r0, n, c->S, nt, dU, c->stream));
+  }
+  c->state_ready = true;
+  return FIB_OK;
+}
+
 int fib_step_diffusion(fib_t* c, double span) {
   if (int rc = check_ctx(c)) return rc;
   if (!(std::isfinite(span) && span > 0.0)) return fail(FIB_EINVAL, "span must be > 0");

@@ -190,6 +190,13 @@ hipError_t launch_observe(int32_t step, const KArgs& a, hipStream_t s);
 hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise, const KArgs& a,
                        hipStream_t s);
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s);
+// Node-major copies for training data: U[i][k] = state[k][i]; state[k][i] =
+// U[r0 + i][k] (0 past n); dU[r0 + i][k] = state[k][i] - U[r0 + i][k].
+hipError_t launch_state_rows(const float* state, int64_t nt, int S, float* U, hipStream_t s);
+hipError_t launch_rows_to_state(const float* U, int64_t r0, int64_t n, int S, float* state,
+                                int64_t nt, hipStream_t s);
+hipError_t launch_state_minus_rows(const float* state, const float* U, int64_t r0, int64_t n, int S,
+                                   int64_t nt, float* dU, hipStream_t s);
 // *p = v (set) or *p += v, by one thread: the step base of graph replays.
 hipError_t launch_step_base(int32_t* p, int32_t v, bool set, hipStream_t s);
 

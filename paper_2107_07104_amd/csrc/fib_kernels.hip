@@ -1046,6 +1046,39 @@ __global__ __launch_bounds__(256) void k_init(KArgs A, int S, const float* __res
   A.v_prev[i] = A.state[i];
 }
 
+// Node-major copies of the state for training data: U[i][k] = state[k][i].
+__global__ __launch_bounds__(256) void k_state_rows(const float* __restrict__ state, int64_t nt,
+                                                    int S, float* __restrict__ U) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt * S) return;
+  const int64_t i = e / S;
+  const int k = (int)(e % S);
+  U[e] = state[k * nt + i];
+}
+
+// state[k][i] = U[r0 + i][k] for i < n, 0 for n <= i < nt.
+__global__ __launch_bounds__(256) void k_rows_to_state(const float* __restrict__ U, int64_t r0,
+                                                       int64_t n, int S, float* __restrict__ state,
+                                                       int64_t nt) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nt * S) return;
+  const int64_t i = e / S;
+  const int k = (int)(e % S);
+  state[k * nt + i] = i < n ? U[(r0 + i) * S + k] : 0.0f;
+}
+
+// dU[r0 + i][k] = state[k][i] - U[r0 + i][k] for i < n.
+__global__ __launch_bounds__(256) void k_state_minus_rows(const float* __restrict__ state,
+                                                          const float* __restrict__ U, int64_t r0,
+                                                          int64_t n, int S, int64_t nt,
+                                                          float* __restrict__ dU) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * S) return;
+  const int64_t i = e / S;
+  const int k = (int)(e % S);
+  dU[(r0 + i) * S + k] = state[k * nt + i] - U[(r0 + i) * S + k];
+}
+
 __global__ __launch_bounds__(64) void k_step_base(int32_t* p, int32_t v, int set) {
   if (threadIdx.x == 0) *p = set ? v : *p + v;
 }
@@ -1273,6 +1306,28 @@ hipError_t launch_init(int model, const float* vm_noise, const float* rel_noise,
 hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_rows(const float* state, int64_t nt, int S, float* U, hipStream_t s) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_state_rows, dim3(blocks_for(nt * S, 256)), dim3(256), 0, s, state, nt, S, U);
+  return hipGetLastError();
+}
+
+hipError_t launch_rows_to_state(const float* U, int64_t r0, int64_t n, int S, float* state,
+                                int64_t nt, hipStream_t s) {
+  if (nt == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_rows_to_state, dim3(blocks_for(nt * S, 256)), dim3(256), 0, s, U, r0, n, S,
+                     state, nt);
+  return hipGetLastError();
+}
+
+hipError_t launch_state_minus_rows(const float* state, const float* U, int64_t r0, int64_t n, int S,
+                                   int64_t nt, float* dU, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_state_minus_rows, dim3(blocks_for(n * S, 256)), dim3(256), 0, s, state, U,
+                     r0, n, S, nt, dU);
   return hipGetLastError();
 }
 

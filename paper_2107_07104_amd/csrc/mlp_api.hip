@@ -1,6 +1,7 @@
 // Host runtime of the surrogate network (C ABI in include/fib.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -216,6 +217,66 @@ int fib_mlp_gradient_noalloc(fib_mlp_t* n, const float* X, const float* T, int64
   float* loss_part = base + chunks * (int64_t)n->shape.n_params;
   MHIP(fib::launch_mlp_grad(n->shape, n->d_params, X, T, B, part, loss_part,
                             grad ? grad : n->d_grad, loss, n->stream));
+  return FIB_OK;
+}
+
+int fib_column_stats(const float* A, int64_t rows, int32_t cols, void* stream, double* mean,
+                     double* std, float* cmin, float* cmax) {
+  if (!A || rows < 1 || cols < 1 || cols > 64 || !mean || !std || !cmin || !cmax)
+    return mfail(FIB_EINVAL, "bad arguments (1 <= cols <= 64, rows >= 1)");
+  hipStream_t st = (hipStream_t)stream;
+  const int blocks = (int)std::min<int64_t>(1024, (rows + 255) / 256);
+  double* d = nullptr;
+  float* f = nullptr;
+  const size_t nd = (size_t)blocks * cols + 3 * (size_t)cols, nf = 2 * ((size_t)blocks + 1) * cols;
+  if (hipMalloc(&d, sizeof(double) * nd) != hipSuccess || hipMalloc(&f, sizeof(float) * nf) != hipSuccess) {
+    (void)hipFree(d);
+    return mfail(FIB_ENOMEM, "device allocation failed");
+  }
+  double *part = d, *sum = part + (size_t)blocks * cols, *mu = sum + cols, *sq = mu + cols;
+  float *pmin = f, *pmax = pmin + (size_t)blocks * cols, *lo = pmax + (size_t)blocks * cols,
+        *hi = lo + cols;
+  std::vector<double> hsum(cols), hsq(cols);
+  int rc = FIB_OK;
+  hipError_t e = fib::launch_col_stats(A, rows, cols, part, pmin, pmax, blocks, sum, lo, hi,
+                                       nullptr, nullptr, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hsum.data(), sum, sizeof(double) * cols, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    for (int k = 0; k < cols; ++k) mean[k] = hsum[k] / (double)rows;
+    e = hipMemcpyAsync(mu, mean, sizeof(double) * cols, hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess)
+    e = fib::launch_col_stats(A, rows, cols, part, pmin, pmax, blocks, sum, lo, hi, mu, sq, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(hsq.data(), sq, sizeof(double) * cols, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(cmin, lo, sizeof(float) * cols, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(cmax, hi, sizeof(float) * cols, hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e == hipSuccess) {
+    for (int k = 0; k < cols; ++k) std[k] = rows > 1 ? std::sqrt(hsq[k] / (double)(rows - 1)) : 0.0;
+  } else {
+    rc = mfail(FIB_EHIP, "column statistics: %s", hipGetErrorString(e));
+  }
+  (void)hipFree(d);
+  (void)hipFree(f);
+  return rc;
+}
+
+int fib_normalize_rows(const float* A, int64_t rows, int32_t cols, const float* shift,
+                       const float* scale, double extra, float* Y, int32_t ldy, void* stream) {
+  if (!A || !Y || !shift || !scale || rows < 0 || cols < 1 || cols > 64 || ldy < cols)
+    return mfail(FIB_EINVAL, "bad arguments (1 <= cols <= 64, ldy >= cols)");
+  if (rows == 0) return FIB_OK;
+  hipStream_t st = (hipStream_t)stream;
+  float* d = nullptr;
+  if (hipMalloc(&d, sizeof(float) * 2 * cols) != hipSuccess)
+    return mfail(FIB_ENOMEM, "device allocation failed");
+  hipError_t e = hipMemcpyAsync(d, shift, sizeof(float) * cols, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(d + cols, scale, sizeof(float) * cols, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess) e = fib::launch_normalize(A, rows, cols, d, d + cols, (float)extra, Y, ldy, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(d);
+  if (e != hipSuccess) return mfail(FIB_EHIP, "normalize: %s", hipGetErrorString(e));
   return FIB_OK;
 }
 

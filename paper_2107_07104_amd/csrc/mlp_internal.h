@@ -32,6 +32,15 @@ hipError_t launch_mlp_grad(const MlpShape& s, const float* params, const float* 
                            hipStream_t st);
 hipError_t launch_mlp_adam(float* params, float* m, float* v, const float* grad, int64_t n, float lr,
                            float b1, float b2, float eps, int64_t t, hipStream_t st);
+// Column sums, minima and maxima of A (rows x cols, cols <= 64) into
+// device arrays sum/cmin/cmax; with `mean` (device) also the sums of
+// squared deviations into sq.  part/pmin/pmax hold blocks x cols.
+hipError_t launch_col_stats(const float* A, int64_t rows, int cols, double* part, float* pmin,
+                            float* pmax, int blocks, double* sum, float* cmin, float* cmax,
+                            const double* mean, double* sq, hipStream_t st);
+// Y[r][k] = (A[r][k] - shift[k]) scale[k]; Y[r][cols] = extra if ldy > cols.
+hipError_t launch_normalize(const float* A, int64_t rows, int cols, const float* shift,
+                            const float* scale, float extra, float* Y, int ldy, hipStream_t st);
 
 }  // namespace fib
 

@@ -264,8 +264,129 @@ __global__ __launch_bounds__(256) void k_mlp_adam(float* __restrict__ params, fl
 }
 
 // ---------------------------------------------------------------------------
+// Training data: column statistics and normalization of row-major arrays
+// ---------------------------------------------------------------------------
+
+// Per-block partial statistics of the columns of A (rows x cols, row-major,
+// cols <= kStatCols): block b takes rows [b rb, (b+1) rb), thread (x, y)
+// column x and every kStatRows-th row from y.  Without `mean` it sums x
+// and records min and max; with `mean` it sums (x - mean)^2.  FP64 sums,
+// combined in a fixed order, so the statistics are deterministic.
+constexpr int kStatCols = 64, kStatRows = 4;
+__global__ __launch_bounds__(kStatCols * kStatRows) void k_col_partial(
+    const float* __restrict__ A, int64_t rows, int cols, int64_t rb,
+    const double* __restrict__ mean, double* __restrict__ part, float* __restrict__ pmin,
+    float* __restrict__ pmax) {
+  __shared__ double ssum[kStatRows][kStatCols];
+  __shared__ float smin[kStatRows][kStatCols], smax[kStatRows][kStatCols];
+  const int x = threadIdx.x, y = threadIdx.y;
+  double acc = 0.0;
+  float lo = __builtin_inff(), hi = -__builtin_inff();
+  if (x < cols) {
+    const double m = mean ? mean[x] : 0.0;
+    const int64_t r0 = (int64_t)blockIdx.x * rb;
+    const int64_t r1 = r0 + rb < rows ? r0 + rb : rows;
+    for (int64_t r = r0 + y; r < r1; r += kStatRows) {
+      const float v = A[r * cols + x];
+      if (mean) {
+        const double d = (double)v - m;
+        acc += d * d;
+      } else {
+        acc += (double)v;
+        lo = fminf(lo, v);
+        hi = fmaxf(hi, v);
+      }
+    }
+  }
+  ssum[y][x] = acc;
+  smin[y][x] = lo;
+  smax[y][x] = hi;
+  __syncthreads();
+  if (y == 0 && x < cols) {
+    for (int j = 1; j < kStatRows; ++j) {
+      acc += ssum[j][x];
+      lo = fminf(lo, smin[j][x]);
+      hi = fmaxf(hi, smax[j][x]);
+    }
+    part[(int64_t)blockIdx.x * cols + x] = acc;
+    if (!mean) {
+      pmin[(int64_t)blockIdx.x * cols + x] = lo;
+      pmax[(int64_t)blockIdx.x * cols + x] = hi;
+    }
+  }
+}
+
+// Sums the block partials of every column in block order: out[k] = total
+// (stage 0 also min and max).
+__global__ __launch_bounds__(kStatCols) void k_col_final(const double* __restrict__ part,
+                                                        const float* __restrict__ pmin,
+                                                        const float* __restrict__ pmax, int blocks,
+                                                        int cols, double* __restrict__ out,
+                                                        float* __restrict__ omin,
+                                                        float* __restrict__ omax) {
+  const int x = threadIdx.x;
+  if (x >= cols) return;
+  double acc = 0.0;
+  float lo = __builtin_inff(), hi = -__builtin_inff();
+  for (int b = 0; b < blocks; ++b) {
+    acc += part[(int64_t)b * cols + x];
+    if (omin) {
+      lo = fminf(lo, pmin[(int64_t)b * cols + x]);
+      hi = fmaxf(hi, pmax[(int64_t)b * cols + x]);
+    }
+  }
+  out[x] = acc;
+  if (omin) {
+    omin[x] = lo;
+    omax[x] = hi;
+  }
+}
+
+// Y[r][k] = (A[r][k] - shift[k]) * scale[k] for k < cols, Y[r][cols] =
+// extra when ldy > cols, other columns of Y untouched.
+__global__ __launch_bounds__(256) void k_normalize(const float* __restrict__ A, int64_t rows,
+                                                   int cols, const float* __restrict__ shift,
+                                                   const float* __restrict__ scale, float extra,
+                                                   float* __restrict__ Y, int ldy) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int w = ldy > cols ? cols + 1 : cols;
+  if (e >= rows * w) return;
+  const int64_t r = e / w;
+  const int k = (int)(e % w);
+  Y[r * ldy + k] = k < cols ? (A[r * cols + k] - shift[k]) * scale[k] : extra;
+}
+
+// ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+
+hipError_t launch_col_stats(const float* A, int64_t rows, int cols, double* part, float* pmin,
+                            float* pmax, int blocks, double* sum, float* cmin, float* cmax,
+                            const double* mean, double* sq, hipStream_t st) {
+  const int64_t rb = (rows + blocks - 1) / blocks;
+  const dim3 blk(kStatCols, kStatRows);
+  hipLaunchKernelGGL(k_col_partial, dim3((unsigned)blocks), blk, 0, st, A, rows, cols, rb,
+                     (const double*)nullptr, part, pmin, pmax);
+  hipLaunchKernelGGL(k_col_final, dim3(1), dim3(kStatCols), 0, st, part, pmin, pmax, blocks,
+                     cols, sum, cmin, cmax);
+  if (mean) {
+    hipLaunchKernelGGL(k_col_partial, dim3((unsigned)blocks), blk, 0, st, A, rows, cols, rb, mean,
+                       part, pmin, pmax);
+    hipLaunchKernelGGL(k_col_final, dim3(1), dim3(kStatCols), 0, st, part, pmin, pmax, blocks,
+                       cols, sq, (float*)nullptr, (float*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_normalize(const float* A, int64_t rows, int cols, const float* shift,
+                            const float* scale, float extra, float* Y, int ldy, hipStream_t st) {
+  const int w = ldy > cols ? cols + 1 : cols;
+  const int64_t n = rows * w;
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_normalize, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, A, rows,
+                     cols, shift, scale, extra, Y, ldy);
+  return hipGetLastError();
+}
 
 hipError_t launch_mlp_forward(const MlpShape& s, const float* params, const float* X, int64_t B,
                               float* O, hipStream_t st) {

@@ -667,7 +667,10 @@ static hipError_t sur_launch(const KArgs& a, const SurrogateNet& net, const __bf
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || pred) return e;
   if (mid && (e = hipEventRecord(mid, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fallback<M>, dim3((unsigned)grid), dim3(256), 0, s, a, list, counts + slot,
+  // the rejected nodes are few and each takes the whole Heun pair: spread
+  // them over many more threads than the step kernel's resident grid
+  const unsigned fb_grid = (unsigned)(grid < 2048 ? 2048 : grid);
+  hipLaunchKernelGGL(k_fallback<M>, dim3(fb_grid), dim3(256), 0, s, a, list, counts + slot,
                      step_a, total);
   return hipGetLastError();
 }

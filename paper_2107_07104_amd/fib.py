@@ -70,7 +70,8 @@ EXPORTS = (
     "fib_set_surrogate", "fib_clear_surrogate",
     "fib_surrogate_last_fallbacks", "fib_step_surrogate", "fib_surrogate_fallbacks",
     "fib_set_predictor", "fib_set_kernel_timing", "fib_kernel_time", "fib_probe",
-    "fib_set_graphs", "fib_graph_replays",
+    "fib_set_graphs", "fib_graph_replays", "fib_column_stats", "fib_normalize_rows",
+    "fib_state_rows", "fib_reaction_increments",
     "fib_surrogate_predict", "fib_autotune", "fib_set_adaptive", "fib_adaptive_solved",
     "fib_adaptive_points", "fib_emg_create", "fib_emg_destroy", "fib_emg_dims",
     "fib_emg_solve", "fib_emg_get_phi", "fib_emg_get_rhs",
@@ -165,6 +166,11 @@ def lib():
             "fib_set_predictor": ([_vp, C.c_int32, _fp, C.c_double], C.c_int),
             "fib_set_kernel_timing": ([_vp, C.c_int32], C.c_int),
             "fib_set_graphs": ([_vp, C.c_int32], C.c_int),
+            "fib_column_stats": ([_vp, C.c_int64, C.c_int32, _vp, _dp, _dp, _fp, _fp], C.c_int),
+            "fib_normalize_rows": ([_vp, C.c_int64, C.c_int32, _fp, _fp, C.c_double, _vp,
+                                    C.c_int32, _vp], C.c_int),
+            "fib_state_rows": ([_vp, _vp], C.c_int),
+            "fib_reaction_increments": ([_vp, _vp, C.c_int64, C.c_int64, _vp], C.c_int),
             "fib_graph_replays": ([_vp, C.POINTER(C.c_int64)], C.c_int),
             "fib_kernel_time": ([_vp, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)],
                                 C.c_int),
@@ -500,6 +506,33 @@ def fib_surrogate_fallbacks(ctx):
     t, n = C.c_int64(), C.c_int64()
     _check(lib().fib_surrogate_fallbacks(_vp(ctx), C.byref(t), C.byref(n)))
     return t.value, n.value
+
+
+def fib_column_stats(A_ptr: int, rows: int, cols: int, stream=None):
+    """(mean, std, min, max) of the columns of a device array (host arrays)."""
+    mean, std = np.zeros(cols), np.zeros(cols)
+    lo, hi = np.zeros(cols, np.float32), np.zeros(cols, np.float32)
+    _check(lib().fib_column_stats(_vp(A_ptr), int(rows), int(cols), _vp(stream),
+                                  mean.ctypes.data_as(_dp), std.ctypes.data_as(_dp),
+                                  lo.ctypes.data_as(_fp), hi.ctypes.data_as(_fp)))
+    return mean, std, lo, hi
+
+
+def fib_normalize_rows(A_ptr: int, rows: int, cols: int, shift, scale, extra: float, Y_ptr: int,
+                       ldy: int, stream=None) -> None:
+    sh = np.ascontiguousarray(shift, dtype=np.float32)
+    sc = np.ascontiguousarray(scale, dtype=np.float32)
+    _check(lib().fib_normalize_rows(_vp(A_ptr), int(rows), int(cols), sh.ctypes.data_as(_fp),
+                                    sc.ctypes.data_as(_fp), float(extra), _vp(Y_ptr), int(ldy),
+                                    _vp(stream)))
+
+
+def fib_state_rows(ctx, U_ptr: int) -> None:
+    _check(lib().fib_state_rows(_vp(ctx), _vp(U_ptr)))
+
+
+def fib_reaction_increments(ctx, U_ptr: int, rows: int, step: int, dU_ptr: int) -> None:
+    _check(lib().fib_reaction_increments(_vp(ctx), _vp(U_ptr), int(rows), int(step), _vp(dU_ptr)))
 
 
 def fib_set_graphs(ctx, enable: bool) -> None:

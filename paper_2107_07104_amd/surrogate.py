@@ -66,48 +66,39 @@ def _solver(w: I.Workload, **kw) -> F.Solver:
 
 def collect_states(w: I.Workload, snapshot_steps, log=print):
     """Offsets u = y - rest of every node at the given split steps of a plain
-    run of `w` (device tensor [len(snapshots) * n_total, S])."""
+    run of `w` (device tensor [len(snapshots) * n_total, S], node-major, as
+    fib_state_rows writes it)."""
     import torch
     s = _solver(w)
     s.set_stimulus(w.stims)
     s.init_state(vm_noise=w.vm_noise.astype(np.float32),
                  rel_noise=None if w.rel_noise is None else w.rel_noise.astype(np.float32))
-    out, done = [], 0
-    for step in sorted(snapshot_steps):
+    snaps = sorted(snapshot_steps)
+    U = torch.empty((len(snaps) * s.n_total, s.S), dtype=torch.float32, device="cuda")
+    done = 0
+    for j, step in enumerate(snaps):
         if step > done:
             s.run(done, step - done)
             done = step
-        st, _ = s.state_tensor()
-        out.append(st.t().contiguous().clone())
+        F.fib_state_rows(s.ctx, U[j * s.n_total:].data_ptr())
         log(f"  snapshot at step {step} ({step * w.dt_split:.2f} ms)")
     s.sync()
     s.close()
-    return torch.cat(out, 0)
+    return U
 
 
 def reaction_targets(w: I.Workload, U, amp: float):
     """Increment of the plain reaction pair R(dt/2) R(dt/2) from every row of
     U (offsets) with stimulus `amp` on every node (amp = 0: off), computed
-    by fib_step_reaction on a context of the workload's shape, one
-    n_total-row chunk at a time."""
+    by fib_reaction_increments on a context of the workload's shape."""
     import torch
-    N, S = U.shape
     s = _solver(w)
-    n = s.n_total
     if amp != 0.0:
         s.set_stimulus([dict(fiber=f, node=0, half_width=int(w.n_nodes[f]), step_on=0,
                              n_steps=1, period=0, amp=amp) for f in range(len(w.n_nodes))])
-    s.init_state()
-    st, _ = s.state_tensor()
+    U = U.contiguous()
     dU = torch.empty_like(U)
-    for a in range(0, N, n):
-        b = min(a + n, N)
-        st.zero_()
-        st[:, : b - a].copy_(U[a:b].t())
-        s.step_reaction(0, 0.5 * w.dt_split)
-        s.step_reaction(0, 0.5 * w.dt_split)
-        torch.cuda.synchronize()
-        dU[a:b] = st[:, : b - a].t() - U[a:b]
+    F.fib_reaction_increments(s.ctx, U.data_ptr(), U.shape[0], 0, dU.data_ptr())
     s.sync()
     s.close()
     return dU
@@ -115,28 +106,44 @@ def reaction_targets(w: I.Workload, U, amp: float):
 
 def fit_scales(U, dU, model: int):
     """Per-state normalisation of inputs and targets, and residual scales
-    (the range of each state in the data)."""
-    u = U.double()
-    d = dU.double()
-    in_shift = u.mean(0)
-    in_std = u.std(0)
-    out_shift = d.mean(0)
-    out_std = d.std(0)
-    rng = (u.max(0).values - u.min(0).values)
-    floor_in = 1e-6 * u.abs().max(0).values + 1e-8
-    scales = dict(
-        in_shift=in_shift.float().cpu().numpy(),
-        in_scale=(1.0 / torch_max(in_std, floor_in)).float().cpu().numpy(),
-        out_shift=out_shift.float().cpu().numpy(),
-        out_scale=torch_max(out_std, 1e-12 + 0 * out_std).float().cpu().numpy(),
-        res_scale=torch_max(rng, 1e-9 + 0 * rng).float().cpu().numpy(),
+    (the range of each state in the data), from the column statistics
+    fib_column_stats computes on the device (FP64 sums, sample standard
+    deviation)."""
+    rows, S = U.shape
+    u_mean, u_std, u_min, u_max = F.fib_column_stats(U.data_ptr(), rows, S)
+    d_mean, d_std, _, _ = F.fib_column_stats(dU.data_ptr(), rows, S)
+    u_min, u_max = u_min.astype(np.float64), u_max.astype(np.float64)
+    floor_in = 1e-6 * np.maximum(np.abs(u_min), np.abs(u_max)) + 1e-8
+    return dict(
+        in_shift=u_mean.astype(np.float32),
+        in_scale=(1.0 / np.maximum(u_std, floor_in)).astype(np.float32),
+        out_shift=d_mean.astype(np.float32),
+        out_scale=np.maximum(d_std, 1e-12).astype(np.float32),
+        res_scale=np.maximum(u_max - u_min, 1e-9).astype(np.float32),
     )
-    return scales
 
 
-def torch_max(a, b):
+def normalized_pairs(parts, scales, use_flag: bool):
+    """Network inputs X = (u - in_shift) in_scale (and the stimulus flag of
+    each part as the last input) and targets T = (du - out_shift) /
+    out_scale, written by fib_normalize_rows; `parts` is a list of
+    (U, dU, flag) with device tensors of shape [rows, S]."""
     import torch
-    return torch.maximum(a, b)
+    S = parts[0][0].shape[1]
+    n = sum(p[0].shape[0] for p in parts)
+    ldx = S + 1 if use_flag else S
+    X = torch.empty((n, ldx), dtype=torch.float32, device="cuda")
+    T = torch.empty((n, S), dtype=torch.float32, device="cuda")
+    inv_out = (1.0 / scales["out_scale"].astype(np.float64)).astype(np.float32)
+    r = 0
+    for U, dU, flag in parts:
+        m = U.shape[0]
+        F.fib_normalize_rows(U.data_ptr(), m, S, scales["in_shift"], scales["in_scale"],
+                             float(flag), X[r:].data_ptr(), ldx)
+        F.fib_normalize_rows(dU.data_ptr(), m, S, scales["out_shift"], inv_out, 0.0,
+                             T[r:].data_ptr(), S)
+        r += m
+    return X, T
 
 
 def _init_params(sizes, seed):
@@ -164,33 +171,19 @@ def train_surrogate(model: int, w: I.Workload, snapshot_steps, steps: int = 2000
     S = U.shape[1]
     use_flag = sizes[0] == S + 1
     dU0 = reaction_targets(w, U, 0.0)
-    X_parts, T_parts, flags = [U], [dU0], [torch.zeros(U.shape[0], device=U.device)]
+    parts = [(U, dU0, 0.0)]
     if use_flag and flag_share > 0:
         g = torch.Generator(device="cpu").manual_seed(seed)
         k = max(1, int(flag_share * U.shape[0]))
         idx = torch.randperm(U.shape[0], generator=g)[:k].to(U.device)
         Uf = U[idx].contiguous()
-        dUf = reaction_targets(w, Uf, amp)
-        X_parts.append(Uf)
-        T_parts.append(dUf)
-        flags.append(torch.ones(k, device=U.device))
-    Uall = torch.cat(X_parts, 0)
-    dUall = torch.cat(T_parts, 0)
-    fl = torch.cat(flags, 0)
-    log(f"  {Uall.shape[0]} training pairs collected in {time.time() - t0:.1f} s")
+        parts.append((Uf, reaction_targets(w, Uf, amp), 1.0))
+    log(f"  {sum(p[0].shape[0] for p in parts)} training pairs collected in "
+        f"{time.time() - t0:.1f} s")
     scales = fit_scales(U, dU0, model)
     scales["flag_scale"] = (1.0 / amp) if use_flag else 0.0
-    ish = torch.as_tensor(scales["in_shift"], device=U.device)
-    isc = torch.as_tensor(scales["in_scale"], device=U.device)
-    osh = torch.as_tensor(scales["out_shift"], device=U.device)
-    osc = torch.as_tensor(scales["out_scale"], device=U.device)
-    X = (Uall - ish) * isc
-    if use_flag:
-        X = torch.cat([X, fl[:, None]], 1)
-    T = (dUall - osh) / osc
-    X = X.float().contiguous()
-    T = T.float().contiguous()
-    del Uall, dUall
+    X, T = normalized_pairs(parts, scales, use_flag)
+    del parts
     net = F.Mlp(sizes, act=act)
     net.set_params(_init_params(sizes, seed))
     g = torch.Generator(device=U.device.type).manual_seed(seed)
