@@ -259,6 +259,9 @@ struct fib_ctx {
   std::vector<int32_t> slot_gidx;      // groups * cap
   std::vector<uint32_t> slot_base;     // coupling and real-node bits
   std::vector<std::vector<int32_t>> bin_fibers;
+  // fiber entries of the bins (KArgs::bin_ent and following)
+  std::vector<int32_t> bin_ent, ent_s0, ent_gofs, ent_fiber;
+  int32_t max_ents = 1;
 
   // device buffers
   float* d_state = nullptr;
@@ -267,6 +270,8 @@ struct fib_ctx {
   int* d_flag = nullptr;
   int32_t* d_slot_gidx = nullptr;
   uint32_t* d_slot_info = nullptr;
+  int32_t* d_bin_ent = nullptr;  // bin_ent, then ent_s0, ent_gofs, ent_fiber
+  size_t ent_alloc = 0;          // int32 values in d_bin_ent
   int32_t* d_node_stim = nullptr;
   fib::StimDev* d_stim = nullptr;
   int32_t n_stim = 0;
@@ -522,6 +527,25 @@ void build_tables(fib_ctx* c) {
       }
     }
   }
+  c->bin_ent.assign(1, 0);
+  c->ent_s0.clear();
+  c->ent_gofs.clear();
+  c->ent_fiber.clear();
+  c->max_ents = 1;
+  for (int b = 0; b < c->groups; ++b) {
+    int32_t s0 = 0;
+    for (int32_t f : c->bin_fibers[b]) {
+      c->ent_s0.push_back(s0);
+      c->ent_gofs.push_back((int32_t)c->offsets[f]);
+      c->ent_fiber.push_back(f);
+      s0 += c->n_nodes[f];
+    }
+    c->ent_s0.push_back(s0);  // end entry: the bin's load
+    c->ent_gofs.push_back(0);
+    c->ent_fiber.push_back(0);
+    c->bin_ent.push_back((int32_t)c->ent_s0.size());
+    c->max_ents = std::max<int32_t>(c->max_ents, (int32_t)c->bin_fibers[b].size() + 1);
+  }
   // PCR levels for the matrix of the split step's diffusion substep
   const int64_t n_cn = ceil_steps(c->p.dt_split, c->p.dt_1D);
   const double r = 2.0 * theta_of(c->p) * cn_r(c, c->p.dt_split / (double)n_cn);
@@ -542,8 +566,17 @@ int64_t max_bin_load(const fib_ctx* c) {
 }
 
 // Chooses bins, threads per bin and nodes per thread, and fills the slot
-// tables.  Automatic shapes use K <= 8 nodes per thread and a power-of-two
-// workgroup; fib_autotune measures the others.
+// tables.  Automatic shapes use K <= 8 nodes per thread; fib_autotune
+// measures the others.
+//  * Contexts that may run the fused schedule (Hodgkin-Huxley, schedule
+//    auto or fused) get one bin per compute unit if the fibers fit: the
+//    fused kernel keeps every state of its bin in registers for the whole
+//    run, and a power-of-two workgroup.
+//  * Split-schedule contexts (ST57 models, or schedule split) only run the
+//    diffusion with bins: many small bins (one fiber each if fibers have
+//    1024 nodes or more, else about 2048 nodes) of at least 4 nodes per
+//    thread keep several workgroups resident per compute unit, so one
+//    bin's loads overlap another's solve.
 int make_plan(fib_ctx* c) {
   const int64_t max_len =
       c->n_fibers ? *std::max_element(c->n_nodes.begin(), c->n_nodes.end()) : 0;
@@ -553,14 +586,23 @@ int make_plan(fib_ctx* c) {
   if (max_len > max_hold)
     return fail(FIB_EUNSUPPORTED, "fiber of %lld nodes exceeds the %lld nodes one workgroup holds",
                 (long long)max_len, (long long)max_hold);
+  const bool hh_like = c->p.model == FIB_MODEL_HH || c->p.model == FIB_MODEL_HH_APX_EXP;
+  const bool split_plan = !hh_like || c->p.schedule == FIB_SCHED_SPLIT;
   int groups = c->p.groups > 0 ? c->p.groups : c->cu_count;
+  if (split_plan && c->p.groups <= 0)
+    groups = (int)std::min<int64_t>(
+        INT32_MAX, max_len >= 1024 ? c->n_fibers : (c->n_total + 2047) / 2048);
   groups = (int)std::min<int64_t>(groups, std::max<int32_t>(c->n_fibers, 1));
+  groups = std::max(groups, 1);
   for (;;) {
     pack_bins(c, groups);
     const int64_t load = max_bin_load(c);
     int K = c->p.nodes_per_thread;
     int T = c->p.threads_per_group;
-    if (K == 0 && T == 0) {
+    if (K == 0 && T == 0 && split_plan) {
+      K = (int)std::min<int64_t>(8, std::max<int64_t>(4, (load + 1023) / 1024));
+      T = (int)std::max<int64_t>(64, (load + 64LL * K - 1) / (64LL * K) * 64);
+    } else if (K == 0 && T == 0) {
       K = (int)std::min<int64_t>(8, std::max<int64_t>(2, (load + 1023) / 1024));
       T = 64;
       while ((int64_t)T * K < load) T *= 2;
@@ -608,6 +650,22 @@ int upload_plan(fib_ctx* c, size_t old_slots) {
         hipMalloc(&c->d_slot_info, sizeof(uint32_t) * nslots) != hipSuccess)
       return fail(FIB_ENOMEM, "device allocation failed");
   }
+  const size_t ne = c->ent_s0.size(), nent = c->bin_ent.size() + 3 * ne;
+  if (nent != c->ent_alloc) {
+    (void)hipFree(c->d_bin_ent);
+    c->d_bin_ent = nullptr;
+    c->ent_alloc = 0;
+    if (hipMalloc(&c->d_bin_ent, sizeof(int32_t) * nent) != hipSuccess)
+      return fail(FIB_ENOMEM, "device allocation failed");
+    c->ent_alloc = nent;
+  }
+  {
+    std::vector<int32_t> h(c->bin_ent);
+    h.insert(h.end(), c->ent_s0.begin(), c->ent_s0.end());
+    h.insert(h.end(), c->ent_gofs.begin(), c->ent_gofs.end());
+    h.insert(h.end(), c->ent_fiber.begin(), c->ent_fiber.end());
+    HIP_TRY(hipMemcpy(c->d_bin_ent, h.data(), sizeof(int32_t) * nent, hipMemcpyHostToDevice));
+  }
   const std::vector<uint32_t> info = slot_info_with_stim(c);
   if (!c->slot_gidx.empty()) {
     HIP_TRY(hipMemcpy(c->d_slot_gidx, c->slot_gidx.data(), sizeof(int32_t) * c->slot_gidx.size(),
@@ -624,6 +682,15 @@ KArgs base_args(const fib_ctx* c) {
   a.n_total = c->n_total;
   a.slot_gidx = c->d_slot_gidx;
   a.slot_info = c->d_slot_info;
+  if (c->d_bin_ent) {
+    const size_t nb = c->bin_ent.size(), ne = c->ent_s0.size();
+    a.bin_ent = c->d_bin_ent;
+    a.ent_s0 = c->d_bin_ent + nb;
+    a.ent_gofs = a.ent_s0 + ne;
+    a.ent_fiber = a.ent_gofs + ne;
+  }
+  a.max_ents = c->max_ents;
+  a.n_bins = c->groups;
   a.node_stim = c->d_node_stim;
   a.stim = c->d_stim;
   a.t_act = c->d_tact;
@@ -1179,6 +1246,7 @@ void fib_destroy(fib_t* c) {
   (void)hipFree(c->d_flag);
   (void)hipFree(c->d_slot_gidx);
   (void)hipFree(c->d_slot_info);
+  (void)hipFree(c->d_bin_ent);
   (void)hipFree(c->d_node_stim);
   (void)hipFree(c->d_stim);
   (void)hipFree(c->d_sur_frags);
@@ -1399,8 +1467,9 @@ int fib_step_diffusion(fib_t* c, double span) {
     lv = std::max(lv, pcr_levels_needed(c, b, r_mat, c->p.pcr_full != 0));
   if (int rc = check_levels_fit(c, lv)) return rc;
   a.pcr_levels = lv;
-  HIP_TRY(fib::launch_diffusion(c->K, c->groups, c->threads, fib::lds_bytes_for(c->threads, lv),
-                                a, c->stream));
+  KT_LAUNCH(c, FIB_KT_DIFFUSION,
+            fib::launch_diffusion(c->K, c->groups, c->threads, fib::lds_bytes_for(c->threads, lv),
+                                  a, c->stream));
   return FIB_OK;
 }
 

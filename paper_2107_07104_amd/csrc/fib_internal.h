@@ -86,6 +86,15 @@ struct KArgs {
   // graph replays of the split schedule: a device value added to the step
   // arguments of the reaction, surrogate and fallback kernels (null: none)
   const int32_t* step_base;
+  // fibers of each bin for the split-schedule diffusion: entries
+  // bin_ent[b] .. bin_ent[b + 1] - 1 list bin b's fibers in slot order and
+  // end with an entry whose start is the bin's load
+  const int32_t* bin_ent;   // [groups + 1]
+  const int32_t* ent_s0;    // first slot of the entry's fiber in its bin
+  const int32_t* ent_gofs;  // first node of the entry's fiber
+  const int32_t* ent_fiber; // the entry's fiber
+  int32_t max_ents;         // the most entries of one bin (end entry included)
+  int32_t n_bins;           // bins (workgroups of the fused kernels)
   float rest[MAX_STATES];   // resting state (FP32); device rows hold y_k - rest[k]
 };
 
@@ -210,6 +219,20 @@ hipError_t launch_check_finite(const float* p, int64_t n, int* flag, hipStream_t
 // `levels` PCR levels.
 inline size_t lds_bytes_for(int threads, int levels) {
   return sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
+}
+
+// LDS of the split-schedule diffusion: a region that holds first the
+// staged V of every slot (cap floats) and the coupling bits of every slot
+// (cap bytes), then the Crank-Nicolson solve's arrays; after it two
+// buffers of bin entries (starts, first nodes, fibers: 3 max_ents ints
+// each).
+__host__ __device__ inline size_t diffusion_region_bytes(int threads, int levels, int cap) {
+  const size_t cn = sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
+  const size_t st = 5 * (size_t)cap;
+  return ((cn > st ? cn : st) + 15) & ~(size_t)15;
+}
+inline size_t diffusion_lds_bytes(int threads, int levels, int cap, int max_ents) {
+  return diffusion_region_bytes(threads, levels, cap) + 24 * (size_t)max_ents;
 }
 
 // LDS the adaptive fused kernel needs beyond the Crank-Nicolson region for

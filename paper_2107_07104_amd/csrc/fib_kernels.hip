@@ -27,7 +27,9 @@
 // between steps, so all elimination factors and PCR multipliers are
 // computed once per launch; a step only moves right-hand sides.
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <tuple>
 
 #include "fib_internal.h"
 #include "hh_model.h"
@@ -50,6 +52,16 @@ __device__ __forceinline__ void row_weights(uint32_t info, float r, float& wl, f
   wr = R ? (L ? 0.5f * r : r) : 0.0f;
 }
 
+// Coupling bits of a thread's K slots packed two per slot (bits 2q, 2q+1:
+// SLOT_L, SLOT_R of slot q), so that they take one register.
+template <int K>
+__device__ __forceinline__ uint32_t pack_lr(const uint32_t (&info)[K]) {
+  uint32_t lr = 0u;
+#pragma unroll
+  for (int q = 0; q < K; ++q) lr |= (info[q] & (SLOT_L | SLOT_R)) << (2 * q);
+  return lr;
+}
+
 // LDS layout (floats, T = threads):
 //   [0, T)        V of each thread's first slot
 //   [T, 2T)       V of each thread's last slot
@@ -69,15 +81,18 @@ struct CNConst {
 };
 
 // Elimination factors, interior responses and PCR multipliers for the
-// current bin.  Must be called by all threads of the workgroup.
+// current bin.  Must be called by all threads of the workgroup.  The
+// reciprocals are the hardware's (v_rcp_f32, within 1 ulp): the matrix is
+// strictly diagonally dominant, so a pivot off by an ulp changes the
+// solution by a few ulps, as any rounding of the elimination does.
 template <int K>
-__device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, float* lds, int T,
-                         int t, int levels) {
+__device__ void cn_setup(CNConst<K>& cc, uint32_t lr, float r, float* lds, int T, int t,
+                         int levels) {
   float a[K], c[K], d[K];
 #pragma unroll
   for (int q = 0; q < K; ++q) {
     float wl, wr;
-    row_weights(info[q], r, wl, wr);
+    row_weights(lr >> (2 * q), r, wl, wr);
     a[q] = -wl;
     c[q] = -wr;
     d[q] = 1.0f + wl + wr;
@@ -88,7 +103,7 @@ __device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, flo
 #pragma unroll
   for (int q = 0; q < K - 1; ++q) {
     const float den = (q == 0) ? d[0] : fmaf(-a[q], cc.cp[q - 1 < 0 ? 0 : q - 1], d[q]);
-    cc.inv[q] = 1.0f / den;
+    cc.inv[q] = __builtin_amdgcn_rcpf(den);
     cc.ainv[q] = a[q] * cc.inv[q];
     cc.cp[q] = c[q] * cc.inv[q];
     vp[q] = (q == 0) ? -a[0] * cc.inv[0] : -cc.ainv[q] * vp[q - 1 < 0 ? 0 : q - 1];
@@ -135,15 +150,15 @@ __device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, flo
     const float ra_r = hr ? s_ra[t + s] : 0.0f, rd_r = hr ? s_rd[t + s] : 1.0f,
                 rc_r = hr ? s_rc[t + s] : 0.0f;
     __syncthreads();
-    const float al = -Ra / rd_l;
-    const float ga = -Rc / rd_r;
+    const float al = -Ra * __builtin_amdgcn_rcpf(rd_l);
+    const float ga = -Rc * __builtin_amdgcn_rcpf(rd_r);
     s_al[l * T + t] = al;
     s_ga[l * T + t] = ga;
     Rd = Rd + al * rc_l + ga * ra_r;
     Ra = al * ra_l;
     Rc = ga * rc_r;
   }
-  cc.inv_rd = 1.0f / Rd;
+  cc.inv_rd = __builtin_amdgcn_rcpf(Rd);
   __syncthreads();
 }
 
@@ -155,7 +170,7 @@ __device__ void cn_setup(CNConst<K>& cc, const uint32_t (&info)[K], float r, flo
 // slots are all cleared keeps its V exactly (the matrix is block diagonal
 // per fiber and every coupling across a fiber end is an exact zero).
 template <int K>
-__device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K], float r,
+__device__ __forceinline__ void cn_solve(float (&V)[K], uint32_t lr, float r,
                                          float rhs, const CNConst<K>& cc, float* lds, int T,
                                          int t, int levels, uint32_t live) {
   float* s_vf = lds;
@@ -183,7 +198,7 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], const uint32_t (&info)[K
     const float l = (q == 0) ? vleft : V[q == 0 ? 0 : q - 1];
     const float rr = (q == K - 1) ? vright : V[q == K - 1 ? K - 1 : q + 1];
     float wl, wr;
-    row_weights(info[q], r, wl, wr);
+    row_weights(lr >> (2 * q), r, wl, wr);
     // dt L V = (wl (V_l - V) + wr (V_r - V)) / theta with the matrix's
     // weights (theta dt L); a zero weight removes the (possibly unrelated)
     // neighbour value exactly
@@ -259,7 +274,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
     }
   }
   CNConst<K> cc;
-  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);
+  cn_setup<K>(cc, pack_lr<K>(info), A.r_mat, lds, T, t, A.pcr_levels);
   const hh::Ref ref{A.rest[0], A.rest[1], A.rest[2], A.rest[3]};
 
   const uint32_t all = (K >= 32) ? 0xffffffffu : ((1u << K) - 1u);
@@ -281,7 +296,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
 #pragma unroll
       for (int q = 0; q < K; ++q) V[q] = y[q].V;
       for (int c = 0; c < A.n_cn; ++c)
-        cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, ~0u);
+        cn_solve<K>(V, pack_lr<K>(info), A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, ~0u);
 #pragma unroll
       for (int q = 0; q < K; ++q) y[q].V = V[q];
     }
@@ -463,7 +478,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh_adapt(KArgs A) {
   const uint32_t sid_l = t > 0 ? (A.slot_info[bslot + s0 - 1] >> SLOT_STIM_SHIFT) : 0u;
   const uint32_t sid_r = t + 1 < T ? (A.slot_info[bslot + s0 + K] >> SLOT_STIM_SHIFT) : 0u;
   CNConst<K> cc;
-  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);  // its barriers order the clears above
+  cn_setup<K>(cc, pack_lr<K>(info), A.r_mat, lds, T, t, A.pcr_levels);  // its barriers order the clears above
   for (uint32_t m = act0; m; m &= m - 1u) {
     const int sl = s0 + __builtin_ctz(m);
     atomicOr(&s_act[sl >> 5], 1u << (sl & 31));
@@ -587,7 +602,7 @@ __global__ __launch_bounds__(MAXT) void k_run_hh_adapt(KArgs A) {
 #pragma unroll
         for (int q = 0; q < K; ++q) V[q] = s_y[s0 + q];
         for (int c = 0; c < A.n_cn; ++c)
-          cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
+          cn_solve<K>(V, pack_lr<K>(info), A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
 #pragma unroll
         for (int q = 0; q < K; ++q) s_y[s0 + q] = V[q];
       }
@@ -652,36 +667,205 @@ __global__ __launch_bounds__(MAXT) void k_run_hh_adapt(KArgs A) {
 // Diffusion only (states in device memory)
 // ---------------------------------------------------------------------------
 
+// Bin entry of slot s: the last entry starting at or before s (s below the
+// bin's load; n = entries including the end entry).
+__device__ __forceinline__ int bin_entry_of(const int32_t* __restrict__ s0, int n, int s) {
+  int lo = 0, hi = n - 2;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s0[mid] <= s) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// Entries of bin b (starts, first nodes, fibers, max_ents apart) into buf;
+// all threads; returns their number.
+__device__ __forceinline__ int bin_entries(const KArgs& A, int b, int32_t* buf, int T, int t) {
+  const int32_t e0 = A.bin_ent[b];
+  const int ne = A.bin_ent[b + 1] - e0;
+  for (int j = t; j < ne; j += T) {
+    buf[j] = A.ent_s0[e0 + j];
+    buf[A.max_ents + j] = A.ent_gofs[e0 + j];
+    buf[2 * A.max_ents + j] = A.ent_fiber[e0 + j];
+  }
+  return ne;
+}
+
+// V of slots t + i T of the bin whose entries are in buf (0 past its load),
+// and bit i of `live`: the slot's fiber takes part in the step (always, or
+// with adaptive computation when a node of the fiber is solved; padding
+// slots take part without adaptive computation, where they have no
+// couplings and a zero right-hand side).  Consecutive lanes take
+// consecutive slots, i.e. consecutive nodes of one fiber: the loads are
+// coalesced.
+template <int K>
+__device__ __forceinline__ void bin_fetch(const KArgs& A, const int32_t* buf, int ne, int T,
+                                          int t, float (&v)[K], uint32_t& live) {
+  const int32_t load = buf[ne - 1];
+  if (ne == 2) {
+    // one fiber: slot s is node buf[me] + s; `live` is the fiber's flag for
+    // every real slot
+    const float* __restrict__ src = A.state + buf[A.max_ents];
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const int s = t + i * T;
+      v[i] = s < load ? src[s] : 0.0f;
+    }
+    live = ~0u;
+    if (A.fiber_any) {
+      const int32_t f = buf[2 * A.max_ents];
+      if (!A.fiber_any[f]) live = 0u;
+      if (t == 0) A.fiber_any_next[f] = 0;
+    }
+    return;
+  }
+  live = 0u;
+#pragma unroll
+  for (int i = 0; i < K; ++i) {
+    const int s = t + i * T;
+    v[i] = 0.0f;
+    if (s < load) {
+      const int e = bin_entry_of(buf, ne, s);
+      const int32_t s0 = buf[e];
+      v[i] = A.state[buf[A.max_ents + e] + (s - s0)];
+      if (A.fiber_any) {
+        const int32_t f = buf[2 * A.max_ents + e];
+        if (A.fiber_any[f]) live |= 1u << i;
+        // the fiber's first node clears its flag for the step after next
+        if (s == s0) A.fiber_any_next[f] = 0;
+      } else {
+        live |= 1u << i;
+      }
+    } else if (!A.fiber_any) {
+      live |= 1u << i;
+    }
+  }
+}
+
+// Persistent over bins b = blockIdx.x, + gridDim.x, ...: while one bin is
+// solved, the V of the next one (and the entries of the one after) are
+// already on their way, so the load latency overlaps the solve's barriers.
+// Per bin, V is staged through LDS from the coalesced slot order t + i T to
+// the thread-contiguous order t K + q the partitioned solve works in, and
+// back for the coalesced stores.
 template <int K, int MAXT>
 __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
   extern __shared__ float lds[];
   const int T = blockDim.x;
   const int t = threadIdx.x;
-  const int64_t base = (int64_t)blockIdx.x * A.cap + (int64_t)t * K;
-  uint32_t info[K];
-  int32_t gi[K];
-  float V[K];
-  uint32_t live = ~0u;  // adaptive computation: slots of fibers with a solved node
-  if (A.fiber_any) live = 0u;
+  const int cap = A.cap;
+  const int G = gridDim.x;
+  const int me = A.max_ents;
+  float* sV = lds;                                // staged V of every slot
+  uint8_t* sInf = (uint8_t*)(lds + cap);          // SLOT_L | SLOT_R | live << 2
+  int32_t* eb0 = (int32_t*)((char*)lds + diffusion_region_bytes(T, A.pcr_levels, cap));
+  int32_t* eb1 = eb0 + 3 * me;
+  int b = blockIdx.x;
+  if (b >= A.n_bins) return;
+  int ne = bin_entries(A, b, eb0, T, t);
+  int ne_n = b + G < A.n_bins ? bin_entries(A, b + G, eb1, T, t) : 0;
+  __syncthreads();
+  float vn[K];
+  uint32_t live_n;
+  bin_fetch<K>(A, eb0, ne, T, t, vn, live_n);
+  for (int j = 0; b < A.n_bins; ++j, b += G) {
+    int32_t* cur = (j & 1) ? eb1 : eb0;
+    int32_t* nxt = (j & 1) ? eb0 : eb1;
+    const int32_t load = cur[ne - 1];
+    const bool one = ne == 2;  // one fiber in the bin (uniform)
+    if (one) {
 #pragma unroll
-  for (int q = 0; q < K; ++q) {
-    info[q] = A.slot_info[base + q];
-    gi[q] = A.slot_gidx[base + q];
-    V[q] = gi[q] >= 0 ? A.state[gi[q]] : 0.0f;
-    if (A.fiber_any && gi[q] >= 0) {
-      const int32_t f = A.node_fiber[gi[q]];
-      if (A.fiber_any[f]) live |= 1u << q;
-      // the fiber's first node clears its flag for the step after next
-      if (!(info[q] & SLOT_L)) A.fiber_any_next[f] = 0;
+      for (int i = 0; i < K; ++i) sV[t + i * T] = vn[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int s = t + i * T;
+        uint32_t inf = ((live_n >> i) & 1u) << 2;
+        if (s < load) {
+          const int e = bin_entry_of(cur, ne, s);
+          const int32_t s0 = cur[e];
+          inf |= (s > s0 ? SLOT_L : 0u) | (s + 1 < cur[e + 1] ? SLOT_R : 0u);
+        }
+        sV[s] = vn[i];
+        sInf[s] = (uint8_t)inf;
+      }
     }
-  }
-  CNConst<K> cc;
-  cn_setup<K>(cc, info, A.r_mat, lds, T, t, A.pcr_levels);
-  for (int c = 0; c < A.n_cn; ++c)
-    cn_solve<K>(V, info, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
+    __syncthreads();
+    float V[K];
+    uint32_t lr = 0u;    // coupling bits, two per slot
+    uint32_t live = 0u;  // slots whose fiber takes part
 #pragma unroll
-  for (int q = 0; q < K; ++q)
-    if (gi[q] >= 0) A.state[gi[q]] = V[q];
+    for (int q = 0; q < K; ++q) {
+      const int s = t * K + q;
+      V[q] = sV[s];
+      if (one) {
+        // padding slots take part exactly when there is no adaptive
+        // computation (live_n is all ones then)
+        const bool real = s < load;
+        lr |= (real ? ((s > 0 ? SLOT_L : 0u) | (s + 1 < load ? SLOT_R : 0u)) : 0u) << (2 * q);
+        live |= ((real || !A.fiber_any) ? (live_n & 1u) : 0u) << q;
+      } else {
+        const uint32_t bq = sInf[s];
+        lr |= (bq & 3u) << (2 * q);
+        live |= ((bq >> 2) & 1u) << q;
+      }
+    }
+    __syncthreads();  // the Crank-Nicolson arrays overlay the staging
+    // the next bin's V and the entries of the one after it
+    const int bn = b + G, bnn = b + 2 * G;
+    if (bn < A.n_bins) bin_fetch<K>(A, nxt, ne_n, T, t, vn, live_n);
+    int ne_nn = 0;
+    int32_t e0nn = 0, r_s0 = 0, r_go = 0, r_f = 0;
+    if (bnn < A.n_bins) {
+      e0nn = A.bin_ent[bnn];
+      ne_nn = A.bin_ent[bnn + 1] - e0nn;
+      if (t < ne_nn) {
+        r_s0 = A.ent_s0[e0nn + t];
+        r_go = A.ent_gofs[e0nn + t];
+        r_f = A.ent_fiber[e0nn + t];
+      }
+    }
+    CNConst<K> cc;
+    cn_setup<K>(cc, lr, A.r_mat, lds, T, t, A.pcr_levels);
+    for (int c = 0; c < A.n_cn; ++c)
+      cn_solve<K>(V, lr, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < K; ++q) sV[t * K + q] = V[q];
+    __syncthreads();
+    if (one) {
+      float* __restrict__ dst = A.state + cur[me];
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int s = t + i * T;
+        if (s < load) dst[s] = sV[s];
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < K; ++i) {
+        const int s = t + i * T;
+        if (s < load) {
+          const int e = bin_entry_of(cur, ne, s);
+          A.state[cur[me + e] + (s - cur[e])] = sV[s];
+        }
+      }
+    }
+    __syncthreads();  // cur and the staging are free
+    if (bnn < A.n_bins) {
+      if (t < ne_nn) {
+        cur[t] = r_s0;
+        cur[me + t] = r_go;
+        cur[2 * me + t] = r_f;
+      }
+      for (int jj = t + T; jj < ne_nn; jj += T) {
+        cur[jj] = A.ent_s0[e0nn + jj];
+        cur[me + jj] = A.ent_gofs[e0nn + jj];
+        cur[2 * me + jj] = A.ent_fiber[e0nn + jj];
+      }
+    }
+    ne = ne_n;
+    ne_n = ne_nn;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1155,10 +1339,33 @@ struct FusedAdaptLaunch {
   }
 };
 
+// Workgroups of a kernel resident on the current device at once for a
+// block size and dynamic LDS (queried once per device and shape; 0 if the
+// runtime gives no answer).
+template <class Kern>
+static int resident_blocks(Kern kern, int threads, size_t lds) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, size_t>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_tuple(dev, threads, lds);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, threads, lds) != hipSuccess ||
+      cus <= 0 || per_cu <= 0)
+    return 0;
+  return cache[key] = cus * per_cu;
+}
+
 template <int K, int MAXT>
 struct DiffusionLaunch {
   static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL((k_diffusion<K, MAXT>), dim3(groups), dim3(threads), lds, s, a);
+    const int res = resident_blocks(k_diffusion<K, MAXT>, threads, lds);
+    const int grid = res > 0 ? std::min(groups, res) : groups;
+    hipLaunchKernelGGL((k_diffusion<K, MAXT>), dim3(grid), dim3(threads), lds, s, a);
     return hipGetLastError();
   }
 };
@@ -1177,6 +1384,8 @@ hipError_t launch_run_fused_adaptive(int K, int groups, int threads, size_t lds,
 
 hipError_t launch_diffusion(int K, int groups, int threads, size_t lds, const KArgs& a,
                             hipStream_t s) {
+  if (!a.bin_ent || a.cap != threads * K || a.n_bins != groups) return hipErrorInvalidValue;
+  lds = std::max(lds, diffusion_lds_bytes(threads, a.pcr_levels, a.cap, a.max_ents));
   return dispatch_plan<DiffusionLaunch>(K, threads, groups, lds, a, s);
 }
 
