@@ -991,6 +991,10 @@ def emg_bench(args):
     b = -(Ki @ V3)
     b -= b.mean()
     res = float(np.linalg.norm(b - Kt @ phi) / np.linalg.norm(b))
+    # the last phi_e against the oracle's FP64 solution from the same V_m
+    # (conjugate gradients to 1e-13: the mesh is too large for its direct solve)
+    phi_o, _ = E.solve(g, V3, sig["sigma_i"], sig["sigma_el"], sig["sigma_et"], method="cg")
+    phi_err = float(np.max(np.abs(phi - phi_o)) / np.max(np.abs(phi_o)))
     plan = s.plan()
     emg.close()
     s.close()
@@ -1009,9 +1013,14 @@ def emg_bench(args):
                emg_solves=n_solves, cg_iterations_mean=tot_it / n_solves,
                cg_iterations_max=int(max(its)), emg_seconds=t_emg,
                emg_share=t_emg / secs, ms_per_cg_iteration=(t_emg / max(tot_it, 1)) * 1e3,
-               last_phi_fp64_relative_residual=res, mesh_nodes=int(g.n), roofline=roof)
+               last_phi_fp64_relative_residual=res,
+               last_phi_vs_oracle=dict(max_abs_err_over_max_phi=phi_err,
+                                       max_phi_mV=float(np.max(np.abs(phi_o))),
+                                       oracle="FP64 CG to a relative residual of 1e-13"),
+               mesh_nodes=int(g.n), roofline=roof)
     _log(f"emg: {out['value']:.3e} node-steps/s, {n_solves} solves, {tot_it / n_solves:.1f} "
-         f"CG iterations each, EMG share {out['emg_share']:.2f}, residual {res:.1e}")
+         f"CG iterations each, EMG share {out['emg_share']:.2f}, residual {res:.1e}, "
+         f"phi vs oracle {phi_err:.1e}")
     return out
 
 

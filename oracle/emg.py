@@ -95,10 +95,30 @@ def solve_neumann(K: sp.csr_matrix, b: np.ndarray) -> np.ndarray:
     return spla.spsolve(Kb, np.concatenate([b, [0.0]]))[:-1]
 
 
-def solve(g: Grid, V3: np.ndarray, sigma_i: float, sigma_el: float, sigma_et: float):
+def solve_neumann_cg(K: sp.csr_matrix, b: np.ndarray, rtol: float = 1e-13) -> np.ndarray:
+    """Zero-mean solution of the same singular system for meshes too large for
+    the direct solve: the right-hand side's mean (zero in exact arithmetic:
+    every column of K sums to zero) is removed, FP64 conjugate gradients with
+    the diagonal as preconditioner (SciPy's `cg`) run to a relative residual of
+    `rtol`, and the iterate's mean is removed.  CG on a consistent
+    semi-definite system stays in the range of K."""
+    bz = b - b.mean()
+    d = K.diagonal()
+    M = sp.diags(1.0 / d)
+    x, info = spla.cg(K, bz, rtol=rtol, atol=0.0, maxiter=20 * K.shape[0], M=M)
+    if info != 0:
+        raise RuntimeError(f"CG did not converge (info {info})")
+    return x - x.mean()
+
+
+def solve(g: Grid, V3: np.ndarray, sigma_i: float, sigma_el: float, sigma_et: float,
+          method: str = "direct"):
     """Zero-mean phi_e of K_{sigma_i + sigma_e} phi_e = -K_{sigma_i} V3, and the
-    right-hand side."""
+    right-hand side; method "direct" (bordered sparse LU) or "cg" (FP64
+    conjugate gradients to a relative residual of 1e-13)."""
     Ki = stiffness_3d(g, (0.0, 0.0, sigma_i))
     Kt = stiffness_3d(g, (sigma_et, sigma_et, sigma_el + sigma_i))
     b = -(Ki @ V3)
+    if method == "cg":
+        return solve_neumann_cg(Kt, b), b
     return solve_neumann(Kt, b), b

@@ -20,6 +20,11 @@ oracle of oracle/emg.py.
 * a resting V_m gives phi_e = 0 without an iteration; a repeated solve from
   the same V_m starts at the previous phi_e and needs at most a few
   iterations (the true residual of the FP32 iterate sits near the tolerance);
+* at the benchmark's size (37 x 37 fibers of 1481 nodes, every 10th node:
+  37 x 37 x 149 = 2.0e5 mesh nodes) phi_e during a propagating wave equals
+  the oracle's FP64 conjugate-gradient solution (the direct solve does not
+  fit this mesh) to 1e-5 of its largest value after a deep solve, and to
+  1e-3 after the benchmark's tolerance 1e-6;
 * malformed bundles are refused.
 """
 import numpy as np
@@ -97,6 +102,36 @@ def test_deep_solve_converges_and_stays_at_the_solution(nx, ny, n, m):
     say(f"[emg deep] {nx}x{ny}x{n}/{m}: {it} iterations, residual {rel:.2e}, phi err {ep:.2e}")
     assert rel <= 1e-9 and it < 3000
     assert ep < 1e-4
+    emg.close()
+    s.close()
+
+
+def test_bench_size_bundle_matches_oracle():
+    nx = ny = 37
+    n, m, hxy = 1481, 10, 0.05
+    say(f"[emg bench size] {nx}x{ny}x{n}, every {m}th node")
+    w = _bundle(nx, ny, n)
+    s = gpu_solver(w)
+    s.run(0, 2500)
+    s.sync()
+    V = s.get_state()[0]
+    V3 = E.prolongate(V, nx, ny, n, m)
+    g = E.Grid(nx, ny, (n - 1) // m + 1, hxy, hxy, m * w.h)
+    phi_o, _ = E.solve(g, V3, SIG["sigma_i"], SIG["sigma_el"], SIG["sigma_et"], method="cg")
+    emg = F.Emg(s, nx, ny, m, hxy, hxy, **SIG)
+    # the benchmark's tolerance, then deeper from there
+    it1, rel1 = emg.solve(tol=1e-6, max_iter=5000)
+    e1 = np.max(np.abs(emg.phi() - phi_o)) / np.max(np.abs(phi_o))
+    it2, rel2 = emg.solve(tol=1e-9, max_iter=5000)
+    e2 = np.max(np.abs(emg.phi() - phi_o)) / np.max(np.abs(phi_o))
+    say(f"   tol 1e-6: {it1} iterations, residual {rel1:.2e}, phi err {e1:.2e}; "
+        f"tol 1e-9: {it2} more, residual {rel2:.2e}, phi err {e2:.2e}; "
+        f"max |phi| {np.max(np.abs(phi_o)):.3f} mV")
+    assert rel1 <= 1e-6 and rel2 <= 1e-9
+    # FP32 iterates reach a few 1e-6 of max |phi| (measured 1.1e-6); at the
+    # benchmark's tolerance the residual bound leaves 3.8e-5 (measured)
+    assert e2 < 1e-5
+    assert e1 < 1e-3
     emg.close()
     s.close()
 

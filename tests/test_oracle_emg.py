@@ -126,3 +126,23 @@ def test_fiber_aligned_linear_potential_gives_the_bidomain_ratio():
     # a constant V_m drives no current
     phi0, b0 = E.solve(g, np.full(g.n, -75.0), s_i, s_el, s_et)
     assert np.max(np.abs(b0)) < 1e-11 and np.max(np.abs(phi0)) < 1e-11
+
+
+@pytest.mark.parametrize("nx,ny,nz,hz", [(5, 4, 31, 0.1), (3, 7, 121, 0.01), (6, 6, 9, 0.25)])
+def test_cg_route_equals_the_direct_solve(nx, ny, nz, hz):
+    """The FP64 conjugate-gradient route (for meshes too large for the
+    bordered LU) returns the direct solve's zero-mean solution, and its
+    residual, computed here from the matrices, is at the requested level."""
+    g = E.Grid(nx, ny, nz, 0.05, 0.07, hz)
+    rng = np.random.default_rng(nx * ny * nz)
+    z = np.arange(nz) * hz
+    V3 = np.tile(-75.0 + 100.0 * np.exp(-((z - z.mean()) / (3 * hz)) ** 2), nx * ny)
+    V3 = V3.reshape(nx * ny, nz).T.ravel() + rng.uniform(-1.0, 1.0, g.n)
+    pd, b = E.solve(g, V3, 8.93, 6.7, 3.35)
+    pc, b2 = E.solve(g, V3, 8.93, 6.7, 3.35, method="cg")
+    np.testing.assert_array_equal(b, b2)
+    assert np.max(np.abs(pc - pd)) <= 1e-9 * np.max(np.abs(pd))
+    Kt = E.stiffness_3d(g, (3.35, 3.35, 6.7 + 8.93))
+    bz = b - b.mean()
+    assert np.linalg.norm(Kt @ pc - bz) <= 1e-12 * np.linalg.norm(bz)
+    assert abs(pc.mean()) < 1e-12 * np.max(np.abs(pc))
