@@ -1218,6 +1218,10 @@ int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, vo
   if ((rc = fib_rest_state(p, c->rest))) return bail(rc);
   if ((rc = make_plan(c))) return bail(rc);
   if ((rc = check_levels_fit(c, c->levels))) return bail(rc);
+  if (fib::diffusion_lds_bytes(c->threads, c->levels, c->cap, c->max_ents) > c->max_lds)
+    return bail(fail(FIB_EUNSUPPORTED,
+                     "a bin of %d fibers needs more LDS for the diffusion than the device offers",
+                     c->max_ents - 1));
 
   const size_t nt = (size_t)std::max<int64_t>(total, 1);
   if (hipMalloc(&c->d_state, sizeof(float) * nt * c->S) != hipSuccess ||

@@ -221,15 +221,17 @@ inline size_t lds_bytes_for(int threads, int levels) {
   return sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
 }
 
-// LDS of the split-schedule diffusion: a region that holds first the
-// staged V of every slot (cap floats) and the coupling bits of every slot
-// (cap bytes), then the Crank-Nicolson solve's arrays; after it two
-// buffers of bin entries (starts, first nodes, fibers: 3 max_ents ints
-// each).
+// LDS of the split-schedule diffusion: the staged V of every slot (cap
+// floats) and its coupling bits (cap bytes), then the solve's arrays (the
+// separate setup and solve's 6 + 2L floats per thread, or the merged
+// single-substep solve's 12), then two buffers of bin entries (starts,
+// first nodes, fibers: 3 max_ents ints each).
+__host__ __device__ inline size_t diffusion_stage_part(int cap) {
+  return (5 * (size_t)cap + 15) & ~(size_t)15;
+}
 __host__ __device__ inline size_t diffusion_region_bytes(int threads, int levels, int cap) {
-  const size_t cn = sizeof(float) * (size_t)threads * (size_t)(6 + 2 * levels);
-  const size_t st = 5 * (size_t)cap;
-  return ((cn > st ? cn : st) + 15) & ~(size_t)15;
+  const size_t per = (size_t)(6 + 2 * levels) > 12 ? (size_t)(6 + 2 * levels) : 12;
+  return diffusion_stage_part(cap) + sizeof(float) * (size_t)threads * per;
 }
 inline size_t diffusion_lds_bytes(int threads, int levels, int cap, int max_ents) {
   return diffusion_region_bytes(threads, levels, cap) + 24 * (size_t)max_ents;

@@ -238,6 +238,101 @@ __device__ __forceinline__ void cn_solve(float (&V)[K], uint32_t lr, float r,
   V[K - 1] += z;
 }
 
+// One Crank-Nicolson substep with the elimination factors formed on the way,
+// for launches with a single substep: the arithmetic of cn_setup followed by
+// one cn_solve, operation for operation, with the exchanges of the two
+// merged, so a bin needs 3 + L barriers instead of 8 + 2L.  vl and vr are
+// the values of the slots left of the thread's first and right of its last
+// (0 at the bin's ends, where the weights are zero); X3 (3T floats), P (8T,
+// two buffers of four coefficients per thread, alternating by PCR level)
+// and Z (T) are LDS arrays that nothing else uses during the call.
+template <int K>
+__device__ __forceinline__ void cn_merged(float (&V)[K], float vl, float vr, uint32_t lr,
+                                          float r, float rhs, uint32_t live, float* X3,
+                                          float* P, float* Z, int T, int t, int levels) {
+  float a[K], c[K], d[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    float wl, wr;
+    row_weights(lr >> (2 * q), r, wl, wr);
+    a[q] = -wl;
+    c[q] = -wr;
+    d[q] = 1.0f + wl + wr;
+  }
+  float inv[K - 1], ainv[K - 1], cp[K - 1], v[K - 1], w[K - 1];
+#pragma unroll
+  for (int q = 0; q < K - 1; ++q) {
+    const float den = (q == 0) ? d[0] : fmaf(-a[q], cp[q - 1 < 0 ? 0 : q - 1], d[q]);
+    inv[q] = __builtin_amdgcn_rcpf(den);
+    ainv[q] = a[q] * inv[q];
+    cp[q] = c[q] * inv[q];
+    v[q] = (q == 0) ? -a[0] * inv[0] : -ainv[q] * v[q - 1 < 0 ? 0 : q - 1];
+  }
+  w[K - 2] = cp[K - 2] * -1.0f;
+#pragma unroll
+  for (int q = K - 3; q >= 0; --q) {
+    v[q] = fmaf(-cp[q], v[q + 1], v[q]);
+    w[q] = -cp[q] * w[q + 1];
+  }
+  // right-hand side dt L V in increment form and the interior solve
+  float b[K];
+#pragma unroll
+  for (int q = 0; q < K; ++q) {
+    const float l = (q == 0) ? vl : V[q == 0 ? 0 : q - 1];
+    const float rr = (q == K - 1) ? vr : V[q == K - 1 ? K - 1 : q + 1];
+    float wl, wr;
+    row_weights(lr >> (2 * q), r, wl, wr);
+    b[q] = rhs * fmaf(wl, l - V[q], wr * (rr - V[q]));
+    if (!((live >> q) & 1u)) b[q] = 0.0f;
+  }
+  float y[K - 1];
+  y[0] = b[0] * inv[0];
+#pragma unroll
+  for (int q = 1; q < K - 1; ++q) y[q] = fmaf(-ainv[q], y[q - 1], b[q] * inv[q]);
+#pragma unroll
+  for (int q = K - 3; q >= 0; --q) y[q] = fmaf(-cp[q], y[q + 1], y[q]);
+  // the next thread's responses and interior value give the reduced row
+  X3[t] = v[0];
+  X3[T + t] = w[0];
+  X3[2 * T + t] = y[0];
+  __syncthreads();
+  const float vn = (t + 1 < T) ? X3[t + 1] : 0.0f;
+  const float wn = (t + 1 < T) ? X3[T + t + 1] : 0.0f;
+  const float yn = (t + 1 < T) ? X3[2 * T + t + 1] : 0.0f;
+  const float ae = a[K - 1], ce = c[K - 1];
+  float Ra = ae * v[K - 2];
+  float Rd = d[K - 1] + ae * w[K - 2] + ce * vn;
+  float Rc = ce * wn;
+  float rb = fmaf(-ae, y[K - 2], fmaf(-ce, yn, b[K - 1]));
+  for (int l = 0; l < levels; ++l) {
+    const int sh = 1 << l;
+    float* buf = P + (l & 1) * 4 * T;
+    buf[t] = Ra;
+    buf[T + t] = Rd;
+    buf[2 * T + t] = Rc;
+    buf[3 * T + t] = rb;
+    __syncthreads();
+    const bool hl = t - sh >= 0, hr = t + sh < T;
+    const float ra_l = hl ? buf[t - sh] : 0.0f, rd_l = hl ? buf[T + t - sh] : 1.0f,
+                rc_l = hl ? buf[2 * T + t - sh] : 0.0f, rb_l = hl ? buf[3 * T + t - sh] : 0.0f;
+    const float ra_r = hr ? buf[t + sh] : 0.0f, rd_r = hr ? buf[T + t + sh] : 1.0f,
+                rc_r = hr ? buf[2 * T + t + sh] : 0.0f, rb_r = hr ? buf[3 * T + t + sh] : 0.0f;
+    const float al = -Ra * __builtin_amdgcn_rcpf(rd_l);
+    const float ga = -Rc * __builtin_amdgcn_rcpf(rd_r);
+    Rd = Rd + al * rc_l + ga * ra_r;
+    Ra = al * ra_l;
+    Rc = ga * rc_r;
+    rb = fmaf(al, rb_l, fmaf(ga, rb_r, rb));
+  }
+  const float z = rb * __builtin_amdgcn_rcpf(Rd);
+  Z[t] = z;
+  __syncthreads();
+  const float zl = (t > 0) ? Z[t - 1] : 0.0f;
+#pragma unroll
+  for (int q = 0; q < K - 1; ++q) V[q] += fmaf(v[q], zl, fmaf(w[q], z, y[q]));
+  V[K - 1] += z;
+}
+
 // ---------------------------------------------------------------------------
 // Fused persistent kernel, Hodgkin-Huxley
 // ---------------------------------------------------------------------------
@@ -748,7 +843,7 @@ __device__ __forceinline__ void bin_fetch(const KArgs& A, const int32_t* buf, in
 // Per bin, V is staged through LDS from the coalesced slot order t + i T to
 // the thread-contiguous order t K + q the partitioned solve works in, and
 // back for the coalesced stores.
-template <int K, int MAXT>
+template <int K, int MAXT, bool ONE>
 __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
   extern __shared__ float lds[];
   const int T = blockDim.x;
@@ -758,6 +853,7 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
   const int me = A.max_ents;
   float* sV = lds;                                // staged V of every slot
   uint8_t* sInf = (uint8_t*)(lds + cap);          // SLOT_L | SLOT_R | live << 2
+  float* cn = (float*)((char*)lds + diffusion_stage_part(cap));  // the solve's arrays
   int32_t* eb0 = (int32_t*)((char*)lds + diffusion_region_bytes(T, A.pcr_levels, cap));
   int32_t* eb1 = eb0 + 3 * me;
   int b = blockIdx.x;
@@ -794,6 +890,8 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
     float V[K];
     uint32_t lr = 0u;    // coupling bits, two per slot
     uint32_t live = 0u;  // slots whose fiber takes part
+    const float vl = t > 0 ? sV[t * K - 1] : 0.0f;
+    const float vr = t + 1 < T ? sV[t * K + K] : 0.0f;
 #pragma unroll
     for (int q = 0; q < K; ++q) {
       const int s = t * K + q;
@@ -810,7 +908,6 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
         live |= ((bq >> 2) & 1u) << q;
       }
     }
-    __syncthreads();  // the Crank-Nicolson arrays overlay the staging
     // the next bin's V and the entries of the one after it
     const int bn = b + G, bnn = b + 2 * G;
     if (bn < A.n_bins) bin_fetch<K>(A, nxt, ne_n, T, t, vn, live_n);
@@ -825,11 +922,17 @@ __global__ __launch_bounds__(MAXT) void k_diffusion(KArgs A) {
         r_f = A.ent_fiber[e0nn + t];
       }
     }
-    CNConst<K> cc;
-    cn_setup<K>(cc, lr, A.r_mat, lds, T, t, A.pcr_levels);
-    for (int c = 0; c < A.n_cn; ++c)
-      cn_solve<K>(V, lr, A.r_mat, A.rhs, cc, lds, T, t, A.pcr_levels, live);
-    __syncthreads();
+    if constexpr (ONE) {  // launched for exactly one substep
+      cn_merged<K>(V, vl, vr, lr, A.r_mat, A.rhs, live, cn, cn + 3 * T, cn + 11 * T, T, t,
+                   A.pcr_levels);
+    } else {
+      CNConst<K> cc;
+      cn_setup<K>(cc, lr, A.r_mat, cn, T, t, A.pcr_levels);
+      for (int c = 0; c < A.n_cn; ++c)
+        cn_solve<K>(V, lr, A.r_mat, A.rhs, cc, cn, T, t, A.pcr_levels, live);
+    }
+    // every read of the staged V (own slots, neighbours) came before the
+    // solve's first barrier
 #pragma unroll
     for (int q = 0; q < K; ++q) sV[t * K + q] = V[q];
     __syncthreads();
@@ -1345,11 +1448,11 @@ struct FusedAdaptLaunch {
 template <class Kern>
 static int resident_blocks(Kern kern, int threads, size_t lds) {
   static std::mutex mu;
-  static std::map<std::tuple<int, int, size_t>, int> cache;
+  static std::map<std::tuple<int, const void*, int, size_t>, int> cache;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   std::lock_guard<std::mutex> lock(mu);
-  const auto key = std::make_tuple(dev, threads, lds);
+  const auto key = std::make_tuple(dev, reinterpret_cast<const void*>(kern), threads, lds);
   auto it = cache.find(key);
   if (it != cache.end()) return it->second;
   int cus = 0, per_cu = 0;
@@ -1363,9 +1466,15 @@ static int resident_blocks(Kern kern, int threads, size_t lds) {
 template <int K, int MAXT>
 struct DiffusionLaunch {
   static hipError_t go(int groups, int threads, size_t lds, const KArgs& a, hipStream_t s) {
-    const int res = resident_blocks(k_diffusion<K, MAXT>, threads, lds);
-    const int grid = res > 0 ? std::min(groups, res) : groups;
-    hipLaunchKernelGGL((k_diffusion<K, MAXT>), dim3(grid), dim3(threads), lds, s, a);
+    if (a.n_cn == 1) {
+      const int res = resident_blocks(k_diffusion<K, MAXT, true>, threads, lds);
+      const int grid = res > 0 ? std::min(groups, res) : groups;
+      hipLaunchKernelGGL((k_diffusion<K, MAXT, true>), dim3(grid), dim3(threads), lds, s, a);
+    } else {
+      const int res = resident_blocks(k_diffusion<K, MAXT, false>, threads, lds);
+      const int grid = res > 0 ? std::min(groups, res) : groups;
+      hipLaunchKernelGGL((k_diffusion<K, MAXT, false>), dim3(grid), dim3(threads), lds, s, a);
+    }
     return hipGetLastError();
   }
 };
