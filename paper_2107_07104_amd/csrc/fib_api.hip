@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -262,6 +263,10 @@ struct fib_ctx {
   // fiber entries of the bins (KArgs::bin_ent and following)
   std::vector<int32_t> bin_ent, ent_s0, ent_gofs, ent_fiber;
   int32_t max_ents = 1;
+  // PCR levels of fib_step_diffusion's last span (for the plan version)
+  uint64_t lv_cache_version = ~0ull;
+  double lv_cache_r = -1.0;
+  int lv_cache_levels = 0;
 
   // device buffers
   float* d_state = nullptr;
@@ -423,8 +428,10 @@ int pcr_levels_needed(const fib_ctx* c, int bin, double r, bool full) {
   const int full_levels = (int)std::ceil(std::log2((double)T) - 1e-12);
   if (full) return full_levels;
   std::vector<double> Ra(T), Rd(T), Rc(T), v0(T), w0(T), vL(T), wL(T), ae(T), ce(T), de(T);
+  constexpr int KM = 16;  // nodes per thread of any built shape (at most 14)
+  if (K > KM) return full_levels;
   for (int t = 0; t < T; ++t) {
-    std::vector<double> a(K), cc(K), d(K);
+    double a[KM], cc[KM], d[KM];
     for (int q = 0; q < K; ++q) {
       const uint32_t info = c->slot_base[(size_t)bin * c->cap + (size_t)t * K + q];
       const bool L = info & fib::SLOT_L, R = info & fib::SLOT_R;
@@ -435,7 +442,7 @@ int pcr_levels_needed(const fib_ctx* c, int bin, double r, bool full) {
     }
     // interior responses to z_{t-1} (v) and z_t (w) by dense elimination
     const int m = K - 1;
-    std::vector<double> inv(m), cp(m), vp(m), v(m), w(m);
+    double inv[KM], cp[KM], vp[KM], v[KM], w[KM];
     for (int q = 0; q < m; ++q) {
       const double den = q == 0 ? d[0] : d[q] - a[q] * cp[q - 1];
       inv[q] = 1.0 / den;
@@ -487,6 +494,24 @@ int pcr_levels_needed(const fib_ctx* c, int bin, double r, bool full) {
     ++l;
   }
   return l;
+}
+
+// The most PCR levels any bin needs for row weight r.  Bins with the same
+// sequence of fiber lengths have the same matrix, so each distinct sequence
+// is evaluated once.
+int max_pcr_levels(const fib_ctx* c, double r) {
+  std::map<std::vector<int32_t>, int> seen;
+  int lv = 0;
+  for (int b = 0; b < c->groups; ++b) {
+    std::vector<int32_t> key;
+    key.reserve(c->bin_fibers[b].size());
+    for (int32_t f : c->bin_fibers[b]) key.push_back(c->n_nodes[f]);
+    auto it = seen.find(key);
+    if (it == seen.end())
+      it = seen.emplace(std::move(key), pcr_levels_needed(c, b, r, c->p.pcr_full != 0)).first;
+    lv = std::max(lv, it->second);
+  }
+  return lv;
 }
 
 double cn_r(const fib_ctx* c, double dt_cn) {
@@ -549,10 +574,7 @@ void build_tables(fib_ctx* c) {
   // PCR levels for the matrix of the split step's diffusion substep
   const int64_t n_cn = ceil_steps(c->p.dt_split, c->p.dt_1D);
   const double r = 2.0 * theta_of(c->p) * cn_r(c, c->p.dt_split / (double)n_cn);
-  int lv = 0;
-  for (int b = 0; b < c->groups; ++b)
-    lv = std::max(lv, pcr_levels_needed(c, b, r, c->p.pcr_full != 0));
-  c->levels = lv;
+  c->levels = max_pcr_levels(c, r);
 }
 
 int64_t max_bin_load(const fib_ctx* c) {
@@ -1466,9 +1488,12 @@ int fib_step_diffusion(fib_t* c, double span) {
   a.n_cn = (int32_t)m;
   set_diffusion(c, span / (double)m, a);
   const double r_mat = 2.0 * theta_of(c->p) * cn_r(c, span / (double)m);
-  int lv = 0;
-  for (int b = 0; b < c->groups; ++b)
-    lv = std::max(lv, pcr_levels_needed(c, b, r_mat, c->p.pcr_full != 0));
+  if (c->lv_cache_version != c->plan_version || c->lv_cache_r != r_mat) {
+    c->lv_cache_levels = max_pcr_levels(c, r_mat);
+    c->lv_cache_r = r_mat;
+    c->lv_cache_version = c->plan_version;
+  }
+  const int lv = c->lv_cache_levels;
   if (int rc = check_levels_fit(c, lv)) return rc;
   a.pcr_levels = lv;
   KT_LAUNCH(c, FIB_KT_DIFFUSION,
