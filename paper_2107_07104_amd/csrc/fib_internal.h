@@ -29,6 +29,12 @@ constexpr int SLOT_STIM_SHIFT = 3;
 
 constexpr int MAX_STATES = 64;
 
+// FP32 in global memory.  Kernels that hide a pointer from the optimizer
+// (an empty asm with the pointer as operand) type it this way: through a
+// generic pointer the accesses compile to flat instructions, which also
+// count against the LDS wait counter.
+typedef __attribute__((address_space(1))) float gfloat;
+
 // Point flags of the adaptive computation, one byte per node and step:
 //   PT_SOLVE:  the node is solved in this step (set by the start kernel,
 //              consumed by the finish kernel of a Strang step);

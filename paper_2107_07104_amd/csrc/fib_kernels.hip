@@ -450,11 +450,14 @@ __global__ __launch_bounds__(MAXT) void k_run_hh(KArgs A) {
 template <int S>
 __device__ __forceinline__ bool state_moved(const float (&u)[S], const float* col, int64_t stride,
                                             const float* rest, float tol) {
-  __asm__("" : "+v"(col));  // a new read, not the registers of the first one
+  // a new read, not the registers of the first one; typed global so that
+  // the loads do not compile to flat instructions
+  gfloat* g = (gfloat*)const_cast<float*>(col);
+  __asm__("" : "+v"(g));
   bool m = false;
 #pragma unroll
   for (int k = 0; k < S; ++k) {
-    const float b = col[k * stride];
+    const float b = g[k * stride];
     m |= fabsf(u[k] - b) > tol * fabsf(b + rest[k]);
   }
   return m;

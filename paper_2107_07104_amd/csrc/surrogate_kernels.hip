@@ -169,10 +169,16 @@ struct SurST57 {
 // Walks the S columns of the state array at one node: the column stride
 // n_total is added to a pointer held in a vector register and hidden from
 // the optimizer, which would otherwise keep all S 64-bit column offsets in
-// scalar registers across the persistent loop (hundreds for ST57).
+// scalar registers across the persistent loop (hundreds for ST57).  The
+// pointer is typed global (address space 1): through a generic pointer the
+// accesses compile to flat instructions, which also count against the LDS
+// wait counter, so LDS waits would wait for outstanding state loads and
+// stores as well (3-4 % of the ST57 step).
 struct Column {
-  const float* p;
+  gfloat* p;
   int64_t stride;
+  __device__ __forceinline__ Column(const float* q, int64_t s)
+      : p((gfloat*)const_cast<float*>(q)), stride(s) {}
   __device__ __forceinline__ void next() {
     p += stride;
     __asm__("" : "+v"(p));
@@ -386,7 +392,12 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
       }
     }
     __builtin_amdgcn_wave_barrier();
+    // the matrix-core phase at raised issue priority: with two waves per
+    // SIMD, the other wave's vector work then fills the gaps of this one's
+    // matrix-core chain instead of delaying it (2-3 % of the ST57 step)
+    __builtin_amdgcn_s_setprio(1);
     wave_network<KIN_PAD, H, NHID, OUT_PAD, ACT, NG>(stage, wfr, wb, net, lane);
+    __builtin_amdgcn_s_setprio(0);
     // this lane's network outputs, four FP16 values per LDS read
     const v4h* O4 = reinterpret_cast<const v4h*>(reinterpret_cast<const _Float16*>(stage) + lane * St::OS);
     auto out = [&](int k) { return (float)O4[k >> 2][k & 3]; };
@@ -397,7 +408,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
 #pragma unroll
         for (int k = 0; k < S; ++k) {
           const float4 t = tchk[k];
-          const_cast<float*>(col.p)[0] = fmaf(out(k), t.x, t.y);
+          col.p[0] = fmaf(out(k), t.x, t.y);
           col.next();
         }
       }
@@ -437,7 +448,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         Column col{A.state + i, nt};
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-          const_cast<float*>(col.p)[0] = fmaf(span, G[k], u[k]);
+          col.p[0] = fmaf(span, G[k], u[k]);
           col.next();
         }
       }
