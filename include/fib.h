@@ -122,6 +122,10 @@ typedef struct {
                                 fiber bins, i.e. workgroups of the fused kernel */
   int32_t splitting;         /* FIB_SPLIT_* (0: Strang) */
   int32_t time_1d;           /* FIB_1D_* (0: Crank-Nicolson) */
+  int32_t tune;              /* 0: keep the plan; 1: the first fib_run that advances any
+                                step first runs fib_autotune (100 trial steps, 8
+                                candidates) from the state it is given, which the
+                                autotuner restores, then runs on the chosen plan */
 } fib_params;
 
 /* One stimulus entry on nodes node-half_width .. node+half_width of fiber

@@ -282,6 +282,7 @@ struct fib_ctx {
   int32_t n_stim = 0;
   std::vector<int32_t> node_stim;      // host copy: stimulus entry + 1 per node (0: none)
   bool state_ready = false;
+  bool tune_pending = false;  // fib_params.tune: autotune before the first run
 
   // surrogate
   bool sur_on = false;
@@ -1154,6 +1155,7 @@ int fib_check_params(const fib_params* p) {
     return fail(FIB_EINVAL, "unknown splitting %d", p->splitting);
   if (p->time_1d != FIB_1D_CRANK_NICOLSON && p->time_1d != FIB_1D_IMPLICIT_EULER)
     return fail(FIB_EINVAL, "unknown 1D time stepping %d", p->time_1d);
+  if (p->tune != 0 && p->tune != 1) return fail(FIB_EINVAL, "tune must be 0 or 1");
   if (ceil_steps(p->dt_split, p->dt_0D) > (1 << 20) || ceil_steps(p->dt_split, p->dt_1D) > (1 << 20))
     return fail(FIB_EINVAL, "more than 2^20 substeps per split step");
   return FIB_OK;
@@ -1219,6 +1221,7 @@ int fib_create(const fib_params* p, int32_t n_fibers, const int32_t* n_nodes, vo
   fib_ctx* c = new (std::nothrow) fib_ctx();
   if (!c) return fail(FIB_ENOMEM, "host allocation failed");
   c->p = *p;
+  c->tune_pending = p->tune != 0;
   c->S = n_states_of(p->model);
   c->n_fibers = n_fibers;
   c->n_nodes.assign(n_nodes, n_nodes + n_fibers);
@@ -1511,6 +1514,10 @@ int fib_run(fib_t* c, int64_t step0, int64_t n_steps, int64_t sample_every, floa
   if (sample_every < 0) return fail(FIB_EINVAL, "sample_every must be >= 0");
   if (!c->state_ready) return fail(FIB_ESTATE, "state not initialized");
   if (n_steps == 0 || c->n_total == 0) return FIB_OK;
+  if (c->tune_pending) {
+    c->tune_pending = false;  // first: the autotuner's trials run fib_run themselves
+    if (int rc = fib_autotune(c, 100, 8, nullptr)) return rc;
+  }
   KArgs a = base_args(c);
   if (samples && sample_every > 0) {
     const int64_t rows = (step0 + n_steps) / sample_every - step0 / sample_every;

@@ -84,7 +84,8 @@ class fib_params(C.Structure):
                 ("dt_0D", C.c_double), ("dt_1D", C.c_double), ("dt_split", C.c_double),
                 ("v_th", C.c_double), ("pcr_full", C.c_int32),
                 ("threads_per_group", C.c_int32), ("nodes_per_thread", C.c_int32),
-                ("groups", C.c_int32), ("splitting", C.c_int32), ("time_1d", C.c_int32)]
+                ("groups", C.c_int32), ("splitting", C.c_int32), ("time_1d", C.c_int32),
+                ("tune", C.c_int32)]
 
 
 class fib_stim(C.Structure):
@@ -203,10 +204,10 @@ def _check(rc):
 def make_params(model=FIB_MODEL_HH, schedule=FIB_SCHED_AUTO, Cm=1.0, Am=500.0, sigma=3.828,
                 h=0.01, dt_0D=1e-3, dt_1D=1e-3, dt_split=1e-3, v_th=-20.0, pcr_full=0,
                 threads_per_group=0, nodes_per_thread=0, groups=0, splitting=0,
-                time_1d=0) -> fib_params:
+                time_1d=0, tune=0) -> fib_params:
     return fib_params(model, schedule, Cm, Am, sigma, h, dt_0D, dt_1D, dt_split, v_th,
                       pcr_full, threads_per_group, nodes_per_thread, groups, splitting,
-                      time_1d)
+                      time_1d, tune)
 
 
 def _stim_array(stims):

@@ -209,6 +209,28 @@ def test_autotune_restores_the_state_and_keeps_parity():
     s.close()
 
 
+def test_tune_parameter_autotunes_before_the_first_run():
+    """fib_params.tune = 1: the first fib_run tunes the workgroup shape from
+    the state it is given, which the autotuner restores, then runs its steps
+    from that state on the chosen plan.  Its results equal, bit for bit,
+    those of an untuned context created with that plan, and keep parity
+    with the oracle."""
+    w = I.batched_hh(n_fibers=24, t_end=4.0)
+    say("[tune parameter]")
+    gpu = gpu_run(w, tune=1)
+    plan = gpu[3].plan()
+    say("  chosen", plan)
+    ref = gpu_run(w, threads_per_group=plan["threads"], nodes_per_thread=plan["nodes_per_thread"],
+                  groups=plan["groups"])
+    assert ref[3].plan() == plan
+    for a, b in zip(gpu[:3], ref[:3]):
+        np.testing.assert_array_equal(a, b)
+    res = compare_runs(w, gpu, oracle_run(w))
+    _assert_parity(w, res, w.n_steps * w.dt_split)
+    gpu[3].close()
+    ref[3].close()
+
+
 def test_ragged_and_degenerate_fibers_run():
     # fibers of 1..9 nodes mixed with long ones, several per bin
     n = np.array([1, 2, 3, 1500, 4, 5, 6, 7, 8, 9, 1, 1, 250], dtype=np.int32)

@@ -41,7 +41,7 @@ def test_n_states():
     ("dt_1D", float("inf")), ("dt_split", -1e-3), ("v_th", float("nan")),
     ("threads_per_group", 96), ("threads_per_group", 2048), ("nodes_per_thread", 1),
     ("nodes_per_thread", 15), ("groups", -1), ("model", 7), ("model", 4), ("schedule", 3),
-    ("splitting", 2), ("time_1d", 2), ("time_1d", -1)])
+    ("splitting", 2), ("time_1d", 2), ("time_1d", -1), ("tune", 2), ("tune", -1)])
 def test_check_params_rejects(field, value):
     p = F.make_params()
     setattr(p, field, value)
@@ -54,6 +54,7 @@ def test_check_params_accepts_defaults():
     for split in (F.FIB_SPLIT_STRANG, F.FIB_SPLIT_GODUNOV):
         for t1 in (F.FIB_1D_CRANK_NICOLSON, F.FIB_1D_IMPLICIT_EULER):
             assert F.fib_check_params(F.make_params(splitting=split, time_1d=t1)) == F.FIB_OK
+    assert F.fib_check_params(F.make_params(tune=1)) == F.FIB_OK
 
 
 def test_implicit_euler_matrix_couples_more_strongly():
