@@ -1073,9 +1073,9 @@ __global__ __launch_bounds__(256) void k_react(KArgs A, int32_t step_a, int32_t 
 
 // The same phases over a grid that fits on the device at once: a thread
 // takes nodes i, i + stride, ... and loads the next node's states before it
-// solves the current one.  A model whose right-hand side holds a wave at
-// one per SIMD (ST57) has no other wave there to cover the loads; this way
-// they run under the wave's own arithmetic.  Loads return in issue order,
+// solves the current one.  A model whose right-hand side holds few waves
+// per SIMD (ST57: two, at 242 VGPRs) has little else there to cover the
+// loads; this way they run under the wave's own arithmetic.  Loads return in issue order,
 // so everything the current node reads (stimulus entry, v_prev, t_act) is
 // read before the next node's loads are issued: waiting for it then does
 // not wait for them.
