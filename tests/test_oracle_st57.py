@@ -12,7 +12,15 @@ against properties its written specification fixes:
     P_{i+1}/P_i = k_f,i/k_b,i = exp(2 (V_t - V_i) / 25);
   * the model is second order in time under Strang splitting, fires and
     propagates an action potential of the Hodgkin-Huxley shape, and keeps
-    concentrations and probabilities non-negative.
+    concentrations and probabilities non-negative;
+  * every kinetic block (sensor chain, pump cycle, thin-filament chain,
+    cross-bridge cycle) is first order in its own states, so the block's
+    Jacobian is its kinetic generator: its off-diagonal entries are
+    non-zero exactly on the edges the specification draws (chain or cycle,
+    both directions), and positive there, and its columns sum to zero; the
+    thin-filament chain's links share one forward and one backward rate.
+    A mis-indexed, mis-signed or dropped transition in a block fails this
+    without the test restating any rate formula.
 """
 import numpy as np
 import pytest
@@ -82,3 +90,62 @@ def test_time_order_and_action_potential(rest):
     errs = np.array([np.max(np.abs(solve(dt)[0] - ref[0])) for dt in (2e-3, 1e-3, 5e-4)])
     order = np.log2(errs[:-1] / errs[1:])
     assert np.all(np.abs(order - 2.0) < 0.2), order
+
+
+def _block_generator(y, lo, n):
+    """d G[lo:lo+n] / d y[lo:lo+n] by central differences (exact up to
+    rounding for a block that is first order in its own states)."""
+    J = np.zeros((n, n))
+    for c in range(n):
+        h = 1e-3
+        yp, ym = y.copy(), y.copy()
+        yp[lo + c] += h
+        ym[lo + c] -= h
+        J[:, c] = (O.st57_rhs(yp)[lo:lo + n] - O.st57_rhs(ym)[lo:lo + n]) / (2 * h)
+    return J
+
+
+def _chain(n):
+    return {(i, i + 1) for i in range(n - 1)} | {(i + 1, i) for i in range(n - 1)}
+
+
+def _cycle(n):
+    return _chain(n) | {(n - 1, 0), (0, n - 1)}
+
+
+@pytest.mark.parametrize("name,lo,n,edges", [
+    ("sensor chain P", 8, 10, _chain(10)),
+    ("pump cycle Q", 35, 4, _cycle(4)),
+    ("thin-filament chain R", 39, 8, _chain(8)),
+    ("cross-bridge cycle X", 47, 8, _cycle(8))])
+def test_kinetic_blocks_have_the_specified_generators(rest, name, lo, n, edges):
+    # a state away from rest, so that every rate takes a generic value
+    rng = np.random.default_rng(7)
+    y = rest * (1.0 + 0.2 * rng.random(57))
+    y[4] = -35.0                      # tubular voltage: sensor rates far from rest's
+    y[21] = 90.0                      # b_T: thin-filament activation theta = 0.64
+    y[46] = 0.2                       # R_7: the cross-bridge attachment rate
+    for x0, x1 in ((8, 18), (35, 39), (39, 47), (47, 55)):
+        y[x0:x1] /= y[x0:x1].sum()    # each chain a distribution again
+    J = _block_generator(y, lo, n)
+    scale = np.max(np.abs(J))
+    # A non-linear term in the block would make the generator depend on the
+    # point: the same generator at a second point of the block.
+    y2 = y.copy()
+    y2[lo:lo + n] = rng.random(n)
+    np.testing.assert_allclose(_block_generator(y2, lo, n), J, rtol=1e-6, atol=1e-9 * scale)
+    for i in range(n):
+        for j in range(n):
+            if i == j:
+                continue
+            if (j, i) in edges:       # transition j -> i feeds state i
+                assert J[i, j] > 1e-6 * scale, (name, j, i, J[i, j])
+            else:
+                assert abs(J[i, j]) <= 1e-9 * scale, (name, j, i, J[i, j])
+    assert np.all(np.diag(J) < 0)
+    np.testing.assert_allclose(J.sum(axis=0), 0.0, atol=1e-9 * scale)
+    if name.startswith("thin"):
+        fwd = np.array([J[i + 1, i] for i in range(n - 1)])
+        bwd = np.array([J[i, i + 1] for i in range(n - 1)])
+        np.testing.assert_allclose(fwd, fwd[0], rtol=1e-7)
+        np.testing.assert_allclose(bwd, bwd[0], rtol=1e-7)
