@@ -20,7 +20,10 @@ against properties its written specification fixes:
     both directions), and positive there, and its columns sum to zero; the
     thin-filament chain's links share one forward and one backward rate.
     A mis-indexed, mis-signed or dropped transition in a block fails this
-    without the test restating any rate formula.
+    without the test restating any rate formula;
+  * the signs and zeros of Jacobian entries that the modelled processes fix
+    (which way a flux moves a state, which states an equation involves),
+    and the SR uptake's Hill coefficient of 2 from its low-calcium slope.
 """
 import numpy as np
 import pytest
@@ -149,3 +152,80 @@ def test_kinetic_blocks_have_the_specified_generators(rest, name, lo, n, edges):
         bwd = np.array([J[i, i + 1] for i in range(n - 1)])
         np.testing.assert_allclose(fwd, fwd[0], rtol=1e-7)
         np.testing.assert_allclose(bwd, bwd[0], rtol=1e-7)
+
+
+def _jacobian_entries(y, pairs):
+    """dG_i / dy_j by central differences for (i, j) in pairs."""
+    out = {}
+    for j in sorted({j for _, j in pairs}):
+        h = 1e-4 * max(1.0, abs(y[j]))
+        yp, ym = y.copy(), y.copy()
+        yp[j] += h
+        ym[j] -= h
+        g = (O.st57_rhs(yp) - O.st57_rhs(ym)) / (2 * h)
+        for i, jj in pairs:
+            if jj == j:
+                out[(i, j)] = g[i]
+    return out
+
+
+# (derivative of state i, state j, sign) fixed by what the specification
+# models, not by its formulas: +1 the flux raises state i when state j
+# grows, -1 it lowers it, 0 state i's equation does not involve state j.
+_SIGNS = [
+    # electrical coupling of surface (0) and tubular (4) membranes
+    (0, 4, +1), (4, 0, +1),
+    # each membrane's currents use its own gates only
+    (0, 5, 0), (0, 6, 0), (0, 7, 0), (4, 1, 0), (4, 2, 0), (4, 3, 0),
+    # pump turnover (J_p grows with Q_1): outward pump current, Na out of
+    # the cell into the tubule, K from the tubule into the cell
+    (0, 36, -1), (29, 36, -1), (32, 36, +1), (30, 36, +1), (33, 36, -1),
+    # an outward chloride current carries Cl into the cell: the surface
+    # current with V, the tubular one with V_t takes Cl from the tubule
+    (31, 0, +1), (34, 4, -1),
+    # SR: uptake from the myoplasm, transfer network -> junctional SR,
+    # release through open channels (the junctional SR is loaded)
+    (19, 18, +1), (20, 19, +1), (19, 20, +1), (18, 17, +1), (20, 17, -1),
+    # unbinding from troponin, parvalbumin, ATP releases Ca; Mg likewise
+    (18, 21, +1), (18, 22, +1), (18, 24, +1), (26, 23, +1), (26, 25, +1),
+    # sensor chain: depolarization of the tubule moves sensors forward
+    (8, 4, -1),
+    # thin filament: Ca-bound troponin speeds activation
+    (39, 21, -1),
+    # cross-bridges: attachment driven by the last thin-filament state,
+    # detachment from the last cross-bridge state speeded by Mg-free ATP
+    (47, 46, -1), (48, 46, +1), (54, 25, -1), (47, 25, +1),
+    # force: the strongly bound states X_4..X_7 only; it shortens L_s
+    (56, 47, 0), (56, 48, 0), (56, 49, 0), (56, 50, 0),
+    (56, 51, +1), (56, 52, +1), (56, 53, +1), (56, 54, +1), (55, 54, -1),
+]
+
+
+def test_jacobian_signs_follow_what_the_model_describes(rest):
+    rng = np.random.default_rng(11)
+    y = rest * (1.0 + 0.1 * rng.random(57))
+    for x0, x1 in ((8, 18), (35, 39), (39, 47), (47, 55)):
+        y[x0:x1] /= y[x0:x1].sum()
+    J = _jacobian_entries(y, [(i, j) for i, j, _ in _SIGNS])
+    scale = {i: max(abs(v) for (ii, _), v in J.items() if ii == i) for i, _, _ in _SIGNS}
+    for i, j, sgn in _SIGNS:
+        v = J[(i, j)]
+        if sgn == 0:
+            # a state that does not enter an equation leaves it bit for bit
+            assert v == 0.0, (i, j, v)
+        else:
+            # well above the differences' rounding floor, with the sign
+            assert v * sgn > 1e-10 * scale[i], (i, j, v)
+
+
+def test_sr_uptake_is_cooperative_with_hill_coefficient_two(rest):
+    # the network SR gains Ca only through uptake from the myoplasm, so
+    # d(dc_s/dt)/dc_m is the uptake's slope, 8 c_m / (1 + c_m^2)^2 times a
+    # constant: proportional to c_m at small c_m for a Hill coefficient of 2
+    y = rest.copy()
+    slope = []
+    for c in (1e-3, 2e-3, 4e-3):
+        y[18] = c
+        J = _jacobian_entries(y, [(19, 18)])
+        slope.append(J[(19, 18)])
+    np.testing.assert_allclose(np.array(slope[1:]) / np.array(slope[:-1]), 2.0, rtol=2e-3)
