@@ -150,3 +150,16 @@ def test_fibers_are_independent():
     parts = np.concatenate([O.diffusion(cfg, [7], V[:7], 5e-3), V[7:8],
                             O.diffusion(cfg, [30], V[8:], 5e-3)])
     np.testing.assert_array_equal(whole, parts)
+
+
+def test_only_sigma_over_am_cm_enters_the_diffusion():
+    # eq. monodomain: the fiber operator is sigma / (Am Cm) times the second
+    # derivative, so doubling Cm or Am and halving sigma give the same step
+    from dataclasses import replace
+    rng = np.random.default_rng(8)
+    V = rng.uniform(-80, 20, 40)
+    base = _cfg(5e-3)
+    ref = O.diffusion(replace(base, sigma=base.sigma / 2), [40], V, 5e-3)
+    assert np.max(np.abs(ref - O.diffusion(base, [40], V, 5e-3))) > 1e-3  # sigma matters
+    for cfg in (replace(base, Cm=2 * base.Cm), replace(base, Am=2 * base.Am)):
+        np.testing.assert_allclose(O.diffusion(cfg, [40], V, 5e-3), ref, rtol=0, atol=1e-11)

@@ -201,3 +201,14 @@ def test_exp_star_membrane_fires_and_propagates():
     y, s, ta = O.run(cfg, w.n_nodes, y0, w.stims, w.n_steps, sample_every=w.sample_every)
     assert np.all(np.isfinite(ta))
     assert np.nanmax(s) > 20.0
+
+
+def test_capacitance_scales_only_the_voltage_equation():
+    # eq. subcellular_model_helper3: Cm dV/dt = -I_ion + I_stim; the gates'
+    # equations do not involve Cm
+    y = np.array([-40.0, 0.3, 0.4, 0.5])
+    for I in (0.0, 50.0):
+        g1, g2 = O.hh_rhs(y, I, Cm=1.0), O.hh_rhs(y, I, Cm=2.5)
+        assert g1[0] != 0.0
+        np.testing.assert_allclose(g2[0], g1[0] / 2.5, rtol=1e-15)
+        np.testing.assert_array_equal(g2[1:], g1[1:])
