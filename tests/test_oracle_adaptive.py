@@ -14,7 +14,10 @@ sec:adaptive_computation_for_fiber_based, figure state_chart).
   unchanged before that step and nothing of it is solved;
 * from an equilibrium start (no V_m noise, the premise of the scheme) with a
   small tolerance the adaptive run stays within 0.01 mV of the plain run
-  while solving a minority of the node-steps.
+  while solving a minority of the node-steps;
+* the equilibrium check is relative to each state: at a tolerance just
+  below or above the largest relative change of the step's last reaction
+  part (from the reaction alone) a node is solved again or not.
 """
 from dataclasses import replace
 
@@ -116,3 +119,30 @@ def test_equilibrium_start_stays_close_to_the_plain_run():
     assert fin.sum() > 300
     assert np.max(np.abs(ta[fin] - tp[fin])) < 0.1 * w.dt_split
     assert share < 0.5
+
+
+@pytest.mark.parametrize("scheme", [O.SCHEME_STRANG, O.SCHEME_GODUNOV])
+def test_the_equilibrium_check_is_relative_to_each_state(scheme):
+    """One node (no diffusion coupling), V_m 1 mV off rest, and a zero-
+    current entry on in step 0 only (so the fiber takes part from step 0).
+    The check compares the two ends of the step's last reaction part, which
+    the pinned reaction alone gives: with the tolerance just below the
+    largest relative change max_k |y+_k - y_k| / |y_k| the node is solved
+    again in step 1, just above it it is not."""
+    dt = 1e-3
+    cfg = O.Config(scheme=scheme, dt_0D=dt, dt_1D=dt, dt_split=dt)
+    y0 = O.rest_state()[:, None].copy()
+    y0[0] += 1.0
+    if scheme == O.SCHEME_STRANG:
+        y1 = O.reaction(cfg, y0, 0.5 * dt)       # first half; one node: no diffusion
+        y2 = O.reaction(cfg, y1, 0.5 * dt)
+    else:
+        y1, y2 = y0, O.reaction(cfg, y0, dt)
+    rel = np.abs(y2[:, 0] - y1[:, 0]) / np.abs(y1[:, 0])
+    # an absolute test |y+_k - y_k| > tol would keep the node active at both
+    # tolerances: V_m changes by more than the larger one
+    assert np.max(np.abs(y2[:, 0] - y1[:, 0])) > 1.01 * rel.max()
+    stims = [dict(fiber=0, node=0, half_width=0, step_on=0, n_steps=1, period=0, amp=0.0)]
+    for factor, solved in ((0.99, 2), (1.01, 1)):
+        *_, cnt = O.run_adaptive(cfg, [1], y0, stims, 2, tol=factor * rel.max())
+        assert cnt == solved, (factor, cnt)
