@@ -37,6 +37,19 @@ def test_taylor_pieces_exact_at_expansion_points():
     assert O.log_star(1.0) == 0.0
 
 
+def test_taylor_pieces_meet_only_at_the_breaks_2_and_6():
+    # three polynomials, discontinuous exactly at x = 2 and x = 6: the value
+    # jumps there and nowhere else on [0.2, 20)
+    eps = 1e-9
+    def jump(b):
+        return abs(O.log_star_taylor(b) - O.log_star_taylor(b - eps))
+    for b in (2.0, 6.0):
+        assert jump(b) > 1e-4, b
+    for b in np.linspace(0.25, 19.75, 157):
+        if min(abs(b - 2.0), abs(b - 6.0)) > 1e-6:
+            assert jump(b) < 1e-7, b
+
+
 def test_taylor_error_bound_of_figure_apxlog():
     x = np.linspace(0.2, 20.0, 40001)
     x = x[np.abs(x - 1.0) > 1e-9]
