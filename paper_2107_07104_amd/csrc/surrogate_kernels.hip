@@ -186,14 +186,19 @@ struct Column {
 };
 
 // Observables at the end of split step `step` from V offset v1 (the same
-// rules as the plain reaction kernel).
-__device__ __forceinline__ void observe(const KArgs& A, int64_t i, int32_t step, float v1) {
-  const float v0 = A.v_prev[i];
-  const float uth = A.v_th - A.rest[0];
-  if (isinf(A.t_act[i]) && v0 < uth && v1 >= uth)
+// rules as the plain reaction kernel), given the node's V offset v0 at the
+// end of the previous step, its activation time t0 so far and the threshold
+// offset uth = v_th - rest_V.
+__device__ __forceinline__ void observe_with(const KArgs& A, int64_t i, int32_t step, float v1,
+                                             float v0, float t0, float uth) {
+  if (isinf(t0) && v0 < uth && v1 >= uth)
     A.t_act[i] = fmaf(A.dt, (uth - v0) / (v1 - v0), (float)step * A.dt);
   A.v_prev[i] = v1;
   if (!isfinite(v1)) atomicOr(A.flag, 1);
+}
+
+__device__ __forceinline__ void observe(const KArgs& A, int64_t i, int32_t step, float v1) {
+  observe_with(A, i, step, v1, A.v_prev[i], A.t_act[i], A.v_th - A.rest[0]);
 }
 
 template <int KIN_PAD, int OUT_PAD>
@@ -325,6 +330,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
   char* stage_base = reinterpret_cast<char*>(tab + kSurTabFloats);
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   char* stage = stage_base + wave * St::kBytes;
+  // each lane's (v_prev, t_act), loaded with the tile's states and read back
+  // by the observables after the corrector, and the threshold offset: kept
+  // in LDS because with ST57 no register is free across the network (in
+  // registers they were spilled to scratch, whose reload waits for every
+  // outstanding load and store of the wave)
+  float2* obs = reinterpret_cast<float2*>(stage_base + WAVES * St::kBytes) + wave * 64;
+  float* uth_lds = reinterpret_cast<float*>(stage_base + WAVES * (St::kBytes + 64 * sizeof(float2)));
 
   {
     const uint4* src = reinterpret_cast<const uint4*>(frags);
@@ -332,6 +344,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     for (int e = threadIdx.x; e < net.frag_elems / 8; e += 64 * WAVES) dst[e] = src[e];
     for (int e = threadIdx.x; e < net.bias_elems; e += 64 * WAVES) wb[e] = biases[e];
     for (int e = threadIdx.x; e < kSurTabFloats; e += 64 * WAVES) tab[e] = tab_g[e];
+    if (threadIdx.x == 0) *uth_lds = A.v_th - A.rest[0];
   }
   __syncthreads();
   int* count = counts ? counts + slot : nullptr;
@@ -351,14 +364,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     const bool real = i < nt;
     // lanes past the end read the last node (their results are dropped)
     const int64_t ic = real ? i : nt - 1;
-    float Ia = 0.0f, Ib = 0.0f;
-    bool pres_b = false;  // V_m prescribed at the start of step_b: plain path
-    {
-      const uint32_t sid = (uint32_t)A.node_stim[ic];
-      float vp;
-      Ia = stim_current(sid, A.stim, step_a);
-      pres_b = stim_eval(sid, A.stim, step_b, Ib, vp);
-    }
+    // every load of the tile is issued before the first wait: the stimulus
+    // id, the observables' inputs and the states (the stimulus evaluation
+    // then waits for the id alone)
+    const uint32_t sid = (uint32_t)A.node_stim[ic];
+    obs[lane] = make_float2(A.v_prev[ic], A.t_act[ic]);
     // this lane's node: offsets in registers for the whole tile
     float u[S];
     {
@@ -368,6 +378,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         u[k] = *col.p;
         col.next();
       }
+    }
+    float Ia = 0.0f, Ib = 0.0f;
+    bool pres_b = false;  // V_m prescribed at the start of step_b: plain path
+    {
+      float vp;
+      Ia = stim_current(sid, A.stim, step_a);
+      pres_b = stim_eval(sid, A.stim, step_b, Ib, vp);
     }
     // network inputs, one 16-byte row chunk at a time
     {
@@ -444,7 +461,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
           for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tchk[k].w;
           M::rhs_abs(y, Ia, A.inv_cm, G);
         }
-        observe(A, i, step_a, fmaf(0.5f * span, G[0], u[0]));
+        const float2 ob = obs[lane];
+        observe_with(A, i, step_a, fmaf(0.5f * span, G[0], u[0]), ob.x, ob.y, *uth_lds);
         Column col{A.state + i, nt};
 #pragma unroll
         for (int k = 0; k < S; ++k) {
@@ -658,7 +676,8 @@ static size_t sur_lds(const SurrogateNet& net) {
   using C = SurCfg<M>;
   return (size_t)net.frag_elems * 2 + (size_t)net.bias_elems * 4 +
          (size_t)kSurTabFloats * 4 +
-         (size_t)C::WAVES * Stage<C::KIN_PAD, C::OUT_PAD>::kBytes;
+         (size_t)C::WAVES * (Stage<C::KIN_PAD, C::OUT_PAD>::kBytes + 64 * sizeof(float2)) +
+         sizeof(float);
 }
 
 template <class M, int ACT>
