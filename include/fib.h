@@ -59,7 +59,7 @@ typedef enum {
   FIB_EHIP = -3,         /* a HIP runtime call failed */
   FIB_ENONFINITE = -4,   /* a non-finite state value was detected */
   FIB_ESTATE = -5,       /* call not valid in the context's current state */
-  FIB_EUNSUPPORTED = -6  /* valid request that this build cannot serve */
+  FIB_EUNSUPPORTED = -6  /* valid request that the library does not support */
 } fib_status;
 
 /* Subcellular models: Hodgkin-Huxley (4 states), the 57-state ST57 stand-in

@@ -4,7 +4,7 @@
  * Simulations of the Neuromuscular System", 2021).
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously correct
- * reference that the GPU library is judged against.  Only the test suite,
+ * reference that the GPU library is checked against.  Only the test suite,
  * the smoke check and the CPU-baseline leg of the benchmark may build, load
  * or call it.  It shares no code, header or table with the GPU library.
  *
