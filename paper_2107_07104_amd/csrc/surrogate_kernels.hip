@@ -343,15 +343,28 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
     uint4* dst = reinterpret_cast<uint4*>(wfr);
     for (int e = threadIdx.x; e < net.frag_elems / 8; e += 64 * WAVES) dst[e] = src[e];
     for (int e = threadIdx.x; e < net.bias_elems; e += 64 * WAVES) wb[e] = biases[e];
-    for (int e = threadIdx.x; e < kSurTabFloats; e += 64 * WAVES) tab[e] = tab_g[e];
+    // the input table (the corrector's tables are read as scalars)
+    for (int e = threadIdx.x; e < kTabMid; e += 64 * WAVES) tab[e] = tab_g[e];
     if (threadIdx.x == 0) *uth_lds = A.v_th - A.rest[0];
   }
   __syncthreads();
   int* count = counts ? counts + slot : nullptr;
   if (counts && blockIdx.x == 0 && threadIdx.x == 0) counts[slot ^ 1] = 0;
-  const float2* tin = reinterpret_cast<const float2*>(tab + kTabIn);    // scale, bias
-  const float2* tmid = reinterpret_cast<const float2*>(tab + kTabMid);  // scale/2, shift/2 + rest
-  const float4* tchk = reinterpret_cast<const float4*>(tab + kTabChk);  // scale, shift, thr, rest
+  const float2* tin = reinterpret_cast<const float2*>(tab + kTabIn);  // scale, bias
+  // The corrector's per-state tables are the same for every lane: they are
+  // read through the scalar cache (constant address space), not as LDS
+  // broadcasts, which moved 20 bytes per state and lane through the LDS
+  // next to the weight fragments.  The input table stays in LDS: as scalars
+  // its fused multiply-adds would each need a register move.
+  typedef __attribute__((address_space(4))) const float cfloat;
+  cfloat* tc = (cfloat*)tab_g;
+  auto tmid = [&](int k) {  // scale/2, shift/2 + rest
+    return make_float2(tc[kTabMid + 2 * k], tc[kTabMid + 2 * k + 1]);
+  };
+  auto tchk = [&](int k) {  // scale, shift, thr, rest
+    return make_float4(tc[kTabChk + 4 * k], tc[kTabChk + 4 * k + 1], tc[kTabChk + 4 * k + 2],
+                       tc[kTabChk + 4 * k + 3]);
+  };
 
   const int64_t nt = A.n_total;
   const int64_t tiles = (nt + 63) / 64;
@@ -424,7 +437,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
         Column col{pred + i, nt};
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-          const float4 t = tchk[k];
+          const float4 t = tchk(k);
           col.p[0] = fmaf(out(k), t.x, t.y);
           col.next();
         }
@@ -440,7 +453,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
       float y[S], G[S];
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float2 t = tmid[k];
+        const float2 t = tmid(k);
         y[k] = fmaf(out(k), t.x, u[k] + t.y);  // rest + u + du / 2
       }
       M::rhs_abs(y, Ia, A.inv_cm, G);
@@ -448,7 +461,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
       bool within = true;
 #pragma unroll
       for (int k = 0; k < S; ++k) {
-        const float4 t = tchk[k];
+        const float4 t = tchk(k);
         const float du = fmaf(out(k), t.x, t.y);
         within &= fabsf(fmaf(span, G[k], -du)) <= t.z;
       }
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_surrogate(
 #pragma unroll
         for (int c = 1; c < NCORR; ++c) {
 #pragma unroll
-          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tchk[k].w;
+          for (int k = 0; k < S; ++k) y[k] = fmaf(0.5f * span, G[k], u[k]) + tchk(k).w;
           M::rhs_abs(y, Ia, A.inv_cm, G);
         }
         const float2 ob = obs[lane];
